@@ -1,0 +1,569 @@
+/*
+ * grpic_oracle.cpp -- plain FP64 CPU oracle for the GRPIC particle step of
+ * Chen, Luepker & Yuan, "Introducing APERTURE: A GPU-based General
+ * Relativistic Particle-in-Cell Simulation Framework" (arXiv:2503.04558).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct reference
+ * the HIP library is checked against.  It shares no code, header, table or
+ * helper with the HIP library, and nothing in the library calls it.  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark load
+ * it (through oracle/oracle.py).
+ *
+ * What one step computes, per particle, in the paper's order:
+ *   1. Kerr-Schild 3+1 metric at the particle (App. A, eqs. ks-coefficients,
+ *      ks-variables, gamma-inverse, ks-alpha-beta, with the mass M written
+ *      back in) and its analytic first derivatives.
+ *   2. First-order (cloud-in-cell) interpolation of the six staggered field
+ *      components D^i, B^i (Sec. 2.1, Fig. Yee; CIC is the default shape of
+ *      Sec. 2.3), bilinear in grid-index space.
+ *   3. One full-step generalised Boris kick at x^n (Sec. 2.2, eqs.
+ *      boris-step, boris-plus-minus, u0bar, boris-scheme; the two half kicks
+ *      of the Strang split bundled into one, as the paper does).
+ *   4. Geodesic predictor-corrector (eqs. geodesic-predictor,
+ *      geodesic-corrector) on the right-hand sides of eq. particle-eom
+ *      without the Lorentz force, iterated ncorr times (3 by default).
+ *   5. Axis reflection and radial outflow (Sec. 2.1 boundary conditions).
+ *   6. Esirkepov charge-conserving deposit (Sec. 2.3, eqs.
+ *      esirkepov-decomp, J-integral-eqn, j-phi-deposit) with a local prefix
+ *      sum, in flux form F^r = J^r A_r, F^th = J^th A_th, G^ph = J^ph dV.
+ *
+ * Readings where the paper is silent or garbled (each is also listed in the
+ * design notes of the repository):
+ *   - positions are integrated in grid units xi = (ln r - ln r0)/dlnr,
+ *     eta = theta/dtheta; momenta are the covariant KS components u_i;
+ *   - metric derivatives are analytic at the particle position;
+ *   - "3 iterations" = predictor + 3 trapezoid corrector passes;
+ *   - J^ph carries +q (a positive charge moving in +phi gives J^ph > 0, as
+ *     dD/dt = curl H - J requires) and is stored multiplied by the cell
+ *     volume, like the other two components;
+ *   - the axis reflects the end point (eta -> -eta, u_th -> -u_th); a
+ *     particle leaving [0, Nr) in xi deposits its full move into the guard
+ *     vertices and is then removed (cell = -1);
+ *   - a particle whose end point is not finite or that moved one cell or more
+ *     in either direction is removed without depositing and counted.
+ *
+ * Build: g++ -O2 -std=c++17 -fPIC -shared -ffp-contract=off -fopenmp
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <algorithm>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+/* ------------------------------------------------------------------ */
+/* Scalar type plumbing.  Every formula below is written once over a   */
+/* scalar type T; T = double is the oracle.  T = Dual (forward-mode    */
+/* dual numbers) gives exact directional derivatives of the same code. */
+/* ------------------------------------------------------------------ */
+inline double val(double x) { return x; }
+
+struct Dual {
+    double v, d;
+    Dual(double x = 0.0, double dx = 0.0) : v(x), d(dx) {}
+};
+inline double val(const Dual& x) { return x.v; }
+inline Dual operator+(const Dual& a, const Dual& b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(const Dual& a, const Dual& b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(const Dual& a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(const Dual& a, const Dual& b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(const Dual& a, const Dual& b) {
+    return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual operator+(double a, const Dual& b) { return Dual(a + b.v, b.d); }
+inline Dual operator+(const Dual& a, double b) { return Dual(a.v + b, a.d); }
+inline Dual operator-(double a, const Dual& b) { return Dual(a - b.v, -b.d); }
+inline Dual operator-(const Dual& a, double b) { return Dual(a.v - b, a.d); }
+inline Dual operator*(double a, const Dual& b) { return Dual(a * b.v, a * b.d); }
+inline Dual operator*(const Dual& a, double b) { return Dual(a.v * b, a.d * b); }
+inline Dual operator/(const Dual& a, double b) { return Dual(a.v / b, a.d / b); }
+inline Dual operator/(double a, const Dual& b) { return Dual(a / b.v, -a * b.d / (b.v * b.v)); }
+inline Dual& operator+=(Dual& a, const Dual& b) { a = a + b; return a; }
+inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+inline Dual exp(const Dual& a) { double e = std::exp(a.v); return Dual(e, e * a.d); }
+inline Dual sin(const Dual& a) { return Dual(std::sin(a.v), std::cos(a.v) * a.d); }
+inline Dual cos(const Dual& a) { return Dual(std::cos(a.v), -std::sin(a.v) * a.d); }
+inline Dual fabs(const Dual& a) { return a.v < 0 ? -a : a; }
+using std::sqrt; using std::exp; using std::sin; using std::cos; using std::fabs;
+
+/* ------------------------------------------------------------------ */
+/* Problem description (mirrored by ctypes structures in oracle.py).   */
+/* ------------------------------------------------------------------ */
+struct Geom {
+    double a, M;                    /* spin and mass of the hole            */
+    int32_t nr, nth, guard, pitch;  /* cells in r and theta; guard vertices; row pitch */
+    double lnr0, dlnr, dth;         /* ln r at vertex 0; ln r step; theta step */
+};
+
+struct Species {
+    double q, m;
+    int32_t massless, pad;
+};
+
+/* Array element holding grid point (i, j) of any staggered quantity:
+ * rows run along r, theta is the contiguous direction.                 */
+inline long idx(const Geom& g, int i, int j) {
+    return (long)(i + g.guard) * g.pitch + (j + g.guard);
+}
+
+/* Stagger of each field component, Fig. Yee:
+ * D^r, B^th at (i+1/2, j); D^th, B^r at (i, j+1/2); D^ph at (i, j);
+ * B^ph at (i+1/2, j+1/2).  Order: D^r, D^th, D^ph, B^r, B^th, B^ph.   */
+const double kStagR[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
+const double kStagT[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
+
+/* ------------------------------------------------------------------ */
+/* 1. Kerr-Schild metric, App. A, with M reinstated.                   */
+/* ------------------------------------------------------------------ */
+template <class T>
+struct KS {
+    T alpha, beta;                      /* lapse; radial shift beta^r        */
+    T g_rr, g_rp, g_tt, g_pp;           /* gamma_ij                          */
+    T h_rr, h_rp, h_tt, h_pp;           /* gamma^ij                          */
+    T sqrtg;                            /* sqrt(det gamma_ij)                */
+    T dal[2], dbe[2];                   /* d/dr, d/dtheta of alpha, beta^r   */
+    T dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];   /* of gamma^ij               */
+};
+
+template <class T>
+void ks_metric(double a, double M, const T& r, const T& th, KS<T>& k) {
+    const T s = sin(th), c = cos(th);
+    const T s2 = s * s, c2 = c * c;
+    const T rho2 = r * r + a * a * c2;                      /* rho^2        */
+    const T z = 2.0 * M * r / rho2;                         /* z = 2Mr/rho^2 */
+    const T Delta = r * r + a * a - 2.0 * M * r;
+    const T Sigma = (r * r + a * a) * (r * r + a * a) - a * a * Delta * s2;
+
+    k.g_rr = 1.0 + z;
+    k.g_rp = -a * s2 * (1.0 + z);
+    k.g_tt = rho2;
+    k.g_pp = Sigma * s2 / rho2;
+
+    k.h_rr = (a * a + r * r) / rho2 - 2.0 * M * r / (rho2 + 2.0 * M * r);
+    k.h_rp = a / rho2;
+    k.h_tt = 1.0 / rho2;
+    k.h_pp = 1.0 / (rho2 * s2);
+
+    k.alpha = 1.0 / sqrt(1.0 + z);
+    k.beta = z / (1.0 + z);
+    /* det gamma_ij = (1+z) rho^4 sin^2(theta): not printed in the paper,
+     * follows from the printed gamma_ij.                                  */
+    k.sqrtg = rho2 * s * sqrt(1.0 + z);
+
+    /* Analytic derivatives (the paper does not say how they are formed). */
+    const T rho4 = rho2 * rho2;
+    const T drho2[2] = {2.0 * r, -2.0 * a * a * s * c};
+    const T dz[2] = {2.0 * M * (rho2 - 2.0 * r * r) / rho4,
+                     4.0 * M * a * a * r * s * c / rho4};
+    const T al3 = k.alpha * k.alpha * k.alpha;
+    const T al4 = al3 * k.alpha;
+    for (int d = 0; d < 2; ++d) {
+        k.dal[d] = -0.5 * al3 * dz[d];              /* alpha = (1+z)^(-1/2) */
+        k.dbe[d] = al4 * dz[d];                     /* beta = z/(1+z)       */
+        k.dh_rp[d] = -a * drho2[d] / rho4;
+        k.dh_tt[d] = -drho2[d] / rho4;
+    }
+    /* gamma^rr = (r^2+a^2)/rho^2 - beta^r */
+    k.dh_rr[0] = -2.0 * r * a * a * s2 / rho4 - k.dbe[0];
+    k.dh_rr[1] = 2.0 * a * a * (r * r + a * a) * s * c / rho4 - k.dbe[1];
+    /* gamma^phph = 1/(rho^2 sin^2) */
+    k.dh_pp[0] = -2.0 * r / (rho4 * s2);
+    k.dh_pp[1] = -(drho2[1] * s2 + 2.0 * rho2 * s * c) / (rho4 * s2 * s2);
+}
+
+/* ------------------------------------------------------------------ */
+/* 4a. Right-hand sides X^i, U_i of eq. particle-eom without F_i, in    */
+/*     grid units: y = (xi, eta, phi, u_r, u_th, u_ph).                  */
+/* ------------------------------------------------------------------ */
+template <class T>
+void geodesic_rhs(const Geom& g, double eps, const T y[6], T f[6]) {
+    const T r = exp(g.lnr0 + y[0] * g.dlnr);
+    const T th = y[1] * g.dth;
+    KS<T> k;
+    ks_metric(g.a, g.M, r, th, k);
+    const T ur = y[3], ut = y[4], up = y[5];
+    const T uu = k.h_rr * ur * ur + 2.0 * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
+    const T u0 = sqrt(eps + uu) / k.alpha;                  /* u^0 */
+    /* dx^i/dt = gamma^ij u_j / u^0 - beta^i; xi = (ln r - ln r0)/dlnr */
+    f[0] = ((k.h_rr * ur + k.h_rp * up) / u0 - k.beta) / (r * g.dlnr);
+    f[1] = k.h_tt * ut / u0 / g.dth;
+    f[2] = (k.h_rp * ur + k.h_pp * up) / u0;
+    /* du_i/dt = -alpha u^0 d_i alpha + u_k d_i beta^k - u_j u_k d_i gamma^jk / (2 u^0) */
+    for (int d = 0; d < 2; ++d) {
+        const T quad = ur * ur * k.dh_rr[d] + 2.0 * ur * up * k.dh_rp[d]
+                     + ut * ut * k.dh_tt[d] + up * up * k.dh_pp[d];
+        f[3 + d] = -k.alpha * u0 * k.dal[d] + ur * k.dbe[d] - quad / (2.0 * u0);
+    }
+    f[5] = T(0.0);                                          /* d_phi of nothing */
+}
+
+/* ------------------------------------------------------------------ */
+/* 2. CIC gather of one staggered component, bilinear in index space.  */
+/* ------------------------------------------------------------------ */
+template <class T, class F>
+T cic_gather(const Geom& g, const F* arr, double sr, double st, const T& xi, const T& eta) {
+    const T f = xi - sr, h = eta - st;
+    const int i = (int)std::floor(val(f)), j = (int)std::floor(val(h));
+    const T wf = f - (double)i, wh = h - (double)j;
+    return (1.0 - wf) * (1.0 - wh) * arr[idx(g, i, j)]
+         + wf * (1.0 - wh) * arr[idx(g, i + 1, j)]
+         + (1.0 - wf) * wh * arr[idx(g, i, j + 1)]
+         + wf * wh * arr[idx(g, i + 1, j + 1)];
+}
+
+/* ------------------------------------------------------------------ */
+/* 3. Generalised Boris kick, full step, metric and fields at x^n.     */
+/* ------------------------------------------------------------------ */
+/* (v x w)_i = e_ijk v^j w^k with e_ijk = sqrt(gamma) eps_ijk; v given   */
+/* covariant (raised with gamma^ij), w contravariant.                   */
+template <class T>
+void cross_lower(const KS<T>& k, const T v[3], const T w[3], T out[3]) {
+    const T vr = k.h_rr * v[0] + k.h_rp * v[2];
+    const T vt = k.h_tt * v[1];
+    const T vp = k.h_rp * v[0] + k.h_pp * v[2];
+    out[0] = k.sqrtg * (vt * w[2] - vp * w[1]);
+    out[1] = k.sqrtg * (vp * w[0] - vr * w[2]);
+    out[2] = k.sqrtg * (vr * w[1] - vt * w[0]);
+}
+
+template <class T>
+void boris_kick(const KS<T>& k, double qm, double dt, const T D[3], const T B[3], T u[3]) {
+    /* half electric kick (q/m)(alpha dt/2) gamma_ij D^j */
+    const T Dl[3] = {k.g_rr * D[0] + k.g_rp * D[2], k.g_tt * D[1], k.g_rp * D[0] + k.g_pp * D[2]};
+    const T h = qm * k.alpha * dt * 0.5;
+    T um[3];
+    for (int c = 0; c < 3; ++c) um[c] = u[c] + h * Dl[c];
+    /* ubar^0 from u^- (eq. u0bar) */
+    const T uu = k.h_rr * um[0] * um[0] + 2.0 * k.h_rp * um[0] * um[2]
+               + k.h_tt * um[1] * um[1] + k.h_pp * um[2] * um[2];
+    const T u0bar = sqrt(1.0 + uu) / k.alpha;
+    T t[3];
+    for (int c = 0; c < 3; ++c) t[c] = qm * B[c] * dt / (2.0 * u0bar);
+    /* t^k t_k with t_k = gamma_kl t^l */
+    const T tt = k.g_rr * t[0] * t[0] + 2.0 * k.g_rp * t[0] * t[2]
+               + k.g_tt * t[1] * t[1] + k.g_pp * t[2] * t[2];
+    T x[3], ut[3], s[3], up[3];
+    cross_lower(k, um, t, x);
+    for (int c = 0; c < 3; ++c) ut[c] = um[c] + x[c];
+    for (int c = 0; c < 3; ++c) s[c] = 2.0 * t[c] / (1.0 + tt);
+    cross_lower(k, ut, s, x);
+    for (int c = 0; c < 3; ++c) up[c] = um[c] + x[c];
+    for (int c = 0; c < 3; ++c) u[c] = up[c] + h * Dl[c];
+}
+
+/* ------------------------------------------------------------------ */
+/* 3+4. Kick at x^n, then the geodesic predictor-corrector.            */
+/* Returns the raw end point y1 = (xi, eta, phi, u_r, u_th, u_ph).     */
+/* ------------------------------------------------------------------ */
+template <class T>
+void push_with_fields(const Geom& g, const Species& sp, double dt, int ncorr,
+                      const T& xi, const T& eta, const T u[3], const T D[3], const T B[3], T y1[6]) {
+    T uk[3] = {u[0], u[1], u[2]};
+    const double eps = sp.massless ? 0.0 : 1.0;
+    if (!sp.massless) {                 /* photons skip the Boris step */
+        const T r = exp(g.lnr0 + xi * g.dlnr);
+        const T th = eta * g.dth;
+        KS<T> k;
+        ks_metric(g.a, g.M, r, th, k);
+        boris_kick(k, sp.q / sp.m, dt, D, B, uk);
+    }
+    const T y0[6] = {xi, eta, T(0.0), uk[0], uk[1], uk[2]};
+    T f0[6], f1[6], yt[6];
+    geodesic_rhs(g, eps, y0, f0);
+    for (int c = 0; c < 6; ++c) yt[c] = y0[c] + dt * f0[c];            /* predictor */
+    for (int it = 0; it < ncorr; ++it) {                                 /* corrector */
+        geodesic_rhs(g, eps, yt, f1);
+        for (int c = 0; c < 6; ++c) yt[c] = y0[c] + 0.5 * dt * (f1[c] + f0[c]);
+    }
+    for (int c = 0; c < 6; ++c) y1[c] = yt[c];
+}
+
+/* ------------------------------------------------------------------ */
+/* 6. Esirkepov deposit of one move (xi0,eta0) -> (xi1,eta1).          */
+/* ------------------------------------------------------------------ */
+template <class T>
+T shape1(const T& x) {                  /* CIC: W(x) = max(0, 1 - |x|) */
+    const T ax = fabs(x);
+    return val(ax) >= 1.0 ? T(0.0) : 1.0 - ax;
+}
+
+/* Accumulator with Neumaier compensation, so that the summed J is close
+ * to correctly rounded whatever the particle order.                    */
+struct Acc {
+    double* sum;
+    double* comp;
+    double* abs_sum;        /* optional: sum of |contribution| per element */
+    void add(long e, double x) {
+        const double s = sum[e], t = s + x;
+        if (std::fabs(s) >= std::fabs(x)) comp[e] += (s - t) + x;
+        else comp[e] += (x - t) + s;
+        sum[e] = t;
+        if (abs_sum) abs_sum[e] += std::fabs(x);
+    }
+};
+
+struct PlainAcc {
+    double* sum;
+    void add(long e, double x) { sum[e] += x; }
+};
+
+template <class T>
+struct Move {
+    int i0, j0;
+    T Fr[2][3];     /* flux through (i0+a+1/2, j0+b) */
+    T Ft[3][2];     /* flux through (i0+a, j0+b+1/2) */
+    T Gp[3][3];     /* J^ph dV at (i0+a, j0+b)       */
+};
+
+template <class T>
+void esirkepov(double qw, double dt, const T& xi0, const T& eta0, const T& xi1, const T& eta1,
+               const T& dphi, Move<T>& mv) {
+    mv.i0 = (int)std::floor(std::min(val(xi0), val(xi1)));
+    mv.j0 = (int)std::floor(std::min(val(eta0), val(eta1)));
+    T Wr[3][3], Wt[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const T wx0 = shape1(xi0 - (double)(mv.i0 + a));
+        const T wx1 = shape1(xi1 - (double)(mv.i0 + a));
+        for (int b = 0; b < 3; ++b) {
+            const T wy0 = shape1(eta0 - (double)(mv.j0 + b));
+            const T wy1 = shape1(eta1 - (double)(mv.j0 + b));
+            /* S_ab = S(xi^a, eta^b), superscripts 0 = step n, 1 = step n+1 */
+            const T S00 = wx0 * wy0, S01 = wx0 * wy1, S10 = wx1 * wy0, S11 = wx1 * wy1;
+            Wr[a][b] = 0.5 * (S11 - S01 + S10 - S00);       /* Delta rho_r / q */
+            Wt[a][b] = 0.5 * (S11 - S10 + S01 - S00);       /* Delta rho_th / q */
+            mv.Gp[a][b] = qw * dphi / dt * (S11 / 3.0 + S10 / 6.0 + S01 / 6.0 + S00 / 3.0);
+        }
+    }
+    /* local prefix sums, zero flux on the low side of the window */
+    for (int b = 0; b < 3; ++b) {
+        T run(0.0);
+        for (int a = 0; a < 2; ++a) { run = run + Wr[a][b]; mv.Fr[a][b] = -qw / dt * run; }
+    }
+    for (int a = 0; a < 3; ++a) {
+        T run(0.0);
+        for (int b = 0; b < 2; ++b) { run = run + Wt[a][b]; mv.Ft[a][b] = -qw / dt * run; }
+    }
+}
+
+template <class AccT>
+void scatter_move(const Geom& g, const Move<double>& mv, AccT& Fr, AccT& Ft, AccT& Gp) {
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) Fr.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Fr[a][b]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 2; ++b) Ft.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Ft[a][b]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Gp.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Gp[a][b]);
+}
+
+/* ------------------------------------------------------------------ */
+/* One particle, one step: gather, push, boundaries, deposit, store.   */
+/* ------------------------------------------------------------------ */
+enum { ST_ALIVE = 0, ST_OUT = 1, ST_BAD = 2, ST_DEAD = 3 };
+
+struct Outcome {
+    int status;
+    int reflected;
+    Move<double> mv;
+    int32_t cell;
+    double xr, xth, u[3], dphi;
+};
+
+Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], double w, double dt, int ncorr,
+                 int32_t cell, double xr, double xth, const double u[3]) {
+    Outcome o;
+    o.reflected = 0;
+    o.status = ST_DEAD;
+    if (cell < 0) return o;
+    const int ci = cell / g.nth, cj = cell % g.nth;
+    const double xi0 = ci + xr, eta0 = cj + xth;
+
+    double D[3], B[3];
+    for (int c = 0; c < 3; ++c) {
+        D[c] = cic_gather(g, F[c], kStagR[c], kStagT[c], xi0, eta0);
+        B[c] = cic_gather(g, F[3 + c], kStagR[3 + c], kStagT[3 + c], xi0, eta0);
+    }
+    double y1[6];
+    push_with_fields(g, sp, dt, ncorr, xi0, eta0, u, D, B, y1);
+
+    double xi1 = y1[0], eta1 = y1[1];
+    double u1[3] = {y1[3], y1[4], y1[5]};
+    bool finite = std::isfinite(xi1) && std::isfinite(eta1) && std::isfinite(y1[2]);
+    for (int c = 0; c < 3; ++c) finite = finite && std::isfinite(u1[c]);
+    if (!finite || std::fabs(xi1 - xi0) >= 1.0 || std::fabs(eta1 - eta0) >= 1.0) {
+        o.status = ST_BAD;
+        o.cell = -1;
+        return o;
+    }
+    /* 5. axis reflection */
+    if (eta1 < 0.0) { eta1 = -eta1; u1[1] = -u1[1]; o.reflected = 1; }
+    else if (eta1 > (double)g.nth) { eta1 = 2.0 * g.nth - eta1; u1[1] = -u1[1]; o.reflected = 1; }
+
+    esirkepov(sp.q * w, dt, xi0, eta0, xi1, eta1, y1[2], o.mv);
+    o.dphi = y1[2];
+    if (xi1 < 0.0 || xi1 >= (double)g.nr) {     /* radial outflow: removed after depositing */
+        o.status = ST_OUT;
+        o.cell = -1;
+        return o;
+    }
+    /* 7. store as cell + offset */
+    const int i1 = (int)std::floor(xi1);
+    int j1 = (int)std::floor(eta1);
+    if (j1 >= g.nth) j1 = g.nth - 1;
+    o.status = ST_ALIVE;
+    o.cell = i1 * g.nth + j1;
+    o.xr = xi1 - i1;
+    o.xth = eta1 - j1;
+    for (int c = 0; c < 3; ++c) o.u[c] = u1[c];
+    return o;
+}
+
+}  // namespace
+
+/* ==================================================================== */
+/* C entry points used by oracle/oracle.py (ctypes).                    */
+/* ==================================================================== */
+extern "C" {
+
+/* Metric at (r, theta).  out[23]: alpha, beta^r, g_rr, g_rph, g_thth, g_phph,
+ * h_rr, h_rph, h_thth, h_phph, sqrtg, then d/dr and d/dtheta of alpha,
+ * beta^r, h_rr, h_rph, h_thth, h_phph (interleaved r, theta).            */
+void orc_metric(double a, double M, double r, double th, double* out) {
+    KS<double> k;
+    ks_metric(a, M, r, th, k);
+    const double v[11] = {k.alpha, k.beta, k.g_rr, k.g_rp, k.g_tt, k.g_pp,
+                          k.h_rr, k.h_rp, k.h_tt, k.h_pp, k.sqrtg};
+    std::memcpy(out, v, sizeof v);
+    const double* d[6] = {k.dal, k.dbe, k.dh_rr, k.dh_rp, k.dh_tt, k.dh_pp};
+    for (int q = 0; q < 6; ++q) { out[11 + 2 * q] = d[q][0]; out[12 + 2 * q] = d[q][1]; }
+}
+
+void orc_rhs(const Geom* g, double eps, const double* y, double* f) { geodesic_rhs(*g, eps, y, f); }
+
+void orc_boris(const Geom* g, double qm, double dt, double xi, double eta,
+               const double* u, const double* D, const double* B, double* out) {
+    const double r = std::exp(g->lnr0 + xi * g->dlnr), th = eta * g->dth;
+    KS<double> k;
+    ks_metric(g->a, g->M, r, th, k);
+    double uk[3] = {u[0], u[1], u[2]};
+    boris_kick(k, qm, dt, D, B, uk);
+    for (int c = 0; c < 3; ++c) out[c] = uk[c];
+}
+
+/* Kick with the given fields at x^n, then the geodesic PC; no boundaries. */
+void orc_push_point(const Geom* g, const Species* sp, double dt, int ncorr, double xi, double eta,
+                    const double* u, const double* D, const double* B, double* y1) {
+    push_with_fields(*g, *sp, dt, ncorr, xi, eta, u, D, B, y1);
+}
+
+void orc_gather(const Geom* g, const double* const* F, double xi, double eta, double* out) {
+    for (int c = 0; c < 6; ++c) out[c] = cic_gather(*g, F[c], kStagR[c], kStagT[c], xi, eta);
+}
+
+/* Deposit one move into Fr, Fth, Gph (plain +=). */
+void orc_deposit_move(const Geom* g, double qw, double dt, double xi0, double eta0,
+                      double xi1, double eta1, double dphi, double* Fr, double* Fth, double* Gph) {
+    Move<double> mv;
+    esirkepov(qw, dt, xi0, eta0, xi1, eta1, dphi, mv);
+    PlainAcc a{Fr}, b{Fth}, c{Gph};
+    scatter_move(*g, mv, a, b, c);
+}
+
+/* Charge Q_ij = sum_p q w S_ij(x_p) over live particles (Q is +=). */
+void orc_charge(const Geom* g, const Species* sp, int nsp, int64_t n, const int32_t* cell,
+                const double* xr, const double* xth, const double* w, const uint8_t* spi, double* Q) {
+    (void)nsp;
+    for (int64_t p = 0; p < n; ++p) {
+        if (cell[p] < 0) continue;
+        const int i = cell[p] / g->nth, j = cell[p] % g->nth;
+        const double qw = sp[spi[p]].q * w[p];
+        const double fx = xr[p], fy = xth[p];
+        Q[idx(*g, i, j)] += qw * (1.0 - fx) * (1.0 - fy);
+        Q[idx(*g, i + 1, j)] += qw * fx * (1.0 - fy);
+        Q[idx(*g, i, j + 1)] += qw * (1.0 - fx) * fy;
+        Q[idx(*g, i + 1, j + 1)] += qw * fx * fy;
+    }
+}
+
+/* nsteps full steps over all particles, updated in place.  J arrays are +=.
+ * nthreads == 1: serial, Neumaier-compensated J (parity mode), optional
+ * A arrays receive sum |contribution|.  nthreads > 1: OpenMP over particles
+ * with thread-private J reduced in thread order (timing mode).
+ * stats[4] (+=): particles removed at the radial edges, removed as
+ * non-finite or moving >= 1 cell, axis reflections, live particle-steps.  */
+void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
+             int32_t* cell, double* xr, double* xth, double* ur, double* uth, double* uph,
+             const double* w, const uint8_t* spi, double* phi,
+             const double* const* F, double* Fr, double* Fth, double* Gph,
+             double* Afr, double* Afth, double* Agph,
+             double dt, int nsteps, int ncorr, int nthreads, int64_t* stats) {
+    (void)nsp;
+    const Geom& g = *gp;
+    const long ncell = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
+    int64_t st_out = 0, st_bad = 0, st_refl = 0, st_live = 0;
+
+    if (nthreads <= 1) {
+        std::vector<double> cr(ncell, 0.0), ct(ncell, 0.0), cp(ncell, 0.0);
+        Acc A_r{Fr, cr.data(), Afr}, A_t{Fth, ct.data(), Afth}, A_p{Gph, cp.data(), Agph};
+        for (int s = 0; s < nsteps; ++s) {
+            for (int64_t p = 0; p < n; ++p) {
+                const double u[3] = {ur[p], uth[p], uph[p]};
+                Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
+                if (o.status == ST_DEAD) continue;
+                ++st_live;
+                if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
+                st_refl += o.reflected;
+                scatter_move(g, o.mv, A_r, A_t, A_p);
+                if (phi) phi[p] += o.dphi;
+                if (o.status == ST_OUT) { ++st_out; cell[p] = -1; continue; }
+                cell[p] = o.cell; xr[p] = o.xr; xth[p] = o.xth;
+                ur[p] = o.u[0]; uth[p] = o.u[1]; uph[p] = o.u[2];
+            }
+        }
+        for (long e = 0; e < ncell; ++e) { Fr[e] += cr[e]; Fth[e] += ct[e]; Gph[e] += cp[e]; }
+    } else {
+#ifdef _OPENMP
+        const int nt = nthreads;
+        std::vector<std::vector<double>> priv(nt, std::vector<double>(3 * ncell, 0.0));
+        for (int s = 0; s < nsteps; ++s) {
+#pragma omp parallel num_threads(nt) reduction(+ : st_out, st_bad, st_refl, st_live)
+            {
+                const int tid = omp_get_thread_num();
+                PlainAcc A_r{priv[tid].data()}, A_t{priv[tid].data() + ncell}, A_p{priv[tid].data() + 2 * ncell};
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < n; ++p) {
+                    const double u[3] = {ur[p], uth[p], uph[p]};
+                    Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
+                    if (o.status == ST_DEAD) continue;
+                    ++st_live;
+                    if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
+                    st_refl += o.reflected;
+                    scatter_move(g, o.mv, A_r, A_t, A_p);
+                    if (phi) phi[p] += o.dphi;
+                    if (o.status == ST_OUT) { ++st_out; cell[p] = -1; continue; }
+                    cell[p] = o.cell; xr[p] = o.xr; xth[p] = o.xth;
+                    ur[p] = o.u[0]; uth[p] = o.u[1]; uph[p] = o.u[2];
+                }
+            }
+        }
+        for (int t = 0; t < nt; ++t)
+            for (long e = 0; e < ncell; ++e) {
+                Fr[e] += priv[t][e]; Fth[e] += priv[t][ncell + e]; Gph[e] += priv[t][2 * ncell + e];
+            }
+#endif
+    }
+    if (stats) { stats[0] += st_out; stats[1] += st_bad; stats[2] += st_refl; stats[3] += st_live; }
+}
+
+int orc_has_openmp(void) {
+#ifdef _OPENMP
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+}  /* extern "C" */

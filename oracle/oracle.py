@@ -1,0 +1,202 @@
+"""ctypes front end of the FP64 CPU oracle in grpic_oracle.cpp.
+
+TEST INFRASTRUCTURE ONLY: the plain, slow reference that the HIP library is
+checked against.  Only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark import this module; the library never does.  It imports
+nothing from the HIP package: grids are duck-typed (any object with the
+attributes a, M, nr, nth, guard, pitch, lnr0, dlnr, dth works).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "grpic_oracle.cpp")
+SO = os.path.join(_HERE, "libgrpic_oracle.so")
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("M", ctypes.c_double),
+                ("nr", ctypes.c_int32), ("nth", ctypes.c_int32),
+                ("guard", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("lnr0", ctypes.c_double), ("dlnr", ctypes.c_double), ("dth", ctypes.c_double)]
+
+
+class Species(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double),
+                ("massless", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+def build() -> str:
+    """Compile the oracle (g++, no FMA contraction, OpenMP for timing mode)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+           SRC, "-o", SO + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(SO + ".tmp", SO)
+    return SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            build()
+        _lib = ctypes.CDLL(SO)
+    return _lib
+
+
+def geom(grid) -> Geom:
+    return Geom(float(grid.a), float(grid.M), int(grid.nr), int(grid.nth), int(grid.guard),
+                int(grid.pitch), float(grid.lnr0), float(grid.dlnr), float(grid.dth))
+
+
+def _p(x: np.ndarray):
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+METRIC_KEYS = ("alpha", "beta", "g_rr", "g_rph", "g_thth", "g_phph",
+               "h_rr", "h_rph", "h_thth", "h_phph", "sqrtg")
+METRIC_DKEYS = ("alpha", "beta", "h_rr", "h_rph", "h_thth", "h_phph")
+
+
+def metric(a: float, M: float, r: float, th: float) -> dict:
+    out = np.zeros(23)
+    lib().orc_metric(ctypes.c_double(a), ctypes.c_double(M), ctypes.c_double(r),
+                     ctypes.c_double(th), _p(out))
+    d = {k: out[i] for i, k in enumerate(METRIC_KEYS)}
+    for q, k in enumerate(METRIC_DKEYS):
+        d["dr_" + k] = out[11 + 2 * q]
+        d["dth_" + k] = out[12 + 2 * q]
+    return d
+
+
+def rhs(grid, y, eps: float = 1.0) -> np.ndarray:
+    g = geom(grid)
+    y = _f64(y)
+    f = np.zeros(6)
+    lib().orc_rhs(ctypes.byref(g), ctypes.c_double(eps), _p(y), _p(f))
+    return f
+
+
+def boris(grid, qm, dt, xi, eta, u, D, B) -> np.ndarray:
+    g = geom(grid)
+    u, D, B = _f64(u), _f64(D), _f64(B)
+    out = np.zeros(3)
+    lib().orc_boris(ctypes.byref(g), ctypes.c_double(qm), ctypes.c_double(dt), ctypes.c_double(xi),
+                    ctypes.c_double(eta), _p(u), _p(D), _p(B), _p(out))
+    return out
+
+
+def push_point(grid, q, m, dt, xi, eta, u, D, B, ncorr: int = 3, massless: bool = False) -> np.ndarray:
+    """Kick with point fields D, B at x^n, then the geodesic PC (no boundaries).
+
+    Returns y1 = (xi, eta, dphi, u_r, u_th, u_ph)."""
+    g = geom(grid)
+    sp = Species(float(q), float(m), int(massless), 0)
+    u, D, B = _f64(u), _f64(D), _f64(B)
+    y1 = np.zeros(6)
+    lib().orc_push_point(ctypes.byref(g), ctypes.byref(sp), ctypes.c_double(dt), ctypes.c_int(ncorr),
+                         ctypes.c_double(xi), ctypes.c_double(eta), _p(u), _p(D), _p(B), _p(y1))
+    return y1
+
+
+def gather(grid, fields, xi, eta) -> np.ndarray:
+    g = geom(grid)
+    fl = [_f64(f) for f in fields]
+    ptrs = (ctypes.c_void_p * 6)(*[f.ctypes.data for f in fl])
+    out = np.zeros(6)
+    lib().orc_gather(ctypes.byref(g), ptrs, ctypes.c_double(xi), ctypes.c_double(eta), _p(out))
+    return out
+
+
+def deposit_move(grid, qw, dt, xi0, eta0, xi1, eta1, dphi, J=None):
+    """Deposit of one move; returns (Fr, Fth, Gph) arrays (added to J if given)."""
+    g = geom(grid)
+    if J is None:
+        J = [np.zeros((grid.nr + 1 + 2 * grid.guard, grid.pitch)) for _ in range(3)]
+    lib().orc_deposit_move(ctypes.byref(g), ctypes.c_double(qw), ctypes.c_double(dt),
+                           ctypes.c_double(xi0), ctypes.c_double(eta0), ctypes.c_double(xi1),
+                           ctypes.c_double(eta1), ctypes.c_double(dphi), _p(J[0]), _p(J[1]), _p(J[2]))
+    return J
+
+
+def _species_array(species):
+    arr = (Species * len(species))()
+    for i, s in enumerate(species):
+        arr[i] = Species(float(s["q"]), float(s["m"]), int(s.get("massless", 0)), 0)
+    return arr
+
+
+def charge(grid, species, parts) -> np.ndarray:
+    """Q_ij = sum over live particles of q w S_ij(x_p)."""
+    g = geom(grid)
+    sp = _species_array(species)
+    cell = np.ascontiguousarray(parts["cell"], dtype=np.int32)
+    xr, xth, w = _f64(parts["xr"]), _f64(parts["xth"]), _f64(parts["w"])
+    spi = np.ascontiguousarray(parts["sp"], dtype=np.uint8)
+    Q = np.zeros((grid.nr + 1 + 2 * grid.guard, grid.pitch))
+    lib().orc_charge(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(len(cell)),
+                     _p(cell), _p(xr), _p(xth), _p(w), _p(spi), _p(Q))
+    return Q
+
+
+PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
+
+
+def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int = 1,
+        with_abs: bool = False, track_phi: bool = False, J=None):
+    """Advance copies of the particle arrays nsteps steps.
+
+    Returns (parts_out, J, A, stats): J = [Fr, Fth, Gph] (added to the given
+    J if any), A = the matching sums of |contribution| (with_abs, serial
+    only) and stats = dict(out, bad, reflected, live_steps).
+    """
+    g = geom(grid)
+    sp = _species_array(species)
+    p = {
+        "cell": np.array(parts["cell"], dtype=np.int32, copy=True),
+        "xr": np.array(parts["xr"], dtype=np.float64, copy=True),
+        "xth": np.array(parts["xth"], dtype=np.float64, copy=True),
+        "ur": np.array(parts["ur"], dtype=np.float64, copy=True),
+        "uth": np.array(parts["uth"], dtype=np.float64, copy=True),
+        "uph": np.array(parts["uph"], dtype=np.float64, copy=True),
+        "w": _f64(parts["w"]),
+        "sp": np.ascontiguousarray(parts["sp"], dtype=np.uint8),
+    }
+    n = len(p["cell"])
+    if track_phi:
+        p["phi"] = np.array(parts.get("phi", np.zeros(n)), dtype=np.float64, copy=True)
+    shape = (grid.nr + 1 + 2 * grid.guard, grid.pitch)
+    if J is None:
+        J = [np.zeros(shape) for _ in range(3)]
+    A = [np.zeros(shape) for _ in range(3)] if with_abs else None
+    fl = [_f64(f) for f in fields]
+    fptr = (ctypes.c_void_p * 6)(*[f.ctypes.data for f in fl])
+    stats = np.zeros(4, dtype=np.int64)
+    null = ctypes.c_void_p(0)
+    lib().orc_run(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(n),
+                  _p(p["cell"]), _p(p["xr"]), _p(p["xth"]), _p(p["ur"]), _p(p["uth"]), _p(p["uph"]),
+                  _p(p["w"]), _p(p["sp"]), _p(p["phi"]) if track_phi else null,
+                  fptr, _p(J[0]), _p(J[1]), _p(J[2]),
+                  _p(A[0]) if A else null, _p(A[1]) if A else null, _p(A[2]) if A else null,
+                  ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(ncorr),
+                  ctypes.c_int(nthreads), _p(stats))
+    st = dict(out=int(stats[0]), bad=int(stats[1]), reflected=int(stats[2]), live_steps=int(stats[3]))
+    return p, J, A, st
+
+
+def has_openmp() -> bool:
+    return bool(lib().orc_has_openmp())
