@@ -1,0 +1,214 @@
+"""Benchmark of the GRPIC push + deposit hot path on one MI355X.
+
+Workload (the largest single-GPU configuration): 2048 x 2048 Kerr-Schild
+log-r grid (r from 0.9 r_+ to 50 r_g), spin a = 0.99, M = 1, vacuum Wald
+field B0 = 1, 2e8 e+- particles (1e8 pairs placed per cell, Maxwell-Juttner
+momenta at T = 0.1 m c^2 plus a 0.1c bulk rotation in phi, seed 0), dt = half
+the light-crossing time of the smallest cell, ncorr = 3, particles re-sorted
+by cell every 20 steps.  A step is one push + deposit of every particle (with
+the sort on every 20th step), FP64.
+
+Output: one JSON line.  value = live particle-steps per second over the timed
+steps.  roofline: the push+deposit kernel's duration from HIP events on its
+stream, against the binding ceiling (see the design notes); cpu_baseline: the
+FP64 CPU oracle on a bounded sample of the same workload (rank 0, N = 1 only).
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, TFLOP/s
+
+# Algorithmic HBM bytes of one FP64 particle-step: read cell (4) + xr, xth,
+# ur, uth, uph, w (48) + sp (1); write cell (4) + xr, xth, ur, uth, uph (40).
+FP64_PARTICLE_BYTES = 53 + 44
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(npairs: int, nr: int, nth: int, a: float, device: str = "cuda", workers: int = 16):
+    import torch
+
+    from paper_2503_04558_amd import grpic
+    from paper_2503_04558_amd import workload as wl
+
+    g = wl.make_grid(nr, nth, a)
+    F = [torch.as_tensor(f).to(device) for f in wl.wald_fields(g, B0=1.0)]
+    n = 2 * npairs
+    parts = grpic.empty_particles(n, device=device)
+
+    def sink(start, arrs):
+        m = len(arrs["cell"])
+        for k, v in arrs.items():
+            parts[k][start:start + m].copy_(torch.from_numpy(np.ascontiguousarray(v)))
+
+    wl.pairs(g, npairs, kind="mj", seed=0, params=dict(T=0.1, vphi=0.1), workers=workers, sink=sink)
+    return g, F, parts
+
+
+def run_gpu(args):
+    import torch
+
+    from paper_2503_04558_amd import grpic
+    from paper_2503_04558_amd import workload as wl
+
+    dev = "cuda"
+    t0 = time.time()
+    g, F, parts = make_workload(args.pairs, args.nr, args.nth, args.spin, workers=args.workers)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f}s: grid {g.nr}x{g.nth}, {2 * args.pairs} particles")
+    sp = wl.species_table()
+    metric = grpic.make_metric(g.a, g.M)
+    dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+    J = [torch.zeros(g.shape, dtype=torch.float64, device=dev) for _ in range(3)]
+    spare = grpic.empty_particles(parts["cell"].numel(), device=dev)
+    ws = torch.empty(grpic.grpic_sort_workspace_bytes(g, parts["cell"].numel()), dtype=torch.uint8, device=dev)
+    nal = torch.zeros(1, dtype=torch.int64, device=dev)
+    counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device=dev)
+
+    state = {"p": parts, "q": spare}
+
+    def do_sort():
+        grpic.grpic_sort(g, state["p"], state["q"], None, ws, nal)
+        state["p"], state["q"] = state["q"], state["p"]
+
+    ev_push = []
+
+    def step(k, timed):
+        if k % args.sort_every == 0:
+            do_sort()
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        grpic.grpic_push_deposit(metric, g, sp, state["p"], F, J, dt, 1, args.ncorr,
+                                 counters=counters if timed else None)
+        if timed:
+            e1.record()
+            ev_push.append((e0, e1))
+
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.time()
+    start.record()
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k, True)
+    stop.record()
+    torch.cuda.synchronize()
+    t_wall = time.time() - t_wall
+    total_ms = start.elapsed_time(stop)
+    push_ms = [a.elapsed_time(b) for a, b in ev_push]
+    cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
+    log(f"timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), counters {cnt}")
+    live = cnt["live_steps"]
+    value = live / (total_ms * 1e-3)
+    avg_push_ms = float(np.mean(push_ms))
+    # roofline of the push + deposit kernel (one launch per step)
+    live_per_launch = live / args.steps
+    grid_bytes = g.rows * g.pitch * 8 * (6 + 2 * 3)   # fields read once, J read + written once
+    bytes_per_launch = live_per_launch * FP64_PARTICLE_BYTES + grid_bytes
+    hbm_gbs = bytes_per_launch / (avg_push_ms * 1e-3) / 1e9
+    return dict(value=value, total_ms=total_ms, avg_push_ms=avg_push_ms, push_ms=push_ms, counters=cnt,
+                hbm_gbs=hbm_gbs, bytes_per_launch=bytes_per_launch, dt=dt, grid=g,
+                live_per_launch=live_per_launch, wall_s=t_wall)
+
+
+def run_cpu_baseline(args, grid):
+    """The FP64 oracle (OpenMP over particles) on a bounded sample."""
+    from oracle import oracle as orc
+    from paper_2503_04558_amd import workload as wl
+
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    sample_pairs = args.cpu_pairs
+    parts = wl.pairs(grid, sample_pairs, kind="mj", seed=0, params=dict(T=0.1, vphi=0.1), workers=8)
+    F = wl.wald_fields(grid, B0=1.0)
+    dt = wl.crossing_dt(grid)
+    t = time.time()
+    _, _, _, st = orc.run(grid, wl.species_table(), parts, F, dt, args.cpu_steps, ncorr=args.ncorr,
+                          nthreads=nthreads)
+    el = time.time() - t
+    rate = st["live_steps"] / el
+    return dict(value=rate, unit="particle-steps/s", cores=nthreads if orc.has_openmp() else 1, kind="oracle",
+                sample=f"first {2 * sample_pairs} particles of the same workload, {args.cpu_steps} steps, "
+                       f"no sort, {el:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--pairs", type=int, default=100_000_000)
+    ap.add_argument("--nr", type=int, default=2048)
+    ap.add_argument("--nth", type=int, default=2048)
+    ap.add_argument("--spin", type=float, default=0.99)
+    ap.add_argument("--ncorr", type=int, default=3)
+    ap.add_argument("--sort-every", type=int, default=20)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-pairs", type=int, default=1 << 20)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    r = run_gpu(args)
+    g = r["grid"]
+    cpu = None if args.no_cpu else run_cpu_baseline(args, g)
+    hbm = dict(bound="hbm", achieved=round(r["hbm_gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(r["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+    out = {
+        "metric": "particle push+deposit/s (FP64 vs FP32-split) at stated error; bwd/fwd time ratio",
+        "value": r["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["total_ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.nr}x{args.nth} Kerr-Schild log-r grid, a={args.spin}, Wald B0=1, "
+                        f"{2 * args.pairs} e+- (Maxwell-Juttner T=0.1, 0.1c phi rotation), "
+                        f"sort every {args.sort_every} steps, ncorr={args.ncorr}",
+            "grid": [args.nr, args.nth], "particles": 2 * args.pairs, "spin": args.spin,
+            "dt": r["dt"], "sort_every": args.sort_every, "ncorr": args.ncorr, "precision": "FP64",
+        },
+        "roofline": hbm,
+        "kernel": {"name": "push_deposit_f64", "avg_ms": r["avg_push_ms"],
+                   "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
+                   "live_particles_per_launch": r["live_per_launch"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * grpic.h -- C ABI of libgrpic.so, the MI355X (gfx950) implementation of the
+ * GRPIC particle step of Chen, Luepker & Yuan, "Introducing APERTURE: A
+ * GPU-based General Relativistic Particle-in-Cell Simulation Framework"
+ * (arXiv:2503.04558): field gather, generalised Boris kick, geodesic
+ * predictor-corrector and Esirkepov current deposition on a 2D axisymmetric
+ * Kerr-Schild (ln r, theta) grid.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: c = 1, Heaviside-Lorentz (Sec. 2.1).  Momenta u_i are the covariant
+ * Kerr-Schild components per unit mass; positions are stored as a cell index
+ * plus an offset in grid units.
+ *
+ * Grid: nr x nth cells.  Vertex i lies at ln r = lnr0 + i*dlnr (natural log),
+ * vertex j at theta = j*dth with dth = pi/nth.  Every grid array (the six
+ * field components, the three current components) has nr + 1 + 2*guard rows
+ * of `pitch` elements; grid point (i, j) of a component lives at element
+ * (i + guard)*pitch + (j + guard), rows along r, theta contiguous.  A
+ * component with Yee stagger (s_r, s_th) (Sec. 2.1, Fig. Yee) stores the
+ * value at (i + s_r, j + s_th):
+ *   D^r, B^th, F^r : (1/2, 0)     D^th, B^r, F^th : (0, 1/2)
+ *   D^ph, G^ph     : (0, 0)       B^ph            : (1/2, 1/2)
+ * guard >= 2 and pitch >= nth + 1 + 2*guard are required.
+ *
+ * Particles (structure of arrays, one element per particle):
+ *   cell  int32   i*nth + j of the cell holding the particle, -1 = removed
+ *   xr,xth        offsets in the cell, xi = i + xr, eta = j + xth, in [0, 1]
+ *   ur,uth,uph    covariant momenta u_r, u_th, u_ph
+ *   w             macro-particle weight
+ *   sp    uint8   species index into the species table
+ *   phi           optional accumulated azimuth (NULL: not tracked)
+ * Precision GRPIC_FP64: xr..w and phi are double.  GRPIC_FP32_SPLIT: xr..w are
+ * float (the position keeps its integer cell exactly; fields are float too),
+ * the deposit and the current arrays stay double.
+ *
+ * Current output is in flux form (the quantities eq. integral-form consumes):
+ *   F^r_{i+1/2,j} = J^r A^D_r,  F^th_{i,j+1/2} = J^th A^D_th,  G^ph_{ij} = J^ph dV,
+ * accumulated (+=) over all steps of a call.  Dividing by the areas A^D and
+ * volumes dV (Sec. 2.3, after the deposit loop) is left to the caller.
+ *
+ * Memory: every array pointer is a DEVICE pointer owned by the caller; the
+ * library allocates no device memory.  Workspaces are caller-provided and
+ * sized by the *_bytes helpers.  Structures passed by pointer are read on the
+ * host during the call only.
+ *
+ * Streams: every call is enqueued on `stream` (a hipStream_t, NULL = the
+ * default stream) and returns once enqueued; results are valid after the
+ * stream is synchronised.
+ *
+ * Errors: every int-returning call returns 0 on success or a negative
+ * GRPIC_E* code and then enqueues nothing; grpic_last_error() returns a
+ * thread-local message for the last failure.  No C++ exception crosses the
+ * ABI.
+ */
+#ifndef GRPIC_H_
+#define GRPIC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRPIC_OK 0
+#define GRPIC_EINVAL (-1)   /* bad argument: NULL pointer, bad size, inconsistent grid, ... */
+#define GRPIC_ERANGE (-2)   /* dt above the light-crossing time of the smallest cell        */
+#define GRPIC_ENOMEM (-3)   /* caller-provided workspace too small                          */
+#define GRPIC_EHIP   (-4)   /* HIP runtime or launch failure                                */
+
+#define GRPIC_FP64 0
+#define GRPIC_FP32_SPLIT 1
+
+#define GRPIC_MAX_SPECIES 8
+
+/* Kerr metric parameters: spin a and mass M, |a| <= M; M = a = 0 is flat
+ * space (App. A, with the mass written back into z = 2Mr/rho^2 and
+ * Delta = r^2 + a^2 - 2Mr). */
+typedef struct {
+    double a, M;
+} grpic_metric;
+
+/* Grid, see the conventions above. */
+typedef struct {
+    int32_t nr, nth, guard, pitch;
+    double lnr0, dlnr, dth;
+} grpic_grid;
+
+/* One species: charge q, mass m.  massless != 0 marks photons, which follow
+ * geodesics with u^0 = |u|/alpha and skip the Boris step (Sec. 2.2). */
+typedef struct {
+    double q, m;
+    int32_t massless, reserved;
+} grpic_species;
+
+typedef struct {
+    int64_t n;
+    int32_t* cell;
+    void *xr, *xth, *ur, *uth, *uph, *w;
+    uint8_t* sp;
+    void* phi;
+    int32_t precision;   /* GRPIC_FP64 or GRPIC_FP32_SPLIT */
+    int32_t reserved;
+} grpic_particles;
+
+/* Contravariant D^i and B^i, i = r, th, ph, on the Yee stagger; double for
+ * GRPIC_FP64, float for GRPIC_FP32_SPLIT. */
+typedef struct {
+    const void* D[3];
+    const void* B[3];
+} grpic_fields;
+
+/* F^r, F^th, G^ph (double, accumulated). */
+typedef struct {
+    double *Fr, *Fth, *Gph;
+} grpic_current;
+
+/* Device counters, accumulated (+=) by grpic_push_deposit when non-NULL. */
+#define GRPIC_CNT_OUT 0        /* particles removed at the radial edges          */
+#define GRPIC_CNT_BAD 1        /* removed as non-finite or moving >= 1 cell      */
+#define GRPIC_CNT_REFLECT 2    /* reflections at the axis                         */
+#define GRPIC_CNT_LIVE 3       /* particle-steps taken by live particles          */
+#define GRPIC_NCOUNTERS 4
+
+/*
+ * grpic_push_deposit -- advance every live particle `nsteps` steps through
+ * fixed fields and accumulate the current it carries.
+ *
+ * Per particle and step (Sec. 2.2, 2.3): CIC-interpolate D^i, B^i at x^n;
+ * one full-step generalised Boris kick at x^n (eqs. boris-plus-minus, u0bar,
+ * boris-scheme; the two half kicks of the Strang split bundled, as the paper
+ * does); geodesic predictor (eq. geodesic-predictor) followed by `ncorr`
+ * trapezoid corrector passes (eq. geodesic-corrector; the paper's default
+ * is 3) on the right-hand sides of eq. particle-eom, with positions in grid
+ * units; reflection at the axis (eta -> -eta or 2 nth - eta, u_th -> -u_th);
+ * Esirkepov deposit of the move x^n -> x^{n+1} on the 3x3 vertex window
+ * (eqs. esirkepov-decomp, j-phi-deposit, local prefix sum); a particle that
+ * leaves [0, nr) in xi deposits its move into the guard vertices and is
+ * removed (cell = -1).  A particle whose end point is not finite or that
+ * moved one cell or more is removed without depositing (counted as BAD).
+ *
+ * species: host array of nsp entries (1 <= nsp <= GRPIC_MAX_SPECIES).
+ * parts: updated in place.  fields: read only.  J: accumulated.
+ * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
+ * ckpt, ckpt_every: reserved for the adjoint (pass NULL, 0).
+ * counters: optional device int64[GRPIC_NCOUNTERS], accumulated.
+ */
+int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
+                       const grpic_species* species, int nsp,
+                       grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                       double dt, int nsteps, int ncorr,
+                       void* ckpt, int ckpt_every,
+                       int64_t* counters, void* stream);
+
+/*
+ * grpic_charge -- Q_ij += sum over live particles of q w S_ij(x_p), the CIC
+ * charge at the vertices (rho dV; the left-hand side of eq. J-integral-eqn).
+ * Used to check discrete charge continuity.  Q is a double grid array.
+ */
+int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
+                 const grpic_particles* parts, double* Q, void* stream);
+
+/*
+ * grpic_sort -- counting sort of the particles by cell (stable within a
+ * cell is not promised), removed particles (cell < 0) dropped.
+ *
+ * in, out: particle sets of the same precision; out must hold in->n
+ * particles and must not alias in; out->n is not read.  On completion the
+ * first *n_alive_dev elements of out hold the live particles ordered by
+ * cell; the remaining in->n - *n_alive_dev elements have cell = -1 (removed)
+ * and their other fields unspecified, so out can be pushed with n = in->n.  cell_offsets (optional, device
+ * int64[nr*nth + 1]) receives the exclusive prefix sum of the per-cell
+ * counts.  ws: device workspace of at least grpic_sort_workspace_bytes().
+ * n_alive_dev: device int64 receiving the live count.
+ * Not described by the paper: particles are kept ordered by cell so that a
+ * wavefront's particles share field and current cache lines.
+ */
+size_t grpic_sort_workspace_bytes(const grpic_grid* grid, int64_t n);
+int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+               int64_t* cell_offsets, void* ws, size_t ws_bytes, int64_t* n_alive_dev,
+               void* stream);
+
+/*
+ * grpic_crossing_time -- minimum over cell centres of the time light needs to
+ * cross one cell, from |dxi/dt| <= (alpha sqrt(gamma^rr) + |beta^r|)/(r dlnr)
+ * and |deta/dt| <= alpha sqrt(gamma^thth)/dth.  Host computation.  Returns a
+ * negative value for an invalid metric or grid.
+ */
+double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid);
+
+/* Thread-local message for the last failing call ("" if none). */
+const char* grpic_last_error(void);
+
+/* Library version string. */
+const char* grpic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRPIC_H_ */

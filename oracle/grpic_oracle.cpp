@@ -40,7 +40,9 @@
  *     particle leaving [0, Nr) in xi deposits its full move into the guard
  *     vertices and is then removed (cell = -1);
  *   - a particle whose end point is not finite or that moved one cell or more
- *     in either direction is removed without depositing and counted.
+ *     in either direction is removed without depositing and counted, and so
+ *     is a particle whose cell, offsets or species index lie outside their
+ *     ranges (such input would index outside the arrays).
  *
  * Build: g++ -O2 -std=c++17 -fPIC -shared -ffp-contract=off -fopenmp
  */
@@ -296,19 +298,19 @@ T shape1(const T& x) {                  /* CIC: W(x) = max(0, 1 - |x|) */
 struct Acc {
     double* sum;
     double* comp;
-    double* abs_sum;        /* optional: sum of |contribution| per element */
-    void add(long e, double x) {
+    double* scale;          /* optional: sum of the contributions' magnitude scales */
+    void add(long e, double x, double sc) {
         const double s = sum[e], t = s + x;
         if (std::fabs(s) >= std::fabs(x)) comp[e] += (s - t) + x;
         else comp[e] += (x - t) + s;
         sum[e] = t;
-        if (abs_sum) abs_sum[e] += std::fabs(x);
+        if (scale) scale[e] += sc;
     }
 };
 
 struct PlainAcc {
     double* sum;
-    void add(long e, double x) { sum[e] += x; }
+    void add(long e, double x, double) { sum[e] += x; }
 };
 
 template <class T>
@@ -317,6 +319,11 @@ struct Move {
     T Fr[2][3];     /* flux through (i0+a+1/2, j0+b) */
     T Ft[3][2];     /* flux through (i0+a, j0+b+1/2) */
     T Gp[3][3];     /* J^ph dV at (i0+a, j0+b)       */
+    /* Magnitude scales |q w|/dt and |q w dphi|/dt of the terms that make up
+     * each F and G value (shape weights are at most 1): a bound for the
+     * rounding error of a value is a few ulps of its scale, whatever
+     * cancellation happened inside it. */
+    double scale_f, scale_p;
 };
 
 template <class T>
@@ -338,6 +345,8 @@ void esirkepov(double qw, double dt, const T& xi0, const T& eta0, const T& xi1, 
             mv.Gp[a][b] = qw * dphi / dt * (S11 / 3.0 + S10 / 6.0 + S01 / 6.0 + S00 / 3.0);
         }
     }
+    mv.scale_f = std::fabs(qw) / dt;
+    mv.scale_p = std::fabs(qw * val(dphi)) / dt;
     /* local prefix sums, zero flux on the low side of the window */
     for (int b = 0; b < 3; ++b) {
         T run(0.0);
@@ -352,11 +361,11 @@ void esirkepov(double qw, double dt, const T& xi0, const T& eta0, const T& xi1, 
 template <class AccT>
 void scatter_move(const Geom& g, const Move<double>& mv, AccT& Fr, AccT& Ft, AccT& Gp) {
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 3; ++b) Fr.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Fr[a][b]);
+        for (int b = 0; b < 3; ++b) Fr.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Fr[a][b], mv.scale_f);
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 2; ++b) Ft.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Ft[a][b]);
+        for (int b = 0; b < 2; ++b) Ft.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Ft[a][b], mv.scale_f);
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) Gp.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Gp[a][b]);
+        for (int b = 0; b < 3; ++b) Gp.add(idx(g, mv.i0 + a, mv.j0 + b), mv.Gp[a][b], mv.scale_p);
 }
 
 /* ------------------------------------------------------------------ */
@@ -378,6 +387,12 @@ Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], dou
     o.reflected = 0;
     o.status = ST_DEAD;
     if (cell < 0) return o;
+    /* inputs that would index outside the grid arrays: removed, no deposit */
+    if (cell >= g.nr * g.nth || !(xr >= 0.0 && xr <= 1.0 && xth >= 0.0 && xth <= 1.0)) {
+        o.status = ST_BAD;
+        o.cell = -1;
+        return o;
+    }
     const int ci = cell / g.nth, cj = cell % g.nth;
     const double xi0 = ci + xr, eta0 = cj + xth;
 
@@ -490,7 +505,8 @@ void orc_charge(const Geom* g, const Species* sp, int nsp, int64_t n, const int3
 
 /* nsteps full steps over all particles, updated in place.  J arrays are +=.
  * nthreads == 1: serial, Neumaier-compensated J (parity mode), optional
- * A arrays receive sum |contribution|.  nthreads > 1: OpenMP over particles
+ * A arrays receive, per element, the sum of the contributions' magnitude
+ * scales (|q w|/dt for F^r and F^th, |q w dphi|/dt for G^ph).  nthreads > 1: OpenMP over particles
  * with thread-private J reduced in thread order (timing mode).
  * stats[4] (+=): particles removed at the radial edges, removed as
  * non-finite or moving >= 1 cell, axis reflections, live particle-steps.  */
@@ -500,7 +516,6 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
              const double* const* F, double* Fr, double* Fth, double* Gph,
              double* Afr, double* Afth, double* Agph,
              double dt, int nsteps, int ncorr, int nthreads, int64_t* stats) {
-    (void)nsp;
     const Geom& g = *gp;
     const long ncell = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
     int64_t st_out = 0, st_bad = 0, st_refl = 0, st_live = 0;
@@ -511,6 +526,7 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
         for (int s = 0; s < nsteps; ++s) {
             for (int64_t p = 0; p < n; ++p) {
                 const double u[3] = {ur[p], uth[p], uph[p]};
+                if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
                 Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
                 if (o.status == ST_DEAD) continue;
                 ++st_live;
@@ -536,6 +552,7 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
 #pragma omp for schedule(static)
                 for (int64_t p = 0; p < n; ++p) {
                     const double u[3] = {ur[p], uth[p], uph[p]};
+                    if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
                     Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
                     if (o.status == ST_DEAD) continue;
                     ++st_live;

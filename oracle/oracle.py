@@ -161,8 +161,9 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
     """Advance copies of the particle arrays nsteps steps.
 
     Returns (parts_out, J, A, stats): J = [Fr, Fth, Gph] (added to the given
-    J if any), A = the matching sums of |contribution| (with_abs, serial
-    only) and stats = dict(out, bad, reflected, live_steps).
+    J if any); A (with_abs, serial only) = per element, the sum over the
+    contributions of their magnitude scale, |q w|/dt for F^r and F^th and
+    |q w dphi|/dt for G^ph; stats = dict(out, bad, reflected, live_steps).
     """
     g = geom(grid)
     sp = _species_array(species)

@@ -1,0 +1,241 @@
+// api.hip -- the C ABI of libgrpic.so (declared in include/grpic.h):
+// argument validation, launch configuration and error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "grpic.h"
+#include "grpic_launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return GRPIC_OK;
+    return fail(GRPIC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_metric(const grpic_metric* m) {
+    if (!m) return fail(GRPIC_EINVAL, "metric is NULL");
+    if (!isfinite(m->a) || !isfinite(m->M) || m->M < 0.0 || fabs(m->a) > m->M)
+        return fail(GRPIC_EINVAL, "metric: need M >= 0 and |a| <= M (a=%g, M=%g)", m->a, m->M);
+    return GRPIC_OK;
+}
+
+int check_grid(const grpic_grid* g) {
+    if (!g) return fail(GRPIC_EINVAL, "grid is NULL");
+    if (g->nr <= 0 || g->nth <= 0) return fail(GRPIC_EINVAL, "grid: nr, nth must be positive");
+    if ((int64_t)g->nr * g->nth >= (int64_t)INT32_MAX) return fail(GRPIC_EINVAL, "grid: nr*nth too large");
+    if (g->guard < 2) return fail(GRPIC_EINVAL, "grid: guard must be >= 2 (got %d)", g->guard);
+    if (g->pitch < g->nth + 1 + 2 * g->guard)
+        return fail(GRPIC_EINVAL, "grid: pitch %d < nth + 1 + 2*guard", g->pitch);
+    if (!isfinite(g->lnr0) || !(g->dlnr > 0.0) || !isfinite(g->dlnr))
+        return fail(GRPIC_EINVAL, "grid: lnr0 must be finite and dlnr > 0");
+    const double dth = M_PI / g->nth;
+    if (!(fabs(g->dth - dth) <= 1e-12 * dth)) return fail(GRPIC_EINVAL, "grid: dth must equal pi/nth");
+    return GRPIC_OK;
+}
+
+int check_species(const grpic_species* sp, int nsp) {
+    if (!sp) return fail(GRPIC_EINVAL, "species is NULL");
+    if (nsp < 1 || nsp > GRPIC_MAX_SPECIES) return fail(GRPIC_EINVAL, "nsp must be in [1, %d]", GRPIC_MAX_SPECIES);
+    for (int s = 0; s < nsp; ++s) {
+        if (!isfinite(sp[s].q) || !isfinite(sp[s].m)) return fail(GRPIC_EINVAL, "species %d: q, m not finite", s);
+        if (!sp[s].massless && !(sp[s].m > 0.0)) return fail(GRPIC_EINVAL, "species %d: m must be > 0", s);
+    }
+    return GRPIC_OK;
+}
+
+int check_particles(const grpic_particles* p, const char* name) {
+    if (!p) return fail(GRPIC_EINVAL, "%s is NULL", name);
+    if (p->n < 0) return fail(GRPIC_EINVAL, "%s: n < 0", name);
+    if (p->precision != GRPIC_FP64 && p->precision != GRPIC_FP32_SPLIT)
+        return fail(GRPIC_EINVAL, "%s: unknown precision %d", name, p->precision);
+    if (p->n > 0 && (!p->cell || !p->xr || !p->xth || !p->ur || !p->uth || !p->uph || !p->w || !p->sp))
+        return fail(GRPIC_EINVAL, "%s: NULL particle array", name);
+    return GRPIC_OK;
+}
+
+// Host evaluation of the light-crossing bound (own formulas of App. A).
+double crossing_time_uncached(const grpic_metric* m, const grpic_grid* g) {
+    double best = INFINITY;
+    const double a = m->a, M = m->M;
+    for (int i = 0; i < g->nr; ++i) {
+        const double r = exp(g->lnr0 + (i + 0.5) * g->dlnr);
+        for (int j = 0; j < g->nth; ++j) {
+            const double th = (j + 0.5) * g->dth;
+            const double c = cos(th);
+            const double rho2 = r * r + a * a * c * c;
+            const double z = 2.0 * M * r / rho2;
+            const double alpha = 1.0 / sqrt(1.0 + z);
+            const double beta = z / (1.0 + z);
+            const double h_rr = (r * r + a * a) / rho2 - beta;
+            const double v_xi = (alpha * sqrt(h_rr) + fabs(beta)) / (r * g->dlnr);
+            const double v_eta = alpha / sqrt(rho2) / g->dth;
+            const double v = v_xi > v_eta ? v_xi : v_eta;
+            if (1.0 / v < best) best = 1.0 / v;
+        }
+    }
+    return best;
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<double, double, int, int, double, double>, double> g_cross_cache;
+
+double crossing_time_cached(const grpic_metric* m, const grpic_grid* g) {
+    const auto key = std::make_tuple(m->a, m->M, g->nr, g->nth, g->lnr0, g->dlnr);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cross_cache.find(key);
+        if (it != g_cross_cache.end()) return it->second;
+    }
+    const double t = crossing_time_uncached(m, g);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cross_cache.size() > 64) g_cross_cache.clear();
+    g_cross_cache[key] = t;
+    return t;
+}
+
+void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
+                 const grpic_species* sp, int nsp, const grpic_particles* p) {
+    memset(&A, 0, sizeof A);
+    A.a = m ? m->a : 0.0;
+    A.M = m ? m->M : 0.0;
+    A.nr = g->nr; A.nth = g->nth; A.guard = g->guard; A.pitch = g->pitch;
+    A.lnr0 = g->lnr0; A.dlnr = g->dlnr; A.dth = g->dth;
+    A.nsp = nsp;
+    for (int s = 0; s < nsp; ++s) {
+        A.q[s] = sp[s].q;
+        A.m[s] = sp[s].m;
+        A.massless[s] = sp[s].massless;
+    }
+    A.n = p->n;
+    A.cell = p->cell;
+    A.xr = p->xr; A.xth = p->xth; A.ur = p->ur; A.uth = p->uth; A.uph = p->uph; A.w = p->w;
+    A.sp = p->sp;
+    A.phi = p->phi;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grpic_last_error(void) { return g_last_error.c_str(); }
+
+const char* grpic_version(void) { return "grpic 0.1 (gfx950)"; }
+
+double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid) {
+    if (check_metric(metric) || check_grid(grid)) return -1.0;
+    return crossing_time_cached(metric, grid);
+}
+
+int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
+                       const grpic_species* species, int nsp,
+                       grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                       double dt, int nsteps, int ncorr,
+                       void* ckpt, int ckpt_every,
+                       int64_t* counters, void* stream) {
+    int rc;
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
+        (rc = check_particles(parts, "parts")))
+        return rc;
+    if (!fields) return fail(GRPIC_EINVAL, "fields is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!fields->D[c] || !fields->B[c]) return fail(GRPIC_EINVAL, "fields: NULL component");
+    if (!J || !J->Fr || !J->Fth || !J->Gph) return fail(GRPIC_EINVAL, "current: NULL array");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(GRPIC_EINVAL, "dt must be positive and finite");
+    if (nsteps < 0) return fail(GRPIC_EINVAL, "nsteps < 0");
+    if (ncorr < 0 || ncorr > 16) return fail(GRPIC_EINVAL, "ncorr must be in [0, 16]");
+    if (ckpt || ckpt_every) return fail(GRPIC_EINVAL, "checkpoints are not supported by this entry point yet");
+    if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "only GRPIC_FP64 particles are supported yet");
+    const double tc = crossing_time_cached(metric, grid);
+    if (dt > tc * (1.0 + 1e-12))
+        return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
+    if (parts->n == 0 || nsteps == 0) return GRPIC_OK;
+
+    grpic::StepArgs A;
+    fill_common(A, metric, grid, species, nsp, parts);
+    A.dt = dt;
+    A.ncorr = ncorr;
+    for (int c = 0; c < 3; ++c) { A.F[c] = fields->D[c]; A.F[3 + c] = fields->B[c]; }
+    A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;
+    A.counters = reinterpret_cast<unsigned long long*>(counters);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int step = 0; step < nsteps; ++step) {
+        if ((rc = hip_status(grpic::launch_push_deposit_f64(A, s), "push_deposit launch"))) return rc;
+    }
+    return GRPIC_OK;
+}
+
+int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
+                 const grpic_particles* parts, double* Q, void* stream) {
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_species(species, nsp)) || (rc = check_particles(parts, "parts")))
+        return rc;
+    if (!Q) return fail(GRPIC_EINVAL, "Q is NULL");
+    grpic::StepArgs A;
+    fill_common(A, nullptr, grid, species, nsp, parts);
+    return hip_status(grpic::launch_charge(A, parts->precision == GRPIC_FP32_SPLIT, Q,
+                                           static_cast<hipStream_t>(stream)), "charge launch");
+}
+
+size_t grpic_sort_workspace_bytes(const grpic_grid* grid, int64_t n) {
+    (void)n;
+    if (!grid || grid->nr <= 0 || grid->nth <= 0) return 0;
+    const int64_t len = (int64_t)grid->nr * grid->nth + 1;
+    return (size_t)(len + grpic::sort_scan_blocks(len) + 1) * sizeof(unsigned long long);
+}
+
+int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+               int64_t* cell_offsets, void* ws, size_t ws_bytes, int64_t* n_alive_dev, void* stream) {
+    int rc;
+    if ((rc = check_grid(grid)) || (rc = check_particles(in, "in")) || (rc = check_particles(out, "out")))
+        return rc;
+    if (in->precision != out->precision) return fail(GRPIC_EINVAL, "in and out precision differ");
+    if (in->n > 0 && (!out->cell || !out->xr || !out->xth || !out->ur || !out->uth || !out->uph || !out->w ||
+                      !out->sp))
+        return fail(GRPIC_EINVAL, "out: NULL particle array");
+    if ((in->phi == nullptr) != (out->phi == nullptr)) return fail(GRPIC_EINVAL, "phi given for only one of in/out");
+    if (in->n > 0 && (in->cell == out->cell || in->xr == out->xr)) return fail(GRPIC_EINVAL, "in and out alias");
+    if (!n_alive_dev) return fail(GRPIC_EINVAL, "n_alive_dev is NULL");
+    const size_t need = grpic_sort_workspace_bytes(grid, in->n);
+    if (!ws || ws_bytes < need) return fail(GRPIC_ENOMEM, "sort workspace needs %zu bytes, got %zu", need, ws_bytes);
+    grpic::SortArgs S;
+    memset(&S, 0, sizeof S);
+    S.n = in->n;
+    S.ncell = grid->nr * grid->nth;
+    S.elem = in->precision == GRPIC_FP64 ? 8 : 4;
+    S.cell_in = in->cell;
+    const void* ins[6] = {in->xr, in->xth, in->ur, in->uth, in->uph, in->w};
+    void* outs[6] = {out->xr, out->xth, out->ur, out->uth, out->uph, out->w};
+    for (int k = 0; k < 6; ++k) { S.in[k] = ins[k]; S.out[k] = outs[k]; }
+    S.sp_in = in->sp;
+    S.phi_in = in->phi;
+    S.cell_out = out->cell;
+    S.sp_out = out->sp;
+    S.phi_out = out->phi;
+    S.counts = static_cast<unsigned long long*>(ws);
+    S.blocksums = S.counts + (S.ncell + 1);
+    S.cell_offsets = cell_offsets;
+    S.n_alive = n_alive_dev;
+    return hip_status(grpic::launch_sort(S, static_cast<hipStream_t>(stream)), "sort launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// grpic_device.hpp -- device-side building blocks of the GRPIC particle step
+// (arXiv:2503.04558, Sec. 2.2-2.3, App. A), written once over the real type R
+// so that the FP64 kernel and the split-precision kernel share them.
+//
+// Positions are handled in grid units: xi = (ln r - lnr0)/dlnr and
+// eta = theta/dth, so a cell is the unit square.  Momenta are the covariant
+// Kerr-Schild components u_r, u_th, u_ph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grpic {
+
+constexpr int kMaxSpecies = 8;
+
+// Everything a push+deposit launch needs, passed by value.
+struct StepArgs {
+    double a, M;
+    int nr, nth, guard, pitch;
+    double lnr0, dlnr, dth;
+    double dt;
+    int ncorr, nsp;
+    double q[kMaxSpecies], m[kMaxSpecies];
+    int massless[kMaxSpecies];
+    int64_t n;
+    int32_t* cell;
+    void *xr, *xth, *ur, *uth, *uph, *w;
+    const uint8_t* sp;
+    void* phi;
+    const void* F[6];                       // D^r, D^th, D^ph, B^r, B^th, B^ph
+    double *Fr, *Fth, *Gph;
+    unsigned long long* counters;           // optional, GRPIC_NCOUNTERS entries
+};
+
+template <class R>
+struct Metric {
+    R alpha, beta;                          // lapse, radial shift beta^r
+    R g_rr, g_rp, g_tt, g_pp;               // gamma_ij
+    R h_rr, h_rp, h_tt, h_pp;               // gamma^ij
+    R sqrtg;                                // sqrt(det gamma_ij) = rho^2 sin sqrt(1+z)
+};
+
+template <class R>
+struct MetricDeriv {                        // [0] = d/dr, [1] = d/dtheta
+    R dal[2], dbe[2], dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];
+};
+
+// Kerr-Schild 3+1 quantities of App. A (mass M reinstated) at radius r and
+// polar angle with sine s, cosine c; with D set, their r and theta
+// derivatives (analytic).
+template <class R, bool D>
+__device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k, MetricDeriv<R>* d) {
+    const R a2 = a * a, r2 = r * r, s2 = s * s;
+    const R rho2 = r2 + a2 * (c * c);
+    const R irho2 = R(1) / rho2;
+    const R z = R(2) * M * r * irho2;
+    const R opz = R(1) + z;
+    const R iopz = R(1) / opz;
+    const R sq = sqrt(opz);
+    const R is2 = R(1) / s2;
+    const R ra2 = r2 + a2;
+    const R Delta = ra2 - R(2) * M * r;
+    const R Sigma = ra2 * ra2 - a2 * Delta * s2;
+    k.alpha = R(1) / sq;
+    k.beta = z * iopz;
+    k.g_rr = opz;
+    k.g_rp = -a * s2 * opz;
+    k.g_tt = rho2;
+    k.g_pp = Sigma * s2 * irho2;
+    k.h_rr = ra2 * irho2 - k.beta;
+    k.h_rp = a * irho2;
+    k.h_tt = irho2;
+    k.h_pp = irho2 * is2;
+    k.sqrtg = rho2 * s * sq;
+    if constexpr (D) {
+        const R irho4 = irho2 * irho2;
+        const R dr_rho2 = R(2) * r;
+        const R dt_rho2 = R(-2) * a2 * s * c;
+        const R dz_r = R(2) * M * (rho2 - R(2) * r2) * irho4;
+        const R dz_t = R(4) * M * a2 * r * s * c * irho4;
+        const R al3 = k.alpha * iopz;            // (1+z)^(-3/2)
+        const R al4 = iopz * iopz;               // (1+z)^(-2)
+        d->dal[0] = R(-0.5) * al3 * dz_r;
+        d->dal[1] = R(-0.5) * al3 * dz_t;
+        d->dbe[0] = al4 * dz_r;
+        d->dbe[1] = al4 * dz_t;
+        d->dh_rp[0] = -a * dr_rho2 * irho4;
+        d->dh_rp[1] = -a * dt_rho2 * irho4;
+        d->dh_tt[0] = -dr_rho2 * irho4;
+        d->dh_tt[1] = -dt_rho2 * irho4;
+        d->dh_rr[0] = R(-2) * r * a2 * s2 * irho4 - d->dbe[0];
+        d->dh_rr[1] = R(2) * a2 * ra2 * s * c * irho4 - d->dbe[1];
+        d->dh_pp[0] = R(-2) * r * irho4 * is2;
+        d->dh_pp[1] = -(dt_rho2 * s2 + R(2) * rho2 * s * c) * irho4 * is2 * is2;
+    }
+}
+
+// r, sin(theta), cos(theta) of a point in grid units.
+template <class R>
+__device__ __forceinline__ void grid_point(const StepArgs& A, R xi, R eta, R& r, R& s, R& c) {
+    r = exp(R(A.lnr0) + xi * R(A.dlnr));
+    const R th = eta * R(A.dth);
+    s = sin(th);
+    c = cos(th);
+}
+
+// Geodesic right-hand side of eq. particle-eom (no Lorentz force) in grid
+// units; f = (dxi/dt, deta/dt, dphi/dt, du_r/dt, du_th/dt), du_ph/dt = 0.
+template <class R>
+__device__ __forceinline__ void geodesic_rhs(const StepArgs& A, R eps, R xi, R eta,
+                                             R ur, R ut, R up, R f[5]) {
+    R r, s, c;
+    grid_point(A, xi, eta, r, s, c);
+    Metric<R> k;
+    MetricDeriv<R> d;
+    ks_metric<R, true>(R(A.a), R(A.M), r, s, c, k, &d);
+    const R uu = k.h_rr * ur * ur + R(2) * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
+    const R u0 = sqrt(eps + uu) / k.alpha;
+    const R iu0 = R(1) / u0;
+    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) / (r * R(A.dlnr));
+    f[1] = k.h_tt * ut * iu0 / R(A.dth);
+    f[2] = (k.h_rp * ur + k.h_pp * up) * iu0;
+    for (int q = 0; q < 2; ++q) {
+        const R quad = ur * ur * d.dh_rr[q] + R(2) * ur * up * d.dh_rp[q]
+                     + ut * ut * d.dh_tt[q] + up * up * d.dh_pp[q];
+        f[3 + q] = -k.alpha * u0 * d.dal[q] + ur * d.dbe[q] - quad * iu0 * R(0.5);
+    }
+}
+
+// (v x w)_i = sqrt(gamma) eps_ijk v^j w^k; v covariant (raised here), w contravariant.
+template <class R>
+__device__ __forceinline__ void cross_lower(const Metric<R>& k, const R v[3], const R w[3], R o[3]) {
+    const R vr = k.h_rr * v[0] + k.h_rp * v[2];
+    const R vt = k.h_tt * v[1];
+    const R vp = k.h_rp * v[0] + k.h_pp * v[2];
+    o[0] = k.sqrtg * (vt * w[2] - vp * w[1]);
+    o[1] = k.sqrtg * (vp * w[0] - vr * w[2]);
+    o[2] = k.sqrtg * (vr * w[1] - vt * w[0]);
+}
+
+// Full-step generalised Boris kick (eqs. boris-plus-minus, u0bar, boris-scheme).
+template <class R>
+__device__ __forceinline__ void boris_kick(const Metric<R>& k, R qm, R dt, const R D[3], const R B[3], R u[3]) {
+    const R Dl[3] = {k.g_rr * D[0] + k.g_rp * D[2], k.g_tt * D[1], k.g_rp * D[0] + k.g_pp * D[2]};
+    const R h = qm * k.alpha * dt * R(0.5);
+    R um[3];
+    for (int i = 0; i < 3; ++i) um[i] = u[i] + h * Dl[i];
+    const R uu = k.h_rr * um[0] * um[0] + R(2) * k.h_rp * um[0] * um[2]
+               + k.h_tt * um[1] * um[1] + k.h_pp * um[2] * um[2];
+    const R u0bar = sqrt(R(1) + uu) / k.alpha;
+    const R tf = qm * dt / (R(2) * u0bar);
+    const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
+    const R tt = k.g_rr * t[0] * t[0] + R(2) * k.g_rp * t[0] * t[2]
+               + k.g_tt * t[1] * t[1] + k.g_pp * t[2] * t[2];
+    R x[3], ut[3], sv[3];
+    cross_lower(k, um, t, x);
+    for (int i = 0; i < 3; ++i) ut[i] = um[i] + x[i];
+    const R sf = R(2) / (R(1) + tt);
+    for (int i = 0; i < 3; ++i) sv[i] = sf * t[i];
+    cross_lower(k, ut, sv, x);
+    for (int i = 0; i < 3; ++i) u[i] = um[i] + x[i] + h * Dl[i];
+}
+
+// CIC weight W(x) = max(0, 1 - |x|).
+template <class R>
+__device__ __forceinline__ R shape1(R x) {
+    const R ax = fabs(x);
+    return ax >= R(1) ? R(0) : R(1) - ax;
+}
+
+// Esirkepov fluxes of one move on the 3x3 vertex window anchored at
+// (floor(min xi), floor(min eta)): 6 F^r, 6 F^th, 9 G^ph values
+// (eqs. esirkepov-decomp, j-phi-deposit, with the local prefix sum).
+struct MoveFlux {
+    int i0, j0;
+    double Fr[2][3];        // through (i0+a+1/2, j0+b)
+    double Ft[3][2];        // through (i0+a, j0+b+1/2)
+    double Gp[3][3];        // J^ph dV at (i0+a, j0+b)
+};
+
+__device__ __forceinline__ void esirkepov(double qw, double dt, double xi0, double eta0,
+                                          double xi1, double eta1, double dphi, MoveFlux& mv) {
+    mv.i0 = (int)floor(fmin(xi0, xi1));
+    mv.j0 = (int)floor(fmin(eta0, eta1));
+    double wx0[3], wx1[3], wy0[3], wy1[3];
+    for (int a = 0; a < 3; ++a) {
+        wx0[a] = shape1(xi0 - (double)(mv.i0 + a));
+        wx1[a] = shape1(xi1 - (double)(mv.i0 + a));
+        wy0[a] = shape1(eta0 - (double)(mv.j0 + a));
+        wy1[a] = shape1(eta1 - (double)(mv.j0 + a));
+    }
+    const double cf = -qw / dt;
+    const double cp = qw * dphi / dt;
+    double runr[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        double runt = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            const double S00 = wx0[a] * wy0[b], S01 = wx0[a] * wy1[b];
+            const double S10 = wx1[a] * wy0[b], S11 = wx1[a] * wy1[b];
+            const double Wr = 0.5 * (S11 - S01 + S10 - S00);
+            const double Wt = 0.5 * (S11 - S10 + S01 - S00);
+            mv.Gp[a][b] = cp * (S11 / 3.0 + S10 / 6.0 + S01 / 6.0 + S00 / 3.0);
+            if (a < 2) { runr[b] += Wr; mv.Fr[a][b] = cf * runr[b]; }
+            if (b < 2) { runt += Wt; mv.Ft[a][b] = cf * runt; }
+        }
+    }
+}
+
+__device__ __forceinline__ long grid_index(const StepArgs& A, int i, int j) {
+    return (long)(i + A.guard) * A.pitch + (j + A.guard);
+}
+
+}  // namespace grpic

@@ -1,0 +1,264 @@
+"""ctypes binding of libgrpic.so (C ABI in include/grpic.h).
+
+Argument marshalling only: every function here checks tensor devices, dtypes
+and sizes, builds the C structures and calls the function of the same name in
+the library, which does all the work on the GPU.  There is no fallback: if
+the library is missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgrpic.so")
+
+GRPIC_OK, GRPIC_EINVAL, GRPIC_ERANGE, GRPIC_ENOMEM, GRPIC_EHIP = 0, -1, -2, -3, -4
+GRPIC_FP64, GRPIC_FP32_SPLIT = 0, 1
+GRPIC_MAX_SPECIES = 8
+GRPIC_NCOUNTERS = 4
+COUNTER_NAMES = ("out", "bad", "reflected", "live_steps")
+
+PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
+REAL_KEYS = ("xr", "xth", "ur", "uth", "uph", "w")
+
+
+class grpic_metric(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("M", ctypes.c_double)]
+
+
+class grpic_grid(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("nth", ctypes.c_int32), ("guard", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("lnr0", ctypes.c_double), ("dlnr", ctypes.c_double),
+                ("dth", ctypes.c_double)]
+
+
+class grpic_species(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double), ("massless", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class grpic_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cell", ctypes.c_void_p), ("xr", ctypes.c_void_p),
+                ("xth", ctypes.c_void_p), ("ur", ctypes.c_void_p), ("uth", ctypes.c_void_p),
+                ("uph", ctypes.c_void_p), ("w", ctypes.c_void_p), ("sp", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class grpic_fields(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
+
+
+class grpic_current(ctypes.Structure):
+    _fields_ = [("Fr", ctypes.c_void_p), ("Fth", ctypes.c_void_p), ("Gph", ctypes.c_void_p)]
+
+
+EXPORTED = ("grpic_push_deposit", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
+            "grpic_crossing_time", "grpic_last_error", "grpic_version")
+
+
+class GrpicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"grpic error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgrpic.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2503_04558_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        L.grpic_push_deposit.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, i32, vp, vp]
+        L.grpic_push_deposit.restype = ctypes.c_int
+        L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.grpic_charge.restype = ctypes.c_int
+        L.grpic_sort_workspace_bytes.argtypes = [vp, i64]
+        L.grpic_sort_workspace_bytes.restype = ctypes.c_size_t
+        L.grpic_sort.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, vp]
+        L.grpic_sort.restype = ctypes.c_int
+        L.grpic_crossing_time.argtypes = [vp, vp]
+        L.grpic_crossing_time.restype = ctypes.c_double
+        L.grpic_last_error.restype = ctypes.c_char_p
+        L.grpic_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != GRPIC_OK:
+        raise GrpicError(rc, lib().grpic_last_error().decode())
+
+
+# ---------------------------------------------------------------- marshalling
+def make_metric(a: float, M: float = 1.0) -> grpic_metric:
+    return grpic_metric(float(a), float(M))
+
+
+def make_grid(g) -> grpic_grid:
+    """From any object with nr, nth, guard, pitch, lnr0, dlnr, dth."""
+    return grpic_grid(int(g.nr), int(g.nth), int(g.guard), int(g.pitch), float(g.lnr0),
+                      float(g.dlnr), float(g.dth))
+
+
+def make_species(table) -> ctypes.Array:
+    arr = (grpic_species * len(table))()
+    for i, s in enumerate(table):
+        arr[i] = grpic_species(float(s["q"]), float(s["m"]), int(s.get("massless", 0)), 0)
+    return arr
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _need(t: torch.Tensor, dtype, numel: int | None, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+
+
+def particle_precision(parts: dict) -> int:
+    return GRPIC_FP64 if parts["xr"].dtype == torch.float64 else GRPIC_FP32_SPLIT
+
+
+def make_particles(parts: dict) -> grpic_particles:
+    """dict of device tensors cell (int32), xr, xth, ur, uth, uph, w (float64 or
+    float32), sp (uint8), optional phi."""
+    n = parts["cell"].numel()
+    prec = particle_precision(parts)
+    real = torch.float64 if prec == GRPIC_FP64 else torch.float32
+    _need(parts["cell"], torch.int32, n, "cell")
+    _need(parts["sp"], torch.uint8, n, "sp")
+    for k in REAL_KEYS:
+        _need(parts[k], real, n, k)
+    phi = parts.get("phi")
+    if phi is not None:
+        _need(phi, real, n, "phi")
+    return grpic_particles(n, *[_ptr(parts[k]) for k in PARTICLE_KEYS], _ptr(phi), prec, 0)
+
+
+def _grid_numel(g) -> int:
+    return (int(g.nr) + 1 + 2 * int(g.guard)) * int(g.pitch)
+
+
+def make_fields(g, fields, dtype) -> grpic_fields:
+    if len(fields) != 6:
+        raise ValueError("fields: need D^r, D^th, D^ph, B^r, B^th, B^ph")
+    for i, f in enumerate(fields):
+        _need(f, dtype, _grid_numel(g), f"field {i}")
+    f = grpic_fields()
+    for c in range(3):
+        f.D[c] = fields[c].data_ptr()
+        f.B[c] = fields[3 + c].data_ptr()
+    return f
+
+
+def make_current(g, J) -> grpic_current:
+    if len(J) != 3:
+        raise ValueError("current: need F^r, F^th, G^ph")
+    for i, t in enumerate(J):
+        _need(t, torch.float64, _grid_numel(g), f"current {i}")
+    return grpic_current(*[t.data_ptr() for t in J])
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------- entry points
+def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float,
+                       nsteps: int, ncorr: int = 3, ckpt=None, ckpt_every: int = 0,
+                       counters: torch.Tensor | None = None, stream=None) -> None:
+    g = make_grid(grid)
+    sp = make_species(species)
+    P = make_particles(parts)
+    real = torch.float64 if P.precision == GRPIC_FP64 else torch.float32
+    F = make_fields(grid, fields, real)
+    C = make_current(grid, J)
+    if counters is not None:
+        _need(counters, torch.int64, GRPIC_NCOUNTERS, "counters")
+    _check(lib().grpic_push_deposit(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
+                                    ctypes.byref(F), ctypes.byref(C), float(dt), int(nsteps), int(ncorr),
+                                    _ptr(ckpt), int(ckpt_every), _ptr(counters), _stream(stream)))
+
+
+def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None) -> None:
+    g = make_grid(grid)
+    sp = make_species(species)
+    P = make_particles(parts)
+    _need(Q, torch.float64, _grid_numel(grid), "Q")
+    _check(lib().grpic_charge(ctypes.byref(g), sp, len(species), ctypes.byref(P), Q.data_ptr(), _stream(stream)))
+
+
+def grpic_sort_workspace_bytes(grid, n: int) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_sort_workspace_bytes(ctypes.byref(g), int(n)))
+
+
+def grpic_sort(grid, parts_in: dict, parts_out: dict, cell_offsets: torch.Tensor | None,
+               ws: torch.Tensor, n_alive: torch.Tensor, stream=None) -> None:
+    g = make_grid(grid)
+    Pi = make_particles(parts_in)
+    Po = make_particles(parts_out)
+    if Po.n < Pi.n:
+        raise ValueError("parts_out must hold as many particles as parts_in")
+    if cell_offsets is not None:
+        _need(cell_offsets, torch.int64, int(grid.nr) * int(grid.nth) + 1, "cell_offsets")
+    _need(n_alive, torch.int64, 1, "n_alive")
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("ws: expected a contiguous device tensor")
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().grpic_sort(ctypes.byref(g), ctypes.byref(Pi), ctypes.byref(Po), _ptr(cell_offsets),
+                            ws.data_ptr(), nbytes, n_alive.data_ptr(), _stream(stream)))
+
+
+def grpic_crossing_time(metric: grpic_metric, grid) -> float:
+    g = make_grid(grid)
+    return float(lib().grpic_crossing_time(ctypes.byref(metric), ctypes.byref(g)))
+
+
+def grpic_version() -> str:
+    return lib().grpic_version().decode()
+
+
+# ---------------------------------------------------------------- conveniences
+def to_device(parts_np: dict, precision: int = GRPIC_FP64, device="cuda") -> dict:
+    """Copy host particle arrays (numpy) to device tensors of the given precision."""
+    real = torch.float64 if precision == GRPIC_FP64 else torch.float32
+    out = {"cell": torch.as_tensor(parts_np["cell"], dtype=torch.int32).to(device),
+           "sp": torch.as_tensor(parts_np["sp"], dtype=torch.uint8).to(device)}
+    for k in REAL_KEYS:
+        out[k] = torch.as_tensor(parts_np[k]).to(device=device, dtype=real)
+    if "phi" in parts_np:
+        out["phi"] = torch.as_tensor(parts_np["phi"]).to(device=device, dtype=real)
+    return out
+
+
+def to_host(parts: dict) -> dict:
+    return {k: v.detach().cpu().numpy() for k, v in parts.items()}
+
+
+def empty_particles(n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda") -> dict:
+    real = torch.float64 if precision == GRPIC_FP64 else torch.float32
+    out = {"cell": torch.empty(n, dtype=torch.int32, device=device),
+           "sp": torch.empty(n, dtype=torch.uint8, device=device)}
+    for k in REAL_KEYS:
+        out[k] = torch.empty(n, dtype=real, device=device)
+    if with_phi:
+        out["phi"] = torch.empty(n, dtype=real, device=device)
+    return out

@@ -117,12 +117,14 @@ def _ks_pieces(a, M, r, th):
     z = 2.0 * M * r / rho2
     delta = r * r + a * a - 2.0 * M * r
     sigma = (r * r + a * a) ** 2 - a * a * delta * s * s
+    with np.errstate(divide="ignore", invalid="ignore"):     # gamma^phph is infinite on the axis
+        h_pp = 1.0 / (rho2 * s * s)
     return dict(
         s=s, c=c, rho2=rho2, z=z,
         alpha=1.0 / np.sqrt(1.0 + z), beta=z / (1.0 + z),
         g_rr=1.0 + z, g_rp=-a * s * s * (1.0 + z), g_tt=rho2, g_pp=sigma * s * s / rho2,
         h_rr=(a * a + r * r) / rho2 - 2.0 * M * r / (rho2 + 2.0 * M * r),
-        h_rp=a / rho2, h_tt=1.0 / rho2,
+        h_rp=a / rho2, h_tt=1.0 / rho2, h_pp=h_pp,
     )
 
 
@@ -169,17 +171,21 @@ def wald_fields(grid: Grid, B0: float = 1.0, axis_bc: bool = True) -> list[np.nd
     rows, pitch, g = grid.rows, grid.pitch, grid.guard
     ii = np.arange(rows, dtype=np.float64)[:, None] - g
     jj = np.arange(pitch, dtype=np.float64)[None, :] - g
-    out = []
+    by_stagger = {}
     for name in FIELD_NAMES:
-        sr, st = STAGGER[name]
+        by_stagger.setdefault(STAGGER[name], []).append(name)
+    out = {}
+    for (sr, st), names in by_stagger.items():
         r = grid.r(ii + sr) * np.ones_like(jj)
         th = grid.theta(jj + st) * np.ones_like(ii)
-        v = np.ascontiguousarray(wald_point(grid.a, grid.M, B0, r, th)[name], dtype=np.float64)
-        if axis_bc and st == 0.0 and name in ("Dph", "Bth"):
-            v[:, g] = 0.0                 # theta = 0
-            v[:, g + grid.nth] = 0.0      # theta = pi
-        out.append(v)
-    return out
+        vals = wald_point(grid.a, grid.M, B0, r, th)
+        for name in names:
+            v = np.ascontiguousarray(vals[name], dtype=np.float64)
+            if axis_bc and st == 0.0 and name in ("Dph", "Bth"):
+                v[:, g] = 0.0                 # theta = 0
+                v[:, g + grid.nth] = 0.0      # theta = pi
+            out[name] = v
+    return [out[name] for name in FIELD_NAMES]
 
 
 def zero_fields(grid: Grid) -> list[np.ndarray]:
