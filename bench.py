@@ -76,16 +76,12 @@ def run_gpu(args):
     metric = grpic.make_metric(g.a, g.M)
     dt = 0.5 * grpic.grpic_crossing_time(metric, g)
     J = [torch.zeros(g.shape, dtype=torch.float64, device=dev) for _ in range(3)]
-    spare = grpic.empty_particles(parts["cell"].numel(), device=dev)
-    ws = torch.empty(grpic.grpic_sort_workspace_bytes(g, parts["cell"].numel()), dtype=torch.uint8, device=dev)
-    nal = torch.zeros(1, dtype=torch.int64, device=dev)
     counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device=dev)
-
-    state = {"p": parts, "q": spare}
+    sorter = grpic.Sorter(g, parts["cell"].numel(), device=dev)
+    state = {"p": parts}
 
     def do_sort():
-        grpic.grpic_sort(g, state["p"], state["q"], None, ws, nal)
-        state["p"], state["q"] = state["q"], state["p"]
+        state["p"] = sorter.sort(state["p"])
 
     ev_push = []
 
@@ -96,7 +92,7 @@ def run_gpu(args):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-        grpic.grpic_push_deposit(metric, g, sp, state["p"], F, J, dt, 1, args.ncorr,
+        grpic.grpic_push_deposit(metric, g, sp, state["p"], F, J, dt, 1, args.ncorr, tiling=sorter.tiling,
                                  counters=counters if timed else None)
         if timed:
             e1.record()
@@ -202,7 +198,7 @@ def main():
             "dt": r["dt"], "sort_every": args.sort_every, "ncorr": args.ncorr, "precision": "FP64",
         },
         "roofline": hbm,
-        "kernel": {"name": "push_deposit_f64", "avg_ms": r["avg_push_ms"],
+        "kernel": {"name": "push_deposit_f64_tiled", "avg_ms": r["avg_push_ms"],
                    "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
                    "live_particles_per_launch": r["live_per_launch"]},
         "cpu_baseline": cpu,

@@ -121,7 +121,8 @@ typedef struct {
 #define GRPIC_CNT_BAD 1        /* removed as non-finite or moving >= 1 cell      */
 #define GRPIC_CNT_REFLECT 2    /* reflections at the axis                         */
 #define GRPIC_CNT_LIVE 3       /* particle-steps taken by live particles          */
-#define GRPIC_NCOUNTERS 4
+#define GRPIC_CNT_SPILL 4      /* tiled path: deposits outside the LDS window     */
+#define GRPIC_NCOUNTERS 5
 
 /*
  * grpic_push_deposit -- advance every live particle `nsteps` steps through
@@ -138,10 +139,19 @@ typedef struct {
  * (eqs. esirkepov-decomp, j-phi-deposit, local prefix sum); a particle that
  * leaves [0, nr) in xi deposits its move into the guard vertices and is
  * removed (cell = -1).  A particle whose end point is not finite or that
- * moved one cell or more is removed without depositing (counted as BAD).
+ * moved one cell or more is removed without depositing (counted as BAD), and
+ * so is one whose cell, offsets or species index are out of range.
  *
  * species: host array of nsp entries (1 <= nsp <= GRPIC_MAX_SPECIES).
  * parts: updated in place.  fields: read only.  J: accumulated.
+ * tiling: NULL, or the tiling written by the grpic_sort call that produced
+ *   the current particle order (same n and grid; checked, GRPIC_EINVAL
+ *   otherwise).  With a tiling each workgroup accumulates the current of
+ *   one slice of cell-sorted particles in LDS and flushes it once; particles
+ *   that have drifted out of their tile's LDS window since the sort deposit
+ *   straight to global memory, so results do not depend on how fresh the
+ *   sort is.  Only particles live at the sort are pushed (the sort marks the
+ *   rest removed); without a tiling any particle order works.
  * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
  * ckpt, ckpt_every: reserved for the adjoint (pass NULL, 0).
  * counters: optional device int64[GRPIC_NCOUNTERS], accumulated.
@@ -149,7 +159,7 @@ typedef struct {
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                       double dt, int nsteps, int ncorr,
+                       const void* tiling, double dt, int nsteps, int ncorr,
                        void* ckpt, int ckpt_every,
                        int64_t* counters, void* stream);
 
@@ -169,17 +179,21 @@ int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
  * particles and must not alias in; out->n is not read.  On completion the
  * first *n_alive_dev elements of out hold the live particles ordered by
  * cell; the remaining in->n - *n_alive_dev elements have cell = -1 (removed)
- * and their other fields unspecified, so out can be pushed with n = in->n.  cell_offsets (optional, device
- * int64[nr*nth + 1]) receives the exclusive prefix sum of the per-cell
- * counts.  ws: device workspace of at least grpic_sort_workspace_bytes().
- * n_alive_dev: device int64 receiving the live count.
+ * and their other fields unspecified, so out can be pushed with n = in->n.
+ * cell_offsets (optional, device int64[nr*nth + 1]) receives the exclusive
+ * prefix sum of the per-cell counts.  tiling (optional, device, at least
+ * grpic_tiling_bytes(grid, in->n) bytes) receives the slice table that
+ * grpic_push_deposit's tiled path runs on.  ws: device workspace of at least
+ * grpic_sort_workspace_bytes() bytes.  n_alive_dev: device int64 receiving
+ * the live count.
  * Not described by the paper: particles are kept ordered by cell so that a
- * wavefront's particles share field and current cache lines.
+ * workgroup's particles share field cache lines and one LDS current window.
  */
 size_t grpic_sort_workspace_bytes(const grpic_grid* grid, int64_t n);
+size_t grpic_tiling_bytes(const grpic_grid* grid, int64_t n);
 int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
-               int64_t* cell_offsets, void* ws, size_t ws_bytes, int64_t* n_alive_dev,
-               void* stream);
+               int64_t* cell_offsets, void* tiling, size_t tiling_bytes, void* ws, size_t ws_bytes,
+               int64_t* n_alive_dev, void* stream);
 
 /*
  * grpic_crossing_time -- minimum over cell centres of the time light needs to

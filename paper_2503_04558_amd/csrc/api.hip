@@ -113,6 +113,15 @@ double crossing_time_cached(const grpic_metric* m, const grpic_grid* g) {
     return t;
 }
 
+// Host-side record of the tilings written by grpic_sort, so that a push can
+// check without a device round trip that a tiling describes its particles.
+struct TilingInfo {
+    int64_t n;
+    int nr, nth;
+};
+std::mutex g_tiling_mu;
+std::map<const void*, TilingInfo> g_tilings;
+
 void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
                  const grpic_species* sp, int nsp, const grpic_particles* p) {
     memset(&A, 0, sizeof A);
@@ -149,7 +158,7 @@ double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid) {
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                       double dt, int nsteps, int ncorr,
+                       const void* tiling, double dt, int nsteps, int ncorr,
                        void* ckpt, int ckpt_every,
                        int64_t* counters, void* stream) {
     int rc;
@@ -168,6 +177,14 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     const double tc = crossing_time_cached(metric, grid);
     if (dt > tc * (1.0 + 1e-12))
         return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
+    if (tiling) {
+        std::lock_guard<std::mutex> lk(g_tiling_mu);
+        auto it = g_tilings.find(tiling);
+        if (it == g_tilings.end() || it->second.n != parts->n || it->second.nr != grid->nr ||
+            it->second.nth != grid->nth)
+            return fail(GRPIC_EINVAL, "tiling was not written by grpic_sort for %lld particles on this grid",
+                        (long long)parts->n);
+    }
     if (parts->n == 0 || nsteps == 0) return GRPIC_OK;
 
     grpic::StepArgs A;
@@ -178,8 +195,11 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;
     A.counters = reinterpret_cast<unsigned long long*>(counters);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
     for (int step = 0; step < nsteps; ++step) {
-        if ((rc = hip_status(grpic::launch_push_deposit_f64(A, s), "push_deposit launch"))) return rc;
+        const hipError_t e = tiling ? grpic::launch_push_deposit_f64_tiled(A, tiling, cap, s)
+                                    : grpic::launch_push_deposit_f64(A, s);
+        if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
     return GRPIC_OK;
 }
@@ -199,12 +219,17 @@ int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
 size_t grpic_sort_workspace_bytes(const grpic_grid* grid, int64_t n) {
     (void)n;
     if (!grid || grid->nr <= 0 || grid->nth <= 0) return 0;
-    const int64_t len = (int64_t)grid->nr * grid->nth + 1;
-    return (size_t)(len + grpic::sort_scan_blocks(len) + 1) * sizeof(unsigned long long);
+    return grpic::sort_workspace_bytes(grid->nr, grid->nth);
+}
+
+size_t grpic_tiling_bytes(const grpic_grid* grid, int64_t n) {
+    if (!grid || grid->nr <= 0 || grid->nth <= 0 || n < 0) return 0;
+    return grpic::tiling_bytes(n, grid->nr, grid->nth);
 }
 
 int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
-               int64_t* cell_offsets, void* ws, size_t ws_bytes, int64_t* n_alive_dev, void* stream) {
+               int64_t* cell_offsets, void* tiling, size_t tiling_bytes, void* ws, size_t ws_bytes,
+               int64_t* n_alive_dev, void* stream) {
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_particles(in, "in")) || (rc = check_particles(out, "out")))
         return rc;
@@ -217,9 +242,15 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
     if (!n_alive_dev) return fail(GRPIC_EINVAL, "n_alive_dev is NULL");
     const size_t need = grpic_sort_workspace_bytes(grid, in->n);
     if (!ws || ws_bytes < need) return fail(GRPIC_ENOMEM, "sort workspace needs %zu bytes, got %zu", need, ws_bytes);
+    if (tiling) {
+        const size_t tneed = grpic_tiling_bytes(grid, in->n);
+        if (tiling_bytes < tneed) return fail(GRPIC_ENOMEM, "tiling needs %zu bytes, got %zu", tneed, tiling_bytes);
+    }
     grpic::SortArgs S;
     memset(&S, 0, sizeof S);
     S.n = in->n;
+    S.nr = grid->nr;
+    S.nth = grid->nth;
     S.ncell = grid->nr * grid->nth;
     S.elem = in->precision == GRPIC_FP64 ? 8 : 4;
     S.cell_in = in->cell;
@@ -233,9 +264,17 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
     S.phi_out = out->phi;
     S.counts = static_cast<unsigned long long*>(ws);
     S.blocksums = S.counts + (S.ncell + 1);
+    S.tile_slices = S.blocksums + grpic::sort_scan_blocks((int64_t)S.ncell + 1) + 1;
     S.cell_offsets = cell_offsets;
     S.n_alive = n_alive_dev;
-    return hip_status(grpic::launch_sort(S, static_cast<hipStream_t>(stream)), "sort launch");
+    S.tiling = tiling;
+    if ((rc = hip_status(grpic::launch_sort(S, static_cast<hipStream_t>(stream)), "sort launch"))) return rc;
+    if (tiling) {
+        std::lock_guard<std::mutex> lk(g_tiling_mu);
+        if (g_tilings.size() > 4096) g_tilings.clear();
+        g_tilings[tiling] = TilingInfo{in->n, grid->nr, grid->nth};
+    }
+    return GRPIC_OK;
 }
 
 }  // extern "C"

@@ -1,6 +1,6 @@
 // grpic_launch.hpp -- host-side launchers of the device kernels, called by
-// the C ABI in api.hip.  Every launcher enqueues on `stream` and returns the
-// launch status.
+// the C ABI in api.hip, and the layout of the tiling buffer shared by the
+// sort (which writes it) and the tiled push kernels (which read it).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,12 +11,51 @@
 
 namespace grpic {
 
+// ---------------------------------------------------------------- tiling
+// A tile is a segment of kTileCells consecutive cells of one grid row
+// (theta is the contiguous direction, so a tile's particles are contiguous
+// in a cell-sorted particle array).  Each tile's particles are cut into
+// balanced slices of at most kSliceMax particles; one workgroup pushes one
+// slice and accumulates its current in an LDS window that covers the tile
+// plus kMarginRows rows and kMarginCols columns of drift on each side.
+constexpr int kTileCells = 64;
+constexpr int kSliceMax = 2048;
+constexpr int kPushThreads = 256;
+constexpr int kPushIter = kSliceMax / kPushThreads;       // particles per thread
+constexpr int kMarginRows = 6;
+constexpr int kMarginCols = 4;
+constexpr int kWinRows = 2 * kMarginRows + 4;              // vertex rows of the LDS window
+constexpr int kWinCols = kTileCells + 2 * kMarginCols + 3; // vertex columns of the LDS window
+
+struct TilingHeader {
+    int64_t nslices;          // written by the sort on the device
+    int64_t n;                // particle count the tiling was built for
+    int32_t nr, nth, tiles_per_row, tile_cells;
+};
+
+struct Slice {
+    int64_t start;            // first particle
+    int32_t len;              // particles in the slice (<= kSliceMax)
+    int32_t tile;             // row * tiles_per_row + column block
+};
+
+inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; }
+inline int64_t slice_capacity(int64_t n, int nr, int nth) {
+    return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 1;
+}
+inline size_t tiling_bytes(int64_t n, int nr, int nth) {
+    return sizeof(TilingHeader) + (size_t)slice_capacity(n, nr, nth) * sizeof(Slice);
+}
+
+// ---------------------------------------------------------------- launchers
 hipError_t launch_push_deposit_f64(const StepArgs& A, hipStream_t stream);
+hipError_t launch_push_deposit_f64_tiled(const StepArgs& A, const void* tiling, int64_t slice_cap,
+                                         hipStream_t stream);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream);
 
 struct SortArgs {
     int64_t n;
-    int ncell;
+    int nr, nth, ncell;
     size_t elem;                      // bytes of one xr/xth/ur/uth/uph/w element (8 or 4)
     const int32_t* cell_in;
     const void* in[6];                // xr, xth, ur, uth, uph, w
@@ -28,11 +67,14 @@ struct SortArgs {
     void* phi_out;
     unsigned long long* counts;       // ncell + 1 entries of workspace
     unsigned long long* blocksums;    // sort_scan_blocks(ncell + 1) + 1 entries of workspace
+    unsigned long long* tile_slices;  // ntiles + 1 entries of workspace (tiling only)
     int64_t* cell_offsets;            // optional output, ncell + 1
     int64_t* n_alive;                 // device output
+    void* tiling;                     // optional output, tiling_bytes()
 };
 
 int64_t sort_scan_blocks(int64_t len);
+size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
 
 }  // namespace grpic

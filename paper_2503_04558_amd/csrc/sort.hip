@@ -1,8 +1,12 @@
-// sort.hip -- counting sort of particles by cell.
+// sort.hip -- counting sort of particles by cell, and the tiling the tiled
+// push kernel runs on.
 //
 // histogram of live cells -> exclusive scan (two-level, 4096 entries per
-// block) -> scatter with one atomic cursor per cell.  Removed particles
-// (cell < 0) are dropped; the order inside a cell is not specified.
+// block) -> [tiling: per-tile slice counts -> scan -> slice table] ->
+// scatter.  The scatter finds runs of equal cells among the lanes of a wave
+// (the input is usually almost sorted) and takes one atomic per run.
+// Removed particles (cell < 0) are dropped and the tail of the output is
+// marked removed; the order inside a cell is not specified.
 #include "grpic_launch.hpp"
 
 namespace grpic {
@@ -12,6 +16,12 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 int64_t sort_scan_blocks(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
+
+size_t sort_workspace_bytes(int nr, int nth) {
+    const int64_t len = (int64_t)nr * nth + 1;
+    const int64_t ntiles = (int64_t)nr * tiles_per_row(nth);
+    return (size_t)(len + sort_scan_blocks(len) + 1 + ntiles + 1) * sizeof(unsigned long long);
+}
 
 __global__ __launch_bounds__(256) void fill_u64(unsigned long long* __restrict__ a, int64_t n, unsigned long long v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,6 +93,65 @@ __global__ __launch_bounds__(256) void scan_add(unsigned long long* __restrict__
     if (i < len) a[i] += bs[i / kScanTile];
 }
 
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Exclusive scan of a[0..len) in place (a[len-1] should be a zero sentinel
+// so that it receives the total).
+static void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* blocksums, hipStream_t stream) {
+    const int64_t nb = sort_scan_blocks(len);
+    hipLaunchKernelGGL(scan_tiles, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, a, len, blocksums);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kScanThreads), 0, stream, blocksums, nb);
+    hipLaunchKernelGGL(scan_add, dim3(nblk(len)), dim3(256), 0, stream, a, len, blocksums);
+}
+
+// Number of slices of each tile, from the scanned cell offsets.
+__global__ __launch_bounds__(256) void tile_slice_counts(const unsigned long long* __restrict__ offs, int nr, int nth,
+                                                         int tpr, unsigned long long* __restrict__ ns) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntiles = (int64_t)nr * tpr;
+    if (t > ntiles) return;
+    if (t == ntiles) { ns[t] = 0ull; return; }
+    const int i = (int)(t / tpr), jb = (int)(t - (int64_t)i * tpr);
+    const int64_t c0 = (int64_t)i * nth + (int64_t)jb * kTileCells;
+    const int64_t c1 = c0 + min(kTileCells, nth - jb * kTileCells);
+    const unsigned long long cnt = offs[c1] - offs[c0];
+    ns[t] = (cnt + kSliceMax - 1) / kSliceMax;
+}
+
+// Slice table: tile t's particles cut into ns balanced slices.
+__global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __restrict__ offs,
+                                                   const unsigned long long* __restrict__ base, int nr, int nth,
+                                                   int tpr, int64_t n, TilingHeader* hdr, Slice* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntiles = (int64_t)nr * tpr;
+    if (t == 0) {
+        hdr->nslices = (int64_t)base[ntiles];
+        hdr->n = n;
+        hdr->nr = nr;
+        hdr->nth = nth;
+        hdr->tiles_per_row = tpr;
+        hdr->tile_cells = kTileCells;
+    }
+    if (t >= ntiles) return;
+    const int i = (int)(t / tpr), jb = (int)(t - (int64_t)i * tpr);
+    const int64_t c0 = (int64_t)i * nth + (int64_t)jb * kTileCells;
+    const int64_t c1 = c0 + min(kTileCells, nth - jb * kTileCells);
+    const int64_t start = (int64_t)offs[c0];
+    const int64_t cnt = (int64_t)offs[c1] - start;
+    const int64_t b = (int64_t)base[t];
+    const int64_t ns = (int64_t)base[t + 1] - b;
+    if (ns <= 0) return;
+    const int64_t each = (cnt + ns - 1) / ns;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int64_t s0 = s * each;
+        Slice sl;
+        sl.start = start + s0;
+        sl.len = (int32_t)(cnt - s0 < each ? cnt - s0 : each);
+        sl.tile = (int32_t)t;
+        out[b + s] = sl;
+    }
+}
+
 __global__ __launch_bounds__(256) void sort_offsets_out(const unsigned long long* __restrict__ counts, int ncell,
                                                         int64_t* __restrict__ offsets, int64_t* __restrict__ n_alive) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,27 +169,49 @@ __global__ __launch_bounds__(256) void sort_mark_tail(int32_t* __restrict__ cell
 template <class T>
 __global__ __launch_bounds__(256) void sort_scatter(const SortArgs S) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= S.n) return;
-    const int c = S.cell_in[p];
-    if (c < 0 || c >= S.ncell) return;
-    const int64_t q = (int64_t)atomicAdd(S.counts + c, 1ull);
+    const int c = p < S.n ? S.cell_in[p] : -1;
+    const bool valid = c >= 0 && c < S.ncell;
+    // runs of equal cells among adjacent lanes: one atomic per run
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(c, 1);
+    const int next = __shfl_down(c, 1);
+    const unsigned long long heads = __ballot(valid && (lane == 0 || prev != c));
+    const unsigned long long tails = __ballot(valid && (lane == 63 || next != c));
+    int head = 0, tail = 0;
+    if (valid) {
+        const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+        head = 63 - __clzll(heads & upto);
+        const unsigned long long from = ~((1ull << head) - 1ull);
+        tail = __ffsll((long long)(tails & from)) - 1;
+    }
+    long long base = 0;
+    if (valid && lane == head) base = (long long)atomicAdd(S.counts + c, (unsigned long long)(tail - head + 1));
+    base = __shfl(base, head);          // every lane takes part
+    if (!valid) return;
+    const int64_t q = (int64_t)base + (lane - head);
     S.cell_out[q] = c;
     for (int k = 0; k < 6; ++k) static_cast<T*>(S.out[k])[q] = static_cast<const T*>(S.in[k])[p];
     S.sp_out[q] = S.sp_in[p];
     if (S.phi_in) static_cast<T*>(S.phi_out)[q] = static_cast<const T*>(S.phi_in)[p];
 }
 
-static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
-
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
     const int64_t len = (int64_t)S.ncell + 1;
-    const int64_t nb = sort_scan_blocks(len);
     hipLaunchKernelGGL(fill_u64, dim3(nblk(len)), dim3(256), 0, stream, S.counts, len, 0ull);
     if (S.n > 0)
         hipLaunchKernelGGL(sort_hist, dim3(nblk(S.n)), dim3(256), 0, stream, S.cell_in, S.n, S.ncell, S.counts);
-    hipLaunchKernelGGL(scan_tiles, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, S.counts, len, S.blocksums);
-    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kScanThreads), 0, stream, S.blocksums, nb);
-    hipLaunchKernelGGL(scan_add, dim3(nblk(len)), dim3(256), 0, stream, S.counts, len, S.blocksums);
+    scan_exclusive(S.counts, len, S.blocksums, stream);
+    if (S.tiling) {
+        const int tpr = tiles_per_row(S.nth);
+        const int64_t ntiles = (int64_t)S.nr * tpr;
+        TilingHeader* hdr = static_cast<TilingHeader*>(S.tiling);
+        Slice* slices = reinterpret_cast<Slice*>(hdr + 1);
+        hipLaunchKernelGGL(tile_slice_counts, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.nr, S.nth,
+                           tpr, S.tile_slices);
+        scan_exclusive(S.tile_slices, ntiles + 1, S.blocksums, stream);
+        hipLaunchKernelGGL(tile_slices, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.tile_slices, S.nr,
+                           S.nth, tpr, S.n, hdr, slices);
+    }
     hipLaunchKernelGGL(sort_offsets_out, dim3(nblk(len)), dim3(256), 0, stream, S.counts, S.ncell,
                        S.cell_offsets, S.n_alive);
     if (S.n > 0) {

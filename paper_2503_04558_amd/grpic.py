@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(PKG, "libgrpic.so")
 GRPIC_OK, GRPIC_EINVAL, GRPIC_ERANGE, GRPIC_ENOMEM, GRPIC_EHIP = 0, -1, -2, -3, -4
 GRPIC_FP64, GRPIC_FP32_SPLIT = 0, 1
 GRPIC_MAX_SPECIES = 8
-GRPIC_NCOUNTERS = 4
-COUNTER_NAMES = ("out", "bad", "reflected", "live_steps")
+GRPIC_NCOUNTERS = 5
+COUNTER_NAMES = ("out", "bad", "reflected", "live_steps", "spilled")
 
 PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
 REAL_KEYS = ("xr", "xth", "ur", "uth", "uph", "w")
@@ -56,7 +56,7 @@ class grpic_current(ctypes.Structure):
 
 
 EXPORTED = ("grpic_push_deposit", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
-            "grpic_crossing_time", "grpic_last_error", "grpic_version")
+            "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version")
 
 
 class GrpicError(RuntimeError):
@@ -76,13 +76,15 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2503_04558_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
-        L.grpic_push_deposit.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, i32, vp, vp]
+        L.grpic_push_deposit.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, i32, vp, vp]
         L.grpic_push_deposit.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge.restype = ctypes.c_int
         L.grpic_sort_workspace_bytes.argtypes = [vp, i64]
         L.grpic_sort_workspace_bytes.restype = ctypes.c_size_t
-        L.grpic_sort.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, vp]
+        L.grpic_sort.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp]
+        L.grpic_tiling_bytes.argtypes = [vp, i64]
+        L.grpic_tiling_bytes.restype = ctypes.c_size_t
         L.grpic_sort.restype = ctypes.c_int
         L.grpic_crossing_time.argtypes = [vp, vp]
         L.grpic_crossing_time.restype = ctypes.c_double
@@ -182,8 +184,8 @@ def _stream(stream) -> int | None:
 
 # ---------------------------------------------------------------- entry points
 def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float,
-                       nsteps: int, ncorr: int = 3, ckpt=None, ckpt_every: int = 0,
-                       counters: torch.Tensor | None = None, stream=None) -> None:
+                       nsteps: int, ncorr: int = 3, tiling: torch.Tensor | None = None, ckpt=None,
+                       ckpt_every: int = 0, counters: torch.Tensor | None = None, stream=None) -> None:
     g = make_grid(grid)
     sp = make_species(species)
     P = make_particles(parts)
@@ -192,9 +194,11 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
     C = make_current(grid, J)
     if counters is not None:
         _need(counters, torch.int64, GRPIC_NCOUNTERS, "counters")
+    if tiling is not None and (not tiling.is_cuda or not tiling.is_contiguous()):
+        raise ValueError("tiling: expected a contiguous device tensor")
     _check(lib().grpic_push_deposit(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
-                                    ctypes.byref(F), ctypes.byref(C), float(dt), int(nsteps), int(ncorr),
-                                    _ptr(ckpt), int(ckpt_every), _ptr(counters), _stream(stream)))
+                                    ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(nsteps),
+                                    int(ncorr), _ptr(ckpt), int(ckpt_every), _ptr(counters), _stream(stream)))
 
 
 def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None) -> None:
@@ -210,8 +214,13 @@ def grpic_sort_workspace_bytes(grid, n: int) -> int:
     return int(lib().grpic_sort_workspace_bytes(ctypes.byref(g), int(n)))
 
 
+def grpic_tiling_bytes(grid, n: int) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_tiling_bytes(ctypes.byref(g), int(n)))
+
+
 def grpic_sort(grid, parts_in: dict, parts_out: dict, cell_offsets: torch.Tensor | None,
-               ws: torch.Tensor, n_alive: torch.Tensor, stream=None) -> None:
+               ws: torch.Tensor, n_alive: torch.Tensor, tiling: torch.Tensor | None = None, stream=None) -> None:
     g = make_grid(grid)
     Pi = make_particles(parts_in)
     Po = make_particles(parts_out)
@@ -220,11 +229,32 @@ def grpic_sort(grid, parts_in: dict, parts_out: dict, cell_offsets: torch.Tensor
     if cell_offsets is not None:
         _need(cell_offsets, torch.int64, int(grid.nr) * int(grid.nth) + 1, "cell_offsets")
     _need(n_alive, torch.int64, 1, "n_alive")
-    if not ws.is_cuda or not ws.is_contiguous():
-        raise ValueError("ws: expected a contiguous device tensor")
+    for t, name in ((ws, "ws"), (tiling, "tiling")):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous device tensor")
     nbytes = ws.numel() * ws.element_size()
+    tbytes = 0 if tiling is None else tiling.numel() * tiling.element_size()
     _check(lib().grpic_sort(ctypes.byref(g), ctypes.byref(Pi), ctypes.byref(Po), _ptr(cell_offsets),
-                            ws.data_ptr(), nbytes, n_alive.data_ptr(), _stream(stream)))
+                            _ptr(tiling), tbytes, ws.data_ptr(), nbytes, n_alive.data_ptr(), _stream(stream)))
+
+
+class Sorter:
+    """Buffers for repeated grpic_sort calls on one grid and particle count:
+    a spare particle set, the workspace, the tiling and the live count."""
+
+    def __init__(self, grid, n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda"):
+        self.grid = grid
+        self.spare = empty_particles(n, precision, with_phi, device)
+        self.ws = torch.empty(max(1, grpic_sort_workspace_bytes(grid, n)), dtype=torch.uint8, device=device)
+        self.tiling = torch.empty(max(1, grpic_tiling_bytes(grid, n)), dtype=torch.uint8, device=device)
+        self.n_alive = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def sort(self, parts: dict, cell_offsets=None, stream=None) -> dict:
+        """Sorts `parts` into the spare set and returns it; `parts` becomes the spare."""
+        out = self.spare
+        grpic_sort(self.grid, parts, out, cell_offsets, self.ws, self.n_alive, self.tiling, stream)
+        self.spare = parts
+        return out
 
 
 def grpic_crossing_time(metric: grpic_metric, grid) -> float:

@@ -46,7 +46,7 @@ def _call_push(metric, grid, species, nsp, parts, fields, cur, dt, nsteps=1, nco
         ctypes.byref(parts) if parts is not None else None,
         ctypes.byref(fields) if fields is not None else None,
         ctypes.byref(cur) if cur is not None else None,
-        dt, nsteps, ncorr, None, 0, None, None)
+        None, dt, nsteps, ncorr, None, 0, None, None)
 
 
 def _fake_args(g):
@@ -107,8 +107,23 @@ def test_sort_workspace_and_validation():
     fake = 0x1000
     pin = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP64, 0)
     pout = grpic.grpic_particles(10, *([fake + 64] * 8), None, grpic.GRPIC_FP64, 0)
-    rc = L.grpic_sort(ctypes.byref(G), ctypes.byref(pin), ctypes.byref(pout), None, fake, need - 8, fake, None)
+    rc = L.grpic_sort(ctypes.byref(G), ctypes.byref(pin), ctypes.byref(pout), None, None, 0, fake, need - 8,
+                      fake, None)
+    assert rc == grpic.GRPIC_ENOMEM
+    tneed = grpic.grpic_tiling_bytes(g, 10)
+    rc = L.grpic_sort(ctypes.byref(G), ctypes.byref(pin), ctypes.byref(pout), None, fake, tneed - 1, fake, need,
+                      fake, None)
     assert rc == grpic.GRPIC_ENOMEM
     pout.precision = grpic.GRPIC_FP32_SPLIT
-    rc = L.grpic_sort(ctypes.byref(G), ctypes.byref(pin), ctypes.byref(pout), None, fake, need, fake, None)
+    rc = L.grpic_sort(ctypes.byref(G), ctypes.byref(pin), ctypes.byref(pout), None, None, 0, fake, need, fake, None)
     assert rc == grpic.GRPIC_EINVAL
+
+
+def test_push_rejects_unknown_tiling():
+    g = wl.make_grid(32, 32, 0.9)
+    parts, fields, cur = _fake_args(g)
+    L = grpic.lib()
+    rc = L.grpic_push_deposit(ctypes.byref(grpic.make_metric(0.9, 1.0)), ctypes.byref(grpic.make_grid(g)),
+                              grpic.make_species(wl.species_table()), 2, ctypes.byref(parts), ctypes.byref(fields),
+                              ctypes.byref(cur), 0x2000, wl.crossing_dt(g), 1, 3, None, 0, None, None)
+    assert rc == grpic.GRPIC_EINVAL and b"tiling" in L.grpic_last_error()

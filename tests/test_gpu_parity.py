@@ -28,24 +28,29 @@ def test_device_present():
     assert "libgrpic" in grpic.lib()._name
 
 
-def test_parity_small_wald_config():
+TILED = [pytest.param(False, id="untiled"), pytest.param(True, id="tiled")]
+
+
+@pytest.mark.parametrize("tiled", TILED)
+def test_parity_small_wald_config(tiled):
     """256^2, a = 0.99, 1e5 e+- pairs, |u| uniform in [0, 1], Wald B0 = 1,
     dt = half the light-crossing time, 10 steps."""
-    _announce("parity 256x256 a=0.99 2e5 particles 10 steps")
+    _announce(f"parity 256x256 a=0.99 2e5 particles 10 steps tiled={tiled}")
     g = wl.make_grid(256, 256, 0.99)
     parts = wl.pairs(g, 100_000, kind="uniform", seed=0)
-    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 10, TOL)
+    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 10, TOL, tiled=tiled)
     _announce(f"errors {e} counters {c}")
     assert c["out"] > 0 and c["reflected"] > 0     # both boundaries exercised
 
 
+@pytest.mark.parametrize("tiled", TILED)
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257, 1001])
-def test_parity_ragged_sizes(n):
-    _announce(f"parity ragged n={n}")
-    g = wl.make_grid(40, 24, 0.9)
+def test_parity_ragged_sizes(n, tiled):
+    _announce(f"parity ragged n={n} tiled={tiled}")
+    g = wl.make_grid(40, 100, 0.9)        # 100 theta cells: a partial last tile per row
     parts = wl.pairs(g, (n + 1) // 2, kind="mj", seed=n, params=dict(T=0.5))
     parts = {k: v[:n] for k, v in parts.items()}
-    assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=3.0), wl.crossing_dt(g), 5, TOL)
+    assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=3.0), wl.crossing_dt(g), 5, TOL, tiled=tiled)
 
 
 def test_empty_and_zero_steps_are_noops():
@@ -59,7 +64,8 @@ def test_empty_and_zero_steps_are_noops():
     assert all(not j.any() for j in Jg)
 
 
-def test_parity_axis_and_edges():
+@pytest.mark.parametrize("tiled", TILED)
+def test_parity_axis_and_edges(tiled):
     """Particles driven into both axes and out through both radial edges."""
     _announce("parity axis/edges")
     g = wl.make_grid(24, 24, 0.99)
@@ -76,7 +82,8 @@ def test_parity_axis_and_edges():
     ur, uth, uph = wl.frame_to_covariant(g.a, g.M, r, th, uh)
     parts = dict(cell=(i * g.nth + j).astype(np.int32), xr=rng.uniform(0, 1, n), xth=rng.uniform(0, 1, n),
                  ur=ur, uth=uth, uph=uph, w=rng.uniform(0.5, 2.0, n), sp=rng.integers(0, 2, n).astype(np.uint8))
-    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=2.0), wl.crossing_dt(g), 6, TOL)
+    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=2.0), wl.crossing_dt(g), 6, TOL,
+                         tiled=tiled)
     assert c["reflected"] > 20 and c["out"] > 100
 
 
@@ -108,13 +115,48 @@ def test_parity_flat_space_uniform_field():
     assert_parity(g, wl.species_table(), parts, F, wl.crossing_dt(g), 8, TOL)
 
 
-def test_parity_photons_and_ions():
+@pytest.mark.parametrize("tiled", TILED)
+def test_parity_photons_and_ions(tiled):
     g = wl.make_grid(32, 32, 0.9)
     parts = wl.pairs(g, 2000, kind="mj", seed=6, params=dict(T=1.0))
     parts["sp"] = np.arange(len(parts["sp"])) % 3
     parts["sp"] = parts["sp"].astype(np.uint8)
     species = [dict(q=-1.0, m=1.0), dict(q=2.0, m=50.0), dict(q=0.0, m=0.0, massless=1)]
-    assert_parity(g, species, parts, wl.wald_fields(g, B0=5.0), wl.crossing_dt(g), 6, TOL)
+    assert_parity(g, species, parts, wl.wald_fields(g, B0=5.0), wl.crossing_dt(g), 6, TOL, tiled=tiled)
+
+
+def test_tiled_equals_untiled_with_drift_beyond_window():
+    """One sort, then 40 steps: particles near the horizon and the fast ones
+    leave their tile's LDS window and deposit to global memory.  On identical
+    sorted inputs the tiled push must reproduce the untiled one bit for bit
+    for every particle, and its current up to summation order."""
+    _announce("tiled vs untiled with drift")
+    g = wl.make_grid(64, 128, 0.99)
+    host = wl.pairs(g, 40_000, kind="uniform", seed=12, params=dict(umax=3.0))
+    n = len(host["cell"])
+    sorter = grpic.Sorter(g, n)
+    base = sorter.sort(grpic.to_device(host))
+    copies = [{k: v.clone() for k, v in base.items()} for _ in range(2)]
+    F = [torch.as_tensor(f).cuda() for f in wl.wald_fields(g, B0=2.0)]
+    Js = [[torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)] for _ in range(2)]
+    cnts = [torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda") for _ in range(2)]
+    m = grpic.make_metric(g.a, g.M)
+    dt = wl.crossing_dt(g)
+    for step in range(40):
+        grpic.grpic_push_deposit(m, g, wl.species_table(), copies[0], F, Js[0], dt, 1, counters=cnts[0])
+        grpic.grpic_push_deposit(m, g, wl.species_table(), copies[1], F, Js[1], dt, 1, tiling=sorter.tiling,
+                                 counters=cnts[1])
+    torch.cuda.synchronize()
+    for k in copies[0]:
+        assert torch.equal(copies[0][k], copies[1][k]), k
+    for a, b in zip(*Js):
+        assert (a - b).abs().max().item() <= 1e-13 * a.abs().max().item()
+    c0 = dict(zip(grpic.COUNTER_NAMES, cnts[0].tolist()))
+    c1 = dict(zip(grpic.COUNTER_NAMES, cnts[1].tolist()))
+    _announce(f"untiled {c0} tiled {c1}")
+    assert {k: c0[k] for k in ("out", "bad", "reflected", "live_steps")} == \
+           {k: c1[k] for k in ("out", "bad", "reflected", "live_steps")}
+    assert c1["spilled"] > 1000 and c0["spilled"] == 0
 
 
 def test_ncorr_variants():
