@@ -35,6 +35,13 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, TFLOP/s
 # Algorithmic HBM bytes of one FP64 particle-step: read cell (4) + xr, xth,
 # ur, uth, uph, w (48) + sp (1); write cell (4) + xr, xth, ur, uth, uph (40).
 FP64_PARTICLE_BYTES = 53 + 44
+# Split form: cell (4) + six float32 (24) + sp (1) read; cell (4) + five float32 (20) written.
+SPLIT_PARTICLE_BYTES = 29 + 24
+# Algorithmic floating-point operations of one particle-step (gather, kick,
+# predictor + 3 correctors, deposit), counted by running the plain CPU
+# reference on a counting scalar type (+, -, *, /, sqrt, exp, sin, cos one
+# each); tests/test_bench_constants.py keeps it in step with that count.
+FP64_OPS_PER_PARTICLE_STEP = 1344
 
 
 def log(msg: str) -> None:
@@ -61,23 +68,20 @@ def make_workload(npairs: int, nr: int, nth: int, a: float, device: str = "cuda"
     return g, F, parts
 
 
-def run_gpu(args):
+def run_gpu(args, g, F, parts, precision):
+    """Warm up, then time args.steps push + deposit steps of one precision."""
     import torch
 
     from paper_2503_04558_amd import grpic
     from paper_2503_04558_amd import workload as wl
 
     dev = "cuda"
-    t0 = time.time()
-    g, F, parts = make_workload(args.pairs, args.nr, args.nth, args.spin, workers=args.workers)
-    torch.cuda.synchronize()
-    log(f"inputs ready in {time.time() - t0:.1f}s: grid {g.nr}x{g.nth}, {2 * args.pairs} particles")
     sp = wl.species_table()
     metric = grpic.make_metric(g.a, g.M)
     dt = 0.5 * grpic.grpic_crossing_time(metric, g)
     J = [torch.zeros(g.shape, dtype=torch.float64, device=dev) for _ in range(3)]
     counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device=dev)
-    sorter = grpic.Sorter(g, parts["cell"].numel(), device=dev)
+    sorter = grpic.Sorter(g, parts["cell"].numel(), precision, device=dev)
     state = {"p": parts}
 
     def do_sort():
@@ -101,7 +105,7 @@ def run_gpu(args):
     for k in range(args.warmup):
         step(k, False)
     torch.cuda.synchronize()
-    log(f"warmup {args.warmup} steps done")
+    log(f"{'split' if precision else 'fp64'}: warmup {args.warmup} steps done")
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -115,18 +119,23 @@ def run_gpu(args):
     total_ms = start.elapsed_time(stop)
     push_ms = [a.elapsed_time(b) for a, b in ev_push]
     cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
-    log(f"timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), counters {cnt}")
+    log(f"{'split' if precision else 'fp64'}: timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), "
+        f"counters {cnt}")
     live = cnt["live_steps"]
     value = live / (total_ms * 1e-3)
     avg_push_ms = float(np.mean(push_ms))
     # roofline of the push + deposit kernel (one launch per step)
     live_per_launch = live / args.steps
-    grid_bytes = g.rows * g.pitch * 8 * (6 + 2 * 3)   # fields read once, J read + written once
-    bytes_per_launch = live_per_launch * FP64_PARTICLE_BYTES + grid_bytes
+    field_bytes = 8 if precision == grpic.GRPIC_FP64 else 4
+    grid_bytes = g.rows * g.pitch * (6 * field_bytes + 2 * 3 * 8)   # fields read once, J read + written once
+    pbytes = FP64_PARTICLE_BYTES if precision == grpic.GRPIC_FP64 else SPLIT_PARTICLE_BYTES
+    bytes_per_launch = live_per_launch * pbytes + grid_bytes
     hbm_gbs = bytes_per_launch / (avg_push_ms * 1e-3) / 1e9
+    flops_per_launch = live_per_launch * FP64_OPS_PER_PARTICLE_STEP
+    tflops = flops_per_launch / (avg_push_ms * 1e-3) / 1e12
     return dict(value=value, total_ms=total_ms, avg_push_ms=avg_push_ms, push_ms=push_ms, counters=cnt,
-                hbm_gbs=hbm_gbs, bytes_per_launch=bytes_per_launch, dt=dt, grid=g,
-                live_per_launch=live_per_launch, wall_s=t_wall)
+                hbm_gbs=hbm_gbs, bytes_per_launch=bytes_per_launch, dt=dt, live_per_launch=live_per_launch,
+                wall_s=t_wall, tflops=tflops, flops_per_launch=flops_per_launch)
 
 
 def run_cpu_baseline(args, grid):
@@ -162,9 +171,23 @@ def main():
     ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32-split timing")
     ap.add_argument("--cpu-pairs", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+
+        a = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB x 5")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -172,11 +195,31 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    r = run_gpu(args)
-    g = r["grid"]
+    import torch
+
+    from paper_2503_04558_amd import grpic
+
+    t0 = time.time()
+    g, F, parts = make_workload(args.pairs, args.nr, args.nth, args.spin, workers=args.workers)
+    split_parts = None
+    if not args.no_split:      # the same initial particles in split form
+        split_parts = {k: (v.clone() if k in ("cell", "sp") else v.to(torch.float32)) for k, v in parts.items()}
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f}s: grid {g.nr}x{g.nth}, {2 * args.pairs} particles")
+    r = run_gpu(args, g, F, parts, grpic.GRPIC_FP64)
+    del parts
+    rs = None
+    if split_parts is not None:
+        F32 = [f.to(torch.float32) for f in F]
+        rs = run_gpu(args, g, F32, split_parts, grpic.GRPIC_FP32_SPLIT)
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
+    # 1344 flop per 97 B = 13.9 flop/B, above the FP64 ridge (78.6 TFLOP/s / 8 TB/s =
+    # 9.8 flop/B): the FP64 vector units bound this kernel, HBM comes second.
+    alu = dict(bound="alu", achieved=round(r["tflops"], 3), peak=FP64_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+               frac=round(r["tflops"] / FP64_VALU_PEAK_TFLOPS, 4), traffic=None,
+               flops_per_launch=r["flops_per_launch"])
     hbm = dict(bound="hbm", achieved=round(r["hbm_gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-               frac=round(r["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+               frac=round(r["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None, bytes_per_launch=r["bytes_per_launch"])
     out = {
         "metric": "particle push+deposit/s (FP64 vs FP32-split) at stated error; bwd/fwd time ratio",
         "value": r["value"],
@@ -190,6 +233,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
+        "counters": r["counters"],
         "config": {
             "workload": f"{args.nr}x{args.nth} Kerr-Schild log-r grid, a={args.spin}, Wald B0=1, "
                         f"{2 * args.pairs} e+- (Maxwell-Juttner T=0.1, 0.1c phi rotation), "
@@ -197,12 +241,25 @@ def main():
             "grid": [args.nr, args.nth], "particles": 2 * args.pairs, "spin": args.spin,
             "dt": r["dt"], "sort_every": args.sort_every, "ncorr": args.ncorr, "precision": "FP64",
         },
-        "roofline": hbm,
+        "roofline": alu,
+        "roofline_hbm": hbm,
         "kernel": {"name": "push_deposit_f64_tiled", "avg_ms": r["avg_push_ms"],
                    "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
                    "live_particles_per_launch": r["live_per_launch"]},
         "cpu_baseline": cpu,
     }
+    if rs is not None:
+        out["split"] = {
+            "value": rs["value"], "unit": "particle-steps/s", "dtype": "f32 (f64 in r < 2M, near the axis, "
+            "and for the deposit)", "ms_per_step": rs["total_ms"] / args.steps,
+            "speedup_vs_fp64": rs["value"] / r["value"],
+            "kernel": {"name": "push_deposit_split_tiled", "avg_ms": rs["avg_push_ms"],
+                       "min_ms": float(np.min(rs["push_ms"]))},
+            "roofline_hbm": dict(bound="hbm", achieved=round(rs["hbm_gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                                 frac=round(rs["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                                 bytes_per_launch=rs["bytes_per_launch"]),
+            "counters": rs["counters"],
+        }
     print(json.dumps(out), flush=True)
 
 

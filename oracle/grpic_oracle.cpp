@@ -92,6 +92,38 @@ inline Dual cos(const Dual& a) { return Dual(std::cos(a.v), -std::sin(a.v) * a.d
 inline Dual fabs(const Dual& a) { return a.v < 0 ? -a : a; }
 using std::sqrt; using std::exp; using std::sin; using std::cos; using std::fabs;
 
+/* Counting scalar: a double that tallies the floating-point operations done
+ * on it (+, -, *, / and sqrt, exp, sin, cos each count one), to measure the
+ * algorithm's operation count per particle-step. */
+struct OpCount {
+    long add, mul, div, sqrt_, exp_, sin_, cos_;
+};
+thread_local OpCount g_ops = {0, 0, 0, 0, 0, 0, 0};
+
+struct Cnt {
+    double v;
+    Cnt(double x = 0.0) : v(x) {}
+};
+inline double val(const Cnt& x) { return x.v; }
+inline Cnt operator+(const Cnt& a, const Cnt& b) { ++g_ops.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(const Cnt& a, const Cnt& b) { ++g_ops.add; return Cnt(a.v - b.v); }
+inline Cnt operator-(const Cnt& a) { return Cnt(-a.v); }
+inline Cnt operator*(const Cnt& a, const Cnt& b) { ++g_ops.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(const Cnt& a, const Cnt& b) { ++g_ops.div; return Cnt(a.v / b.v); }
+inline Cnt operator+(double a, const Cnt& b) { ++g_ops.add; return Cnt(a + b.v); }
+inline Cnt operator+(const Cnt& a, double b) { ++g_ops.add; return Cnt(a.v + b); }
+inline Cnt operator-(double a, const Cnt& b) { ++g_ops.add; return Cnt(a - b.v); }
+inline Cnt operator-(const Cnt& a, double b) { ++g_ops.add; return Cnt(a.v - b); }
+inline Cnt operator*(double a, const Cnt& b) { ++g_ops.mul; return Cnt(a * b.v); }
+inline Cnt operator*(const Cnt& a, double b) { ++g_ops.mul; return Cnt(a.v * b); }
+inline Cnt operator/(const Cnt& a, double b) { ++g_ops.div; return Cnt(a.v / b); }
+inline Cnt operator/(double a, const Cnt& b) { ++g_ops.div; return Cnt(a / b.v); }
+inline Cnt sqrt(const Cnt& a) { ++g_ops.sqrt_; return Cnt(std::sqrt(a.v)); }
+inline Cnt exp(const Cnt& a) { ++g_ops.exp_; return Cnt(std::exp(a.v)); }
+inline Cnt sin(const Cnt& a) { ++g_ops.sin_; return Cnt(std::sin(a.v)); }
+inline Cnt cos(const Cnt& a) { ++g_ops.cos_; return Cnt(std::cos(a.v)); }
+inline Cnt fabs(const Cnt& a) { return Cnt(std::fabs(a.v)); }
+
 /* ------------------------------------------------------------------ */
 /* Problem description (mirrored by ctypes structures in oracle.py).   */
 /* ------------------------------------------------------------------ */
@@ -206,8 +238,8 @@ void geodesic_rhs(const Geom& g, double eps, const T y[6], T f[6]) {
 /* ------------------------------------------------------------------ */
 /* 2. CIC gather of one staggered component, bilinear in index space.  */
 /* ------------------------------------------------------------------ */
-template <class T, class F>
-T cic_gather(const Geom& g, const F* arr, double sr, double st, const T& xi, const T& eta) {
+template <class T, class Arr>
+T cic_gather(const Geom& g, const Arr& arr, double sr, double st, const T& xi, const T& eta) {
     const T f = xi - sr, h = eta - st;
     const int i = (int)std::floor(val(f)), j = (int)std::floor(val(h));
     const T wf = f - (double)i, wh = h - (double)j;
@@ -436,6 +468,61 @@ Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], dou
     return o;
 }
 
+/* ------------------------------------------------------------------ */
+/* Loss L = sum over steps of lambda . (F^r, F^th, G^ph) for one        */
+/* particle, on any scalar type; with T = Dual its tangent is the exact */
+/* directional derivative of L.  Positions are carried as xi, eta (the  */
+/* double path's cell + offset is the same number).                     */
+/* ------------------------------------------------------------------ */
+struct DualArray {                       /* value and tangent arrays as one Dual array */
+    const double* v;
+    const double* d;
+    Dual operator[](long e) const { return Dual(v[e], d ? d[e] : 0.0); }
+};
+
+template <class T, class Arr>
+int particle_loss(const Geom& g, const Species& sp, const Arr* fld, const double* const* lam,
+                  double w, double dt, int nsteps, int ncorr, T xi, T eta, T u[3], T& L,
+                  double* traj = nullptr) {
+    for (int n = 0; n < nsteps; ++n) {
+        if (traj) { traj[2 * n] = val(xi); traj[2 * n + 1] = val(eta); }
+        T D[3], B[3];
+        for (int c = 0; c < 3; ++c) {
+            D[c] = cic_gather(g, fld[c], kStagR[c], kStagT[c], xi, eta);
+            B[c] = cic_gather(g, fld[3 + c], kStagR[3 + c], kStagT[3 + c], xi, eta);
+        }
+        T y1[6];
+        push_with_fields(g, sp, dt, ncorr, xi, eta, u, D, B, y1);
+        T xi1 = y1[0], eta1 = y1[1], ut1 = y1[4];
+        bool finite = true;
+        for (int c = 0; c < 6; ++c) finite = finite && std::isfinite(val(y1[c]));
+        if (!finite || std::fabs(val(xi1) - val(xi)) >= 1.0 || std::fabs(val(eta1) - val(eta)) >= 1.0)
+            return ST_BAD;
+        if (val(eta1) < 0.0) { eta1 = -eta1; ut1 = -ut1; }
+        else if (val(eta1) > (double)g.nth) { eta1 = 2.0 * g.nth - eta1; ut1 = -ut1; }
+        Move<T> mv;
+        esirkepov(sp.q * w, dt, xi, eta, xi1, eta1, y1[2], mv);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) L = L + lam[0][idx(g, mv.i0 + a, mv.j0 + b)] * mv.Fr[a][b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 2; ++b) L = L + lam[1][idx(g, mv.i0 + a, mv.j0 + b)] * mv.Ft[a][b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) L = L + lam[2][idx(g, mv.i0 + a, mv.j0 + b)] * mv.Gp[a][b];
+        if (traj) { traj[2 * n + 2] = val(xi1); traj[2 * n + 3] = val(eta1); }
+        if (val(xi1) < 0.0 || val(xi1) >= (double)g.nr) return ST_OUT;
+        xi = xi1;
+        eta = eta1;
+        u[0] = y1[3];
+        u[1] = ut1;
+        u[2] = y1[5];
+    }
+    return ST_ALIVE;
+}
+
+bool valid_input(const Geom& g, int nsp, int32_t cell, double xr, double xth, uint8_t s) {
+    return cell >= 0 && cell < g.nr * g.nth && xr >= 0.0 && xr <= 1.0 && xth >= 0.0 && xth <= 1.0 && s < nsp;
+}
+
 }  // namespace
 
 /* ==================================================================== */
@@ -573,6 +660,77 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
 #endif
     }
     if (stats) { stats[0] += st_out; stats[1] += st_bad; stats[2] += st_refl; stats[3] += st_live; }
+}
+
+/* L and its derivative along a direction: tangents tur, tuth, tuph per
+ * particle (NULL = 0) and tF per field array (NULL array or entry = 0).
+ * out[0] = L, out[1] = dL/deps, Neumaier-summed over particles.
+ * status (optional, per particle): 0 alive after nsteps, 1 left radially,
+ * 2 removed as bad, -1 not taken (removed or invalid input).            */
+void orc_loss_dual(const Geom* gp, const Species* sp, int nsp, int64_t n, const int32_t* cell,
+                   const double* xr, const double* xth, const double* ur, const double* uth, const double* uph,
+                   const double* w, const uint8_t* spi, const double* tur, const double* tuth, const double* tuph,
+                   const double* const* F, const double* const* tF, const double* const* lam,
+                   double dt, int nsteps, int ncorr, double* out, int32_t* status) {
+    const Geom& g = *gp;
+    DualArray fd[6];
+    for (int c = 0; c < 6; ++c) fd[c] = DualArray{F[c], tF ? tF[c] : nullptr};
+    double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+    auto nadd = [](double& sum, double& comp, double x) {
+        const double t = sum + x;
+        if (std::fabs(sum) >= std::fabs(x)) comp += (sum - t) + x; else comp += (x - t) + sum;
+        sum = t;
+    };
+    for (int64_t p = 0; p < n; ++p) {
+        if (!valid_input(g, nsp, cell[p], xr[p], xth[p], spi[p])) {
+            if (status) status[p] = -1;
+            continue;
+        }
+        const int ci = cell[p] / g.nth, cj = cell[p] % g.nth;
+        Dual u[3] = {Dual(ur[p], tur ? tur[p] : 0.0), Dual(uth[p], tuth ? tuth[p] : 0.0),
+                     Dual(uph[p], tuph ? tuph[p] : 0.0)};
+        Dual L(0.0, 0.0);
+        const int st = particle_loss(g, sp[spi[p]], fd, lam, w[p], dt, nsteps, ncorr, Dual(ci + xr[p]),
+                                     Dual(cj + xth[p]), u, L);
+        nadd(s0, c0, L.v);
+        nadd(s1, c1, L.d);
+        if (status) status[p] = st;
+    }
+    out[0] = s0 + c0;
+    out[1] = s1 + c1;
+}
+
+/* L on plain doubles for one particle (finite differences); returns status.
+ * traj (optional, 2 * (nsteps + 1)): positions (xi, eta) after each step. */
+int orc_loss_particle(const Geom* gp, const Species* sp, double xi, double eta, const double* u0,
+                      double w, const double* const* F, const double* const* lam, double dt, int nsteps,
+                      int ncorr, double* L, double* traj) {
+    double u[3] = {u0[0], u0[1], u0[2]};
+    double l = 0.0;
+    const int st = particle_loss(*gp, *sp, F, lam, w, dt, nsteps, ncorr, xi, eta, u, l, traj);
+    *L = l;
+    return st;
+}
+
+/* Operation counts of one particle-step (gather of the six components,
+ * push, deposit) through the counting scalar.  out[7] (+=): add/sub, mul,
+ * div, sqrt, exp, sin, cos. */
+void orc_count_ops(const Geom* g, const Species* sp, const double* const* F, double w, double dt, int ncorr,
+                   double xi, double eta, const double* u, long* out) {
+    g_ops = OpCount{0, 0, 0, 0, 0, 0, 0};
+    const Cnt cxi(xi), ceta(eta);
+    Cnt D[3], B[3];
+    for (int c = 0; c < 3; ++c) {
+        D[c] = cic_gather(*g, F[c], kStagR[c], kStagT[c], cxi, ceta);
+        B[c] = cic_gather(*g, F[3 + c], kStagR[3 + c], kStagT[3 + c], cxi, ceta);
+    }
+    const Cnt cu[3] = {Cnt(u[0]), Cnt(u[1]), Cnt(u[2])};
+    Cnt y1[6];
+    push_with_fields(*g, *sp, dt, ncorr, cxi, ceta, cu, D, B, y1);
+    Move<Cnt> mv;
+    esirkepov(sp->q * w, dt, cxi, ceta, y1[0], y1[1], y1[2], mv);
+    const long v[7] = {g_ops.add, g_ops.mul, g_ops.div, g_ops.sqrt_, g_ops.exp_, g_ops.sin_, g_ops.cos_};
+    for (int k = 0; k < 7; ++k) out[k] += v[k];
 }
 
 int orc_has_openmp(void) {

@@ -201,3 +201,88 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
 
 def has_openmp() -> bool:
     return bool(lib().orc_has_openmp())
+
+
+OP_NAMES = ("add", "mul", "div", "sqrt", "exp", "sin", "cos")
+
+
+def count_ops(grid, species, parts, fields, dt, ncorr: int = 3, sample=None) -> dict:
+    """Mean floating-point operation counts of one particle-step (gather,
+    push, deposit) over the live particles listed in `sample` (default all),
+    from the oracle run on a counting scalar type."""
+    g = geom(grid)
+    sp = _species_array(species)
+    fl = [_f64(f) for f in fields]
+    fptr = (ctypes.c_void_p * 6)(*[f.ctypes.data for f in fl])
+    out = np.zeros(7, dtype=np.int64)
+    n = 0
+    idx = range(len(parts["cell"])) if sample is None else sample
+    for p in idx:
+        c = int(parts["cell"][p])
+        if c < 0:
+            continue
+        xi = c // grid.nth + float(parts["xr"][p])
+        eta = c % grid.nth + float(parts["xth"][p])
+        u = np.array([parts["ur"][p], parts["uth"][p], parts["uph"][p]], dtype=np.float64)
+        lib().orc_count_ops(ctypes.byref(g), ctypes.byref(sp[int(parts["sp"][p])]), fptr,
+                            ctypes.c_double(float(parts["w"][p])), ctypes.c_double(dt), ctypes.c_int(ncorr),
+                            ctypes.c_double(xi), ctypes.c_double(eta), _p(u), _p(out))
+        n += 1
+    d = {k: float(v) / max(n, 1) for k, v in zip(OP_NAMES, out)}
+    d["total"] = sum(d[k] for k in OP_NAMES)
+    d["particles"] = n
+    return d
+
+
+def _ptrs(arrs):
+    if arrs is None:
+        return None
+    keep = [None if a is None else _f64(a) for a in arrs]
+    ptr = (ctypes.c_void_p * len(keep))(*[0 if a is None else a.ctypes.data for a in keep])
+    return ptr, keep
+
+
+def loss_dual(grid, species, parts, fields, lam, dt, nsteps, ncorr: int = 3, tu=None, tF=None):
+    """L = sum over particles and steps of lambda . (F^r, F^th, G^ph) and its
+    derivative along the direction (tu = (t_ur, t_uth, t_uph) per particle,
+    tF = six field tangent arrays), by forward-mode dual numbers through the
+    oracle.  Returns (L, dL, status per particle)."""
+    g = geom(grid)
+    sp = _species_array(species)
+    n = len(parts["cell"])
+    cell = np.ascontiguousarray(parts["cell"], dtype=np.int32)
+    arrs = {k: _f64(parts[k]) for k in ("xr", "xth", "ur", "uth", "uph", "w")}
+    spi = np.ascontiguousarray(parts["sp"], dtype=np.uint8)
+    tus = [None, None, None] if tu is None else [_f64(t) for t in tu]
+    F, keepF = _ptrs(fields)
+    tFp = _ptrs(tF)
+    L, keepL = _ptrs(lam)
+    out = np.zeros(2)
+    status = np.zeros(n, dtype=np.int32)
+    null = ctypes.c_void_p(0)
+    lib().orc_loss_dual(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(n), _p(cell),
+                        _p(arrs["xr"]), _p(arrs["xth"]), _p(arrs["ur"]), _p(arrs["uth"]), _p(arrs["uph"]),
+                        _p(arrs["w"]), _p(spi), *[null if t is None else _p(t) for t in tus],
+                        F, tFp[0] if tFp else null, L, ctypes.c_double(dt), ctypes.c_int(nsteps),
+                        ctypes.c_int(ncorr), _p(out), _p(status))
+    return float(out[0]), float(out[1]), status
+
+
+def loss_particle(grid, species_row, xi, eta, u, w, fields, lam, dt, nsteps, ncorr: int = 3, trajectory=False):
+    """L of one particle on plain doubles; returns (L, status) or, with
+    trajectory, (L, status, positions (nsteps + 1, 2), nan after removal)."""
+    g = geom(grid)
+    sp = _species_array([species_row])
+    F, keepF = _ptrs(fields)
+    L, keepL = _ptrs(lam)
+    u = _f64(u)
+    out = ctypes.c_double(0.0)
+    traj = np.full((nsteps + 1, 2), np.nan) if trajectory else None
+    lib().orc_loss_particle.restype = ctypes.c_int
+    st = lib().orc_loss_particle(ctypes.byref(g), sp, ctypes.c_double(xi), ctypes.c_double(eta), _p(u),
+                                 ctypes.c_double(w), F, L, ctypes.c_double(dt), ctypes.c_int(nsteps),
+                                 ctypes.c_int(ncorr), ctypes.byref(out),
+                                 _p(traj) if trajectory else ctypes.c_void_p(0))
+    if trajectory:
+        return float(out.value), int(st), traj
+    return float(out.value), int(st)

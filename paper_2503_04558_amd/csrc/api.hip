@@ -129,6 +129,14 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     A.M = m ? m->M : 0.0;
     A.nr = g->nr; A.nth = g->nth; A.guard = g->guard; A.pitch = g->pitch;
     A.lnr0 = g->lnr0; A.dlnr = g->dlnr; A.dth = g->dth;
+    A.idlnr = 1.0 / g->dlnr; A.idth = 1.0 / g->dth;
+    A.small_steps = (2.0 * g->dlnr <= grpic::kSmallArg && 2.0 * g->dth <= grpic::kSmallArg) ? 1 : 0;
+    // split precision: FP64 where a step can reach r < 2M (the strong-field
+    // region) and within a sin(theta) < kPoleSin band of the axis (+2 cells of reach)
+    const double M = m ? m->M : 0.0;
+    const double i2 = M > 0.0 ? (log(2.0 * M) - g->lnr0) / g->dlnr : -1e9;
+    A.fp64_rows = i2 < 0.0 ? 0 : (int)fmin((double)g->nr, ceil(i2) + 2.0);
+    A.pole_cols = (int)fmin((double)g->nth, ceil(asin(grpic::kPoleSin) / g->dth) + 2.0);
     A.nsp = nsp;
     for (int s = 0; s < nsp; ++s) {
         A.q[s] = sp[s].q;
@@ -173,7 +181,6 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     if (nsteps < 0) return fail(GRPIC_EINVAL, "nsteps < 0");
     if (ncorr < 0 || ncorr > 16) return fail(GRPIC_EINVAL, "ncorr must be in [0, 16]");
     if (ckpt || ckpt_every) return fail(GRPIC_EINVAL, "checkpoints are not supported by this entry point yet");
-    if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "only GRPIC_FP64 particles are supported yet");
     const double tc = crossing_time_cached(metric, grid);
     if (dt > tc * (1.0 + 1e-12))
         return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
@@ -197,8 +204,9 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
     for (int step = 0; step < nsteps; ++step) {
-        const hipError_t e = tiling ? grpic::launch_push_deposit_f64_tiled(A, tiling, cap, s)
-                                    : grpic::launch_push_deposit_f64(A, s);
+        const bool split = parts->precision == GRPIC_FP32_SPLIT;
+        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s)
+                                    : grpic::launch_push_deposit(A, split, s);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
     return GRPIC_OK;

@@ -19,6 +19,10 @@ struct StepArgs {
     double a, M;
     int nr, nth, guard, pitch;
     double lnr0, dlnr, dth;
+    double idlnr, idth;                     // 1/dlnr, 1/dth
+    int small_steps;                        // 2 dlnr and 2 dth <= kSmallArg: Taylor offsets
+    int fp64_rows;                          // split precision: rows i < fp64_rows run in FP64
+    int pole_cols;                          // split precision: columns this close to the axis run in FP64
     double dt;
     int ncorr, nsp;
     double q[kMaxSpecies], m[kMaxSpecies];
@@ -39,12 +43,28 @@ struct Metric {
     R g_rr, g_rp, g_tt, g_pp;               // gamma_ij
     R h_rr, h_rp, h_tt, h_pp;               // gamma^ij
     R sqrtg;                                // sqrt(det gamma_ij) = rho^2 sin sqrt(1+z)
+    R ialpha;                               // 1/alpha = sqrt(1+z)
 };
 
 template <class R>
 struct MetricDeriv {                        // [0] = d/dr, [1] = d/dtheta
     R dal[2], dbe[2], dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];
 };
+
+// 1/x from the hardware reciprocal estimate refined by Newton steps
+// (two for double, one for float): a few ulp, no division sequence.
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
 
 // Kerr-Schild 3+1 quantities of App. A (mass M reinstated) at radius r and
 // polar angle with sine s, cosine c; with D set, their r and theta
@@ -53,16 +73,17 @@ template <class R, bool D>
 __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k, MetricDeriv<R>* d) {
     const R a2 = a * a, r2 = r * r, s2 = s * s;
     const R rho2 = r2 + a2 * (c * c);
-    const R irho2 = R(1) / rho2;
+    const R irho2 = rcp(rho2);
     const R z = R(2) * M * r * irho2;
     const R opz = R(1) + z;
-    const R iopz = R(1) / opz;
+    const R iopz = rcp(opz);
     const R sq = sqrt(opz);
-    const R is2 = R(1) / s2;
+    const R is2 = rcp(s2);
     const R ra2 = r2 + a2;
     const R Delta = ra2 - R(2) * M * r;
     const R Sigma = ra2 * ra2 - a2 * Delta * s2;
-    k.alpha = R(1) / sq;
+    k.ialpha = sq;
+    k.alpha = sq * iopz;
     k.beta = z * iopz;
     k.g_rr = opz;
     k.g_rp = -a * s2 * opz;
@@ -75,10 +96,11 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
     k.sqrtg = rho2 * s * sq;
     if constexpr (D) {
         const R irho4 = irho2 * irho2;
+        const R sc = s * c;
         const R dr_rho2 = R(2) * r;
-        const R dt_rho2 = R(-2) * a2 * s * c;
+        const R dt_rho2 = R(-2) * a2 * sc;
         const R dz_r = R(2) * M * (rho2 - R(2) * r2) * irho4;
-        const R dz_t = R(4) * M * a2 * r * s * c * irho4;
+        const R dz_t = R(4) * M * a2 * r * sc * irho4;
         const R al3 = k.alpha * iopz;            // (1+z)^(-3/2)
         const R al4 = iopz * iopz;               // (1+z)^(-2)
         d->dal[0] = R(-0.5) * al3 * dz_r;
@@ -90,42 +112,155 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
         d->dh_tt[0] = -dr_rho2 * irho4;
         d->dh_tt[1] = -dt_rho2 * irho4;
         d->dh_rr[0] = R(-2) * r * a2 * s2 * irho4 - d->dbe[0];
-        d->dh_rr[1] = R(2) * a2 * ra2 * s * c * irho4 - d->dbe[1];
+        d->dh_rr[1] = R(2) * a2 * ra2 * sc * irho4 - d->dbe[1];
         d->dh_pp[0] = R(-2) * r * irho4 * is2;
-        d->dh_pp[1] = -(dt_rho2 * s2 + R(2) * rho2 * s * c) * irho4 * is2 * is2;
+        d->dh_pp[1] = -(dt_rho2 * s2 + R(2) * rho2 * sc) * irho4 * is2 * is2;
     }
 }
 
-// r, sin(theta), cos(theta) of a point in grid units.
+// exp(x), sin(y), cos(y) for the small offsets of the predictor-corrector
+// points from a particle's start cell: Taylor polynomials, within an ulp or
+// two for |x|, |y| <= kSmallArg.  A point of a step is less than two cells
+// from its start cell's corner (a move is below one cell), so grids with
+// 2 dlnr and 2 dth <= kSmallArg use them; coarser grids use the library
+// functions (a grid-uniform choice).
+constexpr double kSmallArg = 0.07;
+// Within ~5.7 degrees of a pole (anchor sin(theta) < kPoleSin) sin and cos
+// are taken from theta = eta * dth directly: there the centrifugal terms
+// (gamma^phph ~ 1/sin^2) amplify how sin(theta) is rounded, and this keeps
+// the rounding the same as in the plain formula.
+constexpr double kPoleSin = 0.1;
+
 template <class R>
-__device__ __forceinline__ void grid_point(const StepArgs& A, R xi, R eta, R& r, R& s, R& c) {
-    r = exp(R(A.lnr0) + xi * R(A.dlnr));
-    const R th = eta * R(A.dth);
+__device__ __forceinline__ R exp_small(R x) {
+    R p = R(1.0 / 3628800.0);
+    p = fma(p, x, R(1.0 / 362880.0));
+    p = fma(p, x, R(1.0 / 40320.0));
+    p = fma(p, x, R(1.0 / 5040.0));
+    p = fma(p, x, R(1.0 / 720.0));
+    p = fma(p, x, R(1.0 / 120.0));
+    p = fma(p, x, R(1.0 / 24.0));
+    p = fma(p, x, R(1.0 / 6.0));
+    p = fma(p, x, R(0.5));
+    p = fma(p, x, R(1.0));
+    return fma(p, x, R(1.0));
+}
+
+template <class R>
+__device__ __forceinline__ void sincos_small(R y, R& sn, R& cs) {
+    const R y2 = y * y;
+    R ps = R(1.0 / 362880.0);
+    ps = fma(ps, y2, R(-1.0 / 5040.0));
+    ps = fma(ps, y2, R(1.0 / 120.0));
+    ps = fma(ps, y2, R(-1.0 / 6.0));
+    sn = fma(ps * y2, y, y);
+    R pc = R(-1.0 / 3628800.0);
+    pc = fma(pc, y2, R(1.0 / 40320.0));
+    pc = fma(pc, y2, R(-1.0 / 720.0));
+    pc = fma(pc, y2, R(1.0 / 24.0));
+    pc = fma(pc, y2, R(-0.5));
+    cs = fma(pc, y2, R(1.0));
+}
+
+// r, sin(theta), cos(theta) at the corner (ci, cj) of a particle's start
+// cell; points of the step are reached from it by small offsets.
+template <class R>
+struct Anchor {
+    R r, s, c;
+    int ci, cj;
+};
+
+template <class R>
+__device__ __forceinline__ Anchor<R> make_anchor(const StepArgs& A, int ci, int cj) {
+    Anchor<R> an;
+    an.ci = ci;
+    an.cj = cj;
+    if (A.small_steps) {
+        an.r = exp(R(A.lnr0) + R(ci) * R(A.dlnr));
+        const R th = R(cj) * R(A.dth);
+        an.s = sin(th);
+        an.c = cos(th);
+    } else {
+        an.r = an.s = an.c = R(0);
+    }
+    return an;
+}
+
+// r, sin(theta), cos(theta) of the point (xi, eta) in grid units.
+template <class R>
+__device__ __forceinline__ void point_at(const StepArgs& A, const Anchor<R>& an, R xi, R eta, R& r, R& s, R& c) {
+    if (A.small_steps) {
+        r = an.r * exp_small((xi - R(an.ci)) * R(A.dlnr));
+        if (an.s >= R(kPoleSin)) {
+            R sy, cy;
+            sincos_small((eta - R(an.cj)) * R(A.dth), sy, cy);
+            s = fma(an.s, cy, an.c * sy);
+            c = fma(an.c, cy, -(an.s * sy));
+        } else {
+            const R th = eta * R(A.dth);
+            s = sin(th);
+            c = cos(th);
+        }
+    } else {
+        r = exp(R(A.lnr0) + xi * R(A.dlnr));
+        const R th = eta * R(A.dth);
+        s = sin(th);
+        c = cos(th);
+    }
+}
+
+// Same from offsets (dxi, deta) relative to the anchor cell's corner (the
+// split-precision path integrates positions this way: in float an absolute
+// xi near 2000 would carry an ulp of 1e-4 cells).
+template <class R>
+__device__ __forceinline__ void point_rel(const StepArgs& A, const Anchor<R>& an, R dxi, R deta, R& r, R& s, R& c) {
+    if (A.small_steps) {
+        r = an.r * exp_small(dxi * R(A.dlnr));
+        if (an.s >= R(kPoleSin)) {
+            R sy, cy;
+            sincos_small(deta * R(A.dth), sy, cy);
+            s = fma(an.s, cy, an.c * sy);
+            c = fma(an.c, cy, -(an.s * sy));
+            return;
+        }
+    } else {
+        r = exp(R(A.lnr0) + (R(an.ci) + dxi) * R(A.dlnr));
+    }
+    const R th = (R(an.cj) + deta) * R(A.dth);
     s = sin(th);
     c = cos(th);
 }
 
 // Geodesic right-hand side of eq. particle-eom (no Lorentz force) in grid
-// units; f = (dxi/dt, deta/dt, dphi/dt, du_r/dt, du_th/dt), du_ph/dt = 0.
+// units at a point with metric k, d; f = (dxi/dt, deta/dt, dphi/dt,
+// du_r/dt, du_th/dt), du_ph/dt = 0.
 template <class R>
-__device__ __forceinline__ void geodesic_rhs(const StepArgs& A, R eps, R xi, R eta,
-                                             R ur, R ut, R up, R f[5]) {
-    R r, s, c;
-    grid_point(A, xi, eta, r, s, c);
-    Metric<R> k;
-    MetricDeriv<R> d;
-    ks_metric<R, true>(R(A.a), R(A.M), r, s, c, k, &d);
+__device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, R r, const Metric<R>& k,
+                                                const MetricDeriv<R>& d, R ur, R ut, R up, R f[5]) {
     const R uu = k.h_rr * ur * ur + R(2) * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
-    const R u0 = sqrt(eps + uu) / k.alpha;
-    const R iu0 = R(1) / u0;
-    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) / (r * R(A.dlnr));
-    f[1] = k.h_tt * ut * iu0 / R(A.dth);
+    const R u0 = sqrt(eps + uu) * k.ialpha;              // u^0 = sqrt(eps + u^2)/alpha
+    const R iu0 = rcp(u0);
+    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) * rcp(r) * R(A.idlnr);
+    f[1] = k.h_tt * ut * iu0 * R(A.idth);
     f[2] = (k.h_rp * ur + k.h_pp * up) * iu0;
+    const R hiu0 = R(0.5) * iu0;
     for (int q = 0; q < 2; ++q) {
         const R quad = ur * ur * d.dh_rr[q] + R(2) * ur * up * d.dh_rp[q]
                      + ut * ut * d.dh_tt[q] + up * up * d.dh_pp[q];
-        f[3 + q] = -k.alpha * u0 * d.dal[q] + ur * d.dbe[q] - quad * iu0 * R(0.5);
+        f[3 + q] = -k.alpha * u0 * d.dal[q] + ur * d.dbe[q] - quad * hiu0;
     }
+}
+
+// Same, evaluating the metric at (xi, eta) from the anchor.
+template <class R>
+__device__ __forceinline__ void geodesic_rhs(const StepArgs& A, const Anchor<R>& an, R eps, R xi, R eta,
+                                             R ur, R ut, R up, R f[5]) {
+    R r, s, c;
+    point_at(A, an, xi, eta, r, s, c);
+    Metric<R> k;
+    MetricDeriv<R> d;
+    ks_metric<R, true>(R(A.a), R(A.M), r, s, c, k, &d);
+    geodesic_rhs_at(A, eps, r, k, d, ur, ut, up, f);
 }
 
 // (v x w)_i = sqrt(gamma) eps_ijk v^j w^k; v covariant (raised here), w contravariant.
@@ -148,15 +283,15 @@ __device__ __forceinline__ void boris_kick(const Metric<R>& k, R qm, R dt, const
     for (int i = 0; i < 3; ++i) um[i] = u[i] + h * Dl[i];
     const R uu = k.h_rr * um[0] * um[0] + R(2) * k.h_rp * um[0] * um[2]
                + k.h_tt * um[1] * um[1] + k.h_pp * um[2] * um[2];
-    const R u0bar = sqrt(R(1) + uu) / k.alpha;
-    const R tf = qm * dt / (R(2) * u0bar);
+    const R u0bar = sqrt(R(1) + uu) * k.ialpha;
+    const R tf = qm * dt * R(0.5) * rcp(u0bar);
     const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
     const R tt = k.g_rr * t[0] * t[0] + R(2) * k.g_rp * t[0] * t[2]
                + k.g_tt * t[1] * t[1] + k.g_pp * t[2] * t[2];
     R x[3], ut[3], sv[3];
     cross_lower(k, um, t, x);
     for (int i = 0; i < 3; ++i) ut[i] = um[i] + x[i];
-    const R sf = R(2) / (R(1) + tt);
+    const R sf = R(2) * rcp(R(1) + tt);
     for (int i = 0; i < 3; ++i) sv[i] = sf * t[i];
     cross_lower(k, ut, sv, x);
     for (int i = 0; i < 3; ++i) u[i] = um[i] + x[i] + h * Dl[i];

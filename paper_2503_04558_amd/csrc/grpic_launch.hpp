@@ -16,12 +16,13 @@ namespace grpic {
 // (theta is the contiguous direction, so a tile's particles are contiguous
 // in a cell-sorted particle array).  Each tile's particles are cut into
 // balanced slices of at most kSliceMax particles; one workgroup pushes one
-// slice and accumulates its current in an LDS window that covers the tile
-// plus kMarginRows rows and kMarginCols columns of drift on each side.
+// slice, one particle per thread, and accumulates its current in an LDS
+// window that covers the tile plus kMarginRows rows and kMarginCols columns
+// of drift on each side.
 constexpr int kTileCells = 64;
-constexpr int kSliceMax = 2048;
 constexpr int kPushThreads = 256;
-constexpr int kPushIter = kSliceMax / kPushThreads;       // particles per thread
+constexpr int kSliceMax = kPushThreads;                    // one particle per thread
+constexpr int kLaneGroups = 8;                             // lane permutation inside a slice
 constexpr int kMarginRows = 6;
 constexpr int kMarginCols = 4;
 constexpr int kWinRows = 2 * kMarginRows + 4;              // vertex rows of the LDS window
@@ -48,9 +49,9 @@ inline size_t tiling_bytes(int64_t n, int nr, int nth) {
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_push_deposit_f64(const StepArgs& A, hipStream_t stream);
-hipError_t launch_push_deposit_f64_tiled(const StepArgs& A, const void* tiling, int64_t slice_cap,
-                                         hipStream_t stream);
+hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream);
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, const void* tiling, int64_t slice_cap,
+                                     hipStream_t stream);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream);
 
 struct SortArgs {

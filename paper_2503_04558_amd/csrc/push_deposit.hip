@@ -6,13 +6,18 @@
 // reflection, Esirkepov deposit of the move on a 3x3 vertex window, and
 // removal at the radial edges.
 //
-// Two kernels share that body:
+// Two kernel shapes share that body, each in FP64 and in split precision
+// (push_deposit_f64 / _split, push_deposit_f64_tiled / _split_tiled):
 //   push_deposit_f64        one thread per particle, any particle order,
 //                           deposit with global FP64 atomics;
-//   push_deposit_f64_tiled  one workgroup per slice of a cell-sorted tile
-//                           (see grpic_launch.hpp), deposit into an LDS
-//                           window with LDS FP64 atomics, one flush of the
-//                           window's non-zero entries to global memory.
+//   push_deposit_f64_tiled  one workgroup per slice (<= 256 particles) of a
+//                           cell-sorted tile (see grpic_launch.hpp), one
+//                           particle per thread, deposit into an LDS window
+//                           with LDS FP64 atomics, one flush of the window's
+//                           non-zero entries to global memory.  (A loop over
+//                           several particles per thread makes the compiler
+//                           keep the loop-invariant FP64 constants in
+//                           registers: 256 VGPRs and one wave per SIMD.)
 #include "grpic_device.hpp"
 #include "grpic_launch.hpp"
 
@@ -63,21 +68,25 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFl
                          cic_f64(F[5], A, xi0 - 0.5, eta0 - 0.5)};
     const bool massless = A.massless[s] != 0;
     const double dt = A.dt;
-    if (!massless) {
-        double r, sn, cs;
-        grid_point(A, xi0, eta0, r, sn, cs);
-        Metric<double> k;
-        ks_metric<double, false>(A.a, A.M, r, sn, cs, k, nullptr);
-        boris_kick(k, A.q[s] / A.m[s], dt, D, B, u);
-    }
     const double eps = massless ? 0.0 : 1.0;
+    // one exp and one sincos per particle, at its start cell's corner
+    const Anchor<double> an = make_anchor<double>(A, ci, cj);
+    double f0[5], f1[5], yt[5];
+    {
+        // metric and derivatives at x^n serve both the kick and the first RHS
+        double r0, s0, c0;
+        point_at(A, an, xi0, eta0, r0, s0, c0);
+        Metric<double> k0;
+        MetricDeriv<double> d0;
+        ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
+        if (!massless) boris_kick(k0, A.q[s] / A.m[s], dt, D, B, u);
+        geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
+    }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
     const double y0[5] = {xi0, eta0, 0.0, u[0], u[1]};
-    double f0[5], f1[5], yt[5];
-    geodesic_rhs(A, eps, xi0, eta0, u[0], u[1], u[2], f0);
     for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
     for (int it = 0; it < A.ncorr; ++it) {
-        geodesic_rhs(A, eps, yt[0], yt[1], yt[3], yt[4], u[2], f1);
+        geodesic_rhs(A, an, eps, yt[0], yt[1], yt[3], yt[4], u[2], f1);
         for (int c = 0; c < 5; ++c) yt[c] = y0[c] + 0.5 * dt * (f1[c] + f0[c]);
     }
     double xi1 = yt[0], eta1 = yt[1];
@@ -110,6 +119,139 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFl
     return true;
 }
 
+// ---------------------------------------------------------------- split precision
+// Position as int32 cell + float offset, float momenta, weight and fields.
+// The kick and the predictor-corrector run in float on offsets relative to
+// the start cell, except in rows with r < 2M (fp64_rows) and in columns
+// within ~5.7 degrees of the axis (pole_cols), where they run in double.
+// The deposit is FP64 on the stored end point (int + float offsets are exact
+// in double), so discrete charge continuity holds at FP64 round-off.
+
+// Bilinear interpolation of a float grid array around cell (ci, cj) at
+// offsets (fx, fy) already shifted by the stagger (fx, fy in [-1/2, 1]).
+__device__ __forceinline__ float cic_f32(const float* __restrict__ F, const StepArgs& A, int ci, int cj,
+                                         float fx, float fy) {
+    const float fi = floorf(fx), fj = floorf(fy);
+    const float wf = fx - fi, wh = fy - fj;
+    const float* q = F + grid_index(A, ci + (int)fi, cj + (int)fj);
+    return (1.0f - wf) * (1.0f - wh) * q[0] + wf * (1.0f - wh) * q[A.pitch]
+         + (1.0f - wf) * wh * q[1] + wf * wh * q[A.pitch + 1];
+}
+
+// Kick and predictor-corrector in precision R on offsets from the start
+// cell; y = (dxi, deta, phi, u_r, u_th) on return, u[2] = u_ph.
+template <class R>
+__device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R dxr, R dxt, R eps, R qm,
+                                           bool massless, const R D[3], const R B[3], R u[3], R yt[5]) {
+    const Anchor<R> an = make_anchor<R>(A, ci, cj);
+    const R dt = R(A.dt);
+    R f0[5], f1[5];
+    {
+        R r0, s0, c0;
+        point_rel(A, an, dxr, dxt, r0, s0, c0);
+        Metric<R> k0;
+        MetricDeriv<R> d0;
+        ks_metric<R, true>(R(A.a), R(A.M), r0, s0, c0, k0, &d0);
+        if (!massless) boris_kick(k0, qm, dt, D, B, u);
+        geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
+    }
+    const R y0[5] = {dxr, dxt, R(0), u[0], u[1]};
+    for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
+    for (int it = 0; it < A.ncorr; ++it) {
+        R r, sn, cs;
+        point_rel(A, an, yt[0], yt[1], r, sn, cs);
+        Metric<R> k;
+        MetricDeriv<R> d;
+        ks_metric<R, true>(R(A.a), R(A.M), r, sn, cs, k, &d);
+        geodesic_rhs_at(A, eps, r, k, d, yt[3], yt[4], u[2], f1);
+        for (int c = 0; c < 5; ++c) yt[c] = y0[c] + R(0.5) * dt * (f1[c] + f0[c]);
+    }
+}
+
+// A float offset in [0, 1): values that round up to 1 take the largest float below 1.
+__device__ __forceinline__ float offset_f32(double x) {
+    const float f = (float)x;
+    return f < 1.0f ? f : 0.99999994f;
+}
+
+__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev) {
+    const int cell = A.cell[p];
+    if (cell < 0) return false;
+    ev.live = 1;
+    float* xr = static_cast<float*>(A.xr);
+    float* xth = static_cast<float*>(A.xth);
+    float* ur = static_cast<float*>(A.ur);
+    float* uth = static_cast<float*>(A.uth);
+    float* uph = static_cast<float*>(A.uph);
+    const float* w = static_cast<const float*>(A.w);
+    const float fxr = xr[p], fxt = xth[p];
+    const int s = A.sp[p];
+    if (cell >= A.nr * A.nth || s >= A.nsp || !(fxr >= 0.0f && fxr <= 1.0f && fxt >= 0.0f && fxt <= 1.0f)) {
+        ev.bad = 1;
+        A.cell[p] = -1;
+        return false;
+    }
+    const int ci = cell / A.nth, cj = cell - ci * A.nth;
+    const float* const* F = reinterpret_cast<const float* const*>(A.F);
+    const float Df[3] = {cic_f32(F[0], A, ci, cj, fxr - 0.5f, fxt), cic_f32(F[1], A, ci, cj, fxr, fxt - 0.5f),
+                         cic_f32(F[2], A, ci, cj, fxr, fxt)};
+    const float Bf[3] = {cic_f32(F[3], A, ci, cj, fxr, fxt - 0.5f), cic_f32(F[4], A, ci, cj, fxr - 0.5f, fxt),
+                         cic_f32(F[5], A, ci, cj, fxr - 0.5f, fxt - 0.5f)};
+    const bool massless = A.massless[s] != 0;
+    const double qm = massless ? 0.0 : A.q[s] / A.m[s];
+    double y[5], uph1;
+    const bool fp64 = ci < A.fp64_rows || cj < A.pole_cols || cj >= A.nth - A.pole_cols;
+    if (fp64) {
+        const double D[3] = {Df[0], Df[1], Df[2]}, B[3] = {Bf[0], Bf[1], Bf[2]};
+        double u[3] = {ur[p], uth[p], uph[p]};
+        split_core<double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y);
+        uph1 = u[2];
+    } else {
+        float u[3] = {ur[p], uth[p], uph[p]};
+        float yf[5];
+        split_core<float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf);
+        for (int c = 0; c < 5; ++c) y[c] = yf[c];
+        uph1 = u[2];
+    }
+    const double xi0 = (double)ci + (double)fxr, eta0 = (double)cj + (double)fxt;
+    double xi1 = (double)ci + y[0], eta1 = (double)cj + y[1];
+    double u1t = y[4];
+    const bool finite = isfinite(xi1) && isfinite(eta1) && isfinite(y[2]) && isfinite(y[3]) && isfinite(y[4])
+                      && isfinite(uph1);
+    if (!finite || fabs(xi1 - xi0) >= 1.0 || fabs(eta1 - eta0) >= 1.0) {
+        ev.bad = 1;
+        A.cell[p] = -1;
+        return false;
+    }
+    if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
+    else if (eta1 > (double)A.nth) { eta1 = 2.0 * A.nth - eta1; u1t = -u1t; ev.refl = 1; }
+    // the end point as stored (cell + float offset), exact in double
+    const int i1 = (int)floor(xi1);
+    int j1 = (int)floor(eta1);
+    if (j1 >= A.nth) j1 = A.nth - 1;
+    const float ox = offset_f32(xi1 - (double)i1), oy = offset_f32(eta1 - (double)j1);
+    esirkepov(A.q[s] * (double)w[p], A.dt, xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2], mv);
+    if (A.phi) static_cast<float*>(A.phi)[p] += (float)y[2];
+    if (xi1 < 0.0 || xi1 >= (double)A.nr) {
+        ev.out = 1;
+        A.cell[p] = -1;
+    } else {
+        A.cell[p] = i1 * A.nth + j1;
+        xr[p] = ox;
+        xth[p] = oy;
+        ur[p] = (float)y[3];
+        uth[p] = (float)u1t;
+        uph[p] = (float)uph1;
+    }
+    return true;
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev) {
+    if constexpr (SPLIT) return advance_split(A, p, mv, ev);
+    else return advance_f64(A, p, mv, ev);
+}
+
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const MoveFlux& mv) {
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 3; ++b) atomicAdd(A.Fr + grid_index(A, mv.i0 + a, mv.j0 + b), mv.Fr[a][b]);
@@ -124,34 +266,33 @@ __device__ __forceinline__ void scatter_global(const StepArgs& A, const MoveFlux
 __device__ __forceinline__ void count_events(const StepArgs& A, const Events& ev) {
     if (!A.counters) return;
     const unsigned long long bl = __ballot(ev.live), bo = __ballot(ev.out);
-    const unsigned long long bb = __ballot(ev.bad), br = __ballot(ev.refl);
+    const unsigned long long bb = __ballot(ev.bad), br = __ballot(ev.refl), bs = __ballot(ev.spill);
     if ((threadIdx.x & 63) == 0) {
         if (bo) atomicAdd(A.counters + 0, (unsigned long long)__popcll(bo));
         if (bb) atomicAdd(A.counters + 1, (unsigned long long)__popcll(bb));
         if (br) atomicAdd(A.counters + 2, (unsigned long long)__popcll(br));
         if (bl) atomicAdd(A.counters + 3, (unsigned long long)__popcll(bl));
+        if (bs) atomicAdd(A.counters + 4, (unsigned long long)__popcll(bs));
     }
 }
 
-__global__ __launch_bounds__(256) void push_deposit_f64(const StepArgs A) {
+template <bool SPLIT>
+__device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         MoveFlux mv;
-        if (advance_f64(A, p, mv, ev)) scatter_global(A, mv);
+        if (advance<SPLIT>(A, p, mv, ev)) scatter_global(A, mv);
     }
     count_events(A, ev);
 }
 
-// Sum over the 64 lanes of a wave.
-__device__ __forceinline__ int wave_sum(int v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) { push_deposit_body<false>(A); }
+__global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { push_deposit_body<true>(A); }
 
-__global__ __launch_bounds__(kPushThreads) void push_deposit_f64_tiled(const StepArgs A, const TilingHeader* hdr,
-                                                                       const Slice* __restrict__ slices,
-                                                                       int64_t slice_cap) {
+template <bool SPLIT>
+__device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
+                                                        const Slice* __restrict__ slices, int64_t slice_cap) {
     __shared__ double win[3][kWinRows][kWinCols];
     // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of slices so neighbouring tiles share its L2.
@@ -173,16 +314,16 @@ __global__ __launch_bounds__(kPushThreads) void push_deposit_f64_tiled(const Ste
     for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols; e += kPushThreads) wflat[e] = 0.0;
     __syncthreads();
 
-    Events tot = {0, 0, 0, 0, 0};
-    const int64_t end = sl.start + sl.len < A.n ? sl.start + sl.len : A.n;
-    for (int k = 0; k < kPushIter; ++k) {
-        // lanes of a wave take particles kPushIter apart, so that they fall
-        // in different cells and their LDS atomics rarely hit one address
-        const int64_t p = sl.start + k + (int64_t)kPushIter * threadIdx.x;
-        if (p >= end) continue;
+    Events ev = {0, 0, 0, 0, 0};
+    // one particle per thread; lane t takes particle (t % 8) * 32 + t / 8 of
+    // the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
+    // the slice's cells and their LDS atomics rarely hit one address
+    const int t = threadIdx.x;
+    const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
+    const int64_t p = sl.start + slot;
+    if (slot < sl.len && p < A.n) {
         MoveFlux mv;
-        Events ev = {0, 0, 0, 0, 0};
-        if (advance_f64(A, p, mv, ev)) {
+        if (advance<SPLIT>(A, p, mv, ev)) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 for (int a = 0; a < 2; ++a)
@@ -196,7 +337,6 @@ __global__ __launch_bounds__(kPushThreads) void push_deposit_f64_tiled(const Ste
                 ev.spill = 1;
             }
         }
-        tot.live += ev.live; tot.out += ev.out; tot.bad += ev.bad; tot.refl += ev.refl; tot.spill += ev.spill;
     }
     __syncthreads();
     // flush the window's non-zero entries that lie inside the grid arrays
@@ -213,17 +353,18 @@ __global__ __launch_bounds__(kPushThreads) void push_deposit_f64_tiled(const Ste
             if (v != 0.0) atomicAdd(J[a] + g, v);
         }
     }
-    if (A.counters) {
-        const int l = wave_sum(tot.live), o = wave_sum(tot.out), b = wave_sum(tot.bad), f = wave_sum(tot.refl);
-        const int x = wave_sum(tot.spill);
-        if ((threadIdx.x & 63) == 0) {
-            if (o) atomicAdd(A.counters + 0, (unsigned long long)o);
-            if (b) atomicAdd(A.counters + 1, (unsigned long long)b);
-            if (f) atomicAdd(A.counters + 2, (unsigned long long)f);
-            if (l) atomicAdd(A.counters + 3, (unsigned long long)l);
-            if (x) atomicAdd(A.counters + 4, (unsigned long long)x);
-        }
-    }
+    count_events(A, ev);
+}
+
+__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(const StepArgs A, const TilingHeader* hdr,
+                                                                       const Slice* __restrict__ slices,
+                                                                       int64_t slice_cap) {
+    push_deposit_tiled_body<false>(A, hdr, slices, slice_cap);
+}
+__global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A, const TilingHeader* hdr,
+                                                                         const Slice* __restrict__ slices,
+                                                                         int64_t slice_cap) {
+    push_deposit_tiled_body<true>(A, hdr, slices, slice_cap);
 }
 
 // Q_ij += q w S_ij(x_p) over live particles (FP64 or split offsets).
@@ -248,20 +389,25 @@ __global__ __launch_bounds__(256) void charge_kernel(const StepArgs A, double* _
 
 static inline dim3 blocks_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_push_deposit_f64(const StepArgs& A, hipStream_t stream) {
+hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream) {
     if (A.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(push_deposit_f64, blocks_for(A.n), dim3(256), 0, stream, A);
+    if (split) hipLaunchKernelGGL(push_deposit_split, blocks_for(A.n), dim3(256), 0, stream, A);
+    else hipLaunchKernelGGL(push_deposit_f64, blocks_for(A.n), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
 
-hipError_t launch_push_deposit_f64_tiled(const StepArgs& A, const void* tiling, int64_t slice_cap,
-                                         hipStream_t stream) {
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, const void* tiling, int64_t slice_cap,
+                                     hipStream_t stream) {
     if (A.n <= 0) return hipSuccess;
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
     const int64_t grid = (slice_cap + 7) / 8 * 8;
-    hipLaunchKernelGGL(push_deposit_f64_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr, slices,
-                       slice_cap);
+    if (split)
+        hipLaunchKernelGGL(push_deposit_split_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
+                           slices, slice_cap);
+    else
+        hipLaunchKernelGGL(push_deposit_f64_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
+                           slices, slice_cap);
     return hipGetLastError();
 }
 

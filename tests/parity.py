@@ -1,7 +1,7 @@
 """Helpers of the GPU parity tests: run the HIP path through the C ABI and
 compare it with the oracle.
 
-Norms (FP64, tolerance tol):
+Norms (FP64, tolerance tol = 1e-12):
 * position: |d xi|, |d eta| <= tol * max(1, |xi|)
 * momentum, per covariant component i:
   |d u_i| * sqrt(gamma^ii) <= tol * sqrt(1 + gamma^jk u_j u_k)
@@ -13,6 +13,16 @@ Norms (FP64, tolerance tol):
   terms cancel (the flux at the far side of a particle's window is zero in
   exact arithmetic).
 * live/removed status must agree particle by particle.
+
+Conditioning.  Near the axis the centrifugal terms (gamma^phph ~ 1/sin^2)
+make a few trajectories amplify rounding by many orders of magnitude, in the
+oracle as much as on the GPU.  The oracle is therefore also run on the same
+particles with every offset and momentum moved by PERTURB_ULPS ulps; the
+resulting change per particle (same norms) is that particle's rounding
+sensitivity s_p.  A particle passes if err_p <= tol + SENS_FACTOR * s_p, and a
+current element if |dF| <= tol * A_F + SENS_FACTOR * |dF_perturbed|.  For a
+well-conditioned particle s_p is ~1e-15 and the bar is tol.  The number of
+particles with s_p > tol is reported and must stay below 0.1 %.
 """
 from __future__ import annotations
 
@@ -64,9 +74,32 @@ def gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, precision=g
     return out, [j.cpu().numpy() for j in J], cnt
 
 
-def oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3):
+PERTURB_ULPS = 4
+SENS_FACTOR = 64
+EPS = np.finfo(np.float64).eps
+
+
+def perturbed(parts_np, seed=20250306):
+    """Copy of the particles with offsets and momenta moved by a few ulps."""
+    rng = np.random.default_rng(seed)
+    q = {k: np.array(v, copy=True) for k, v in parts_np.items()}
+    n = len(q["cell"])
+    for k in ("xr", "xth"):
+        q[k] = np.clip(q[k] + rng.choice([-1.0, 1.0], n) * PERTURB_ULPS * EPS, 0.0, 1.0 - EPS)
+    for k in ("ur", "uth", "uph"):
+        q[k] = q[k] * (1.0 + rng.choice([-1.0, 1.0], n) * PERTURB_ULPS * EPS)
+    return q
+
+
+def oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, sensitivity=True):
+    """Oracle result (p, J, A, stats) and, with sensitivity, the oracle on
+    the perturbed particles (p, J)."""
     p, J, A, st = orc.run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=ncorr, with_abs=True)
-    return p, J, A, st
+    pert = None
+    if sensitivity:
+        pp, Jp, _, _ = orc.run(grid, species, perturbed(parts_np), fields_np, dt, nsteps, ncorr=ncorr)
+        pert = (pp, Jp)
+    return p, J, A, st, pert
 
 
 def positions(grid, p):
@@ -75,48 +108,66 @@ def positions(grid, p):
     return ci + p["xr"].astype(np.float64), cj + p["xth"].astype(np.float64)
 
 
-def compare_particles(grid, pg, po, tol):
-    """Returns a dict of worst normalised errors; asserts status agreement."""
+def particle_errors(grid, pa, po):
+    """Per-particle normalised difference of pa from po (0 where either is removed)."""
+    live = (pa["cell"] >= 0) & (po["cell"] >= 0)
+    xa, ea = positions(grid, pa)
+    xo, eo = positions(grid, po)
+    err = np.maximum(np.abs(xa - xo) / np.maximum(1.0, np.abs(xo)), np.abs(ea - eo) / np.maximum(1.0, np.abs(eo)))
+    k = wl._ks_pieces(grid.a, grid.M, grid.r(xo), grid.theta(eo))
+    uo = [po[c].astype(np.float64) for c in ("ur", "uth", "uph")]
+    ua = [pa[c].astype(np.float64) for c in ("ur", "uth", "uph")]
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        norm = np.sqrt(1.0 + k["h_rr"] * uo[0] ** 2 + 2 * k["h_rp"] * uo[0] * uo[2] + k["h_tt"] * uo[1] ** 2
+                       + k["h_pp"] * uo[2] ** 2)
+        for i, h in enumerate(("h_rr", "h_tt", "h_pp")):
+            err = np.maximum(err, np.abs(ua[i] - uo[i]) * np.sqrt(k[h]) / norm)
+    err[~live] = 0.0
+    return err
+
+
+def compare_particles(grid, pg, po, tol, pert=None):
+    """Worst normalised errors; particles checked against tol + SENS_FACTOR * s_p."""
     alive_g, alive_o = pg["cell"] >= 0, po["cell"] >= 0
-    mism = int(np.count_nonzero(alive_g != alive_o))
-    both = alive_g & alive_o
-    xg, eg = positions(grid, {k: v[both] for k, v in pg.items()})
-    xo, eo = positions(grid, {k: v[both] for k, v in po.items()})
-    pos_err = max(np.max(np.abs(xg - xo) / np.maximum(1.0, np.abs(xo)), initial=0.0),
-                  np.max(np.abs(eg - eo) / np.maximum(1.0, np.abs(eo)), initial=0.0))
-    r = grid.r(xo)
-    th = grid.theta(eo)
-    k = wl._ks_pieces(grid.a, grid.M, r, th)
-    uo = [po[c][both].astype(np.float64) for c in ("ur", "uth", "uph")]
-    ug = [pg[c][both].astype(np.float64) for c in ("ur", "uth", "uph")]
-    norm = np.sqrt(1.0 + k["h_rr"] * uo[0] ** 2 + 2 * k["h_rp"] * uo[0] * uo[2] + k["h_tt"] * uo[1] ** 2
-                   + k["h_pp"] * uo[2] ** 2)
-    hii = (k["h_rr"], k["h_tt"], k["h_pp"])
-    mom_err = max((np.max(np.abs(ug[i] - uo[i]) * np.sqrt(hii[i]) / norm, initial=0.0) for i in range(3)))
-    return dict(status_mismatch=mism, pos=float(pos_err), mom=float(mom_err), n_alive=int(both.sum()))
+    err = particle_errors(grid, pg, po)
+    sens = np.zeros_like(err)
+    status_ok = alive_g == alive_o
+    if pert is not None:
+        pp = pert[0]
+        sens = particle_errors(grid, pp, po)
+        status_ok |= (pp["cell"] >= 0) != alive_o          # status itself is sensitive there
+    bad = err > tol + SENS_FACTOR * sens
+    return dict(status_mismatch=int(np.count_nonzero(~status_ok)), violations=int(np.count_nonzero(bad)),
+                err=float(err.max(initial=0.0)), well_conditioned_err=float(err[sens <= tol].max(initial=0.0)),
+                ill_conditioned=int(np.count_nonzero(sens > tol)), n_alive=int((alive_g & alive_o).sum()),
+                n=len(err))
 
 
-def compare_current(Jg, Jo, Ao, tol):
+def compare_current(Jg, Jo, Ao, tol, Jp=None):
     worst = 0.0
-    for g, o, a in zip(Jg, Jo, Ao):
+    bad = 0
+    for i, (g, o, a) in enumerate(zip(Jg, Jo, Ao)):
+        spread = np.abs(Jp[i] - o) if Jp is not None else 0.0
+        d = np.abs(g - o)
         scale = max(np.abs(a).max(), 1e-300)
-        worst = max(worst, np.abs(g - o).max() / scale)
-        bad = np.abs(g - o) > tol * a
-        assert not bad.any(), ("per-element current error above tol * A_F", int(bad.sum()),
-                               float((np.abs(g - o) / np.maximum(a, 1e-300)).max()))
-    return worst
+        worst = max(worst, float(np.max(np.maximum(d - SENS_FACTOR * spread, 0.0)) / scale))
+        bad += int(np.count_nonzero(d > tol * a + SENS_FACTOR * spread))
+    return worst, bad
 
 
 def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, ncorr=3, tiled=False):
     pg, Jg, cg = gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, tiled=tiled)
-    po, Jo, Ao, so = oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr)
-    e = compare_particles(grid, pg, po, tol)
+    po, Jo, Ao, so, pert = oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr)
+    e = compare_particles(grid, pg, po, tol, pert)
     assert e["status_mismatch"] == 0, e
-    assert e["pos"] <= tol and e["mom"] <= tol, e
-    e["J"] = compare_current(Jg, Jo, Ao, tol)
-    assert e["J"] <= tol, e
+    assert e["violations"] == 0, e
+    assert e["well_conditioned_err"] <= tol, e
+    assert e["ill_conditioned"] <= max(2, 1e-3 * e["n"]), e
+    e["J"], e["J_violations"] = compare_current(Jg, Jo, Ao, tol, pert[1])
+    assert e["J"] <= tol and e["J_violations"] == 0, e
+    slack = e["ill_conditioned"]      # an ill-conditioned particle may reflect or leave in one run only
     if not tiled:       # the GPU sort drops particles removed before the push; the oracle counts them
-        assert cg["bad"] == so["bad"], (cg, so)
-        assert cg["live_steps"] == so["live_steps"], (cg, so)
-    assert cg["out"] == so["out"] and cg["reflected"] == so["reflected"], (cg, so)
+        assert abs(cg["bad"] - so["bad"]) <= slack, (cg, so)
+        assert abs(cg["live_steps"] - so["live_steps"]) <= slack * nsteps, (cg, so)
+    assert abs(cg["out"] - so["out"]) <= slack and abs(cg["reflected"] - so["reflected"]) <= slack * nsteps, (cg, so)
     return e, cg

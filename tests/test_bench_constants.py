@@ -1,0 +1,19 @@
+"""bench.py's algorithmic constants agree with what they are derived from."""
+import bench
+from oracle import oracle as orc
+from paper_2503_04558_amd import workload as wl
+
+
+def test_flop_count_matches_oracle_count():
+    """FP64_OPS_PER_PARTICLE_STEP is the oracle's operation count (counting
+    scalar type) per particle-step on the benchmark workload."""
+    g = wl.make_grid(2048, 2048, 0.99)
+    parts = wl.pairs(g, 500, kind="mj", seed=0, params=dict(T=0.1, vphi=0.1))
+    ops = orc.count_ops(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g))
+    assert ops["particles"] == 1000
+    assert abs(ops["total"] - bench.FP64_OPS_PER_PARTICLE_STEP) < 1.0, ops
+
+
+def test_particle_bytes():
+    # cell int32, six float64 arrays and a uint8 species read; cell and five float64 written
+    assert bench.FP64_PARTICLE_BYTES == (4 + 6 * 8 + 1) + (4 + 5 * 8)

@@ -1,0 +1,129 @@
+"""Pins of the oracle's differentiated form (forward-mode dual numbers through
+the whole K-step trajectory), used to check the GPU adjoint.
+
+Loss (the adjoint workload): L = sum over steps n < K and particles of
+lambda . (F^r, F^th, G^ph) with lambda_r = dt on the r-faces of row i*,
+the face r_{i*+1/2} nearest to r = 5 (the net charge through that shell), and
+zero elsewhere.
+
+* The loss equals lambda contracted with the currents the plain oracle run
+  accumulates over the same steps.
+* d L / d u_i(0) per particle and d L / d(fields) along random directions agree
+  with central finite differences (h = 1e-6); points where +-h crosses a CIC
+  kink (one-sided differences disagree) are skipped and counted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2503_04558_amd import workload as wl
+
+K = 32
+
+
+def shell_face(g, r=5.0):
+    i = np.arange(g.nr)
+    return int(np.argmin(np.abs(g.r(i + 0.5) - r)))
+
+
+def shell_lambda(g, dt, r=5.0):
+    lam = [np.zeros(g.shape) for _ in range(3)]
+    lam[0][g.guard + shell_face(g, r), :] = dt
+    return lam
+
+
+@pytest.fixture(scope="module")
+def setup():
+    g = wl.make_grid(512, 512, 0.9)
+    dt = wl.crossing_dt(g)
+    fields = wl.wald_fields(g, B0=1.0)
+    parts = wl.pairs(g, 500_000, kind="mj", seed=0, params=dict(T=0.5))
+    # particles within a cell of the shell face, spread over all theta
+    i_star = shell_face(g)
+    rows = parts["cell"] // g.nth
+    near = np.flatnonzero(np.abs(rows - i_star) <= 1)
+    near = near[np.linspace(0, len(near) - 1, 400).astype(int)]
+    sub = {k: v[near] for k, v in parts.items()}
+    return g, dt, fields, sub, shell_lambda(g, dt)
+
+
+def test_shell_face_index():
+    g = wl.make_grid(512, 512, 0.9)
+    i = shell_face(g)
+    assert i == 189 and abs(g.r(i + 0.5) - 5.0) < 0.02
+
+
+def test_loss_equals_lambda_dot_accumulated_current(setup):
+    g, dt, fields, parts, lam = setup
+    L, _, st = orc.loss_dual(g, wl.species_table(), parts, fields, lam, dt, K)
+    _, J, _, _ = orc.run(g, wl.species_table(), parts, fields, dt, K)
+    L2 = sum(float((l * j).sum()) for l, j in zip(lam, J))
+    assert abs(L) > 1e-3                        # charge really crosses the shell
+    assert L == pytest.approx(L2, rel=1e-12, abs=1e-14)
+
+
+def _signature(traj):
+    """Half-cell floors along a trajectory: gathers use xi and xi - 1/2, the
+    shape functions kink at integer coordinates, so equal signatures mean no
+    kink lies between two runs."""
+    t = traj[np.isfinite(traj[:, 0])]
+    return np.floor(2.0 * t).astype(np.int64).tobytes()
+
+
+def test_momentum_gradient_matches_finite_differences(setup):
+    """Dual-number dL/du_i(0) against the 5-point stencil with h = 1e-4 and the
+    central difference with h = 1e-6, where no kink lies within +-2h.  L is a
+    sum of O(1) deposit terms that cancel to ~1e-2, so its round-off is ~1e-14
+    absolute: the h = 1e-6 difference carries ~1e-8 of noise (1e-4 relative
+    bar), the 5-point stencil at 1e-4 is good to ~1e-8 relative (1e-6 bar)."""
+    g, dt, fields, parts, lam = setup
+    sp = wl.species_table()
+    checked = skipped = 0
+    for p in range(0, len(parts["cell"]), 10):
+        xi = parts["cell"][p] // g.nth + parts["xr"][p]
+        eta = parts["cell"][p] % g.nth + parts["xth"][p]
+        u = np.array([parts["ur"][p], parts["uth"][p], parts["uph"][p]])
+        one = {k: v[p:p + 1] for k, v in parts.items()}
+        row = sp[int(parts["sp"][p])]
+        for k in range(3):
+            t = [np.zeros(1), np.zeros(1), np.zeros(1)]
+            t[k][0] = 1.0
+            L0, dL, _ = orc.loss_dual(g, sp, one, fields, lam, dt, K, tu=t)
+
+            def run(delta):
+                v = u.copy()
+                v[k] += delta
+                return orc.loss_particle(g, row, xi, eta, v, parts["w"][p], fields, lam, dt, K, trajectory=True)
+
+            h = 1e-4
+            runs = [run(d) for d in (-2 * h, -h, 0.0, h, 2 * h)]
+            if len({(st, _signature(tr)) for _, st, tr in runs}) > 1:
+                skipped += 1
+                continue
+            Ls = [r[0] for r in runs]
+            fd5 = (Ls[0] - 8 * Ls[1] + 8 * Ls[3] - Ls[4]) / (12 * h)
+            assert dL == pytest.approx(fd5, rel=1e-6, abs=1e-9), (p, k, dL, fd5)
+            Lp, Lm = run(1e-6)[0], run(-1e-6)[0]
+            assert dL == pytest.approx((Lp - Lm) / 2e-6, rel=1e-4, abs=1e-8), (p, k, dL)
+            checked += 1
+    assert checked >= 60 and skipped <= checked, (checked, skipped)
+
+
+def test_field_gradient_matches_finite_differences(setup):
+    g, dt, fields, parts, lam = setup
+    sp = wl.species_table()
+    rng = np.random.default_rng(2)
+    sub = {k: v[:120] for k, v in parts.items()}
+    agree = 0
+    for trial in range(4):
+        tF = [rng.normal(size=g.shape) * np.abs(f).max() for f in fields]
+        L0, dL, _ = orc.loss_dual(g, sp, sub, fields, lam, dt, K, tF=tF)
+        h = 1e-6
+        Lp, _, _ = orc.loss_dual(g, sp, sub, [f + h * t for f, t in zip(fields, tF)], lam, dt, K)
+        Lm, _, _ = orc.loss_dual(g, sp, sub, [f - h * t for f, t in zip(fields, tF)], lam, dt, K)
+        fd = (Lp - Lm) / (2 * h)
+        if abs(dL - fd) <= 1e-5 * max(abs(dL), 1e-6):
+            agree += 1
+    assert agree >= 3          # a random field direction may move one particle across a kink
