@@ -138,6 +138,69 @@ def run_gpu(args, g, F, parts, precision):
                 wall_s=t_wall, tflops=tflops, flops_per_launch=flops_per_launch)
 
 
+def run_adjoint(args):
+    """Backward / forward time of K = 32 FP64 steps (checkpoints every 8) on a
+    512 x 512 grid (a = 0.9, Wald B0 = 1) with 1e6 Maxwell-Juttner particles
+    (T = 0.5); loss: the charge carried through the shell r = 5.  Forward: the
+    sorted, tiled push of the K steps in one call, with and without saving the
+    checkpoints; backward: grpic_push_deposit_backward."""
+    import torch
+
+    from paper_2503_04558_amd import grpic
+    from paper_2503_04558_amd import workload as wl
+
+    K, C = 32, 8
+    g = wl.make_grid(512, 512, 0.9)
+    F = [torch.as_tensor(f).to("cuda") for f in wl.wald_fields(g, B0=1.0)]
+    parts = grpic.to_device(wl.pairs(g, args.adj_pairs, kind="mj", seed=0, params=dict(T=0.5),
+                                     workers=args.workers))
+    sp = wl.species_table()
+    metric = grpic.make_metric(g.a, g.M)
+    dt = wl.crossing_dt(g)
+    n = parts["cell"].numel()
+    sorter = grpic.Sorter(g, n, grpic.GRPIC_FP64)
+    start = sorter.sort(parts)
+    start = {k: v.clone() for k, v in start.items()}
+    i = np.arange(g.nr)
+    face = int(np.argmin(np.abs(g.r(i + 0.5) - 5.0)))
+    lam = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    lam[0][g.guard + face, :] = dt
+    ck = torch.empty(grpic.grpic_checkpoint_bytes(n, K, C), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(grpic.grpic_backward_workspace_bytes(n, C), dtype=torch.uint8, device="cuda")
+    gu = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    gF = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def fwd(with_ckpt):
+        p = {k: v.clone() for k, v in start.items()}
+        torch.cuda.synchronize()
+        return timed(lambda: grpic.grpic_push_deposit(metric, g, sp, p, F, J, dt, K, args.ncorr,
+                                                      tiling=sorter.tiling, ckpt=ck if with_ckpt else None,
+                                                      ckpt_every=C if with_ckpt else 0))
+
+    def bwd():
+        return timed(lambda: grpic.grpic_push_deposit_backward(metric, g, sp, start, F, lam, dt, K, args.ncorr, ck,
+                                                               C, ws, gu, gF))
+
+    fwd(True), bwd()                       # warm-up
+    f_plain = [fwd(False) for _ in range(3)]
+    f_ck = [fwd(True) for _ in range(3)]
+    b = [bwd() for _ in range(3)]
+    log(f"adjoint: fwd {f_plain} ms, fwd+ckpt {f_ck} ms, bwd {b} ms")
+    return {"workload": f"512x512, a=0.9, Wald B0=1, {n} particles (Maxwell-Juttner T=0.5), K={K} steps, "
+                        f"checkpoints every {C}, loss = charge through r=5",
+            "fwd_ms": min(f_plain), "fwd_ckpt_ms": min(f_ck), "bwd_ms": min(b),
+            "bwd_over_fwd": min(b) / min(f_ck)}
+
+
 def run_cpu_baseline(args, grid):
     """The FP64 oracle (OpenMP over particles) on a bounded sample."""
     from oracle import oracle as orc
@@ -172,6 +235,8 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the backward / forward timing")
+    ap.add_argument("--adj-pairs", type=int, default=500_000)
     ap.add_argument("--cpu-pairs", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -212,6 +277,8 @@ def main():
     if split_parts is not None:
         F32 = [f.to(torch.float32) for f in F]
         rs = run_gpu(args, g, F32, split_parts, grpic.GRPIC_FP32_SPLIT)
+    del split_parts
+    adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
     # 1344 flop per 97 B = 13.9 flop/B, above the FP64 ridge (78.6 TFLOP/s / 8 TB/s =
     # 9.8 flop/B): the FP64 vector units bound this kernel, HBM comes second.
@@ -260,6 +327,8 @@ def main():
                                  bytes_per_launch=rs["bytes_per_launch"]),
             "counters": rs["counters"],
         }
+    if adj is not None:
+        out["adjoint"] = adj
     print(json.dumps(out), flush=True)
 
 

@@ -153,15 +153,55 @@ typedef struct {
  *   sort is.  Only particles live at the sort are pushed (the sort marks the
  *   rest removed); without a tiling any particle order works.
  * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
- * ckpt, ckpt_every: reserved for the adjoint (pass NULL, 0).
+ * ckpt (optional, device, ckpt_bytes >= grpic_checkpoint_bytes(n, nsteps,
+ *   ckpt_every)): the particle state is saved before every step k with
+ *   k % ckpt_every == 0, for grpic_push_deposit_backward (GRPIC_FP64 only;
+ *   ckpt_every must divide nsteps).  NULL, 0, 0 when not needed.
  * counters: optional device int64[GRPIC_NCOUNTERS], accumulated.
  */
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
                        const void* tiling, double dt, int nsteps, int ncorr,
-                       void* ckpt, int ckpt_every,
+                       void* ckpt, size_t ckpt_bytes, int ckpt_every,
                        int64_t* counters, void* stream);
+
+/* Gradient outputs of grpic_push_deposit_backward (device, double). */
+typedef struct {
+    double *ur, *uth, *uph;          /* per particle, overwritten */
+} grpic_momentum_grads;
+typedef struct {
+    double *D[3], *B[3];             /* grid arrays on the Yee stagger, accumulated (+=) */
+} grpic_field_grads;
+
+/*
+ * grpic_push_deposit_backward -- adjoint of `nsteps` FP64 push + deposit
+ * steps (not in the paper; built on its step, Sec. 2.2-2.3).
+ *
+ * With L = sum over the steps n and the particles of
+ *   lambda_r . F^r_n + lambda_th . F^th_n + lambda_ph . G^ph_n,
+ * lambda = (Fr, Fth, Gph) of `lambda` given per grid element (the cotangent
+ * of the current accumulated over the steps), writes dL/du_i of every
+ * particle's initial momenta to grad_u and adds dL/dD^i, dL/dB^i to
+ * grad_fields.  parts: the particles at the start of the forward call (w and
+ * sp are read; n, precision GRPIC_FP64); fields, dt, nsteps, ncorr (<= 8),
+ * species: as in that call; ckpt: its checkpoints.  ws: device workspace of
+ * grpic_backward_workspace_bytes(n, ckpt_every) bytes.  Per particle, each
+ * checkpoint segment is recomputed from its checkpoint and then reversed
+ * step by step, the last step first; field gradients use FP64 atomics.
+ * The derivative is that of the piecewise-smooth map: where a particle's
+ * CIC weights or deposit window change (cell edges), the one-sided
+ * derivative of the side the trajectory lies on is taken.
+ */
+size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every);
+size_t grpic_backward_workspace_bytes(int64_t n, int ckpt_every);
+int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
+                                const grpic_species* species, int nsp, const grpic_particles* parts,
+                                const grpic_fields* fields, const grpic_current* lambda,
+                                double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
+                                int ckpt_every, void* ws, size_t ws_bytes,
+                                const grpic_momentum_grads* grad_u, const grpic_field_grads* grad_fields,
+                                void* stream);
 
 /*
  * grpic_charge -- Q_ij += sum over live particles of q w S_ij(x_p), the CIC

@@ -167,7 +167,7 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
                        const void* tiling, double dt, int nsteps, int ncorr,
-                       void* ckpt, int ckpt_every,
+                       void* ckpt, size_t ckpt_bytes, int ckpt_every,
                        int64_t* counters, void* stream) {
     int rc;
     if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
@@ -180,7 +180,13 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     if (!(dt > 0.0) || !isfinite(dt)) return fail(GRPIC_EINVAL, "dt must be positive and finite");
     if (nsteps < 0) return fail(GRPIC_EINVAL, "nsteps < 0");
     if (ncorr < 0 || ncorr > 16) return fail(GRPIC_EINVAL, "ncorr must be in [0, 16]");
-    if (ckpt || ckpt_every) return fail(GRPIC_EINVAL, "checkpoints are not supported by this entry point yet");
+    if (ckpt) {
+        if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "checkpoints need GRPIC_FP64 particles");
+        if (ckpt_every < 1 || nsteps % ckpt_every != 0)
+            return fail(GRPIC_EINVAL, "ckpt_every must be >= 1 and divide nsteps");
+        const size_t need = grpic_checkpoint_bytes(parts->n, nsteps, ckpt_every);
+        if (ckpt_bytes < need) return fail(GRPIC_ENOMEM, "checkpoints need %zu bytes, got %zu", need, ckpt_bytes);
+    }
     const double tc = crossing_time_cached(metric, grid);
     if (dt > tc * (1.0 + 1e-12))
         return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
@@ -203,13 +209,88 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
     A.counters = reinterpret_cast<unsigned long long*>(counters);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
+    const size_t slot = grpic::checkpoint_slot_bytes(parts->n);
     for (int step = 0; step < nsteps; ++step) {
+        if (ckpt && step % ckpt_every == 0) {
+            void* dst = static_cast<char*>(ckpt) + (size_t)(step / ckpt_every) * slot;
+            if ((rc = hip_status(grpic::launch_save_state(A, dst, s), "checkpoint launch"))) return rc;
+        }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
         const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s)
                                     : grpic::launch_push_deposit(A, split, s);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
     return GRPIC_OK;
+}
+
+size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every) {
+    if (n < 0 || ckpt_every < 1 || nsteps < 0 || nsteps % ckpt_every != 0) return 0;
+    return (size_t)(nsteps / ckpt_every) * grpic::checkpoint_slot_bytes(n);
+}
+
+size_t grpic_backward_workspace_bytes(int64_t n, int ckpt_every) {
+    if (n < 0 || ckpt_every < 1) return 0;
+    return (size_t)ckpt_every * 5 * sizeof(double) * (size_t)n;
+}
+
+int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
+                                const grpic_species* species, int nsp, const grpic_particles* parts,
+                                const grpic_fields* fields, const grpic_current* lambda,
+                                double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
+                                int ckpt_every, void* ws, size_t ws_bytes,
+                                const grpic_momentum_grads* grad_u, const grpic_field_grads* grad_fields,
+                                void* stream) {
+    int rc;
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
+        (rc = check_particles(parts, "parts")))
+        return rc;
+    if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "the adjoint needs GRPIC_FP64 particles");
+    if (!fields) return fail(GRPIC_EINVAL, "fields is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!fields->D[c] || !fields->B[c]) return fail(GRPIC_EINVAL, "fields: NULL component");
+    if (!lambda || !lambda->Fr || !lambda->Fth || !lambda->Gph) return fail(GRPIC_EINVAL, "lambda: NULL array");
+    if (!grad_u) return fail(GRPIC_EINVAL, "grad_u is NULL");
+    if (parts->n > 0 && (!grad_u->ur || !grad_u->uth || !grad_u->uph))
+        return fail(GRPIC_EINVAL, "grad_u: NULL array");
+    if (!grad_fields) return fail(GRPIC_EINVAL, "grad_fields is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!grad_fields->D[c] || !grad_fields->B[c]) return fail(GRPIC_EINVAL, "grad_fields: NULL component");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(GRPIC_EINVAL, "dt must be positive and finite");
+    if (ncorr < 0 || ncorr > grpic::adj_max_corr()) return fail(GRPIC_EINVAL, "ncorr must be in [0, %d] for the adjoint",
+                                                                 grpic::adj_max_corr());
+    if (ckpt_every < 1 || nsteps < 1 || nsteps % ckpt_every != 0)
+        return fail(GRPIC_EINVAL, "need nsteps >= 1 and ckpt_every >= 1 dividing nsteps");
+    if ((parts->n > 0 && !ckpt) || ckpt_bytes < grpic_checkpoint_bytes(parts->n, nsteps, ckpt_every))
+        return fail(GRPIC_ENOMEM, "checkpoint buffer too small or NULL");
+    if ((parts->n > 0 && !ws) || ws_bytes < grpic_backward_workspace_bytes(parts->n, ckpt_every))
+        return fail(GRPIC_ENOMEM, "backward workspace needs %zu bytes, got %zu",
+                    grpic_backward_workspace_bytes(parts->n, ckpt_every), ws_bytes);
+    const double tc = crossing_time_cached(metric, grid);
+    if (dt > tc * (1.0 + 1e-12))
+        return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
+    if (parts->n > 0 && (!parts->w || !parts->sp)) return fail(GRPIC_EINVAL, "parts: NULL w or sp");
+    grpic::BackArgs B;
+    memset(&B, 0, sizeof B);
+    B.a = metric->a; B.M = metric->M;
+    B.lnr0 = grid->lnr0; B.dlnr = grid->dlnr; B.dth = grid->dth;
+    B.nr = grid->nr; B.nth = grid->nth; B.guard = grid->guard; B.pitch = grid->pitch;
+    B.dt = dt; B.ncorr = ncorr; B.nsteps = nsteps; B.ckpt_every = ckpt_every; B.nsp = nsp;
+    for (int i = 0; i < nsp; ++i) { B.q[i] = species[i].q; B.m[i] = species[i].m; B.massless[i] = species[i].massless; }
+    B.n = parts->n;
+    B.w = static_cast<const double*>(parts->w);
+    B.sp = parts->sp;
+    for (int c = 0; c < 3; ++c) {
+        B.F[c] = static_cast<const double*>(fields->D[c]);
+        B.F[3 + c] = static_cast<const double*>(fields->B[c]);
+        B.gradF[c] = grad_fields->D[c];
+        B.gradF[3 + c] = grad_fields->B[c];
+    }
+    B.lam[0] = lambda->Fr; B.lam[1] = lambda->Fth; B.lam[2] = lambda->Gph;
+    B.ckpt = ckpt;
+    B.slot_bytes = grpic::checkpoint_slot_bytes(parts->n);
+    B.ws = static_cast<double*>(ws);
+    B.grad_u[0] = grad_u->ur; B.grad_u[1] = grad_u->uth; B.grad_u[2] = grad_u->uph;
+    return hip_status(grpic::launch_push_deposit_backward(B, static_cast<hipStream_t>(stream)), "backward launch");
 }
 
 int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,

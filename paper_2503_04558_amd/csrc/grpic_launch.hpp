@@ -74,6 +74,31 @@ struct SortArgs {
     void* tiling;                     // optional output, tiling_bytes()
 };
 
+// Reverse sweep of K push + deposit steps (adjoint.hip).
+struct BackArgs {
+    double a, M, lnr0, dlnr, dth;
+    int nr, nth, guard, pitch;
+    double dt;
+    int ncorr, nsteps, ckpt_every, nsp;
+    double q[kMaxSpecies], m[kMaxSpecies];
+    int massless[kMaxSpecies];
+    int64_t n;
+    const double* w;
+    const uint8_t* sp;
+    const double* F[6];               // D^r, D^th, D^ph, B^r, B^th, B^ph
+    const double* lam[3];             // dL/dF^r, dL/dF^th, dL/dG^ph
+    const void* ckpt;
+    size_t slot_bytes;
+    double* ws;                       // ckpt_every * 5 * n doubles
+    double* grad_u[3];                // out: dL/du_r, dL/du_th, dL/du_ph at step 0
+    double* gradF[6];                 // += dL/dD^i, dL/dB^i
+};
+
+size_t checkpoint_slot_bytes(int64_t n);
+int adj_max_corr();
+hipError_t launch_save_state(const StepArgs& A, void* slot, hipStream_t stream);
+hipError_t launch_push_deposit_backward(const BackArgs& B, hipStream_t stream);
+
 int64_t sort_scan_blocks(int64_t len);
 size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);

@@ -55,7 +55,16 @@ class grpic_current(ctypes.Structure):
     _fields_ = [("Fr", ctypes.c_void_p), ("Fth", ctypes.c_void_p), ("Gph", ctypes.c_void_p)]
 
 
-EXPORTED = ("grpic_push_deposit", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
+class grpic_momentum_grads(ctypes.Structure):
+    _fields_ = [("ur", ctypes.c_void_p), ("uth", ctypes.c_void_p), ("uph", ctypes.c_void_p)]
+
+
+class grpic_field_grads(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
+
+
+EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
+            "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version")
 
 
@@ -76,7 +85,15 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2503_04558_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
-        L.grpic_push_deposit.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, i32, vp, vp]
+        sz = ctypes.c_size_t
+        L.grpic_push_deposit.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, sz, i32, vp, vp]
+        L.grpic_push_deposit_backward.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, sz, i32, vp, sz,
+                                                  vp, vp, vp]
+        L.grpic_push_deposit_backward.restype = ctypes.c_int
+        L.grpic_checkpoint_bytes.argtypes = [i64, i32, i32]
+        L.grpic_checkpoint_bytes.restype = sz
+        L.grpic_backward_workspace_bytes.argtypes = [i64, i32]
+        L.grpic_backward_workspace_bytes.restype = sz
         L.grpic_push_deposit.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge.restype = ctypes.c_int
@@ -183,9 +200,14 @@ def _stream(stream) -> int | None:
 
 
 # ---------------------------------------------------------------- entry points
+def _nbytes(t: torch.Tensor | None) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
 def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float,
-                       nsteps: int, ncorr: int = 3, tiling: torch.Tensor | None = None, ckpt=None,
-                       ckpt_every: int = 0, counters: torch.Tensor | None = None, stream=None) -> None:
+                       nsteps: int, ncorr: int = 3, tiling: torch.Tensor | None = None,
+                       ckpt: torch.Tensor | None = None, ckpt_every: int = 0,
+                       counters: torch.Tensor | None = None, stream=None) -> None:
     g = make_grid(grid)
     sp = make_species(species)
     P = make_particles(parts)
@@ -194,11 +216,52 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
     C = make_current(grid, J)
     if counters is not None:
         _need(counters, torch.int64, GRPIC_NCOUNTERS, "counters")
-    if tiling is not None and (not tiling.is_cuda or not tiling.is_contiguous()):
-        raise ValueError("tiling: expected a contiguous device tensor")
+    for t, name in ((tiling, "tiling"), (ckpt, "ckpt")):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous device tensor")
     _check(lib().grpic_push_deposit(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
                                     ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(nsteps),
-                                    int(ncorr), _ptr(ckpt), int(ckpt_every), _ptr(counters), _stream(stream)))
+                                    int(ncorr), _ptr(ckpt), _nbytes(ckpt), int(ckpt_every), _ptr(counters),
+                                    _stream(stream)))
+
+
+def grpic_checkpoint_bytes(n: int, nsteps: int, ckpt_every: int) -> int:
+    return int(lib().grpic_checkpoint_bytes(int(n), int(nsteps), int(ckpt_every)))
+
+
+def grpic_backward_workspace_bytes(n: int, ckpt_every: int) -> int:
+    return int(lib().grpic_backward_workspace_bytes(int(n), int(ckpt_every)))
+
+
+def grpic_push_deposit_backward(metric: grpic_metric, grid, species, parts: dict, fields, lam, dt: float,
+                                nsteps: int, ncorr: int, ckpt: torch.Tensor, ckpt_every: int, ws: torch.Tensor,
+                                grad_u, grad_fields, stream=None) -> None:
+    """grad_u: three float64 tensors (n,), overwritten; grad_fields: six grid
+    arrays, accumulated; lam: the cotangents of F^r, F^th, G^ph."""
+    g = make_grid(grid)
+    sp = make_species(species)
+    P = make_particles(parts)
+    if P.precision != GRPIC_FP64:
+        raise ValueError("the adjoint needs float64 particles")
+    F = make_fields(grid, fields, torch.float64)
+    Lm = make_current(grid, lam)
+    n = parts["cell"].numel()
+    for i, t in enumerate(grad_u):
+        _need(t, torch.float64, n, f"grad_u {i}")
+    GF = make_fields(grid, grad_fields, torch.float64)
+    GU = grpic_momentum_grads(*[t.data_ptr() for t in grad_u])
+    GFg = grpic_field_grads()
+    for c in range(3):
+        GFg.D[c] = GF.D[c]
+        GFg.B[c] = GF.B[c]
+    for t, name in ((ckpt, "ckpt"), (ws, "ws")):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous device tensor")
+    _check(lib().grpic_push_deposit_backward(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
+                                             ctypes.byref(P), ctypes.byref(F), ctypes.byref(Lm), float(dt),
+                                             int(nsteps), int(ncorr), ckpt.data_ptr(), _nbytes(ckpt),
+                                             int(ckpt_every), ws.data_ptr(), _nbytes(ws), ctypes.byref(GU),
+                                             ctypes.byref(GFg), _stream(stream)))
 
 
 def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None) -> None:

@@ -46,7 +46,7 @@ def _call_push(metric, grid, species, nsp, parts, fields, cur, dt, nsteps=1, nco
         ctypes.byref(parts) if parts is not None else None,
         ctypes.byref(fields) if fields is not None else None,
         ctypes.byref(cur) if cur is not None else None,
-        None, dt, nsteps, ncorr, None, 0, None, None)
+        None, dt, nsteps, ncorr, None, 0, 0, None, None)
 
 
 def _fake_args(g):
@@ -125,5 +125,41 @@ def test_push_rejects_unknown_tiling():
     L = grpic.lib()
     rc = L.grpic_push_deposit(ctypes.byref(grpic.make_metric(0.9, 1.0)), ctypes.byref(grpic.make_grid(g)),
                               grpic.make_species(wl.species_table()), 2, ctypes.byref(parts), ctypes.byref(fields),
-                              ctypes.byref(cur), 0x2000, wl.crossing_dt(g), 1, 3, None, 0, None, None)
+                              ctypes.byref(cur), 0x2000, wl.crossing_dt(g), 1, 3, None, 0, 0, None, None)
     assert rc == grpic.GRPIC_EINVAL and b"tiling" in L.grpic_last_error()
+
+
+def test_checkpoint_and_backward_validation():
+    g = wl.make_grid(32, 32, 0.9)
+    assert grpic.grpic_checkpoint_bytes(1000, 32, 8) == 4 * (4000 + 5 * 8 * 1000)
+    assert grpic.grpic_checkpoint_bytes(1000, 30, 8) == 0          # ckpt_every must divide nsteps
+    assert grpic.grpic_backward_workspace_bytes(1000, 8) == 8 * 5 * 8 * 1000
+    parts, fields, cur = _fake_args(g)
+    L = grpic.lib()
+    m, G, sp = grpic.make_metric(0.9, 1.0), grpic.make_grid(g), grpic.make_species(wl.species_table())
+    dt = wl.crossing_dt(g)
+    # forward with a checkpoint buffer that is too small
+    rc = L.grpic_push_deposit(ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts), ctypes.byref(fields),
+                              ctypes.byref(cur), None, dt, 32, 3, 0x3000, 16, 8, None, None)
+    assert rc == grpic.GRPIC_ENOMEM
+    rc = L.grpic_push_deposit(ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts), ctypes.byref(fields),
+                              ctypes.byref(cur), None, dt, 30, 3, 0x3000, 1 << 30, 8, None, None)
+    assert rc == grpic.GRPIC_EINVAL
+    gu = grpic.grpic_momentum_grads(0x1000, 0x1000, 0x1000)
+    gf = grpic.grpic_field_grads()
+    for c in range(3):
+        gf.D[c] = 0x1000
+        gf.B[c] = 0x1000
+    ck = grpic.grpic_checkpoint_bytes(10, 32, 8)
+    ws = grpic.grpic_backward_workspace_bytes(10, 8)
+    args = [ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts), ctypes.byref(fields), ctypes.byref(cur),
+            dt, 32, 3, 0x3000, ck, 8, 0x4000, ws, ctypes.byref(gu), ctypes.byref(gf), None]
+    bad = list(args)
+    bad[9] = 9                                                     # ncorr above the adjoint's limit
+    assert L.grpic_push_deposit_backward(*bad) == grpic.GRPIC_EINVAL
+    bad = list(args)
+    bad[14] = ws - 8                                               # workspace too small
+    assert L.grpic_push_deposit_backward(*bad) == grpic.GRPIC_ENOMEM
+    bad = list(args)
+    bad[7] = 2.01 * dt
+    assert L.grpic_push_deposit_backward(*bad) == grpic.GRPIC_ERANGE

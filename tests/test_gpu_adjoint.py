@@ -1,0 +1,205 @@
+"""GPU adjoint (grpic_push_deposit_backward) against the oracle differentiated
+in FP64 (forward-mode dual numbers through the whole K-step trajectory) and
+against central finite differences of the GPU forward.
+
+Workload: adjoint_cases.py (K = 32 steps, checkpoints every 8).
+
+* d L / d u_i(0), particle by particle, against the oracle's dual-number
+  derivative: |g_gpu - g_orc| <= 1e-9 |g_orc|_vec + 64 s_p, s_p being the
+  change of the oracle's derivative when the particle's momenta move by 4 ulps
+  (the derivative's own rounding sensitivity; ~0 for almost all particles).
+* d L / d(fields) contracted with random directions against the oracle's
+  dual-number directional derivative (relative 1e-9).
+* The same contractions and d L / d u along random directions against central
+  differences of the GPU forward with h = 1e-6 (relative 1e-4: L cancels to
+  ~1e-2 from O(1) terms, so the difference carries ~1e-8 of rounding).
+* Sorted + tiled forward gives the same gradients as the untiled one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2503_04558_amd import grpic
+from paper_2503_04558_amd import workload as wl
+
+from adjoint_cases import CKPT_EVERY, K, shell_case
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, tiled=False):
+    """GPU forward from parts_np with checkpoints; returns the device particle
+    state at the start (w, sp, order used by the backward), the checkpoint
+    buffer, the accumulated current and the particle index order."""
+    n = len(parts_np["cell"])
+    host = dict(parts_np)
+    order = np.arange(n)
+    if tiled:
+        host["phi"] = order.astype(np.float64)
+    parts = grpic.to_device(host)
+    tiling = None
+    if tiled:
+        sorter = grpic.Sorter(g, n, grpic.GRPIC_FP64, with_phi=True)
+        parts = sorter.sort(parts)
+        order = parts["phi"].cpu().numpy().astype(np.int64)
+        parts = {k: v for k, v in parts.items() if k != "phi"}
+        tiling = sorter.tiling
+    start = {k: v.clone() for k, v in parts.items()}
+    F = [torch.as_tensor(f).to("cuda") for f in fields_np]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ck = torch.empty(grpic.grpic_checkpoint_bytes(n, nsteps, ckpt_every), dtype=torch.uint8, device="cuda")
+    grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, sp, parts, F, J, dt, nsteps, 3, tiling=tiling,
+                             ckpt=ck, ckpt_every=ckpt_every)
+    return start, F, J, ck, order
+
+
+def backward(g, sp, start, F, lam_np, dt, ck, nsteps=K, ckpt_every=CKPT_EVERY):
+    n = start["cell"].numel()
+    lam = [torch.as_tensor(l).to("cuda") for l in lam_np]
+    ws = torch.empty(grpic.grpic_backward_workspace_bytes(n, ckpt_every), dtype=torch.uint8, device="cuda")
+    gu = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    gF = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
+    grpic.grpic_push_deposit_backward(grpic.make_metric(g.a, g.M), g, sp, start, F, lam, dt, nsteps, 3, ck,
+                                      ckpt_every, ws, gu, gF)
+    torch.cuda.synchronize()
+    return np.stack([t.cpu().numpy() for t in gu], axis=1), [t.cpu().numpy() for t in gF]
+
+
+def gpu_loss(g, sp, parts_np, fields_np, lam, dt):
+    n = len(parts_np["cell"])
+    parts = grpic.to_device(parts_np)
+    F = [torch.as_tensor(f).to("cuda") for f in fields_np]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, sp, parts, F, J, dt, K, 3)
+    torch.cuda.synchronize()
+    assert n == parts["cell"].numel()
+    return sum(float((l * j.cpu().numpy()).sum()) for l, j in zip(lam, J))
+
+
+@pytest.fixture(scope="module")
+def case():
+    _announce("adjoint case 512x512, 400 particles near r = 5, K = 32")
+    g, dt, fields, parts, lam = shell_case()
+    sp = wl.species_table()
+    start, F, J, ck, _ = forward(g, sp, parts, fields, dt)
+    gu, gF = backward(g, sp, start, F, lam, dt, ck)
+    L = sum(float((l * j.cpu().numpy()).sum()) for l, j in zip(lam, J))
+    return dict(g=g, dt=dt, fields=fields, parts=parts, lam=lam, sp=sp, gu=gu, gF=gF, L=L)
+
+
+def oracle_grad_u(c, parts):
+    g, sp = c["g"], c["sp"]
+    n = len(parts["cell"])
+    out = np.zeros((n, 3))
+    for p in range(n):
+        one = {k: v[p:p + 1] for k, v in parts.items()}
+        for k in range(3):
+            t = [np.zeros(1), np.zeros(1), np.zeros(1)]
+            t[k][0] = 1.0
+            _, out[p, k], _ = orc.loss_dual(g, sp, one, c["fields"], c["lam"], c["dt"], K, tu=t)
+    return out
+
+
+def test_loss_matches_oracle(case):
+    L, _, _ = orc.loss_dual(case["g"], case["sp"], case["parts"], case["fields"], case["lam"], case["dt"], K)
+    assert abs(L) > 1e-3
+    assert case["L"] == pytest.approx(L, rel=1e-11, abs=1e-13)
+
+
+def test_momentum_gradient_matches_oracle_dual(case):
+    _announce("adjoint d L/d u vs oracle dual numbers")
+    ref = oracle_grad_u(case, case["parts"])
+    pert = {k: np.array(v, copy=True) for k, v in case["parts"].items()}
+    for k in ("ur", "uth", "uph"):
+        pert[k] *= 1.0 + 4 * EPS
+    sens = np.abs(oracle_grad_u(case, pert) - ref).max(axis=1)
+    err = np.abs(case["gu"] - ref).max(axis=1)
+    scale = np.abs(ref).max(axis=1)
+    bad = np.flatnonzero(err > 1e-9 * scale + 64 * sens)
+    _announce(f"adjoint grad_u: max rel err {float((err / np.maximum(scale, 1e-300)).max()):.3e}, "
+              f"nonzero {int((scale > 0).sum())}, ill-conditioned {int((sens > 1e-9 * scale).sum())}")
+    assert (scale > 0).sum() >= 100
+    assert bad.size == 0, [(int(p), case["gu"][p].tolist(), ref[p].tolist()) for p in bad[:5]]
+
+
+def test_field_gradient_matches_oracle_dual(case):
+    _announce("adjoint d L/d fields vs oracle dual numbers")
+    rng = np.random.default_rng(5)
+    for trial in range(4):
+        tF = [rng.normal(size=case["g"].shape) * np.abs(f).max() for f in case["fields"]]
+        _, dL, _ = orc.loss_dual(case["g"], case["sp"], case["parts"], case["fields"], case["lam"], case["dt"], K,
+                                 tF=tF)
+        got = sum(float((a * t).sum()) for a, t in zip(case["gF"], tF))
+        terms = sum(float(np.abs(a * t).sum()) for a, t in zip(case["gF"], tF))
+        assert abs(got - dL) <= 1e-9 * max(abs(dL), 1e-3 * terms), (trial, got, dL)
+
+
+def test_gradients_match_gpu_finite_differences(case):
+    _announce("adjoint vs central differences of the GPU forward")
+    g, sp, lam, dt = case["g"], case["sp"], case["lam"], case["dt"]
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    agree = 0
+    for trial in range(4):
+        tu = rng.normal(size=(len(case["parts"]["cell"]), 3))
+        tF = [rng.normal(size=g.shape) * np.abs(f).max() for f in case["fields"]]
+        dL = float((case["gu"] * tu).sum()) + sum(float((a * t).sum()) for a, t in zip(case["gF"], tF))
+
+        def shifted(s):
+            p = dict(case["parts"])
+            for k, name in enumerate(("ur", "uth", "uph")):
+                p[name] = case["parts"][name] + s * tu[:, k]
+            return p, [f + s * t for f, t in zip(case["fields"], tF)]
+
+        Lp = gpu_loss(g, sp, *shifted(h), lam, dt)
+        Lm = gpu_loss(g, sp, *shifted(-h), lam, dt)
+        fd = (Lp - Lm) / (2 * h)
+        if abs(fd - dL) <= 1e-4 * max(abs(dL), 1e-4):
+            agree += 1
+    assert agree >= 3          # a random direction may move one particle across a CIC kink
+
+
+def test_tiled_forward_gives_same_gradients(case):
+    _announce("adjoint after a sorted, tiled forward")
+    g, sp = case["g"], case["sp"]
+    start, F, J, ck, order = forward(g, sp, case["parts"], case["fields"], case["dt"], tiled=True)
+    gu, gF = backward(g, sp, start, F, case["lam"], case["dt"], ck)
+    alive = start["cell"].cpu().numpy() >= 0
+    ref = case["gu"][order[alive]]
+    scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-300
+    assert np.all(np.abs(gu[alive] - ref) <= 1e-9 * scale + 1e-15)
+    for a, b in zip(gF, case["gF"]):
+        assert np.abs(a - b).max() <= 1e-9 * max(np.abs(b).max(), 1e-300)
+
+
+def test_checkpoint_interval_does_not_change_gradients(case):
+    g, sp = case["g"], case["sp"]
+    for every in (1, 32):
+        start, F, J, ck, _ = forward(g, sp, case["parts"], case["fields"], case["dt"], ckpt_every=every)
+        gu, gF = backward(g, sp, start, F, case["lam"], case["dt"], ck, ckpt_every=every)
+        scale = np.abs(case["gu"]).max(axis=1, keepdims=True) + 1e-300
+        assert np.all(np.abs(gu - case["gu"]) <= 1e-12 * scale), every
+
+
+def test_backward_of_removed_and_empty():
+    """Particles outside the grid from the start get zero gradients; n = 0 is a no-op."""
+    g = wl.make_grid(64, 64, 0.9)
+    sp = wl.species_table()
+    dt = wl.crossing_dt(g)
+    parts = wl.pairs(g, 100, kind="uniform", seed=1)
+    parts["cell"][::3] = -1
+    start, F, J, ck, _ = forward(g, sp, parts, wl.wald_fields(g), dt, nsteps=8, ckpt_every=4)
+    lam = [np.full(g.shape, dt) for _ in range(3)]
+    gu, _ = backward(g, sp, start, F, lam, dt, ck, nsteps=8, ckpt_every=4)
+    assert np.all(gu[::3] == 0.0) and np.all(np.isfinite(gu))
+    empty = {k: v[:0] for k, v in parts.items()}
+    start, F, J, ck, _ = forward(g, sp, empty, wl.wald_fields(g), dt, nsteps=8, ckpt_every=4)
+    gu, gF = backward(g, sp, start, F, lam, dt, ck, nsteps=8, ckpt_every=4)
+    assert gu.shape == (0, 3) and all(np.all(a == 0) for a in gF)

@@ -1,10 +1,9 @@
 """Pins of the oracle's differentiated form (forward-mode dual numbers through
 the whole K-step trajectory), used to check the GPU adjoint.
 
-Loss (the adjoint workload): L = sum over steps n < K and particles of
-lambda . (F^r, F^th, G^ph) with lambda_r = dt on the r-faces of row i*,
-the face r_{i*+1/2} nearest to r = 5 (the net charge through that shell), and
-zero elsewhere.
+Loss (the adjoint workload, adjoint_cases.py): L = sum over steps n < K and
+particles of lambda . (F^r, F^th, G^ph), lambda_r = dt on the r-faces nearest
+to r = 5 (the net charge through that shell), zero elsewhere.
 
 * The loss equals lambda contracted with the currents the plain oracle run
   accumulates over the same steps.
@@ -20,33 +19,12 @@ import pytest
 from oracle import oracle as orc
 from paper_2503_04558_amd import workload as wl
 
-K = 32
-
-
-def shell_face(g, r=5.0):
-    i = np.arange(g.nr)
-    return int(np.argmin(np.abs(g.r(i + 0.5) - r)))
-
-
-def shell_lambda(g, dt, r=5.0):
-    lam = [np.zeros(g.shape) for _ in range(3)]
-    lam[0][g.guard + shell_face(g, r), :] = dt
-    return lam
+from adjoint_cases import K, shell_case, shell_face
 
 
 @pytest.fixture(scope="module")
 def setup():
-    g = wl.make_grid(512, 512, 0.9)
-    dt = wl.crossing_dt(g)
-    fields = wl.wald_fields(g, B0=1.0)
-    parts = wl.pairs(g, 500_000, kind="mj", seed=0, params=dict(T=0.5))
-    # particles within a cell of the shell face, spread over all theta
-    i_star = shell_face(g)
-    rows = parts["cell"] // g.nth
-    near = np.flatnonzero(np.abs(rows - i_star) <= 1)
-    near = near[np.linspace(0, len(near) - 1, 400).astype(int)]
-    sub = {k: v[near] for k, v in parts.items()}
-    return g, dt, fields, sub, shell_lambda(g, dt)
+    return shell_case()
 
 
 def test_shell_face_index():
