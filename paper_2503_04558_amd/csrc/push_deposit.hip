@@ -37,10 +37,36 @@ struct Events {
     int live, out, bad, refl, spill;
 };
 
+// Anchors of one tile (its row, and the kTileCells + 1 column corners it
+// spans), evaluated once per workgroup into LDS; particles that have drifted
+// out of the tile evaluate their own.
+struct TileAnchors {
+    int ti, j_lo;
+    double r;
+    double s[kTileCells + 1], c[kTileCells + 1];
+};
+
+static_assert(kPushThreads >= 64 + kTileCells + 1, "the second wave fills the anchor table");
+
+template <class R>
+__device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int cj, const TileAnchors* T) {
+    if (T && A.small_steps && ci == T->ti && cj >= T->j_lo && cj <= T->j_lo + kTileCells) {
+        Anchor<R> an;
+        an.ci = ci;
+        an.cj = cj;
+        an.r = R(T->r);
+        an.s = R(T->s[cj - T->j_lo]);
+        an.c = R(T->c[cj - T->j_lo]);
+        return an;
+    }
+    return make_anchor<R>(A, ci, cj);
+}
+
 // Advances live particle p by one step in place.  Returns true when the move
 // is to be deposited (mv filled), false when the particle was or became
 // removed without a deposit.
-__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev) {
+__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+                                            const TileAnchors* T) {
     const int cell = A.cell[p];
     if (cell < 0) return false;
     ev.live = 1;
@@ -70,7 +96,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFl
     const double dt = A.dt;
     const double eps = massless ? 0.0 : 1.0;
     // one exp and one sincos per particle, at its start cell's corner
-    const Anchor<double> an = make_anchor<double>(A, ci, cj);
+    const Anchor<double> an = anchor_for<double>(A, ci, cj, T);
     double f0[5], f1[5], yt[5];
     {
         // metric and derivatives at x^n serve both the kick and the first RHS
@@ -142,8 +168,9 @@ __device__ __forceinline__ float cic_f32(const float* __restrict__ F, const Step
 // cell; y = (dxi, deta, phi, u_r, u_th) on return, u[2] = u_ph.
 template <class R>
 __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R dxr, R dxt, R eps, R qm,
-                                           bool massless, const R D[3], const R B[3], R u[3], R yt[5]) {
-    const Anchor<R> an = make_anchor<R>(A, ci, cj);
+                                           bool massless, const R D[3], const R B[3], R u[3], R yt[5],
+                                           const TileAnchors* T) {
+    const Anchor<R> an = anchor_for<R>(A, ci, cj, T);
     const R dt = R(A.dt);
     R f0[5], f1[5];
     {
@@ -174,7 +201,8 @@ __device__ __forceinline__ float offset_f32(double x) {
     return f < 1.0f ? f : 0.99999994f;
 }
 
-__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev) {
+__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+                                              const TileAnchors* T) {
     const int cell = A.cell[p];
     if (cell < 0) return false;
     ev.live = 1;
@@ -204,12 +232,12 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
     if (fp64) {
         const double D[3] = {Df[0], Df[1], Df[2]}, B[3] = {Bf[0], Bf[1], Bf[2]};
         double u[3] = {ur[p], uth[p], uph[p]};
-        split_core<double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y);
+        split_core<double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y, T);
         uph1 = u[2];
     } else {
         float u[3] = {ur[p], uth[p], uph[p]};
         float yf[5];
-        split_core<float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf);
+        split_core<float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf, T);
         for (int c = 0; c < 5; ++c) y[c] = yf[c];
         uph1 = u[2];
     }
@@ -247,9 +275,10 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
 }
 
 template <bool SPLIT>
-__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev) {
-    if constexpr (SPLIT) return advance_split(A, p, mv, ev);
-    else return advance_f64(A, p, mv, ev);
+__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+                                        const TileAnchors* T = nullptr) {
+    if constexpr (SPLIT) return advance_split(A, p, mv, ev, T);
+    else return advance_f64(A, p, mv, ev, T);
 }
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const MoveFlux& mv) {
@@ -261,30 +290,39 @@ __device__ __forceinline__ void scatter_global(const StepArgs& A, const MoveFlux
         for (int b = 0; b < 3; ++b) atomicAdd(A.Gph + grid_index(A, mv.i0 + a, mv.j0 + b), mv.Gp[a][b]);
 }
 
-// Adds the wave's event counts to the global counters (all lanes of the wave
-// must call it).
-__device__ __forceinline__ void count_events(const StepArgs& A, const Events& ev) {
-    if (!A.counters) return;
-    const unsigned long long bl = __ballot(ev.live), bo = __ballot(ev.out);
-    const unsigned long long bb = __ballot(ev.bad), br = __ballot(ev.refl), bs = __ballot(ev.spill);
-    if ((threadIdx.x & 63) == 0) {
-        if (bo) atomicAdd(A.counters + 0, (unsigned long long)__popcll(bo));
-        if (bb) atomicAdd(A.counters + 1, (unsigned long long)__popcll(bb));
-        if (br) atomicAdd(A.counters + 2, (unsigned long long)__popcll(br));
-        if (bl) atomicAdd(A.counters + 3, (unsigned long long)__popcll(bl));
-        if (bs) atomicAdd(A.counters + 4, (unsigned long long)__popcll(bs));
-    }
+// Event counts of a workgroup: each wave adds its ballot counts to five LDS
+// words (cnt, zeroed before the first barrier); after a later barrier one
+// thread adds the non-zero totals to the global counters, so the counters
+// see one atomic per workgroup instead of one per wave.
+__device__ __forceinline__ void wave_events_to_lds(const Events& ev, int* cnt) {
+    const unsigned long long b[5] = {__ballot(ev.out), __ballot(ev.bad), __ballot(ev.refl), __ballot(ev.live),
+                                     __ballot(ev.spill)};
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 5; ++k)
+            if (b[k]) atomicAdd(cnt + k, __popcll(b[k]));
+}
+
+__device__ __forceinline__ void workgroup_events_to_global(const StepArgs& A, const int* cnt) {
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k)
+            if (cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
 }
 
 template <bool SPLIT>
 __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
+    __shared__ int cnt[5];
+    if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         MoveFlux mv;
         if (advance<SPLIT>(A, p, mv, ev)) scatter_global(A, mv);
     }
-    count_events(A, ev);
+    if (!A.counters) return;                                 // uniform
+    __syncthreads();
+    wave_events_to_lds(ev, cnt);
+    __syncthreads();
+    workgroup_events_to_global(A, cnt);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) { push_deposit_body<false>(A); }
@@ -294,6 +332,8 @@ template <bool SPLIT>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
                                                         const Slice* __restrict__ slices, int64_t slice_cap) {
     __shared__ double win[3][kWinRows][kWinCols];
+    __shared__ TileAnchors tab;
+    __shared__ int cnt[5];
     // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of slices so neighbouring tiles share its L2.
     const int64_t nslices = hdr->nslices;
@@ -312,6 +352,21 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
 
     double* wflat = &win[0][0][0];
     for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols; e += kPushThreads) wflat[e] = 0.0;
+    if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+    if (A.small_steps) {
+        if (threadIdx.x == 0) {
+            tab.ti = ti;
+            tab.j_lo = j_lo;
+        }
+        const int k = (int)threadIdx.x - 64;                 // the second wave fills the table
+        if (k >= 0 && k <= kTileCells) {
+            double r, sn, cs;
+            anchor_values(A, ti, j_lo + k, r, sn, cs);
+            tab.s[k] = sn;
+            tab.c[k] = cs;
+            if (k == 0) tab.r = r;
+        }
+    }
     __syncthreads();
 
     Events ev = {0, 0, 0, 0, 0};
@@ -323,7 +378,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int64_t p = sl.start + slot;
     if (slot < sl.len && p < A.n) {
         MoveFlux mv;
-        if (advance<SPLIT>(A, p, mv, ev)) {
+        if (advance<SPLIT>(A, p, mv, ev, &tab)) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 for (int a = 0; a < 2; ++a)
@@ -338,6 +393,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             }
         }
     }
+    if (A.counters) wave_events_to_lds(ev, cnt);
     __syncthreads();
     // flush the window's non-zero entries that lie inside the grid arrays
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
@@ -353,7 +409,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             if (v != 0.0) atomicAdd(J[a] + g, v);
         }
     }
-    count_events(A, ev);
+    if (A.counters) workgroup_events_to_global(A, cnt);
 }
 
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(const StepArgs A, const TilingHeader* hdr,

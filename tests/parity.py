@@ -155,14 +155,18 @@ def compare_current(Jg, Jo, Ao, tol, Jp=None):
     return worst, bad
 
 
-def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, ncorr=3, tiled=False):
+def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, ncorr=3, tiled=False,
+                  max_ill_fraction=1e-3):
+    """max_ill_fraction bounds the share of ill-conditioned particles, a
+    property of the oracle runs alone (0.1 % for representative workloads;
+    stress tests that place every particle at the axis set their own)."""
     pg, Jg, cg = gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, tiled=tiled)
     po, Jo, Ao, so, pert = oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr)
     e = compare_particles(grid, pg, po, tol, pert)
     assert e["status_mismatch"] == 0, e
     assert e["violations"] == 0, e
     assert e["well_conditioned_err"] <= tol, e
-    assert e["ill_conditioned"] <= max(2, 1e-3 * e["n"]), e
+    assert e["ill_conditioned"] <= max(2, max_ill_fraction * e["n"]), e
     e["J"], e["J_violations"] = compare_current(Jg, Jo, Ao, tol, pert[1])
     assert e["J"] <= tol and e["J_violations"] == 0, e
     slack = e["ill_conditioned"]      # an ill-conditioned particle may reflect or leave in one run only

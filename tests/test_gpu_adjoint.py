@@ -5,9 +5,12 @@ against central finite differences of the GPU forward.
 Workload: adjoint_cases.py (K = 32 steps, checkpoints every 8).
 
 * d L / d u_i(0), particle by particle, against the oracle's dual-number
-  derivative: |g_gpu - g_orc| <= 1e-9 |g_orc|_vec + 64 s_p, s_p being the
-  change of the oracle's derivative when the particle's momenta move by 4 ulps
-  (the derivative's own rounding sensitivity; ~0 for almost all particles).
+  derivative: |g_gpu - g_orc| <= 1e-9 |g_orc|_vec + 1e-13 max_p |g_orc|_vec
+  + 64 s_p, s_p being the change of the oracle's derivative when the
+  particle's momenta move by 4 ulps.  The derivative is a sum over steps of
+  deposit terms that largely cancel (charge crossing the shell and coming
+  back), so s_p is that sum's rounding noise; the absolute term covers
+  derivatives that are zero in exact arithmetic and come out as ~1e-17.
 * d L / d(fields) contracted with random directions against the oracle's
   dual-number directional derivative (relative 1e-9).
 * The same contractions and d L / d u along random directions against central
@@ -122,9 +125,11 @@ def test_momentum_gradient_matches_oracle_dual(case):
     sens = np.abs(oracle_grad_u(case, pert) - ref).max(axis=1)
     err = np.abs(case["gu"] - ref).max(axis=1)
     scale = np.abs(ref).max(axis=1)
-    bad = np.flatnonzero(err > 1e-9 * scale + 64 * sens)
-    _announce(f"adjoint grad_u: max rel err {float((err / np.maximum(scale, 1e-300)).max()):.3e}, "
-              f"nonzero {int((scale > 0).sum())}, ill-conditioned {int((sens > 1e-9 * scale).sum())}")
+    bar = 1e-9 * scale + 1e-13 * scale.max() + 64 * sens
+    bad = np.flatnonzero(err > bar)
+    _announce(f"adjoint grad_u: max |g| {scale.max():.3e}, max err/bar {float((err / bar).max()):.3e}, "
+              f"max rel err {float((err / np.maximum(scale, 1e-12 * scale.max())).max()):.3e}, "
+              f"nonzero {int((scale > 0).sum())}, rounding-limited {int((sens > 1e-9 * scale).sum())}")
     assert (scale > 0).sum() >= 100
     assert bad.size == 0, [(int(p), case["gu"][p].tolist(), ref[p].tolist()) for p in bad[:5]]
 

@@ -82,8 +82,10 @@ def test_parity_axis_and_edges(tiled):
     ur, uth, uph = wl.frame_to_covariant(g.a, g.M, r, th, uh)
     parts = dict(cell=(i * g.nth + j).astype(np.int32), xr=rng.uniform(0, 1, n), xth=rng.uniform(0, 1, n),
                  ur=ur, uth=uth, uph=uph, w=rng.uniform(0.5, 2.0, n), sp=rng.integers(0, 2, n).astype(np.uint8))
+    # every particle starts within two cells of an axis and is driven into it: the
+    # centrifugal terms make more of them ill-conditioned than in a bulk workload
     e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=2.0), wl.crossing_dt(g), 6, TOL,
-                         tiled=tiled)
+                         tiled=tiled, max_ill_fraction=1e-2)
     assert c["reflected"] > 20 and c["out"] > 100
 
 

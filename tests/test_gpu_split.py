@@ -9,16 +9,21 @@ fields):
 
 * momentum: max over particles of max_i |d u_i| sqrt(gamma^ii)/sqrt(1+u^2) <= 1e-5,
   median reported;
-* Killing energy E = -u_0 - (q/m) A_0 (eq. ptc_energy): per particle
-  |dE_split - dE_oracle| <= 1e-5 max(1, |E|), the paper's own long-term
-  interpolation error level (Sec. 3.1);
+* Killing energy E = -u_0 - (q/m) A_0 (eq. ptc_energy), evaluated as
+  alpha sqrt(1 + u^2) - beta^r u_r - (q/m) A_t: per particle
+  |dE_split - dE_oracle| <= 1e-5 S_E, the paper's own long-term
+  interpolation error level (Sec. 3.1), S_E = max(1, sum of the three terms'
+  magnitudes) (close to the horizon the terms are large and cancel, and a
+  float rounding of u_r moves E by ~1e-7 of them);
 * discrete continuity per vertex <= 64 eps sum|q w| (FP64 deposit on exact
   end points).
 
-As in the FP64 parity tests, a particle whose oracle result moves by more
-than the stated error under a float-sized (2^-24) perturbation of its initial
-state is ill-conditioned; those are counted (<= 0.1 %) and held to 64 times
-their own sensitivity instead.
+Conditioning, as in the FP64 parity tests: s_p is how far the oracle's
+result moves when the initial state is moved by one float rounding (2^-24).
+The split path rounds the state to float at every step, so its error is a
+few times s_p; a particle with s_p above 1/8 of the stated error is
+ill-conditioned.  Those are counted (<= 0.1 %); every particle, ill-conditioned
+or not, must be within the stated error plus 64 s_p.
 """
 import numpy as np
 import pytest
@@ -61,6 +66,9 @@ def _float_perturbed(parts, seed=7):
 
 
 def killing_energy(grid, parts, B0):
+    """E = alpha sqrt(1 + u^2) - beta^r u_r - (q/m) A_t per particle and the sum
+    of the three terms' magnitudes, the scale its rounding is measured against
+    (near the horizon the terms are large and cancel)."""
     xi, eta = positions(grid, parts)
     r, th = grid.r(xi), grid.theta(eta)
     k = wl._ks_pieces(grid.a, grid.M, r, th)
@@ -69,7 +77,8 @@ def killing_energy(grid, parts, B0):
         uu = k["h_rr"] * u[0] ** 2 + 2 * k["h_rp"] * u[0] * u[2] + k["h_tt"] * u[1] ** 2 + k["h_pp"] * u[2] ** 2
         qm = np.where(parts["sp"] == 0, -1.0, 1.0)
         At = wl.wald_point(grid.a, grid.M, B0, r, th)["At"]
-        return k["alpha"] * np.sqrt(1 + uu) - k["beta"] * u[0] - qm * At
+        terms = (k["alpha"] * np.sqrt(1 + uu), -k["beta"] * u[0], -qm * At)
+        return terms[0] + terms[1] + terms[2], np.abs(terms[0]) + np.abs(terms[1]) + np.abs(terms[2])
 
 
 def split_report(grid, parts, nsteps, B0=1.0, tiled=False):
@@ -84,13 +93,15 @@ def split_report(grid, parts, nsteps, B0=1.0, tiled=False):
     live = (pg["cell"] >= 0) & (po["cell"] >= 0)
     err = particle_errors(grid, pg, po)
     sens = particle_errors(grid, pp, po)
-    E0 = killing_energy(grid, p0, B0)
-    dEg = killing_energy(grid, pg, B0) - E0
-    dEo = killing_energy(grid, po, B0) - E0
-    dEp = killing_energy(grid, pp, B0) - killing_energy(grid, _float_perturbed(p0), B0)
-    e_err = np.where(live, np.abs(dEg - dEo) / np.maximum(1.0, np.abs(E0)), 0.0)
-    e_sens = np.where(live, np.abs(dEp - dEo) / np.maximum(1.0, np.abs(E0)), 0.0)
-    ill = (sens > MOM_TOL) | (e_sens > ENERGY_TOL)
+    E0, scale0 = killing_energy(grid, p0, B0)
+    dEg = killing_energy(grid, pg, B0)[0] - E0
+    Eo, scale1 = killing_energy(grid, po, B0)
+    dEo = Eo - E0
+    dEp = killing_energy(grid, pp, B0)[0] - killing_energy(grid, _float_perturbed(p0), B0)[0]
+    scale = np.maximum(np.maximum(scale0, scale1), 1.0)
+    e_err = np.where(live, np.abs(dEg - dEo) / scale, 0.0)
+    e_sens = np.where(live, np.abs(dEp - dEo) / scale, 0.0)
+    ill = (sens > MOM_TOL / 8) | (e_sens > ENERGY_TOL / 8)
     good = live & ~ill
     return dict(
         n=len(err), n_live=int(live.sum()), ill_conditioned=int((ill & live).sum()),
