@@ -166,7 +166,7 @@ def run_adjoint(args):
     lam = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     lam[0][g.guard + face, :] = dt
     ck = torch.empty(grpic.grpic_checkpoint_bytes(n, K, C), dtype=torch.uint8, device="cuda")
-    ws = torch.empty(grpic.grpic_backward_workspace_bytes(n, C), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(grpic.grpic_backward_workspace_bytes(g, n, C), dtype=torch.uint8, device="cuda")
     gu = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
     gF = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
     J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
@@ -186,19 +186,25 @@ def run_adjoint(args):
                                                       tiling=sorter.tiling, ckpt=ck if with_ckpt else None,
                                                       ckpt_every=C if with_ckpt else 0))
 
-    def bwd():
-        return timed(lambda: grpic.grpic_push_deposit_backward(metric, g, sp, start, F, lam, dt, K, args.ncorr, ck,
+    # a dense cotangent (every grid entry non-zero) for comparison: no step can be skipped
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    lam_dense = [torch.randn(g.shape, dtype=torch.float64, device="cuda", generator=gen) * dt for _ in range(3)]
+
+    def bwd(lm):
+        return timed(lambda: grpic.grpic_push_deposit_backward(metric, g, sp, start, F, lm, dt, K, args.ncorr, ck,
                                                                C, ws, gu, gF))
 
-    fwd(True), bwd()                       # warm-up
+    fwd(True), bwd(lam)                    # warm-up
     f_plain = [fwd(False) for _ in range(3)]
     f_ck = [fwd(True) for _ in range(3)]
-    b = [bwd() for _ in range(3)]
-    log(f"adjoint: fwd {f_plain} ms, fwd+ckpt {f_ck} ms, bwd {b} ms")
+    b = [bwd(lam) for _ in range(3)]
+    bd = [bwd(lam_dense) for _ in range(2)]
+    log(f"adjoint: fwd {f_plain} ms, fwd+ckpt {f_ck} ms, bwd {b} ms, bwd dense lambda {bd} ms")
     return {"workload": f"512x512, a=0.9, Wald B0=1, {n} particles (Maxwell-Juttner T=0.5), K={K} steps, "
                         f"checkpoints every {C}, loss = charge through r=5",
             "fwd_ms": min(f_plain), "fwd_ckpt_ms": min(f_ck), "bwd_ms": min(b),
-            "bwd_over_fwd": min(b) / min(f_ck)}
+            "bwd_over_fwd": min(b) / min(f_ck),
+            "dense_lambda_bwd_ms": min(bd), "dense_lambda_bwd_over_fwd": min(bd) / min(f_ck)}
 
 
 def run_cpu_baseline(args, grid):

@@ -189,12 +189,17 @@ typedef struct {
  * grpic_backward_workspace_bytes(n, ckpt_every) bytes.  Per particle, each
  * checkpoint segment is recomputed from its checkpoint and then reversed
  * step by step, the last step first; field gradients use FP64 atomics.
+ * While a particle's cotangent is zero, steps and whole segments whose
+ * deposits cannot reach a non-zero lambda entry are skipped (their
+ * contribution is exactly zero), so a loss supported on a few grid rows
+ * costs little for particles far from them.  ws also holds the lambda
+ * support tables, hence the grid argument of grpic_backward_workspace_bytes.
  * The derivative is that of the piecewise-smooth map: where a particle's
  * CIC weights or deposit window change (cell edges), the one-sided
  * derivative of the side the trajectory lies on is taken.
  */
 size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every);
-size_t grpic_backward_workspace_bytes(int64_t n, int ckpt_every);
+size_t grpic_backward_workspace_bytes(const grpic_grid* grid, int64_t n, int ckpt_every);
 int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
                                 const grpic_species* species, int nsp, const grpic_particles* parts,
                                 const grpic_fields* fields, const grpic_current* lambda,

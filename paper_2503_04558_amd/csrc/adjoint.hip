@@ -11,15 +11,14 @@
 //     first: replay the step into a tape and run its reverse
 //     (grpic_adjoint.hpp), carrying the state cotangent in registers and
 //     adding field cotangents to the gradient arrays with FP64 atomics.
-// d L / d u_i(0) is the state cotangent left after the first step.
-#include "grpic_adjoint.hpp"
-#include "grpic_launch.hpp"
+// d L / d u_i(0) is the state cotangent left after the first step.  A
+// prepass marks the rows and columns where lambda is non-zero; particles and
+// steps whose deposits cannot reach them while their cotangent is zero are
+// skipped (exactly: their contribution is zero).
+#include "grpic_backward.hpp"
 
 namespace grpic {
 
-// Checkpoint slot layout: cell (int32, padded to 8 bytes) then xr, xth, ur,
-// uth, uph (double), each n long.
-static inline __host__ __device__ size_t slot_cell_bytes(int64_t n) { return ((size_t)n * 4 + 7) / 8 * 8; }
 size_t checkpoint_slot_bytes(int64_t n) { return slot_cell_bytes(n) + (size_t)n * 5 * 8; }
 int adj_max_corr() { return adj::kMaxCorr; }
 
@@ -42,73 +41,72 @@ hipError_t launch_save_state(const StepArgs& A, void* slot, hipStream_t stream) 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- lambda support
+// Rows and columns (storage indices, guards included) holding a non-zero
+// lambda entry, as exclusive prefix counts, so that "is lambda zero on this
+// box" is two subtractions.  A conservative test: a box is reported non-zero
+// when some row and some column in its ranges hold non-zeros.
+__global__ __launch_bounds__(256) void lam_row_any(const BackArgs B, int* __restrict__ row_flag) {
+    const int i = blockIdx.x;
+    int any = 0;
+    const int64_t base = (int64_t)i * B.pitch;
+    for (int j = threadIdx.x; j < B.pitch; j += blockDim.x)
+        any |= (B.lam[0][base + j] != 0.0) | (B.lam[1][base + j] != 0.0) | (B.lam[2][base + j] != 0.0);
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) row_flag[i] = any;
+}
+
+__global__ __launch_bounds__(256) void lam_col_any(const BackArgs B, int* __restrict__ col_flag) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= B.pitch) return;
+    int any = 0;
+    for (int i = 0; i < B.rows; ++i) {
+        const int64_t e = (int64_t)i * B.pitch + j;
+        any |= (B.lam[0][e] != 0.0) | (B.lam[1][e] != 0.0) | (B.lam[2][e] != 0.0);
+    }
+    col_flag[j] = any;
+}
+
+// flag[0..len) -> pre[0..len]; one thread per array (rows: thread 0, columns: thread 64).
+__global__ __launch_bounds__(128) void lam_prefix(const BackArgs B, const int* __restrict__ row_flag,
+                                                  const int* __restrict__ col_flag, int* __restrict__ row_pre,
+                                                  int* __restrict__ col_pre) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < B.rows; ++i) { row_pre[i] = acc; acc += row_flag[i]; }
+        row_pre[B.rows] = acc;
+    } else if (threadIdx.x == 64) {
+        int acc = 0;
+        for (int j = 0; j < B.pitch; ++j) { col_pre[j] = acc; acc += col_flag[j]; }
+        col_pre[B.pitch] = acc;
+    }
+}
+
+template <int NC>
 __global__ __launch_bounds__(256) void push_deposit_backward_f64(const BackArgs B) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= B.n) return;
-    const int64_t n = B.n;
-    const adj::Geo G{B.a, B.M, B.lnr0, B.dlnr, B.dth, B.nr, B.nth, B.guard, B.pitch};
-    const int s = B.sp[p];
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (s < B.nsp) {
-        const bool massless = B.massless[s] != 0;
-        const double qm = massless ? 0.0 : B.q[s] / B.m[s];
-        const double qw = B.q[s] * B.w[p];
-        const int C = B.ckpt_every;
-        const int nseg = B.nsteps / C;
-        double* ws = B.ws;                                       // [m][component][particle]
-        for (int seg = nseg - 1; seg >= 0; --seg) {
-            const char* slot = static_cast<const char*>(B.ckpt) + (size_t)seg * B.slot_bytes;
-            const int32_t cell = reinterpret_cast<const int32_t*>(slot)[p];
-            const double* sd = reinterpret_cast<const double*>(slot + slot_cell_bytes(n));
-            bool alive = cell >= 0 && cell < B.nr * B.nth;
-            double xi = 0.0, eta = 0.0, u[3] = {0.0, 0.0, 0.0};
-            if (alive) {
-                const double xr = sd[p], xth = sd[n + p];
-                alive = xr >= 0.0 && xr <= 1.0 && xth >= 0.0 && xth <= 1.0;
-                xi = (double)(cell / B.nth) + xr;
-                eta = (double)(cell % B.nth) + xth;
-                u[0] = sd[2 * n + p];
-                u[1] = sd[3 * n + p];
-                u[2] = sd[4 * n + p];
-            }
-            // start-of-step states of the segment (xi = NaN marks a removed particle)
-            for (int m = 0; m < C; ++m) {
-                double* w = ws + (size_t)m * 5 * n;
-                w[p] = alive ? xi : NAN;
-                w[n + p] = eta;
-                w[2 * n + p] = u[0];
-                w[3 * n + p] = u[1];
-                w[4 * n + p] = u[2];
-                if (!alive) continue;
-                adj::StepTape T;
-                const int st = adj::replay_step(G, B.F, qm, massless, B.dt, B.ncorr, xi, eta, u, T);
-                if (st != adj::ST_ALIVE) { alive = false; continue; }
-                xi = T.xi1;
-                eta = T.eta1;
-                u[0] = T.y[3];
-                u[1] = T.refl ? -T.y[4] : T.y[4];
-                u[2] = T.up[2];
-            }
-            for (int m = C - 1; m >= 0; --m) {
-                const double* w = ws + (size_t)m * 5 * n;
-                const double x0 = w[p];
-                if (isnan(x0)) continue;
-                const double u0[3] = {w[2 * n + p], w[3 * n + p], w[4 * n + p]};
-                adj::StepTape T;
-                adj::replay_step(G, B.F, qm, massless, B.dt, B.ncorr, x0, w[n + p], u0, T);
-                adj::reverse_step(G, B.F, B.lam, qm, massless, qw, B.dt, B.ncorr, T, a,
-                                  [&](int c, long e, double v) { atomicAdd(B.gradF[c] + e, v); });
-            }
-        }
-    }
-    B.grad_u[0][p] = a[2];
-    B.grad_u[1][p] = a[3];
-    B.grad_u[2][p] = a[4];
+    backward_particle<NC>(B, p, [&](int c, long e, double v) { atomicAdd(B.gradF[c] + e, v); });
 }
 
-hipError_t launch_push_deposit_backward(const BackArgs& B, hipStream_t stream) {
+size_t backward_aux_bytes(int rows, int pitch) {
+    return (size_t)(2 * rows + 2 * pitch + 2) * sizeof(int);
+}
+
+hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t stream) {
     if (B.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(push_deposit_backward_f64, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, stream, B);
+    int* row_flag = static_cast<int*>(aux);
+    int* col_flag = row_flag + B.rows;
+    int* row_pre = col_flag + B.pitch;
+    int* col_pre = row_pre + B.rows + 1;
+    B.row_pre = row_pre;
+    B.col_pre = col_pre;
+    hipLaunchKernelGGL(lam_row_any, dim3((unsigned)B.rows), dim3(256), 0, stream, B, row_flag);
+    hipLaunchKernelGGL(lam_col_any, dim3((unsigned)((B.pitch + 255) / 256)), dim3(256), 0, stream, B, col_flag);
+    hipLaunchKernelGGL(lam_prefix, dim3(1), dim3(128), 0, stream, B, row_flag, col_flag, row_pre, col_pre);
+    const dim3 grid((unsigned)((B.n + 255) / 256));
+    if (B.ncorr == kFastCorr) hipLaunchKernelGGL(push_deposit_backward_f64<kFastCorr>, grid, dim3(256), 0, stream, B);
+    else hipLaunchKernelGGL(push_deposit_backward_f64<adj::kMaxCorr>, grid, dim3(256), 0, stream, B);
     return hipGetLastError();
 }
 

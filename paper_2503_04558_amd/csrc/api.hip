@@ -228,9 +228,13 @@ size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every) {
     return (size_t)(nsteps / ckpt_every) * grpic::checkpoint_slot_bytes(n);
 }
 
-size_t grpic_backward_workspace_bytes(int64_t n, int ckpt_every) {
-    if (n < 0 || ckpt_every < 1) return 0;
-    return (size_t)ckpt_every * 5 * sizeof(double) * (size_t)n;
+static size_t backward_state_bytes(int64_t n, int ckpt_every) {
+    return ((size_t)ckpt_every * 5 * sizeof(double) * (size_t)n + 255) / 256 * 256;
+}
+
+size_t grpic_backward_workspace_bytes(const grpic_grid* grid, int64_t n, int ckpt_every) {
+    if (!grid || grid->nr <= 0 || grid->guard < 0 || grid->pitch <= 0 || n < 0 || ckpt_every < 1) return 0;
+    return backward_state_bytes(n, ckpt_every) + grpic::backward_aux_bytes(grid->nr + 1 + 2 * grid->guard, grid->pitch);
 }
 
 int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
@@ -262,9 +266,9 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
         return fail(GRPIC_EINVAL, "need nsteps >= 1 and ckpt_every >= 1 dividing nsteps");
     if ((parts->n > 0 && !ckpt) || ckpt_bytes < grpic_checkpoint_bytes(parts->n, nsteps, ckpt_every))
         return fail(GRPIC_ENOMEM, "checkpoint buffer too small or NULL");
-    if ((parts->n > 0 && !ws) || ws_bytes < grpic_backward_workspace_bytes(parts->n, ckpt_every))
+    if ((parts->n > 0 && !ws) || ws_bytes < grpic_backward_workspace_bytes(grid, parts->n, ckpt_every))
         return fail(GRPIC_ENOMEM, "backward workspace needs %zu bytes, got %zu",
-                    grpic_backward_workspace_bytes(parts->n, ckpt_every), ws_bytes);
+                    grpic_backward_workspace_bytes(grid, parts->n, ckpt_every), ws_bytes);
     const double tc = crossing_time_cached(metric, grid);
     if (dt > tc * (1.0 + 1e-12))
         return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
@@ -289,8 +293,10 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
     B.ckpt = ckpt;
     B.slot_bytes = grpic::checkpoint_slot_bytes(parts->n);
     B.ws = static_cast<double*>(ws);
+    B.rows = grid->nr + 1 + 2 * grid->guard;
+    void* aux = static_cast<char*>(ws) + backward_state_bytes(parts->n, ckpt_every);
     B.grad_u[0] = grad_u->ur; B.grad_u[1] = grad_u->uth; B.grad_u[2] = grad_u->uph;
-    return hip_status(grpic::launch_push_deposit_backward(B, static_cast<hipStream_t>(stream)), "backward launch");
+    return hip_status(grpic::launch_push_deposit_backward(B, aux, static_cast<hipStream_t>(stream)), "backward launch");
 }
 
 int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,

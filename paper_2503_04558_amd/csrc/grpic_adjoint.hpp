@@ -35,8 +35,9 @@ __host__ __device__ inline Dual2 operator*(Dual2 a, Dual2 b) {
     return {a.v * b.v, a.r * b.v + a.v * b.r, a.t * b.v + a.v * b.t};
 }
 __host__ __device__ inline Dual2 operator/(Dual2 a, Dual2 b) {
-    const double q = a.v / b.v;
-    return {q, (a.r - q * b.r) / b.v, (a.t - q * b.t) / b.v};
+    const double ib = 1.0 / b.v;
+    const double q = a.v * ib;
+    return {q, (a.r - q * b.r) * ib, (a.t - q * b.t) * ib};
 }
 __host__ __device__ inline Dual2 operator+(double a, Dual2 b) { return {a + b.v, b.r, b.t}; }
 __host__ __device__ inline Dual2 operator+(Dual2 a, double b) { return {a.v + b, a.r, a.t}; }
@@ -45,12 +46,14 @@ __host__ __device__ inline Dual2 operator-(Dual2 a, double b) { return {a.v - b,
 __host__ __device__ inline Dual2 operator*(double a, Dual2 b) { return {a * b.v, a * b.r, a * b.t}; }
 __host__ __device__ inline Dual2 operator*(Dual2 a, double b) { return {a.v * b, a.r * b, a.t * b}; }
 __host__ __device__ inline Dual2 operator/(double a, Dual2 b) {
-    const double q = a / b.v;
-    return {q, -q * b.r / b.v, -q * b.t / b.v};
+    const double ib = 1.0 / b.v;
+    const double q = a * ib;
+    return {q, -q * b.r * ib, -q * b.t * ib};
 }
 __host__ __device__ inline Dual2 sqrt(Dual2 a) {
     const double s = ::sqrt(a.v);
-    return {s, a.r / (2.0 * s), a.t / (2.0 * s)};
+    const double h = 0.5 / s;
+    return {s, a.r * h, a.t * h};
 }
 using ::sqrt;          // the double overload stays visible next to the Dual2 one
 
@@ -62,54 +65,68 @@ enum {
     M_N
 };
 
-template <class T>
-__host__ __device__ inline void metric(double a, double M, T r, T s, T c, T m[M_N]) {
+// The quantities are handed to out(index, value) as they are formed, so a
+// caller can contract their derivatives without storing them all.
+template <class T, class Out>
+__host__ __device__ inline void metric_emit(double a, double M, T r, T s, T c, Out&& out) {
     const double a2 = a * a;
     const T r2 = r * r, s2 = s * s, sc = s * c;
     const T rho2 = r2 + a2 * (c * c);
-    const T z = 2.0 * M * r / rho2;
+    const T irho2 = 1.0 / rho2;
+    const T z = 2.0 * M * r * irho2;
     const T opz = 1.0 + z;
     const T sq = sqrt(opz);
+    const T iopz = 1.0 / opz;
+    const T is2 = 1.0 / s2;
     const T ra2 = r2 + a2;
     const T Delta = ra2 - 2.0 * M * r;
     const T Sigma = ra2 * ra2 - a2 * Delta * s2;
-    m[M_IALPHA] = sq;
-    m[M_ALPHA] = 1.0 / sq;
-    m[M_BETA] = z / opz;
-    m[M_GRR] = opz;
-    m[M_GRP] = -a * s2 * opz;
-    m[M_GTT] = rho2;
-    m[M_GPP] = Sigma * s2 / rho2;
-    m[M_HRR] = ra2 / rho2 - m[M_BETA];
-    m[M_HRP] = a / rho2;
-    m[M_HTT] = 1.0 / rho2;
-    m[M_HPP] = 1.0 / (rho2 * s2);
-    m[M_SQRTG] = rho2 * s * sq;
-    const T rho4 = rho2 * rho2;
+    const T alpha = sq * iopz;
+    const T beta = z * iopz;
+    out(M_IALPHA, sq);
+    out(M_ALPHA, alpha);
+    out(M_BETA, beta);
+    out(M_GRR, opz);
+    out(M_GRP, -a * s2 * opz);
+    out(M_GTT, rho2);
+    out(M_GPP, Sigma * s2 * irho2);
+    out(M_HRR, ra2 * irho2 - beta);
+    out(M_HRP, a * irho2);
+    out(M_HTT, irho2);
+    out(M_HPP, irho2 * is2);
+    out(M_SQRTG, rho2 * s * sq);
+    const T irho4 = irho2 * irho2;
     const T dr_rho2 = 2.0 * r;
     const T dt_rho2 = -2.0 * a2 * sc;
-    const T dz_r = 2.0 * M * (rho2 - 2.0 * r2) / rho4;
-    const T dz_t = 4.0 * M * a2 * r * sc / rho4;
-    const T al3 = m[M_ALPHA] / opz;
-    const T al4 = 1.0 / (opz * opz);
-    m[M_DAL0] = -0.5 * al3 * dz_r;
-    m[M_DAL1] = -0.5 * al3 * dz_t;
-    m[M_DBE0] = al4 * dz_r;
-    m[M_DBE1] = al4 * dz_t;
-    m[M_DHRP0] = -a * dr_rho2 / rho4;
-    m[M_DHRP1] = -a * dt_rho2 / rho4;
-    m[M_DHTT0] = -dr_rho2 / rho4;
-    m[M_DHTT1] = -dt_rho2 / rho4;
-    m[M_DHRR0] = -2.0 * r * a2 * s2 / rho4 - m[M_DBE0];
-    m[M_DHRR1] = 2.0 * a2 * ra2 * sc / rho4 - m[M_DBE1];
-    m[M_DHPP0] = -2.0 * r / (rho4 * s2);
-    m[M_DHPP1] = -(dt_rho2 * s2 + 2.0 * rho2 * sc) / (rho4 * s2 * s2);
+    const T dz_r = 2.0 * M * (rho2 - 2.0 * r2) * irho4;
+    const T dz_t = 4.0 * M * a2 * r * sc * irho4;
+    const T al3 = alpha * iopz;
+    const T al4 = iopz * iopz;
+    out(M_DAL0, -0.5 * al3 * dz_r);
+    out(M_DAL1, -0.5 * al3 * dz_t);
+    const T dbe0 = al4 * dz_r, dbe1 = al4 * dz_t;
+    out(M_DBE0, dbe0);
+    out(M_DBE1, dbe1);
+    out(M_DHRP0, -a * dr_rho2 * irho4);
+    out(M_DHRP1, -a * dt_rho2 * irho4);
+    out(M_DHTT0, -dr_rho2 * irho4);
+    out(M_DHTT1, -dt_rho2 * irho4);
+    out(M_DHRR0, -2.0 * r * a2 * s2 * irho4 - dbe0);
+    out(M_DHRR1, 2.0 * a2 * ra2 * sc * irho4 - dbe1);
+    out(M_DHPP0, -2.0 * r * irho4 * is2);
+    out(M_DHPP1, -(dt_rho2 * s2 + 2.0 * rho2 * sc) * irho4 * is2 * is2);
+}
+
+template <class T>
+__host__ __device__ inline void metric(double a, double M, T r, T s, T c, T m[M_N]) {
+    metric_emit<T>(a, M, r, s, c, [&](int i, const T& v) { m[i] = v; });
 }
 
 // Grid and metric constants of a step.
 struct Geo {
     double a, M, lnr0, dlnr, dth;
     int nr, nth, guard, pitch;
+    double idlnr, idth;                        // 1/dlnr, 1/dth
     __host__ __device__ long index(int i, int j) const { return (long)(i + guard) * pitch + (j + guard); }
 };
 
@@ -122,12 +139,21 @@ __host__ __device__ inline void metric_at(const Geo& G, double xi, double eta, d
     metric<double>(G.a, G.M, r, ::sin(th), ::cos(th), m);
 }
 
-// Metric values and their r and theta derivatives at (xi, eta).
-__host__ __device__ inline void metric_d2_at(const Geo& G, double xi, double eta, Dual2 m[M_N], double& r) {
-    r = point_r(G, xi);
+// Cotangents mb of the metric quantities at (xi, eta) -> cotangents of r and
+// theta: the quantities' r and theta derivatives (forward mode, Dual2)
+// contracted with mb as they are formed.
+__host__ __device__ inline void metric_vjp_at(const Geo& G, double xi, double eta, const double mb[M_N], double& rb,
+                                              double& thb) {
+    const double r = point_r(G, xi);
     const double th = eta * G.dth;
     const double s = ::sin(th), c = ::cos(th);
-    metric<Dual2>(G.a, G.M, Dual2{r, 1.0, 0.0}, Dual2{s, 0.0, c}, Dual2{c, 0.0, -s}, m);
+    double ar = 0.0, at = 0.0;
+    metric_emit<Dual2>(G.a, G.M, Dual2{r, 1.0, 0.0}, Dual2{s, 0.0, c}, Dual2{c, 0.0, -s}, [&](int i, const Dual2& v) {
+        ar += mb[i] * v.r;
+        at += mb[i] * v.t;
+    });
+    rb += ar;
+    thb += at;
 }
 
 // ---------------------------------------------------------------- RHS
@@ -137,13 +163,14 @@ __host__ __device__ inline void rhs(const Geo& G, double eps, const double m[M_N
                                     double up, double f[5]) {
     const double uu = m[M_HRR] * ur * ur + 2.0 * m[M_HRP] * ur * up + m[M_HTT] * ut * ut + m[M_HPP] * up * up;
     const double u0 = ::sqrt(eps + uu) * m[M_IALPHA];
-    f[0] = ((m[M_HRR] * ur + m[M_HRP] * up) / u0 - m[M_BETA]) / (r * G.dlnr);
-    f[1] = m[M_HTT] * ut / u0 / G.dth;
-    f[2] = (m[M_HRP] * ur + m[M_HPP] * up) / u0;
+    const double iu0 = 1.0 / u0;
+    f[0] = ((m[M_HRR] * ur + m[M_HRP] * up) * iu0 - m[M_BETA]) * (G.idlnr / r);
+    f[1] = m[M_HTT] * ut * iu0 * G.idth;
+    f[2] = (m[M_HRP] * ur + m[M_HPP] * up) * iu0;
     for (int q = 0; q < 2; ++q) {
         const double quad = ur * ur * m[M_DHRR0 + q] + 2.0 * ur * up * m[M_DHRP0 + q]
                           + ut * ut * m[M_DHTT0 + q] + up * up * m[M_DHPP0 + q];
-        f[3 + q] = -m[M_ALPHA] * u0 * m[M_DAL0 + q] + ur * m[M_DBE0 + q] - quad / (2.0 * u0);
+        f[3 + q] = -m[M_ALPHA] * u0 * m[M_DAL0 + q] + ur * m[M_DBE0 + q] - 0.5 * quad * iu0;
     }
 }
 
@@ -151,26 +178,25 @@ __host__ __device__ inline void rhs(const Geo& G, double eps, const double m[M_N
 // point (added to yb[0..1] = xi, eta and ub[0..2] = u_r, u_th, u_ph).
 __host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, double eta, double ur, double ut,
                                         double up, const double g[5], double yb[2], double ub[3]) {
-    Dual2 md[M_N];
-    double r;
-    metric_d2_at(G, xi, eta, md, r);
-    double m[M_N], mb[M_N];
-    for (int i = 0; i < M_N; ++i) { m[i] = md[i].v; mb[i] = 0.0; }
+    double m[M_N], mb[M_N], r;
+    metric_at(G, xi, eta, m, r);
+    for (int i = 0; i < M_N; ++i) mb[i] = 0.0;
     const double uu = m[M_HRR] * ur * ur + 2.0 * m[M_HRP] * ur * up + m[M_HTT] * ut * ut + m[M_HPP] * up * up;
     const double S = ::sqrt(eps + uu);
     const double u0 = S * m[M_IALPHA];
     const double iu0 = 1.0 / u0;
     const double ir = 1.0 / r;
+    const double iS = 1.0 / S;
     const double A1 = m[M_HRR] * ur + m[M_HRP] * up;
     const double B1 = m[M_HRP] * ur + m[M_HPP] * up;
     double urb = 0.0, utb = 0.0, upb = 0.0, rb = 0.0, iu0b = 0.0, u0b = 0.0;
     // f0 = (A1 iu0 - beta) ir / dlnr
     {
-        const double c = g[0] * ir / G.dlnr;
+        const double c = g[0] * ir * G.idlnr;
         const double A1b = c * iu0;
         iu0b += c * A1;
         mb[M_BETA] -= c;
-        rb -= g[0] * (A1 * iu0 - m[M_BETA]) * ir * ir / G.dlnr;
+        rb -= c * (A1 * iu0 - m[M_BETA]) * ir;
         mb[M_HRR] += A1b * ur;
         mb[M_HRP] += A1b * up;
         urb += A1b * m[M_HRR];
@@ -178,7 +204,7 @@ __host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, dou
     }
     // f1 = h_tt ut iu0 / dth
     {
-        const double c = g[1] / G.dth;
+        const double c = g[1] * G.idth;
         mb[M_HTT] += c * ut * iu0;
         utb += c * m[M_HTT] * iu0;
         iu0b += c * m[M_HTT] * ut;
@@ -216,7 +242,7 @@ __host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, dou
     u0b -= iu0b * iu0 * iu0;
     const double Sb = u0b * m[M_IALPHA];
     mb[M_IALPHA] += u0b * S;
-    const double uub = Sb / (2.0 * S);
+    const double uub = 0.5 * Sb * iS;
     mb[M_HRR] += uub * ur * ur;
     mb[M_HRP] += uub * 2.0 * ur * up;
     mb[M_HTT] += uub * ut * ut;
@@ -226,7 +252,7 @@ __host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, dou
     upb += uub * (2.0 * m[M_HRP] * ur + 2.0 * m[M_HPP] * up);
     // metric quantities -> r, theta -> xi, eta
     double thb = 0.0;
-    for (int i = 0; i < M_N; ++i) { rb += mb[i] * md[i].r; thb += mb[i] * md[i].t; }
+    metric_vjp_at(G, xi, eta, mb, rb, thb);
     yb[0] += rb * r * G.dlnr;
     yb[1] += thb * G.dth;
     ub[0] += urb;
@@ -279,7 +305,7 @@ __host__ __device__ inline void boris(const double m[M_N], double qm, double dt,
                     + m[M_HTT] * T.um[1] * T.um[1] + m[M_HPP] * T.um[2] * T.um[2];
     T.S = ::sqrt(1.0 + uu);
     T.u0b = T.S * m[M_IALPHA];
-    T.tf = qm * dt / (2.0 * T.u0b);
+    T.tf = 0.5 * qm * dt / T.u0b;
     for (int i = 0; i < 3; ++i) T.t[i] = T.tf * B[i];
     T.tt = m[M_GRR] * T.t[0] * T.t[0] + 2.0 * m[M_GRP] * T.t[0] * T.t[2]
          + m[M_GTT] * T.t[1] * T.t[1] + m[M_GPP] * T.t[2] * T.t[2];
@@ -327,7 +353,7 @@ __host__ __device__ inline void boris_vjp(const double m[M_N], double qm, double
     const double u0bb = -tfb * T.tf / T.u0b;
     const double Sb = u0bb * m[M_IALPHA];
     mb[M_IALPHA] += u0bb * T.S;
-    const double uub = Sb / (2.0 * T.S);
+    const double uub = 0.5 * Sb / T.S;
     mb[M_HRR] += uub * T.um[0] * T.um[0];
     mb[M_HRP] += uub * 2.0 * T.um[0] * T.um[2];
     mb[M_HTT] += uub * T.um[1] * T.um[1];
@@ -405,7 +431,9 @@ __host__ __device__ inline void deposit_vjp(const Geo& G, const LamT* lr, const 
         wy0[a] = shape_w(eta0 - (j0 + a)); dy0[a] = shape_dw(eta0 - (j0 + a));
         wy1[a] = shape_w(eta1 - (j0 + a)); dy1[a] = shape_dw(eta1 - (j0 + a));
     }
-    const double cf = -qw / dt, cp = qw * dphi / dt;
+    const double idt = 1.0 / dt;
+    const double cf = -qw * idt, cp = qw * dphi * idt;
+    const double c3 = cp * (1.0 / 3.0), c6 = cp * (1.0 / 6.0);
     double L_dphi = 0.0;
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b) {
@@ -414,19 +442,19 @@ __host__ __device__ inline void deposit_vjp(const Geo& G, const LamT* lr, const 
             for (int a2 = a; a2 < 2; ++a2) Lr += (double)lr[G.index(i0 + a2, j0 + b)];
             for (int b2 = b; b2 < 2; ++b2) Lt += (double)lt[G.index(i0 + a, j0 + b2)];
             const double lpab = (double)lp[G.index(i0 + a, j0 + b)];
-            const double C11 = 0.5 * cf * (Lr + Lt) + cp * lpab / 3.0;
-            const double C10 = 0.5 * cf * (Lr - Lt) + cp * lpab / 6.0;
-            const double C01 = 0.5 * cf * (-Lr + Lt) + cp * lpab / 6.0;
-            const double C00 = -0.5 * cf * (Lr + Lt) + cp * lpab / 3.0;
+            const double C11 = 0.5 * cf * (Lr + Lt) + c3 * lpab;
+            const double C10 = 0.5 * cf * (Lr - Lt) + c6 * lpab;
+            const double C01 = 0.5 * cf * (-Lr + Lt) + c6 * lpab;
+            const double C00 = -0.5 * cf * (Lr + Lt) + c3 * lpab;
             pb[0] += (C01 * wy1[b] + C00 * wy0[b]) * dx0[a];
             pb[1] += (C10 * wx1[a] + C00 * wx0[a]) * dy0[b];
             pb[2] += (C11 * wy1[b] + C10 * wy0[b]) * dx1[a];
             pb[3] += (C11 * wx1[a] + C01 * wx0[a]) * dy1[b];
-            L_dphi += lpab * (wx1[a] * wy1[b] / 3.0 + wx1[a] * wy0[b] / 6.0 + wx0[a] * wy1[b] / 6.0
-                              + wx0[a] * wy0[b] / 3.0);
+            L_dphi += lpab * ((wx1[a] * wy1[b] + wx0[a] * wy0[b]) * (1.0 / 3.0)
+                              + (wx1[a] * wy0[b] + wx0[a] * wy1[b]) * (1.0 / 6.0));
         }
     }
-    pb[4] += qw / dt * L_dphi;
+    pb[4] += qw * idt * L_dphi;
 }
 
 // ---------------------------------------------------------------- one step
@@ -436,11 +464,12 @@ enum { ST_ALIVE = 0, ST_OUT = 1, ST_BAD = 2 };
 __host__ __device__ inline double stag_r(int c) { return (c == 0 || c == 4 || c == 5) ? 0.5 : 0.0; }
 __host__ __device__ inline double stag_t(int c) { return (c == 1 || c == 3 || c == 5) ? 0.5 : 0.0; }
 
+template <int NC>                              // NC: bound on the corrector passes
 struct StepTape {
     double xi0, eta0, u[3];
     double D[3], B[3];
     double up[3];                              // momentum after the kick
-    double pts[kMaxCorr + 1][5];               // y0 and the corrector points f was evaluated at
+    double pts[NC + 1][5];                     // y0 and the corrector points f was evaluated at
     double y[5];                               // raw end of the predictor-corrector
     double xi1, eta1, dphi;                    // end point after reflection
     int refl, status;
@@ -448,10 +477,10 @@ struct StepTape {
 
 // Forward replay of one step from (xi0, eta0, u); fills the tape and returns
 // the status.  The same formulas as the plain reference (Sec. 2.2-2.3).
-template <class FieldT>
+template <int NC, class FieldT>
 __host__ __device__ inline int replay_step(const Geo& G, const FieldT* const F[6], double qm, bool massless,
                                            double dt, int ncorr, double xi0, double eta0, const double u[3],
-                                           StepTape& T) {
+                                           StepTape<NC>& T) {
     T.xi0 = xi0;
     T.eta0 = eta0;
     for (int c = 0; c < 3; ++c) T.u[c] = u[c];
@@ -499,10 +528,10 @@ __host__ __device__ inline int replay_step(const Geo& G, const FieldT* const F[6
 // the step (xi, eta, u_r, u_th, u_ph; zero if the particle did not survive
 // it) and on return the cotangent of the state before it.  Field
 // cotangents go to addF(component, element, value).
-template <class FieldT, class LamT, class AddF>
+template <int NC, class FieldT, class LamT, class AddF>
 __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F[6], const LamT* const lam[3],
                                              double qm, bool massless, double qw, double dt, int ncorr,
-                                             const StepTape& T, double a[5], AddF addF) {
+                                             const StepTape<NC>& T, double a[5], AddF addF) {
     if (T.status == ST_BAD) {
         for (int c = 0; c < 5; ++c) a[c] = 0.0;
         return;
@@ -554,17 +583,15 @@ __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F
     if (massless) {
         for (int c = 0; c < 3; ++c) ub[c] = upb[c];
     } else {
-        Dual2 md[M_N];
-        double r0;
-        metric_d2_at(G, T.xi0, T.eta0, md, r0);
-        double m0[M_N], mb[M_N];
-        for (int i = 0; i < M_N; ++i) { m0[i] = md[i].v; mb[i] = 0.0; }
+        double m0[M_N], mb[M_N], r0;
+        metric_at(G, T.xi0, T.eta0, m0, r0);
+        for (int i = 0; i < M_N; ++i) mb[i] = 0.0;
         BorisTape bt;
         double up[3];
         boris(m0, qm, dt, T.D, T.B, T.u, up, bt);
         boris_vjp(m0, qm, dt, T.D, T.B, bt, upb, ub, Db, Bb, mb);
         double rb = 0.0, thb = 0.0;
-        for (int i = 0; i < M_N; ++i) { rb += mb[i] * md[i].r; thb += mb[i] * md[i].t; }
+        metric_vjp_at(G, T.xi0, T.eta0, mb, rb, thb);
         xib += rb * r0 * G.dlnr;
         etab0 += thb * G.dth;
     }

@@ -92,12 +92,16 @@ struct BackArgs {
     double* ws;                       // ckpt_every * 5 * n doubles
     double* grad_u[3];                // out: dL/du_r, dL/du_th, dL/du_ph at step 0
     double* gradF[6];                 // += dL/dD^i, dL/dB^i
+    int rows;                         // storage rows of the grid arrays (nr + 1 + 2 guard)
+    const int* row_pre;               // lambda support, set by the launcher
+    const int* col_pre;
 };
 
 size_t checkpoint_slot_bytes(int64_t n);
 int adj_max_corr();
 hipError_t launch_save_state(const StepArgs& A, void* slot, hipStream_t stream);
-hipError_t launch_push_deposit_backward(const BackArgs& B, hipStream_t stream);
+size_t backward_aux_bytes(int rows, int pitch);
+hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t stream);
 
 int64_t sort_scan_blocks(int64_t len);
 size_t sort_workspace_bytes(int nr, int nth);

@@ -28,12 +28,35 @@ __global__ __launch_bounds__(256) void fill_u64(unsigned long long* __restrict__
     if (i < n) a[i] = v;
 }
 
+// Runs of equal valid cells among adjacent lanes of a wave: the first lane
+// of each run (head) and the run's last lane (tail).  Every lane of the
+// wave must call it.
+__device__ __forceinline__ void wave_runs(int c, bool valid, int& head, int& tail) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(c, 1);
+    const int next = __shfl_down(c, 1);
+    const unsigned long long heads = __ballot(valid && (lane == 0 || prev != c));
+    const unsigned long long tails = __ballot(valid && (lane == 63 || next != c));
+    head = 0;
+    tail = 0;
+    if (valid) {
+        const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+        head = 63 - __clzll(heads & upto);
+        const unsigned long long from = ~((1ull << head) - 1ull);
+        tail = __ffsll((long long)(tails & from)) - 1;
+    }
+}
+
+// Histogram of live cells; on (almost) sorted input a wave's lanes share a
+// few cells, so each run adds its length with one atomic.
 __global__ __launch_bounds__(256) void sort_hist(const int32_t* __restrict__ cell, int64_t n, int ncell,
                                                  unsigned long long* __restrict__ counts) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int c = cell[p];
-    if (c >= 0 && c < ncell) atomicAdd(counts + c, 1ull);
+    const int c = p < n ? cell[p] : -1;
+    const bool valid = c >= 0 && c < ncell;
+    int head, tail;
+    wave_runs(c, valid, head, tail);
+    if (valid && (int)(threadIdx.x & 63) == head) atomicAdd(counts + c, (unsigned long long)(tail - head + 1));
 }
 
 // Inclusive scan of one value per thread across a 256-thread block.
@@ -173,17 +196,8 @@ __global__ __launch_bounds__(256) void sort_scatter(const SortArgs S) {
     const bool valid = c >= 0 && c < S.ncell;
     // runs of equal cells among adjacent lanes: one atomic per run
     const int lane = threadIdx.x & 63;
-    const int prev = __shfl_up(c, 1);
-    const int next = __shfl_down(c, 1);
-    const unsigned long long heads = __ballot(valid && (lane == 0 || prev != c));
-    const unsigned long long tails = __ballot(valid && (lane == 63 || next != c));
-    int head = 0, tail = 0;
-    if (valid) {
-        const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-        head = 63 - __clzll(heads & upto);
-        const unsigned long long from = ~((1ull << head) - 1ull);
-        tail = __ffsll((long long)(tails & from)) - 1;
-    }
+    int head, tail;
+    wave_runs(c, valid, head, tail);
     long long base = 0;
     if (valid && lane == head) base = (long long)atomicAdd(S.counts + c, (unsigned long long)(tail - head + 1));
     base = __shfl(base, head);          // every lane takes part

@@ -92,7 +92,7 @@ def lib():
         L.grpic_push_deposit_backward.restype = ctypes.c_int
         L.grpic_checkpoint_bytes.argtypes = [i64, i32, i32]
         L.grpic_checkpoint_bytes.restype = sz
-        L.grpic_backward_workspace_bytes.argtypes = [i64, i32]
+        L.grpic_backward_workspace_bytes.argtypes = [vp, i64, i32]
         L.grpic_backward_workspace_bytes.restype = sz
         L.grpic_push_deposit.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -229,8 +229,9 @@ def grpic_checkpoint_bytes(n: int, nsteps: int, ckpt_every: int) -> int:
     return int(lib().grpic_checkpoint_bytes(int(n), int(nsteps), int(ckpt_every)))
 
 
-def grpic_backward_workspace_bytes(n: int, ckpt_every: int) -> int:
-    return int(lib().grpic_backward_workspace_bytes(int(n), int(ckpt_every)))
+def grpic_backward_workspace_bytes(grid, n: int, ckpt_every: int) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_backward_workspace_bytes(ctypes.byref(g), int(n), int(ckpt_every)))
 
 
 def grpic_push_deposit_backward(metric: grpic_metric, grid, species, parts: dict, fields, lam, dt: float,

@@ -133,7 +133,8 @@ def test_checkpoint_and_backward_validation():
     g = wl.make_grid(32, 32, 0.9)
     assert grpic.grpic_checkpoint_bytes(1000, 32, 8) == 4 * (4000 + 5 * 8 * 1000)
     assert grpic.grpic_checkpoint_bytes(1000, 30, 8) == 0          # ckpt_every must divide nsteps
-    assert grpic.grpic_backward_workspace_bytes(1000, 8) == 8 * 5 * 8 * 1000
+    rows, pitch = g.nr + 1 + 2 * g.guard, g.pitch
+    assert grpic.grpic_backward_workspace_bytes(g, 1000, 8) == 320000 + 4 * (2 * rows + 2 * pitch + 2)
     parts, fields, cur = _fake_args(g)
     L = grpic.lib()
     m, G, sp = grpic.make_metric(0.9, 1.0), grpic.make_grid(g), grpic.make_species(wl.species_table())
@@ -151,7 +152,7 @@ def test_checkpoint_and_backward_validation():
         gf.D[c] = 0x1000
         gf.B[c] = 0x1000
     ck = grpic.grpic_checkpoint_bytes(10, 32, 8)
-    ws = grpic.grpic_backward_workspace_bytes(10, 8)
+    ws = grpic.grpic_backward_workspace_bytes(g, 10, 8)
     args = [ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts), ctypes.byref(fields), ctypes.byref(cur),
             dt, 32, 3, 0x3000, ck, 8, 0x4000, ws, ctypes.byref(gu), ctypes.byref(gf), None]
     bad = list(args)

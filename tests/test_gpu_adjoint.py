@@ -57,7 +57,8 @@ def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, til
     start = {k: v.clone() for k, v in parts.items()}
     F = [torch.as_tensor(f).to("cuda") for f in fields_np]
     J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
-    ck = torch.empty(grpic.grpic_checkpoint_bytes(n, nsteps, ckpt_every), dtype=torch.uint8, device="cuda")
+    # buffers start as all-ones bytes (NaN as doubles): nothing may read what the call did not write
+    ck = torch.full((grpic.grpic_checkpoint_bytes(n, nsteps, ckpt_every),), 255, dtype=torch.uint8, device="cuda")
     grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, sp, parts, F, J, dt, nsteps, 3, tiling=tiling,
                              ckpt=ck, ckpt_every=ckpt_every)
     return start, F, J, ck, order
@@ -66,8 +67,8 @@ def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, til
 def backward(g, sp, start, F, lam_np, dt, ck, nsteps=K, ckpt_every=CKPT_EVERY):
     n = start["cell"].numel()
     lam = [torch.as_tensor(l).to("cuda") for l in lam_np]
-    ws = torch.empty(grpic.grpic_backward_workspace_bytes(n, ckpt_every), dtype=torch.uint8, device="cuda")
-    gu = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ws = torch.full((grpic.grpic_backward_workspace_bytes(g, n, ckpt_every),), 255, dtype=torch.uint8, device="cuda")
+    gu = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(3)]
     gF = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
     grpic.grpic_push_deposit_backward(grpic.make_metric(g.a, g.M), g, sp, start, F, lam, dt, nsteps, 3, ck,
                                       ckpt_every, ws, gu, gF)
@@ -130,12 +131,14 @@ def test_momentum_gradient_matches_oracle_dual(case):
     _announce(f"adjoint grad_u: max |g| {scale.max():.3e}, max err/bar {float((err / bar).max()):.3e}, "
               f"max rel err {float((err / np.maximum(scale, 1e-12 * scale.max())).max()):.3e}, "
               f"nonzero {int((scale > 0).sum())}, rounding-limited {int((sens > 1e-9 * scale).sum())}")
+    assert np.all(np.isfinite(case["gu"]))
     assert (scale > 0).sum() >= 100
     assert bad.size == 0, [(int(p), case["gu"][p].tolist(), ref[p].tolist()) for p in bad[:5]]
 
 
 def test_field_gradient_matches_oracle_dual(case):
     _announce("adjoint d L/d fields vs oracle dual numbers")
+    assert all(np.all(np.isfinite(a)) for a in case["gF"])
     rng = np.random.default_rng(5)
     for trial in range(4):
         tF = [rng.normal(size=case["g"].shape) * np.abs(f).max() for f in case["fields"]]
