@@ -88,10 +88,18 @@ def run_gpu(args, g, F, parts, precision):
         state["p"] = sorter.sort(state["p"])
 
     ev_push = []
+    ev_sort = []
 
     def step(k, timed):
         if k % args.sort_every == 0:
+            if timed:
+                s0 = torch.cuda.Event(enable_timing=True)
+                s1 = torch.cuda.Event(enable_timing=True)
+                s0.record()
             do_sort()
+            if timed:
+                s1.record()
+                ev_sort.append((s0, s1))
         if timed:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -118,6 +126,7 @@ def run_gpu(args, g, F, parts, precision):
     t_wall = time.time() - t_wall
     total_ms = start.elapsed_time(stop)
     push_ms = [a.elapsed_time(b) for a, b in ev_push]
+    sort_ms = [a.elapsed_time(b) for a, b in ev_sort]
     cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
     log(f"{'split' if precision else 'fp64'}: timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), "
         f"counters {cnt}")
@@ -133,7 +142,7 @@ def run_gpu(args, g, F, parts, precision):
     hbm_gbs = bytes_per_launch / (avg_push_ms * 1e-3) / 1e9
     flops_per_launch = live_per_launch * FP64_OPS_PER_PARTICLE_STEP
     tflops = flops_per_launch / (avg_push_ms * 1e-3) / 1e12
-    return dict(value=value, total_ms=total_ms, avg_push_ms=avg_push_ms, push_ms=push_ms, counters=cnt,
+    return dict(value=value, total_ms=total_ms, avg_push_ms=avg_push_ms, push_ms=push_ms, sort_ms=sort_ms, counters=cnt,
                 hbm_gbs=hbm_gbs, bytes_per_launch=bytes_per_launch, dt=dt, live_per_launch=live_per_launch,
                 wall_s=t_wall, tflops=tflops, flops_per_launch=flops_per_launch)
 
@@ -316,6 +325,7 @@ def main():
         },
         "roofline": alu,
         "roofline_hbm": hbm,
+        "sort_ms": r["sort_ms"],
         "kernel": {"name": "push_deposit_f64_tiled", "avg_ms": r["avg_push_ms"],
                    "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
                    "live_particles_per_launch": r["live_per_launch"]},

@@ -331,48 +331,67 @@ __device__ __forceinline__ R shape1(R x) {
     return fmax(R(0), R(1) - fabs(x));
 }
 
-// Esirkepov fluxes of one move on the 3x3 vertex window anchored at
-// (floor(min xi), floor(min eta)): 6 F^r, 6 F^th, 9 G^ph values
-// (eqs. esirkepov-decomp, j-phi-deposit, with the local prefix sum).
-struct MoveFlux {
+// One particle move to deposit: charge q w, start and end point in grid
+// units, phi advance, and the lower corner (i0, j0) = (floor(min xi),
+// floor(min eta)) of its 3x3 vertex window.
+struct Move {
+    double qw, xi0, eta0, xi1, eta1, dphi;
     int i0, j0;
-    double Fr[2][3];        // through (i0+a+1/2, j0+b)
-    double Ft[3][2];        // through (i0+a, j0+b+1/2)
-    double Gp[3][3];        // J^ph dV at (i0+a, j0+b)
 };
 
+__device__ __forceinline__ Move make_move(double qw, double xi0, double eta0, double xi1, double eta1, double dphi) {
+    Move m;
+    m.qw = qw;
+    m.xi0 = xi0;
+    m.eta0 = eta0;
+    m.xi1 = xi1;
+    m.eta1 = eta1;
+    m.dphi = dphi;
+    m.i0 = (int)floor(fmin(xi0, xi1));
+    m.j0 = (int)floor(fmin(eta0, eta1));
+    return m;
+}
+
+// Esirkepov fluxes of a move on its 3x3 vertex window (eqs. esirkepov-decomp,
+// j-phi-deposit, with the local prefix sum), handed to add(component, i, j,
+// value) as they are formed: 6 F^r through (i0+a+1/2, j0+b), 6 F^th through
+// (i0+a, j0+b+1/2), 9 G^ph = J^ph dV at (i0+a, j0+b).
 // With CIC shapes S_ab = wx_a wy_b the decomposition factorises:
 //   W^r_ab = (wx1_a - wx0_a)(wy0_b + wy1_b)/2,  W^th_ab = (wx0_a + wx1_a)(wy1_b - wy0_b)/2,
 // so the prefix sums over a (resp. b) act on one factor only, and
 //   S11/3 + S10/6 + S01/6 + S00/3 = (wx1_a (2 wy1_b + wy0_b) + wx0_a (wy1_b + 2 wy0_b))/6.
 // The same values as the term-by-term form, up to rounding.
-__device__ __forceinline__ void esirkepov(double qw, double dt, double xi0, double eta0,
-                                          double xi1, double eta1, double dphi, MoveFlux& mv) {
-    mv.i0 = (int)floor(fmin(xi0, xi1));
-    mv.j0 = (int)floor(fmin(eta0, eta1));
+template <class Add>
+__device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
     double wx0[3], wx1[3], wy0[3], wy1[3];
     for (int a = 0; a < 3; ++a) {
-        wx0[a] = shape1(xi0 - (double)(mv.i0 + a));
-        wx1[a] = shape1(xi1 - (double)(mv.i0 + a));
-        wy0[a] = shape1(eta0 - (double)(mv.j0 + a));
-        wy1[a] = shape1(eta1 - (double)(mv.j0 + a));
+        wx0[a] = shape1(m.xi0 - (double)(m.i0 + a));
+        wx1[a] = shape1(m.xi1 - (double)(m.i0 + a));
+        wy0[a] = shape1(m.eta0 - (double)(m.j0 + a));
+        wy1[a] = shape1(m.eta1 - (double)(m.j0 + a));
     }
     const double idt = rcp(dt);
-    const double hf = -0.5 * qw * idt;                  // -(q w / dt) / 2
-    const double cp6 = qw * dphi * idt * (1.0 / 6.0);   // (q w dphi / dt) / 6
+    const double hf = -0.5 * m.qw * idt;                // -(q w / dt) / 2
+    const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);   // (q w dphi / dt) / 6
+    // A move that stays in one cell row (column) touches vertex rows i0, i0+1
+    // only, and its r-flux prefix sum is zero from the second row on (the
+    // shape weights of both end points sum to 1 over those rows): those
+    // values are exactly zero and are not added.
+    const bool two_r = floor(m.xi0) != floor(m.xi1), two_t = floor(m.eta0) != floor(m.eta1);
     double dx = 0.0, dy = 0.0;
     for (int a = 0; a < 2; ++a) {
         dx += wx1[a] - wx0[a];
         dy += wy1[a] - wy0[a];
         const double fx = hf * dx, fy = hf * dy;
         for (int b = 0; b < 3; ++b) {
-            mv.Fr[a][b] = fx * (wy0[b] + wy1[b]);
-            mv.Ft[b][a] = fy * (wx0[b] + wx1[b]);
+            if ((a == 0 || two_r) && (b < 2 || two_t)) add(0, m.i0 + a, m.j0 + b, fx * (wy0[b] + wy1[b]));
+            if ((a == 0 || two_t) && (b < 2 || two_r)) add(1, m.i0 + b, m.j0 + a, fy * (wx0[b] + wx1[b]));
         }
     }
     for (int b = 0; b < 3; ++b) {
         const double p1 = cp6 * fma(2.0, wy1[b], wy0[b]), p0 = cp6 * fma(2.0, wy0[b], wy1[b]);
-        for (int a = 0; a < 3; ++a) mv.Gp[a][b] = fma(wx1[a], p1, wx0[a] * p0);
+        for (int a = 0; a < 3; ++a)
+            if ((a < 2 || two_r) && (b < 2 || two_t)) add(2, m.i0 + a, m.j0 + b, fma(wx1[a], p1, wx0[a] * p0));
     }
 }
 

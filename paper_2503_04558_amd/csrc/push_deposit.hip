@@ -65,7 +65,7 @@ __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int c
 // Advances live particle p by one step in place.  Returns true when the move
 // is to be deposited (mv filled), false when the particle was or became
 // removed without a deposit.
-__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, Move& mv, Events& ev,
                                             const TileAnchors* T) {
     const int cell = A.cell[p];
     if (cell < 0) return false;
@@ -126,7 +126,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, MoveFl
     }
     if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
     else if (eta1 > (double)A.nth) { eta1 = 2.0 * A.nth - eta1; u1t = -u1t; ev.refl = 1; }
-    esirkepov(A.q[s] * w[p], dt, xi0, eta0, xi1, eta1, yt[2], mv);
+    mv = make_move(A.q[s] * w[p], xi0, eta0, xi1, eta1, yt[2]);
     if (A.phi) static_cast<double*>(A.phi)[p] += yt[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
@@ -201,7 +201,7 @@ __device__ __forceinline__ float offset_f32(double x) {
     return f < 1.0f ? f : 0.99999994f;
 }
 
-__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move& mv, Events& ev,
                                               const TileAnchors* T) {
     const int cell = A.cell[p];
     if (cell < 0) return false;
@@ -258,7 +258,7 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
     int j1 = (int)floor(eta1);
     if (j1 >= A.nth) j1 = A.nth - 1;
     const float ox = offset_f32(xi1 - (double)i1), oy = offset_f32(eta1 - (double)j1);
-    esirkepov(A.q[s] * (double)w[p], A.dt, xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2], mv);
+    mv = make_move(A.q[s] * (double)w[p], xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2]);
     if (A.phi) static_cast<float*>(A.phi)[p] += (float)y[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
@@ -275,19 +275,15 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
 }
 
 template <bool SPLIT>
-__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, MoveFlux& mv, Events& ev,
+__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, Move& mv, Events& ev,
                                         const TileAnchors* T = nullptr) {
     if constexpr (SPLIT) return advance_split(A, p, mv, ev, T);
     else return advance_f64(A, p, mv, ev, T);
 }
 
-__device__ __forceinline__ void scatter_global(const StepArgs& A, const MoveFlux& mv) {
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 3; ++b) atomicAdd(A.Fr + grid_index(A, mv.i0 + a, mv.j0 + b), mv.Fr[a][b]);
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 2; ++b) atomicAdd(A.Fth + grid_index(A, mv.i0 + a, mv.j0 + b), mv.Ft[a][b]);
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) atomicAdd(A.Gph + grid_index(A, mv.i0 + a, mv.j0 + b), mv.Gp[a][b]);
+__device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
+    double* const J[3] = {A.Fr, A.Fth, A.Gph};
+    esirkepov(mv, A.dt, [&](int c, int i, int j, double v) { atomicAdd(J[c] + grid_index(A, i, j), v); });
 }
 
 // Event counts of a workgroup: each wave adds its ballot counts to five LDS
@@ -315,7 +311,7 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
-        MoveFlux mv;
+        Move mv;
         if (advance<SPLIT>(A, p, mv, ev)) scatter_global(A, mv);
     }
     if (!A.counters) return;                                 // uniform
@@ -377,16 +373,12 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
     const int64_t p = sl.start + slot;
     if (slot < sl.len && p < A.n) {
-        MoveFlux mv;
+        Move mv;
         if (advance<SPLIT>(A, p, mv, ev, &tab)) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
-                for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 3; ++b) atomicAdd(&win[0][li + a][lj + b], mv.Fr[a][b]);
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 2; ++b) atomicAdd(&win[1][li + a][lj + b], mv.Ft[a][b]);
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) atomicAdd(&win[2][li + a][lj + b], mv.Gp[a][b]);
+                esirkepov(mv, A.dt,
+                          [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
             } else {
                 scatter_global(A, mv);                   // drifted out of the window
                 ev.spill = 1;

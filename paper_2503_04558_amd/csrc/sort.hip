@@ -198,15 +198,23 @@ __global__ __launch_bounds__(256) void sort_scatter(const SortArgs S) {
     const int lane = threadIdx.x & 63;
     int head, tail;
     wave_runs(c, valid, head, tail);
+    // the particle's data is read before the atomic, so its latency overlaps the atomic's
+    T v[6], ph = T(0);
+    uint8_t spv = 0;
+    if (valid) {
+        for (int k = 0; k < 6; ++k) v[k] = static_cast<const T*>(S.in[k])[p];
+        spv = S.sp_in[p];
+        if (S.phi_in) ph = static_cast<const T*>(S.phi_in)[p];
+    }
     long long base = 0;
     if (valid && lane == head) base = (long long)atomicAdd(S.counts + c, (unsigned long long)(tail - head + 1));
     base = __shfl(base, head);          // every lane takes part
     if (!valid) return;
     const int64_t q = (int64_t)base + (lane - head);
     S.cell_out[q] = c;
-    for (int k = 0; k < 6; ++k) static_cast<T*>(S.out[k])[q] = static_cast<const T*>(S.in[k])[p];
-    S.sp_out[q] = S.sp_in[p];
-    if (S.phi_in) static_cast<T*>(S.phi_out)[q] = static_cast<const T*>(S.phi_in)[p];
+    for (int k = 0; k < 6; ++k) static_cast<T*>(S.out[k])[q] = v[k];
+    S.sp_out[q] = spv;
+    if (S.phi_in) static_cast<T*>(S.phi_out)[q] = ph;
 }
 
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
