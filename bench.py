@@ -44,6 +44,31 @@ SPLIT_PARTICLE_BYTES = 29 + 24
 FP64_OPS_PER_PARTICLE_STEP = 1344
 
 
+KERNEL_SOURCES = ("push_deposit.hip", "grpic_device.hpp", "grpic_launch.hpp")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "push_deposit_tiled_2048x2048_2e8.md")
+
+
+def measured_traffic() -> dict:
+    """HBM bytes per launch of the tiled push kernels from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if the kernel sources are still
+    the ones it was measured on (else empty: the figure is stale)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_04558_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            line = next(ln for ln in fh if ln.startswith("traffic_bytes_per_launch"))
+    except (OSError, StopIteration):
+        return {}
+    fields = dict(kv.split("=", 1) for kv in line.split()[1:])
+    if fields.get("sources") != h.hexdigest():
+        return {}
+    return {k: float(v) for k, v in fields.items() if k != "sources"}
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -297,11 +322,13 @@ def main():
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
     # 1344 flop per 97 B = 13.9 flop/B, above the FP64 ridge (78.6 TFLOP/s / 8 TB/s =
     # 9.8 flop/B): the FP64 vector units bound this kernel, HBM comes second.
+    traffic = measured_traffic()
     alu = dict(bound="alu", achieved=round(r["tflops"], 3), peak=FP64_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-               frac=round(r["tflops"] / FP64_VALU_PEAK_TFLOPS, 4), traffic=None,
+               frac=round(r["tflops"] / FP64_VALU_PEAK_TFLOPS, 4), traffic=traffic.get("f64"),
                flops_per_launch=r["flops_per_launch"])
     hbm = dict(bound="hbm", achieved=round(r["hbm_gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-               frac=round(r["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None, bytes_per_launch=r["bytes_per_launch"])
+               frac=round(r["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic.get("f64"),
+               bytes_per_launch=r["bytes_per_launch"])
     out = {
         "metric": "particle push+deposit/s (FP64 vs FP32-split) at stated error; bwd/fwd time ratio",
         "value": r["value"],
@@ -339,7 +366,7 @@ def main():
             "kernel": {"name": "push_deposit_split_tiled", "avg_ms": rs["avg_push_ms"],
                        "min_ms": float(np.min(rs["push_ms"]))},
             "roofline_hbm": dict(bound="hbm", achieved=round(rs["hbm_gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                                 frac=round(rs["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                                 frac=round(rs["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic.get("split"),
                                  bytes_per_launch=rs["bytes_per_launch"]),
             "counters": rs["counters"],
         }

@@ -17,3 +17,17 @@ def test_flop_count_matches_oracle_count():
 def test_particle_bytes():
     # cell int32, six float64 arrays and a uint8 species read; cell and five float64 written
     assert bench.FP64_PARTICLE_BYTES == (4 + 6 * 8 + 1) + (4 + 5 * 8)
+
+
+def test_traffic_figure_tracks_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reports the measured HBM traffic only for the kernel sources
+    it was measured on."""
+    import bench
+
+    t = bench.measured_traffic()
+    if t:
+        assert set(t) == {"f64", "split"} and all(v > 1e9 for v in t.values())
+    stale = tmp_path / "p.md"
+    stale.write_text("traffic_bytes_per_launch f64=1e10 split=5e9 sources=0000\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(stale))
+    assert bench.measured_traffic() == {}
