@@ -192,9 +192,13 @@ struct Anchor {
 
 // Computed in double for either R, so an anchor does not depend on where it
 // was evaluated (per particle, or once per tile and shared through LDS).
-__device__ __forceinline__ void anchor_values(const StepArgs& A, int ci, int cj, double& r, double& s, double& c) {
-    r = exp(A.lnr0 + (double)ci * A.dlnr);
+__device__ __forceinline__ double anchor_r(const StepArgs& A, int ci) { return exp(A.lnr0 + (double)ci * A.dlnr); }
+__device__ __forceinline__ void anchor_sc(const StepArgs& A, int cj, double& s, double& c) {
     sincos((double)cj * A.dth, &s, &c);
+}
+__device__ __forceinline__ void anchor_values(const StepArgs& A, int ci, int cj, double& r, double& s, double& c) {
+    r = anchor_r(A, ci);
+    anchor_sc(A, cj, s, c);
 }
 
 template <class R>

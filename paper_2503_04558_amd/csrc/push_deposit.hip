@@ -37,27 +37,34 @@ struct Events {
     int live, out, bad, refl, spill;
 };
 
-// Anchors of one tile (its row, and the kTileCells + 1 column corners it
-// spans), evaluated once per workgroup into LDS; particles that have drifted
-// out of the tile evaluate their own.
+// Anchors (r at a row's corner, sin and cos at a column's) of one tile and
+// the drift margin around it (rows ti - kMarginRows .. ti + kMarginRows,
+// columns j_lo - kMarginCols .. j_lo + kTileCells + kMarginCols), evaluated
+// once per workgroup into LDS; particles that have drifted further evaluate
+// their own.
+constexpr int kAnchorRows = 2 * kMarginRows + 1;
+constexpr int kAnchorCols = kTileCells + 2 * kMarginCols + 1;
 struct TileAnchors {
-    int ti, j_lo;
-    double r;
-    double s[kTileCells + 1], c[kTileCells + 1];
+    int i_lo, j_lo;                           // grid indices of r[0] and s[0], c[0]
+    double r[kAnchorRows];
+    double s[kAnchorCols], c[kAnchorCols];
 };
 
-static_assert(kPushThreads >= 64 + kTileCells + 1, "the second wave fills the anchor table");
+static_assert(kPushThreads >= 64 + kAnchorCols, "waves 1 and 2 fill the anchor table's columns");
 
 template <class R>
 __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int cj, const TileAnchors* T) {
-    if (T && A.small_steps && ci == T->ti && cj >= T->j_lo && cj <= T->j_lo + kTileCells) {
-        Anchor<R> an;
-        an.ci = ci;
-        an.cj = cj;
-        an.r = R(T->r);
-        an.s = R(T->s[cj - T->j_lo]);
-        an.c = R(T->c[cj - T->j_lo]);
-        return an;
+    if (T && A.small_steps) {
+        const int di = ci - T->i_lo, dj = cj - T->j_lo;
+        if (di >= 0 && di < kAnchorRows && dj >= 0 && dj < kAnchorCols) {
+            Anchor<R> an;
+            an.ci = ci;
+            an.cj = cj;
+            an.r = R(T->r[di]);
+            an.s = R(T->s[dj]);
+            an.c = R(T->c[dj]);
+            return an;
+        }
     }
     return make_anchor<R>(A, ci, cj);
 }
@@ -350,18 +357,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols; e += kPushThreads) wflat[e] = 0.0;
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
     if (A.small_steps) {
-        if (threadIdx.x == 0) {
-            tab.ti = ti;
-            tab.j_lo = j_lo;
+        const int t0 = threadIdx.x;
+        if (t0 == 0) {
+            tab.i_lo = ti - kMarginRows;
+            tab.j_lo = j_lo - kMarginCols;
         }
-        const int k = (int)threadIdx.x - 64;                 // the second wave fills the table
-        if (k >= 0 && k <= kTileCells) {
-            double r, sn, cs;
-            anchor_values(A, ti, j_lo + k, r, sn, cs);
-            tab.s[k] = sn;
-            tab.c[k] = cs;
-            if (k == 0) tab.r = r;
-        }
+        if (t0 < kAnchorRows) tab.r[t0] = anchor_r(A, ti - kMarginRows + t0);
+        const int k = t0 - 64;                                // columns: from the second wave on
+        if (k >= 0 && k < kAnchorCols) anchor_sc(A, j_lo - kMarginCols + k, tab.s[k], tab.c[k]);
     }
     __syncthreads();
 

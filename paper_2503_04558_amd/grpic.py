@@ -356,3 +356,52 @@ def empty_particles(n: int, precision: int = GRPIC_FP64, with_phi: bool = False,
     if with_phi:
         out["phi"] = torch.empty(n, dtype=real, device=device)
     return out
+
+
+# ---------------------------------------------------------------- autograd
+class PushDeposit(torch.autograd.Function):
+    """``nsteps`` FP64 push + deposit steps as a function of the initial
+    momenta (u_r, u_th, u_ph) and the six field arrays, returning the current
+    (F^r, F^th, G^ph) accumulated over the steps.  The forward saves
+    checkpoints every ``ckpt_every`` steps; the backward is
+    grpic_push_deposit_backward.  The caller's particle tensors are not
+    modified (the push runs on copies).
+
+        Fr, Fth, Gph = PushDeposit.apply(metric, grid, species, parts, dt, nsteps, ncorr, ckpt_every,
+                                         ur, uth, uph, Dr, Dth, Dph, Br, Bth, Bph)
+    """
+
+    @staticmethod
+    def forward(ctx, metric, grid, species, parts, dt, nsteps, ncorr, ckpt_every, ur, uth, uph, *fields):
+        if len(fields) != 6:
+            raise ValueError("PushDeposit: need six field arrays")
+        start = {k: v.detach().clone() for k, v in parts.items() if k != "phi"}
+        start["ur"], start["uth"], start["uph"] = ur.detach().clone(), uth.detach().clone(), uph.detach().clone()
+        n = start["cell"].numel()
+        work = {k: v.clone() for k, v in start.items()}
+        F = [f.detach() for f in fields]
+        J = [torch.zeros(_grid_numel(grid), dtype=torch.float64, device=ur.device).view(fields[0].shape)
+             for _ in range(3)]
+        ckpt = torch.empty(max(1, grpic_checkpoint_bytes(n, nsteps, ckpt_every)), dtype=torch.uint8,
+                           device=ur.device)
+        grpic_push_deposit(metric, grid, species, work, F, J, dt, nsteps, ncorr, ckpt=ckpt if n else None,
+                           ckpt_every=ckpt_every)
+        ctx.save_for_backward(ckpt, *F)
+        ctx.cfg = (metric, grid, species, start, dt, nsteps, ncorr, ckpt_every)
+        return tuple(J)
+
+    @staticmethod
+    def backward(ctx, gFr, gFth, gGph):
+        ckpt, *F = ctx.saved_tensors
+        metric, grid, species, start, dt, nsteps, ncorr, ckpt_every = ctx.cfg
+        n = start["cell"].numel()
+        dev = ckpt.device
+        lam = [(g if g is not None else torch.zeros_like(F[0])).contiguous() for g in (gFr, gFth, gGph)]
+        lam = [l.to(torch.float64) for l in lam]
+        ws = torch.empty(max(1, grpic_backward_workspace_bytes(grid, n, ckpt_every)), dtype=torch.uint8,
+                         device=dev)
+        gu = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        gF = [torch.zeros_like(f) for f in F]
+        grpic_push_deposit_backward(metric, grid, species, start, F, lam, dt, nsteps, ncorr, ckpt, ckpt_every, ws,
+                                    gu, gF)
+        return (None,) * 8 + tuple(gu) + tuple(gF)

@@ -211,3 +211,25 @@ def test_backward_of_removed_and_empty():
     start, F, J, ck, _ = forward(g, sp, empty, wl.wald_fields(g), dt, nsteps=8, ckpt_every=4)
     gu, gF = backward(g, sp, start, F, lam, dt, ck, nsteps=8, ckpt_every=4)
     assert gu.shape == (0, 3) and all(np.all(a == 0) for a in gF)
+
+
+def test_autograd_function_matches_direct_calls(case):
+    """PushDeposit (torch.autograd.Function) gives the same current and, through
+    loss.backward(), the same gradients as the direct forward/backward calls."""
+    _announce("adjoint through torch.autograd")
+    g, sp, dt = case["g"], case["sp"], case["dt"]
+    parts = grpic.to_device(case["parts"])
+    u = [parts[k].clone().requires_grad_(True) for k in ("ur", "uth", "uph")]
+    F = [torch.as_tensor(f).to("cuda").requires_grad_(True) for f in case["fields"]]
+    J = grpic.PushDeposit.apply(grpic.make_metric(g.a, g.M), g, sp, parts, dt, K, 3, CKPT_EVERY, *u, *F)
+    lam = [torch.as_tensor(l).to("cuda") for l in case["lam"]]
+    loss = sum((l * j).sum() for l, j in zip(lam, J))
+    assert float(loss.detach()) == pytest.approx(case["L"], rel=1e-12, abs=1e-14)
+    loss.backward()
+    gu = np.stack([t.grad.cpu().numpy() for t in u], axis=1)
+    scale = np.abs(case["gu"]).max(axis=1, keepdims=True) + 1e-300
+    assert np.all(np.abs(gu - case["gu"]) <= 1e-12 * scale)
+    for f, ref in zip(F, case["gF"]):
+        assert np.abs(f.grad.cpu().numpy() - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
+    # the caller's particles are untouched
+    assert torch.equal(parts["cell"], grpic.to_device(case["parts"])["cell"])
