@@ -256,9 +256,21 @@ def run_cpu_baseline(args, grid):
                           nthreads=nthreads)
     el = time.time() - t
     rate = st["live_steps"] / el
+    # one thread, on the first 1/16 of the sample
+    small = {k: v[: len(v) // 16] for k, v in parts.items()}
+    t = time.time()
+    _, _, _, st1 = orc.run(grid, wl.species_table(), small, F, dt, args.cpu_steps, ncorr=args.ncorr, nthreads=1)
+    el1 = time.time() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=rate, unit="particle-steps/s", cores=nthreads if orc.has_openmp() else 1, kind="oracle",
                 sample=f"first {2 * sample_pairs} particles of the same workload, {args.cpu_steps} steps, "
-                       f"no sort, {el:.1f}s")
+                       f"no sort, {el:.1f}s",
+                one_thread_value=st1["live_steps"] / el1, host_cpus=os.cpu_count(), cpu_model=model)
 
 
 def main():

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <map>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -136,7 +137,9 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     const double M = m ? m->M : 0.0;
     const double i2 = M > 0.0 ? (log(2.0 * M) - g->lnr0) / g->dlnr : -1e9;
     A.fp64_rows = i2 < 0.0 ? 0 : (int)fmin((double)g->nr, ceil(i2) + 2.0);
-    A.pole_cols = (int)fmin((double)g->nth, ceil(asin(grpic::kPoleSin) / g->dth) + 2.0);
+    // rounded up to whole tiles, so that no tile mixes float and double lanes
+    const int pole = (int)ceil(asin(grpic::kPoleSin) / g->dth) + 2;
+    A.pole_cols = std::min(g->nth, (pole + grpic::kTileCells - 1) / grpic::kTileCells * grpic::kTileCells);
     A.nsp = nsp;
     for (int s = 0; s < nsp; ++s) {
         A.q[s] = sp[s].q;
