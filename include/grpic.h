@@ -31,8 +31,12 @@
  *   sp    uint8   species index into the species table
  *   phi           optional accumulated azimuth (NULL: not tracked)
  * Precision GRPIC_FP64: xr..w and phi are double.  GRPIC_FP32_SPLIT: xr..w are
- * float (the position keeps its integer cell exactly; fields are float too),
- * the deposit and the current arrays stay double.
+ * float (the position keeps its integer cell exactly; fields are float too);
+ * the kick and the predictor-corrector run in float on offsets from the start
+ * cell, except in rows with r < 2M and in the 64-cell tiles within ~5.7
+ * degrees of the axis (double there, on the same float state); the deposit
+ * is evaluated in double on the stored end point and the current arrays stay
+ * double.
  *
  * Current output is in flux form (the quantities eq. integral-form consumes):
  *   F^r_{i+1/2,j} = J^r A^D_r,  F^th_{i,j+1/2} = J^th A^D_th,  G^ph_{ij} = J^ph dV,
@@ -186,7 +190,8 @@ typedef struct {
  * grad_fields.  parts: the particles at the start of the forward call (w and
  * sp are read; n, precision GRPIC_FP64); fields, dt, nsteps, ncorr (<= 8),
  * species: as in that call; ckpt: its checkpoints.  ws: device workspace of
- * grpic_backward_workspace_bytes(n, ckpt_every) bytes.  Per particle, each
+ * grpic_backward_workspace_bytes(grid, n, ckpt_every) bytes (its contents on
+ * entry do not matter).  Per particle, each
  * checkpoint segment is recomputed from its checkpoint and then reversed
  * step by step, the last step first; field gradients use FP64 atomics.
  * While a particle's cotangent is zero, steps and whole segments whose
