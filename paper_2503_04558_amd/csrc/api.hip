@@ -144,6 +144,7 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     for (int s = 0; s < nsp; ++s) {
         A.q[s] = sp[s].q;
         A.m[s] = sp[s].m;
+        A.qm[s] = sp[s].massless ? 0.0 : sp[s].q / sp[s].m;
         A.massless[s] = sp[s].massless;
     }
     A.n = p->n;

@@ -26,6 +26,7 @@ struct StepArgs {
     double dt;
     int ncorr, nsp;
     double q[kMaxSpecies], m[kMaxSpecies];
+    double qm[kMaxSpecies];                 // q/m (0 for massless species)
     int massless[kMaxSpecies];
     int64_t n;
     int32_t* cell;

@@ -112,7 +112,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, Move& 
         Metric<double> k0;
         MetricDeriv<double> d0;
         ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
-        if (!massless) boris_kick(k0, A.q[s] / A.m[s], dt, D, B, u);
+        if (!massless) boris_kick(k0, A.qm[s], dt, D, B, u);
         geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
     }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
@@ -233,7 +233,7 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
     const float Bf[3] = {cic_f32(F[3], A, ci, cj, fxr, fxt - 0.5f), cic_f32(F[4], A, ci, cj, fxr - 0.5f, fxt),
                          cic_f32(F[5], A, ci, cj, fxr - 0.5f, fxt - 0.5f)};
     const bool massless = A.massless[s] != 0;
-    const double qm = massless ? 0.0 : A.q[s] / A.m[s];
+    const double qm = A.qm[s];
     double y[5], uph1;
     const bool fp64 = ci < A.fp64_rows || cj < A.pole_cols || cj >= A.nth - A.pole_cols;
     if (fp64) {

@@ -1,0 +1,108 @@
+"""The throughput configuration at full size -- 2048^2 log-r Kerr-Schild grid,
+a = 0.99, Wald B0 = 1, 2e8 e+- (Maxwell-Juttner T = 0.1 with a 0.1c bulk
+rotation in phi) -- through the path bench.py times: a GPU sort that writes a
+tiling, then tiled pushes.
+
+* Sampled parity: 20,000 particles, followed through the sort by their index
+  carried in phi, are compared after 5 steps with the oracle run on those
+  particles alone (a particle's step depends only on itself and the fixed
+  fields), to the FP64 parity norms and conditioning criterion.
+* Charge continuity of the 5 steps holds at every vertex on the GPU's own
+  outputs: |Q^5 - Q^0 + dt div(sum of F)| <= 64 eps (1 + steps) (|Q|^0 + |Q|^5),
+  |Q| being the charge with every |q| = 1 (the scale of the terms that meet at
+  a vertex).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_04558_amd import grpic
+from paper_2503_04558_amd import workload as wl
+
+from parity import compare_particles, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS = 5
+NSAMPLE = 20_000
+TOL = 1e-12
+EPS = np.finfo(np.float64).eps
+KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def test_full_size_sampled_parity_and_continuity():
+    _announce("full size 2048x2048, 2e8 particles: generate")
+    g = wl.make_grid(2048, 2048, 0.99)
+    npairs = 100_000_000
+    n = 2 * npairs
+    parts = grpic.empty_particles(n, with_phi=True)
+
+    def sink(start, arrs):
+        m = len(arrs["cell"])
+        for k, v in arrs.items():
+            parts[k][start:start + m].copy_(torch.from_numpy(np.ascontiguousarray(v)))
+
+    wl.pairs(g, npairs, kind="mj", seed=0, params=dict(T=0.1, vphi=0.1), workers=16, sink=sink)
+    parts["phi"].copy_(torch.arange(n, dtype=torch.float64, device="cuda"))
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(n, NSAMPLE, replace=False))
+    idx_t = torch.as_tensor(idx, device="cuda")
+    sample0 = {k: parts[k][idx_t].cpu().numpy() for k in KEYS}
+
+    fields = wl.wald_fields(g, B0=1.0)
+    F = [torch.as_tensor(f).to("cuda") for f in fields]
+    sp = wl.species_table()
+    metric = grpic.make_metric(g.a, g.M)
+    dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+
+    _announce("sort + 5 tiled steps")
+    sorter = grpic.Sorter(g, n, grpic.GRPIC_FP64, with_phi=True)
+    parts = sorter.sort(parts)
+    n_alive = int(sorter.n_alive.item())
+    assert n_alive == n
+    pos = torch.empty(n, dtype=torch.int64, device="cuda")
+    pos[parts["phi"].round().long()] = torch.arange(n, device="cuda")
+    rows = pos[idx_t]
+
+    unit = [dict(s, q=1.0) for s in sp]
+    Q0 = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    A0 = torch.zeros_like(Q0)
+    grpic.grpic_charge(g, sp, parts, Q0)
+    grpic.grpic_charge(g, unit, parts, A0)
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
+    for _ in range(NSTEPS):
+        grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, 1, 3, tiling=sorter.tiling, counters=counters)
+    Q1 = torch.zeros_like(Q0)
+    A1 = torch.zeros_like(Q0)
+    grpic.grpic_charge(g, sp, parts, Q1)
+    grpic.grpic_charge(g, unit, parts, A1)
+    torch.cuda.synchronize()
+    cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
+    _announce(f"counters {cnt}")
+
+    # continuity at every vertex that a particle can reach
+    Fr, Ft = J[0], J[1]
+    div = torch.zeros_like(Fr)
+    div[1:, :] += Fr[1:, :] - Fr[:-1, :]
+    div[:, 1:] += Ft[:, 1:] - Ft[:, :-1]
+    R = (Q1 - Q0 + dt * div)[g.guard + 1: g.guard + g.nr]
+    bound = (64 * EPS * (1 + NSTEPS) * (A0 + A1))[g.guard + 1: g.guard + g.nr]
+    ratio = (R.abs() / bound.clamp_min(1e-300)).max().item()
+    _announce(f"continuity: max |R| / bound = {ratio:.3e}, max |R| = {R.abs().max().item():.3e}")
+    assert ratio <= 1.0
+
+    # sampled parity
+    got = {k: parts[k][rows].cpu().numpy() for k in KEYS}
+    _announce("oracle on the sample")
+    po, _, _, _, pert = oracle_run(g, sp, sample0, fields, dt, NSTEPS)
+    e = compare_particles(g, got, po, TOL, pert)
+    _announce(f"sampled parity {e}")
+    assert e["status_mismatch"] == 0, e
+    assert e["violations"] == 0, e
+    assert e["well_conditioned_err"] <= TOL, e
+    assert e["ill_conditioned"] <= max(2, 1e-3 * e["n"]), e
