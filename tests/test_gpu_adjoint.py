@@ -37,7 +37,7 @@ def _announce(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, tiled=False):
+def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, tiled=False, ncorr=3):
     """GPU forward from parts_np with checkpoints; returns the device particle
     state at the start (w, sp, order used by the backward), the checkpoint
     buffer, the accumulated current and the particle index order."""
@@ -59,18 +59,18 @@ def forward(g, sp, parts_np, fields_np, dt, nsteps=K, ckpt_every=CKPT_EVERY, til
     J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     # buffers start as all-ones bytes (NaN as doubles): nothing may read what the call did not write
     ck = torch.full((grpic.grpic_checkpoint_bytes(n, nsteps, ckpt_every),), 255, dtype=torch.uint8, device="cuda")
-    grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, sp, parts, F, J, dt, nsteps, 3, tiling=tiling,
+    grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, sp, parts, F, J, dt, nsteps, ncorr, tiling=tiling,
                              ckpt=ck, ckpt_every=ckpt_every)
     return start, F, J, ck, order
 
 
-def backward(g, sp, start, F, lam_np, dt, ck, nsteps=K, ckpt_every=CKPT_EVERY):
+def backward(g, sp, start, F, lam_np, dt, ck, nsteps=K, ckpt_every=CKPT_EVERY, ncorr=3):
     n = start["cell"].numel()
     lam = [torch.as_tensor(l).to("cuda") for l in lam_np]
     ws = torch.full((grpic.grpic_backward_workspace_bytes(g, n, ckpt_every),), 255, dtype=torch.uint8, device="cuda")
     gu = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(3)]
     gF = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
-    grpic.grpic_push_deposit_backward(grpic.make_metric(g.a, g.M), g, sp, start, F, lam, dt, nsteps, 3, ck,
+    grpic.grpic_push_deposit_backward(grpic.make_metric(g.a, g.M), g, sp, start, F, lam, dt, nsteps, ncorr, ck,
                                       ckpt_every, ws, gu, gF)
     torch.cuda.synchronize()
     return np.stack([t.cpu().numpy() for t in gu], axis=1), [t.cpu().numpy() for t in gF]
@@ -233,3 +233,68 @@ def test_autograd_function_matches_direct_calls(case):
         assert np.abs(f.grad.cpu().numpy() - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
     # the caller's particles are untouched
     assert torch.equal(parts["cell"], grpic.to_device(case["parts"])["cell"])
+
+
+def _touched_mask(g, parts, fields, lam, dt, nsteps, ncorr=3):
+    """Grid elements (per component) that the gathers of the given particles
+    read at some step of their oracle trajectories."""
+    sp = wl.species_table()
+    stag = [(0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5)]
+    mask = [np.zeros(g.shape, dtype=bool) for _ in range(6)]
+    for p in range(len(parts["cell"])):
+        xi = parts["cell"][p] // g.nth + parts["xr"][p]
+        eta = parts["cell"][p] % g.nth + parts["xth"][p]
+        u = np.array([parts["ur"][p], parts["uth"][p], parts["uph"][p]])
+        _, _, traj = orc.loss_particle(g, sp[int(parts["sp"][p])], xi, eta, u, parts["w"][p], fields, lam, dt,
+                                       nsteps, ncorr, trajectory=True)
+        for x, e in traj[:-1]:
+            if not np.isfinite(x):
+                break
+            for c, (sr, st) in enumerate(stag):
+                i, j = int(np.floor(x - sr)), int(np.floor(e - st))
+                mask[c][g.guard + i: g.guard + i + 2, g.guard + j: g.guard + j + 2] = True
+    return mask
+
+
+def test_field_gradient_vanishes_where_no_gather_reads(case):
+    """d L / d(field element) is exactly zero unless some particle's gather read
+    that element (within one element: a GPU trajectory may round to the other
+    side of a cell edge that the oracle's trajectory touches)."""
+    from scipy.ndimage import binary_dilation
+
+    _announce("adjoint field gradient support")
+    mask = _touched_mask(case["g"], case["parts"], case["fields"], case["lam"], case["dt"], K)
+    for c, (a, m0) in enumerate(zip(case["gF"], mask)):
+        m = binary_dilation(m0, structure=np.ones((3, 3), dtype=bool))
+        assert np.all(a[~m] == 0.0), (c, int(np.count_nonzero(a[~m])))
+        assert np.count_nonzero(a[m]) > 0, c
+
+
+@pytest.mark.parametrize("ncorr", [0, 2])
+def test_generic_corrector_count_and_mixed_species(ncorr):
+    """The adjoint kernel for corrector counts other than 3, with a photon and
+    a heavy ion species beside e-, against the oracle's dual numbers."""
+    _announce(f"adjoint ncorr={ncorr}, photons and ions")
+    g = wl.make_grid(64, 64, 0.9)
+    dt = wl.crossing_dt(g)
+    fields = wl.wald_fields(g, B0=3.0)
+    parts = wl.pairs(g, 60, kind="mj", seed=12, params=dict(T=1.0))
+    parts["sp"] = (np.arange(len(parts["sp"])) % 3).astype(np.uint8)
+    species = [dict(q=-1.0, m=1.0, massless=0), dict(q=2.0, m=50.0, massless=0), dict(q=0.0, m=0.0, massless=1)]
+    rng = np.random.default_rng(3)
+    lam = [rng.normal(size=g.shape) * dt for _ in range(3)]
+    nsteps, every = 8, 4                   # (the uncharged photons must get exactly zero)
+    start, F, J, ck, _ = forward(g, species, parts, fields, dt, nsteps=nsteps, ckpt_every=every, ncorr=ncorr)
+    gu, gF = backward(g, species, start, F, lam, dt, ck, nsteps=nsteps, ckpt_every=every, ncorr=ncorr)
+    assert np.all(np.isfinite(gu))
+    for p in range(len(parts["cell"])):
+        one = {k: v[p:p + 1] for k, v in parts.items()}
+        for k in range(3):
+            t = [np.zeros(1) for _ in range(3)]
+            t[k][0] = 1.0
+            _, dL, _ = orc.loss_dual(g, species, one, fields, lam, dt, nsteps, ncorr=ncorr, tu=t)
+            assert gu[p, k] == pytest.approx(dL, rel=1e-9, abs=1e-12 * max(1.0, abs(dL))), (p, k, species[p % 3])
+    tF = [rng.normal(size=g.shape) * np.abs(f).max() for f in fields]
+    _, dL, _ = orc.loss_dual(g, species, parts, fields, lam, dt, nsteps, ncorr=ncorr, tF=tF)
+    got = sum(float((a * t).sum()) for a, t in zip(gF, tF))
+    assert got == pytest.approx(dL, rel=1e-9)

@@ -127,6 +127,17 @@ def test_parity_photons_and_ions(tiled):
     assert_parity(g, species, parts, wl.wald_fields(g, B0=5.0), wl.crossing_dt(g), 6, TOL, tiled=tiled)
 
 
+@pytest.mark.parametrize("tiled", TILED)
+def test_parity_schwarzschild_full_crossing_dt(tiled):
+    """a = 0 and the largest dt the library accepts (the full light-crossing
+    time of the smallest cell): moves approach one cell per step."""
+    _announce("parity a=0, dt = crossing time")
+    g = wl.make_grid(96, 80, 0.0)
+    parts = wl.pairs(g, 3000, kind="mj", seed=8, params=dict(T=2.0))
+    dt = grpic.grpic_crossing_time(grpic.make_metric(g.a, g.M), g)
+    assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=3.0), dt, 6, TOL, tiled=tiled)
+
+
 def test_tiled_equals_untiled_with_drift_beyond_window():
     """One sort, then 40 steps: particles near the horizon and the fast ones
     leave their tile's LDS window and deposit to global memory.  On identical
