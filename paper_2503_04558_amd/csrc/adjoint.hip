@@ -82,11 +82,45 @@ __global__ __launch_bounds__(128) void lam_prefix(const BackArgs B, const int* _
     }
 }
 
+// Field cotangents of one particle are summed in LDS (one slot per thread)
+// while successive steps gather from the same 2 x 2 block of a component,
+// and added to the gradient arrays with atomics when the block changes and
+// at the end: a particle stays in a cell for a few steps, so this takes a
+// few times fewer global atomics than adding every step.
+constexpr int kBackThreads = 256;
+
 template <int NC>
-__global__ __launch_bounds__(256) void push_deposit_backward_f64(const BackArgs B) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= B.n) return;
-    backward_particle<NC>(B, p, [&](int c, long e, double v) { atomicAdd(B.gradF[c] + e, v); });
+__global__ __launch_bounds__(kBackThreads) void push_deposit_backward_f64(const BackArgs B) {
+    __shared__ double acc[6][4][kBackThreads];
+    __shared__ long base[6][kBackThreads];
+    const int t = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + t;
+    if (p >= B.n) return;                       // (no barrier below: the slots are per thread)
+    for (int c = 0; c < 6; ++c) base[c][t] = -1;
+    auto flush = [&](int c) {
+        const long e = base[c][t];
+        if (e < 0) return;
+        double* g = B.gradF[c];
+        const long off[4] = {0, B.pitch, 1, B.pitch + 1};
+        for (int k = 0; k < 4; ++k)
+            if (acc[c][k][t] != 0.0) atomicAdd(g + e + off[k], acc[c][k][t]);
+    };
+    backward_particle<NC>(B, p, [&](int c, long e, double g00, double g10, double g01, double g11) {
+        if (base[c][t] != e) {
+            flush(c);
+            base[c][t] = e;
+            acc[c][0][t] = g00;
+            acc[c][1][t] = g10;
+            acc[c][2][t] = g01;
+            acc[c][3][t] = g11;
+        } else {
+            acc[c][0][t] += g00;
+            acc[c][1][t] += g10;
+            acc[c][2][t] += g01;
+            acc[c][3][t] += g11;
+        }
+    });
+    for (int c = 0; c < 6; ++c) flush(c);
 }
 
 size_t backward_aux_bytes(int rows, int pitch) {
@@ -104,9 +138,11 @@ hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t strea
     hipLaunchKernelGGL(lam_row_any, dim3((unsigned)B.rows), dim3(256), 0, stream, B, row_flag);
     hipLaunchKernelGGL(lam_col_any, dim3((unsigned)((B.pitch + 255) / 256)), dim3(256), 0, stream, B, col_flag);
     hipLaunchKernelGGL(lam_prefix, dim3(1), dim3(128), 0, stream, B, row_flag, col_flag, row_pre, col_pre);
-    const dim3 grid((unsigned)((B.n + 255) / 256));
-    if (B.ncorr == kFastCorr) hipLaunchKernelGGL(push_deposit_backward_f64<kFastCorr>, grid, dim3(256), 0, stream, B);
-    else hipLaunchKernelGGL(push_deposit_backward_f64<adj::kMaxCorr>, grid, dim3(256), 0, stream, B);
+    const dim3 grid((unsigned)((B.n + kBackThreads - 1) / kBackThreads));
+    if (B.ncorr == kFastCorr)
+        hipLaunchKernelGGL(push_deposit_backward_f64<kFastCorr>, grid, dim3(kBackThreads), 0, stream, B);
+    else
+        hipLaunchKernelGGL(push_deposit_backward_f64<adj::kMaxCorr>, grid, dim3(kBackThreads), 0, stream, B);
     return hipGetLastError();
 }
 

@@ -390,6 +390,8 @@ __host__ __device__ inline double gather(const Geo& G, const FieldT* F, double f
          + wf * wh * F[e + G.pitch + 1];
 }
 
+// The four field cotangents go to add(e, g00, g10, g01, g11): element e of
+// the lower corner, then the values for e, e + pitch, e + 1, e + pitch + 1.
 template <class FieldT, class Add>
 __host__ __device__ inline void gather_vjp(const Geo& G, const FieldT* F, double f, double h, double gb,
                                            double& fb, double& hb, Add add) {
@@ -399,10 +401,7 @@ __host__ __device__ inline void gather_vjp(const Geo& G, const FieldT* F, double
     const double F00 = F[e], F10 = F[e + G.pitch], F01 = F[e + 1], F11 = F[e + G.pitch + 1];
     fb += gb * ((1.0 - wh) * (F10 - F00) + wh * (F11 - F01));
     hb += gb * ((1.0 - wf) * (F01 - F00) + wf * (F11 - F10));
-    add(e, gb * (1.0 - wf) * (1.0 - wh));
-    add(e + G.pitch, gb * wf * (1.0 - wh));
-    add(e + 1, gb * (1.0 - wf) * wh);
-    add(e + G.pitch + 1, gb * wf * wh);
+    add(e, gb * (1.0 - wf) * (1.0 - wh), gb * wf * (1.0 - wh), gb * (1.0 - wf) * wh, gb * wf * wh);
 }
 
 // ---------------------------------------------------------------- deposit
@@ -527,7 +526,8 @@ __host__ __device__ inline int replay_step(const Geo& G, const FieldT* const F[6
 // Reverse of one step.  a[5] holds on entry the cotangent of the state after
 // the step (xi, eta, u_r, u_th, u_ph; zero if the particle did not survive
 // it) and on return the cotangent of the state before it.  Field
-// cotangents go to addF(component, element, value).
+// cotangents go to addF(component, lower-corner element, four values) as in
+// gather_vjp.
 template <int NC, class FieldT, class LamT, class AddF>
 __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F[6], const LamT* const lam[3],
                                              double qm, bool massless, double qw, double dt, int ncorr,
@@ -601,7 +601,7 @@ __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F
         if (gb == 0.0) continue;
         double fb = 0.0, hb = 0.0;
         gather_vjp(G, F[c], T.xi0 - stag_r(c), T.eta0 - stag_t(c), gb, fb, hb,
-                   [&](long e, double v) { addF(c, e, v); });
+                   [&](long e, double g00, double g10, double g01, double g11) { addF(c, e, g00, g10, g01, g11); });
         xib += fb;
         etab0 += hb;
     }
