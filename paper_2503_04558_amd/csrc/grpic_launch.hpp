@@ -23,7 +23,7 @@ constexpr int kTileCells = 64;
 constexpr int kPushThreads = 256;
 constexpr int kSliceMax = kPushThreads;                    // one particle per thread
 constexpr int kLaneGroups = 8;                             // lane permutation inside a slice
-constexpr int kMarginRows = 3;
+constexpr int kMarginRows = 6;
 constexpr int kMarginCols = 4;
 constexpr int kWinRows = 2 * kMarginRows + 4;              // vertex rows of the LDS window
 constexpr int kWinCols = kTileCells + 2 * kMarginCols + 3; // vertex columns of the LDS window

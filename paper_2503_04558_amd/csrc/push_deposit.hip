@@ -337,6 +337,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __shared__ double win[3][kWinRows][kWinCols];
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
+    __shared__ int touched[2];                           // lowest and highest window row of a deposit
     // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of slices so neighbouring tiles share its L2.
     const int64_t nslices = hdr->nslices;
@@ -353,9 +354,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
 
-    double* wflat = &win[0][0][0];
-    for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols; e += kPushThreads) wflat[e] = 0.0;
+    double2* wflat = reinterpret_cast<double2*>(&win[0][0][0]);
+    static_assert((3 * kWinRows * kWinCols) % 2 == 0, "the window is cleared in pairs");
+    for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols / 2; e += kPushThreads) wflat[e] = make_double2(0.0, 0.0);
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        touched[0] = kWinRows;
+        touched[1] = -1;
+    }
     if (A.small_steps) {
         const int t0 = threadIdx.x;
         if (t0 == 0) {
@@ -375,6 +381,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int t = threadIdx.x;
     const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
     const int64_t p = sl.start + slot;
+    int row_lo = kWinRows, row_hi = -1;                  // window rows this lane deposited on
     if (slot < sl.len && p < A.n) {
         Move mv;
         if (advance<SPLIT>(A, p, mv, ev, &tab)) {
@@ -382,11 +389,21 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 esirkepov(mv, A.dt,
                           [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
+                row_lo = li;
+                row_hi = li + 2;
             } else {
                 scatter_global(A, mv);                   // drifted out of the window
                 ev.spill = 1;
             }
         }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        row_lo = min(row_lo, __shfl_xor(row_lo, off));
+        row_hi = max(row_hi, __shfl_xor(row_hi, off));
+    }
+    if ((threadIdx.x & 63) == 0 && row_hi >= 0) {
+        atomicMin(&touched[0], row_lo);
+        atomicMax(&touched[1], row_hi);
     }
     if (A.counters) wave_events_to_lds(ev, cnt);
     __syncthreads();
@@ -394,8 +411,11 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
     const int rows_lo = -A.guard, rows_hi = A.nr + A.guard;             // inclusive vertex rows
     const int cols_lo = -A.guard, cols_hi = A.pitch - A.guard - 1;      // inclusive vertex columns
-    for (int e = threadIdx.x; e < kWinRows * kWinCols; e += kPushThreads) {
-        const int r = e / kWinCols, c = e - r * kWinCols;
+    // only the rows that received deposits
+    const int r0 = touched[0], nrow = touched[1] - touched[0] + 1;
+    for (int e = threadIdx.x; e < nrow * kWinCols; e += kPushThreads) {
+        const int rr = e / kWinCols, c = e - rr * kWinCols;
+        const int r = r0 + rr;
         const int gi = wi0 + r, gj = wj0 + c;
         if (gi < rows_lo || gi > rows_hi || gj < cols_lo || gj > cols_hi) continue;
         const long g = grid_index(A, gi, gj);
