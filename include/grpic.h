@@ -155,7 +155,10 @@ typedef struct {
  *   that have drifted out of their tile's LDS window since the sort deposit
  *   straight to global memory, so results do not depend on how fresh the
  *   sort is.  Only particles live at the sort are pushed (the sort marks the
- *   rest removed); without a tiling any particle order works.
+ *   rest removed); without a tiling any particle order works.  With
+ *   counters, the push also writes each slice's live count into the tiling
+ *   (pushes that share a tiling must be stream-ordered, as they share the
+ *   particles anyway).
  * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
  * ckpt (optional, device, ckpt_bytes >= grpic_checkpoint_bytes(n, nsteps,
  *   ckpt_every)): the particle state is saved before every step k with
@@ -166,7 +169,7 @@ typedef struct {
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                       const void* tiling, double dt, int nsteps, int ncorr,
+                       void* tiling, double dt, int nsteps, int ncorr,
                        void* ckpt, size_t ckpt_bytes, int ckpt_every,
                        int64_t* counters, void* stream);
 

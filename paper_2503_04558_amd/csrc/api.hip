@@ -170,7 +170,7 @@ double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid) {
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        const grpic_species* species, int nsp,
                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                       const void* tiling, double dt, int nsteps, int ncorr,
+                       void* tiling, double dt, int nsteps, int ncorr,
                        void* ckpt, size_t ckpt_bytes, int ckpt_every,
                        int64_t* counters, void* stream) {
     int rc;

@@ -44,13 +44,19 @@ inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; 
 inline int64_t slice_capacity(int64_t n, int nr, int nth) {
     return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 1;
 }
+// Layout: header, slice table (capacity entries), then one int32 per slice
+// that a push with counters fills with the slice's live particle count (so
+// that the count needs no same-address atomics; a small kernel sums it).
 inline size_t tiling_bytes(int64_t n, int nr, int nth) {
-    return sizeof(TilingHeader) + (size_t)slice_capacity(n, nr, nth) * sizeof(Slice);
+    return sizeof(TilingHeader) + (size_t)slice_capacity(n, nr, nth) * (sizeof(Slice) + sizeof(int32_t));
+}
+inline int32_t* tiling_slice_live(void* tiling, int64_t slice_cap) {
+    return reinterpret_cast<int32_t*>(reinterpret_cast<Slice*>(static_cast<TilingHeader*>(tiling) + 1) + slice_cap);
 }
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream);
-hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, const void* tiling, int64_t slice_cap,
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
                                      hipStream_t stream);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream);
 

@@ -333,7 +333,8 @@ __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { pu
 
 template <bool SPLIT>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
-                                                        const Slice* __restrict__ slices, int64_t slice_cap) {
+                                                        const Slice* __restrict__ slices, int64_t slice_cap,
+                                                        int32_t* __restrict__ slice_live) {
     __shared__ double win[3][kWinRows][kWinCols];
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
@@ -347,7 +348,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int64_t logical = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (logical >= nslices || logical >= slice_cap) return;
     const Slice sl = slices[logical];
-    if (sl.start < 0 || sl.len <= 0) return;
+    if (sl.start < 0 || sl.len <= 0) {
+        if (A.counters && threadIdx.x == 0) slice_live[logical] = 0;
+        return;
+    }
     const int tpr = (A.nth + kTileCells - 1) / kTileCells;
     const int ti = sl.tile / tpr;
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
@@ -424,18 +428,42 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             if (v != 0.0) atomicAdd(J[a] + g, v);
         }
     }
-    if (A.counters) workgroup_events_to_global(A, cnt);
+    if (A.counters && threadIdx.x == 0) {
+        // the live count goes to the slice's own word (summed by slice_live_sum);
+        // the rare events take one atomic each when non-zero
+        slice_live[logical] = cnt[3];
+        for (int k = 0; k < 5; ++k)
+            if (k != 3 && cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
+    }
+}
+
+// counters[LIVE] += sum of the per-slice live counts of one tiled push.
+__global__ __launch_bounds__(256) void slice_live_sum(const TilingHeader* __restrict__ hdr,
+                                                      const int32_t* __restrict__ live, int64_t slice_cap,
+                                                      unsigned long long* __restrict__ counters) {
+    const int64_t n = min(hdr->nslices, slice_cap);
+    unsigned long long v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += (unsigned long long)live[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(counters + 3, t);
+    }
 }
 
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(const StepArgs A, const TilingHeader* hdr,
                                                                        const Slice* __restrict__ slices,
-                                                                       int64_t slice_cap) {
-    push_deposit_tiled_body<false>(A, hdr, slices, slice_cap);
+                                                                       int64_t slice_cap, int32_t* slice_live) {
+    push_deposit_tiled_body<false>(A, hdr, slices, slice_cap, slice_live);
 }
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A, const TilingHeader* hdr,
                                                                          const Slice* __restrict__ slices,
-                                                                         int64_t slice_cap) {
-    push_deposit_tiled_body<true>(A, hdr, slices, slice_cap);
+                                                                         int64_t slice_cap, int32_t* slice_live) {
+    push_deposit_tiled_body<true>(A, hdr, slices, slice_cap, slice_live);
 }
 
 // Q_ij += q w S_ij(x_p) over live particles (FP64 or split offsets).
@@ -467,18 +495,21 @@ hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream
     return hipGetLastError();
 }
 
-hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, const void* tiling, int64_t slice_cap,
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
                                      hipStream_t stream) {
     if (A.n <= 0) return hipSuccess;
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
+    int32_t* live = tiling_slice_live(tiling, slice_cap);
     const int64_t grid = (slice_cap + 7) / 8 * 8;
     if (split)
         hipLaunchKernelGGL(push_deposit_split_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
-                           slices, slice_cap);
+                           slices, slice_cap, live);
     else
         hipLaunchKernelGGL(push_deposit_f64_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
-                           slices, slice_cap);
+                           slices, slice_cap, live);
+    if (A.counters)
+        hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, hdr, live, slice_cap, A.counters);
     return hipGetLastError();
 }
 
