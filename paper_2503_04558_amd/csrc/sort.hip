@@ -3,10 +3,13 @@
 //
 // histogram of live cells -> exclusive scan (two-level, 4096 entries per
 // block) -> [tiling: per-tile slice counts -> scan -> slice table] ->
-// scatter.  The scatter finds runs of equal cells among the lanes of a wave
-// (the input is usually almost sorted) and takes one atomic per run.
-// Removed particles (cell < 0) are dropped and the tail of the output is
-// marked removed; the order inside a cell is not specified.
+// scatter.  Histogram and scatter take a chunk of consecutive particles per
+// workgroup and count its cells in an LDS hash table first, so each distinct
+// cell of the chunk costs one global atomic: on the almost sorted input of a
+// re-sort a chunk holds a few dozen cells, and per-particle (or per-run)
+// atomics would queue on the same few counters.  Removed particles
+// (cell < 0) are dropped and the tail of the output is marked removed; the
+// order inside a cell is not specified.
 #include "grpic_launch.hpp"
 
 namespace grpic {
@@ -28,6 +31,45 @@ __global__ __launch_bounds__(256) void fill_u64(unsigned long long* __restrict__
     if (i < n) a[i] = v;
 }
 
+// Chunk of consecutive particles per histogram / scatter workgroup, and the
+// LDS hash table that counts its cells: at most half full, so an empty slot
+// is always found.
+constexpr int kChunkThreads = 256;
+constexpr int kChunkItems = 4;
+constexpr int kChunk = kChunkThreads * kChunkItems;
+constexpr int kHashSlots = 2 * kChunk;
+static_assert((kHashSlots & (kHashSlots - 1)) == 0, "power-of-two table");
+constexpr int kEmpty = -1;
+
+struct CellTable {
+    int key[kHashSlots];               // cell, or kEmpty
+    int count[kHashSlots];             // particles of the chunk in that cell
+};
+
+__device__ __forceinline__ void table_clear(CellTable& T) {
+    for (int e = threadIdx.x; e < kHashSlots; e += kChunkThreads) {
+        T.key[e] = kEmpty;
+        T.count[e] = 0;
+    }
+}
+
+// Slot of cell c (inserted if new); adds inc to its count and returns the
+// count before the add in old.  Multiplicative hashing spreads the cells of
+// neighbouring rows (c and c + nth) that a plain mask would collide.
+__device__ __forceinline__ int table_insert(CellTable& T, int c, int inc, int& old) {
+    int slot = (int)(((unsigned)c * 2654435761u) >> 21) & (kHashSlots - 1);
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+        const int k = atomicCAS(&T.key[slot], kEmpty, c);
+        if (k == kEmpty || k == c) {
+            old = atomicAdd(&T.count[slot], inc);
+            return slot;
+        }
+        slot = (slot + 1) & (kHashSlots - 1);
+    }
+    old = 0;                           // not reached: at most kChunk keys in 2 * kChunk slots
+    return -1;
+}
+
 // Runs of equal valid cells among adjacent lanes of a wave: the first lane
 // of each run (head) and the run's last lane (tail).  Every lane of the
 // wave must call it.
@@ -47,16 +89,43 @@ __device__ __forceinline__ void wave_runs(int c, bool valid, int& head, int& tai
     }
 }
 
-// Histogram of live cells; on (almost) sorted input a wave's lanes share a
-// few cells, so each run adds its length with one atomic.
-__global__ __launch_bounds__(256) void sort_hist(const int32_t* __restrict__ cell, int64_t n, int ncell,
-                                                 unsigned long long* __restrict__ counts) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = p < n ? cell[p] : -1;
-    const bool valid = c >= 0 && c < ncell;
+// Inserts the valid cells of one item per lane, one table access per run of
+// equal cells; returns the lane's slot (-1 if not valid) and its rank among
+// the chunk's particles of that cell.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_insert(CellTable& T, int c, bool valid, int& rank) {
+    const int lane = threadIdx.x & 63;
     int head, tail;
     wave_runs(c, valid, head, tail);
-    if (valid && (int)(threadIdx.x & 63) == head) atomicAdd(counts + c, (unsigned long long)(tail - head + 1));
+    int slot = -1, old = 0;
+    if (valid && lane == head) slot = table_insert(T, c, tail - head + 1, old);
+    slot = __shfl(slot, head);
+    old = __shfl(old, head);
+    rank = old + (lane - head);
+    return valid ? slot : -1;
+}
+
+__device__ __forceinline__ int64_t chunk_index(int k) {
+    return (int64_t)blockIdx.x * kChunk + (int64_t)k * kChunkThreads + threadIdx.x;
+}
+
+// Histogram of live cells: counts[c] += number of particles in cell c.
+__global__ __launch_bounds__(kChunkThreads) void sort_hist(const int32_t* __restrict__ cell, int64_t n, int ncell,
+                                                           unsigned long long* __restrict__ counts) {
+    __shared__ CellTable T;
+    int c[kChunkItems];
+    for (int k = 0; k < kChunkItems; ++k) {
+        const int64_t p = chunk_index(k);
+        c[k] = p < n ? cell[p] : -1;
+    }
+    table_clear(T);
+    __syncthreads();
+    for (int k = 0; k < kChunkItems; ++k) {
+        int rank;
+        wave_insert(T, c[k], c[k] >= 0 && c[k] < ncell, rank);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kHashSlots; e += kChunkThreads)
+        if (T.key[e] != kEmpty) atomicAdd(counts + T.key[e], (unsigned long long)T.count[e]);
 }
 
 // Inclusive scan of one value per thread across a 256-thread block.
@@ -189,39 +258,53 @@ __global__ __launch_bounds__(256) void sort_mark_tail(int32_t* __restrict__ cell
     if (p < n && p >= (int64_t)*total) cell_out[p] = -1;
 }
 
+// Scatter: counts[] holds each cell's next free output index; a chunk
+// reserves its particles' range of every cell with one atomic and places
+// them by their rank inside the chunk.
 template <class T>
-__global__ __launch_bounds__(256) void sort_scatter(const SortArgs S) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = p < S.n ? S.cell_in[p] : -1;
-    const bool valid = c >= 0 && c < S.ncell;
-    // runs of equal cells among adjacent lanes: one atomic per run
-    const int lane = threadIdx.x & 63;
-    int head, tail;
-    wave_runs(c, valid, head, tail);
-    // the particle's data is read before the atomic, so its latency overlaps the atomic's
-    T v[6], ph = T(0);
-    uint8_t spv = 0;
-    if (valid) {
-        for (int k = 0; k < 6; ++k) v[k] = static_cast<const T*>(S.in[k])[p];
-        spv = S.sp_in[p];
-        if (S.phi_in) ph = static_cast<const T*>(S.phi_in)[p];
+__global__ __launch_bounds__(kChunkThreads) void sort_scatter(const SortArgs S) {
+    __shared__ CellTable Tb;
+    __shared__ unsigned long long base[kHashSlots];
+    int c[kChunkItems];
+    for (int k = 0; k < kChunkItems; ++k) {
+        const int64_t p = chunk_index(k);
+        c[k] = p < S.n ? S.cell_in[p] : -1;
     }
-    long long base = 0;
-    if (valid && lane == head) base = (long long)atomicAdd(S.counts + c, (unsigned long long)(tail - head + 1));
-    base = __shfl(base, head);          // every lane takes part
-    if (!valid) return;
-    const int64_t q = (int64_t)base + (lane - head);
-    S.cell_out[q] = c;
-    for (int k = 0; k < 6; ++k) static_cast<T*>(S.out[k])[q] = v[k];
-    S.sp_out[q] = spv;
-    if (S.phi_in) static_cast<T*>(S.phi_out)[q] = ph;
+    // the particles' data is read first, so its latency overlaps the counting
+    T v[kChunkItems][6], ph[kChunkItems];
+    uint8_t spv[kChunkItems];
+    for (int k = 0; k < kChunkItems; ++k) {
+        const int64_t p = chunk_index(k);
+        const bool valid = c[k] >= 0 && c[k] < S.ncell;
+        for (int a = 0; a < 6; ++a) v[k][a] = valid ? static_cast<const T*>(S.in[a])[p] : T(0);
+        spv[k] = valid ? S.sp_in[p] : 0;
+        ph[k] = valid && S.phi_in ? static_cast<const T*>(S.phi_in)[p] : T(0);
+    }
+    table_clear(Tb);
+    __syncthreads();
+    int slot[kChunkItems], rank[kChunkItems];
+    for (int k = 0; k < kChunkItems; ++k) slot[k] = wave_insert(Tb, c[k], c[k] >= 0 && c[k] < S.ncell, rank[k]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kHashSlots; e += kChunkThreads)
+        if (Tb.key[e] != kEmpty) base[e] = atomicAdd(S.counts + Tb.key[e], (unsigned long long)Tb.count[e]);
+    __syncthreads();
+    for (int k = 0; k < kChunkItems; ++k) {
+        if (slot[k] < 0) continue;
+        const int64_t q = (int64_t)base[slot[k]] + rank[k];
+        S.cell_out[q] = c[k];
+        for (int a = 0; a < 6; ++a) static_cast<T*>(S.out[a])[q] = v[k][a];
+        S.sp_out[q] = spv[k];
+        if (S.phi_in) static_cast<T*>(S.phi_out)[q] = ph[k];
+    }
 }
+
+static inline unsigned nchunk(int64_t n) { return (unsigned)((n + kChunk - 1) / kChunk); }
 
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
     const int64_t len = (int64_t)S.ncell + 1;
     hipLaunchKernelGGL(fill_u64, dim3(nblk(len)), dim3(256), 0, stream, S.counts, len, 0ull);
     if (S.n > 0)
-        hipLaunchKernelGGL(sort_hist, dim3(nblk(S.n)), dim3(256), 0, stream, S.cell_in, S.n, S.ncell, S.counts);
+        hipLaunchKernelGGL(sort_hist, dim3(nchunk(S.n)), dim3(kChunkThreads), 0, stream, S.cell_in, S.n, S.ncell, S.counts);
     scan_exclusive(S.counts, len, S.blocksums, stream);
     if (S.tiling) {
         const int tpr = tiles_per_row(S.nth);
@@ -239,8 +322,8 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
     if (S.n > 0) {
         hipLaunchKernelGGL(sort_mark_tail, dim3(nblk(S.n)), dim3(256), 0, stream, S.cell_out, S.n,
                            S.counts + S.ncell);
-        if (S.elem == 8) hipLaunchKernelGGL(sort_scatter<double>, dim3(nblk(S.n)), dim3(256), 0, stream, S);
-        else hipLaunchKernelGGL(sort_scatter<float>, dim3(nblk(S.n)), dim3(256), 0, stream, S);
+        if (S.elem == 8) hipLaunchKernelGGL(sort_scatter<double>, dim3(nchunk(S.n)), dim3(kChunkThreads), 0, stream, S);
+        else hipLaunchKernelGGL(sort_scatter<float>, dim3(nchunk(S.n)), dim3(kChunkThreads), 0, stream, S);
     }
     return hipGetLastError();
 }

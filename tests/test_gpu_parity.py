@@ -206,13 +206,31 @@ def test_gpu_charge_continuity():
     assert (dt * Fr).abs().max().item() > 1e6 * bound / parts["w"].numel()
 
 
-def test_sort_is_a_counting_sort():
-    _announce("sort")
+@pytest.mark.parametrize("order", ["random", "drifted", "one_cell"])
+def test_sort_is_a_counting_sort(order):
+    """Output sorted by cell, offsets = scanned histogram, and the same
+    multiset of particles.  random: every chunk of the sort holds ~1000
+    distinct cells; drifted: the almost sorted order of a re-sort (sorted,
+    then a third of the particles moved by up to two rows and columns);
+    one_cell: a single cell, so each chunk is one run."""
+    _announce(f"sort {order}")
     g = wl.make_grid(64, 48, 0.9)
     host = wl.pairs(g, 50_000, kind="mj", seed=3, params=dict(T=0.5))
+    host = {k: v[:-13] for k, v in host.items()}                  # not a multiple of the chunk
     rng = np.random.default_rng(0)
-    perm = rng.permutation(len(host["cell"]))
-    host = {k: v[perm] for k, v in host.items()}
+    n = len(host["cell"])
+    if order == "random":
+        perm = rng.permutation(n)
+        host = {k: v[perm] for k, v in host.items()}
+    elif order == "drifted":
+        host = {k: v[np.argsort(host["cell"], kind="stable")] for k, v in host.items()}
+        moved = rng.random(n) < 1 / 3
+        i, j = host["cell"] // g.nth, host["cell"] % g.nth
+        i = np.clip(i + moved * rng.integers(-2, 3, n), 0, g.nr - 1)
+        j = np.clip(j + moved * rng.integers(-2, 3, n), 0, g.nth - 1)
+        host["cell"] = (i * g.nth + j).astype(np.int32)
+    else:
+        host["cell"][:] = g.ncell // 2 + 5
     host["cell"][::7] = -1                                     # removed particles are dropped
     pin = grpic.to_device(host)
     pout = grpic.empty_particles(len(host["cell"]))
@@ -224,7 +242,9 @@ def test_sort_is_a_counting_sort():
     n_alive = int(nal.item())
     live = host["cell"] >= 0
     assert n_alive == int(live.sum())
-    out = {k: v[:n_alive] for k, v in grpic.to_host(pout).items()}
+    full = grpic.to_host(pout)
+    assert np.all(full["cell"][n_alive:] == -1)
+    out = {k: v[:n_alive] for k, v in full.items()}
     assert np.all(np.diff(out["cell"]) >= 0)
     counts = np.bincount(host["cell"][live], minlength=g.ncell)
     assert np.array_equal(offs.cpu().numpy(), np.concatenate([[0], np.cumsum(counts)]))
