@@ -63,9 +63,25 @@ __device__ __forceinline__ double rcp(double x) {
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // 1 ulp
 
-// sqrt: the hardware instruction for float (1 ulp), the library for double.
-__device__ __forceinline__ double sqrt_fast(double x) { return sqrt(x); }
-__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sqrt(x) and 1/sqrt(x) together, for x >= 1 (or a positive normal x):
+// double refines the hardware reciprocal-square-root estimate y by two
+// coupled Newton steps on g ~ sqrt(x) = x y and h ~ 1/(2 sqrt(x)) = y/2
+// (residual r = 1/2 - g h; each step squares the relative error, so a few
+// ulp remain); float takes the estimate (1 ulp) and one product.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& sq, double& rsq) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    sq = fma(g, r, g);
+    rsq = 2.0 * fma(h, r, h);
+}
+__device__ __forceinline__ void sqrt_rsqrt(float x, float& sq, float& rsq) {
+    rsq = __builtin_amdgcn_rsqf(x);
+    sq = x * rsq;
+}
 
 // Kerr-Schild 3+1 quantities of App. A (mass M reinstated) at radius r and
 // polar angle with sine s, cosine c; with D set, their r and theta
@@ -77,14 +93,15 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
     const R irho2 = rcp(rho2);
     const R z = R(2) * M * r * irho2;
     const R opz = R(1) + z;
-    const R iopz = rcp(opz);
-    const R sq = sqrt_fast(opz);
+    R sq, rsq;                                    // sqrt(1+z) = 1/alpha, 1/sqrt(1+z) = alpha
+    sqrt_rsqrt(opz, sq, rsq);
+    const R iopz = rsq * rsq;
     const R is2 = rcp(s2);
     const R ra2 = r2 + a2;
     const R Delta = ra2 - R(2) * M * r;
     const R Sigma = ra2 * ra2 - a2 * Delta * s2;
     k.ialpha = sq;
-    k.alpha = sq * iopz;
+    k.alpha = rsq;
     k.beta = z * iopz;
     k.g_rr = opz;
     k.g_rp = -a * s2 * opz;
@@ -271,8 +288,10 @@ template <class R>
 __device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, R r, const Metric<R>& k,
                                                 const MetricDeriv<R>& d, R ur, R ut, R up, R f[5]) {
     const R uu = k.h_rr * ur * ur + R(2) * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
-    const R u0 = sqrt_fast(eps + uu) * k.ialpha;              // u^0 = sqrt(eps + u^2)/alpha
-    const R iu0 = rcp(u0);
+    R su, rsu;
+    sqrt_rsqrt(eps + uu, su, rsu);
+    const R u0 = su * k.ialpha;                               // u^0 = sqrt(eps + u^2)/alpha
+    const R iu0 = rsu * k.alpha;
     f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) * rcp(r) * R(A.idlnr);
     f[1] = k.h_tt * ut * iu0 * R(A.idth);
     f[2] = (k.h_rp * ur + k.h_pp * up) * iu0;
@@ -316,8 +335,9 @@ __device__ __forceinline__ void boris_kick(const Metric<R>& k, R qm, R dt, const
     for (int i = 0; i < 3; ++i) um[i] = u[i] + h * Dl[i];
     const R uu = k.h_rr * um[0] * um[0] + R(2) * k.h_rp * um[0] * um[2]
                + k.h_tt * um[1] * um[1] + k.h_pp * um[2] * um[2];
-    const R u0bar = sqrt_fast(R(1) + uu) * k.ialpha;
-    const R tf = qm * dt * R(0.5) * rcp(u0bar);
+    R su, rsu;
+    sqrt_rsqrt(R(1) + uu, su, rsu);
+    const R tf = qm * dt * R(0.5) * rsu * k.alpha;            // q/m dt / (2 u0bar), u0bar = sqrt(1 + u^2)/alpha
     const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
     const R tt = k.g_rr * t[0] * t[0] + R(2) * k.g_rp * t[0] * t[2]
                + k.g_tt * t[1] * t[1] + k.g_pp * t[2] * t[2];

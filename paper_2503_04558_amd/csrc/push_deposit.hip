@@ -21,6 +21,8 @@
 #include "grpic_device.hpp"
 #include "grpic_launch.hpp"
 
+#include <type_traits>
+
 namespace grpic {
 
 // Bilinear interpolation in index space of the grid array F at (f, h),
@@ -69,12 +71,35 @@ __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int c
     return make_anchor<R>(A, ci, cj);
 }
 
+// A particle's state as read at the start of a step (element type T: double,
+// or float in split precision); the weight is read later, where the deposit
+// needs it.  The tiled kernel issues these loads before its LDS set-up so
+// that their latency overlaps it.
+template <class T>
+struct ParticleIn {
+    int cell, s;
+    T dxr, dxt, u[3];
+};
+
+template <class T>
+__device__ __forceinline__ ParticleIn<T> load_particle(const StepArgs& A, int64_t p) {
+    ParticleIn<T> in;
+    in.cell = A.cell[p];
+    in.s = A.sp[p];
+    in.dxr = static_cast<const T*>(A.xr)[p];
+    in.dxt = static_cast<const T*>(A.xth)[p];
+    in.u[0] = static_cast<const T*>(A.ur)[p];
+    in.u[1] = static_cast<const T*>(A.uth)[p];
+    in.u[2] = static_cast<const T*>(A.uph)[p];
+    return in;
+}
+
 // Advances live particle p by one step in place.  Returns true when the move
 // is to be deposited (mv filled), false when the particle was or became
 // removed without a deposit.
-__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, Move& mv, Events& ev,
-                                            const TileAnchors* T) {
-    const int cell = A.cell[p];
+__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const ParticleIn<double>& in, Move& mv,
+                                            Events& ev, const TileAnchors* T) {
+    const int cell = in.cell;
     if (cell < 0) return false;
     ev.live = 1;
     double* xr = static_cast<double*>(A.xr);
@@ -83,8 +108,8 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, Move& 
     double* uth = static_cast<double*>(A.uth);
     double* uph = static_cast<double*>(A.uph);
     const double* w = static_cast<const double*>(A.w);
-    const double dxr = xr[p], dxt = xth[p];
-    const int s = A.sp[p];
+    const double dxr = in.dxr, dxt = in.dxt;
+    const int s = in.s;
     // Inputs that would index outside the grid arrays are removed as bad.
     if (cell >= A.nr * A.nth || s >= A.nsp || !(dxr >= 0.0 && dxr <= 1.0 && dxt >= 0.0 && dxt <= 1.0)) {
         ev.bad = 1;
@@ -93,7 +118,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, Move& 
     }
     const int ci = cell / A.nth, cj = cell - ci * A.nth;
     const double xi0 = (double)ci + dxr, eta0 = (double)cj + dxt;
-    double u[3] = {ur[p], uth[p], uph[p]};
+    double u[3] = {in.u[0], in.u[1], in.u[2]};
     const double* const* F = reinterpret_cast<const double* const*>(A.F);
     const double D[3] = {cic_f64(F[0], A, xi0 - 0.5, eta0), cic_f64(F[1], A, xi0, eta0 - 0.5),
                          cic_f64(F[2], A, xi0, eta0)};
@@ -208,9 +233,9 @@ __device__ __forceinline__ float offset_f32(double x) {
     return f < 1.0f ? f : 0.99999994f;
 }
 
-__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move& mv, Events& ev,
-                                              const TileAnchors* T) {
-    const int cell = A.cell[p];
+__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, const ParticleIn<float>& in, Move& mv,
+                                              Events& ev, const TileAnchors* T) {
+    const int cell = in.cell;
     if (cell < 0) return false;
     ev.live = 1;
     float* xr = static_cast<float*>(A.xr);
@@ -219,8 +244,8 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
     float* uth = static_cast<float*>(A.uth);
     float* uph = static_cast<float*>(A.uph);
     const float* w = static_cast<const float*>(A.w);
-    const float fxr = xr[p], fxt = xth[p];
-    const int s = A.sp[p];
+    const float fxr = in.dxr, fxt = in.dxt;
+    const int s = in.s;
     if (cell >= A.nr * A.nth || s >= A.nsp || !(fxr >= 0.0f && fxr <= 1.0f && fxt >= 0.0f && fxt <= 1.0f)) {
         ev.bad = 1;
         A.cell[p] = -1;
@@ -238,11 +263,11 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
     const bool fp64 = ci < A.fp64_rows || cj < A.pole_cols || cj >= A.nth - A.pole_cols;
     if (fp64) {
         const double D[3] = {Df[0], Df[1], Df[2]}, B[3] = {Bf[0], Bf[1], Bf[2]};
-        double u[3] = {ur[p], uth[p], uph[p]};
+        double u[3] = {in.u[0], in.u[1], in.u[2]};
         split_core<double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y, T);
         uph1 = u[2];
     } else {
-        float u[3] = {ur[p], uth[p], uph[p]};
+        float u[3] = {in.u[0], in.u[1], in.u[2]};
         float yf[5];
         split_core<float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf, T);
         for (int c = 0; c < 5; ++c) y[c] = yf[c];
@@ -282,10 +307,13 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, Move
 }
 
 template <bool SPLIT>
-__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, Move& mv, Events& ev,
-                                        const TileAnchors* T = nullptr) {
-    if constexpr (SPLIT) return advance_split(A, p, mv, ev, T);
-    else return advance_f64(A, p, mv, ev, T);
+using Elem = typename std::conditional<SPLIT, float, double>::type;
+
+template <bool SPLIT>
+__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
+                                        Events& ev, const TileAnchors* T = nullptr) {
+    if constexpr (SPLIT) return advance_split(A, p, in, mv, ev, T);
+    else return advance_f64(A, p, in, mv, ev, T);
 }
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
@@ -319,7 +347,7 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         Move mv;
-        if (advance<SPLIT>(A, p, mv, ev)) scatter_global(A, mv);
+        if (advance<SPLIT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev)) scatter_global(A, mv);
     }
     if (!A.counters) return;                                 // uniform
     __syncthreads();
@@ -357,6 +385,17 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
+    // one particle per thread; lane t takes particle (t % 8) * 32 + t / 8 of
+    // the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
+    // the slice's cells and their LDS atomics rarely hit one address.  Its
+    // state is loaded before the LDS set-up and the barrier (which waits for
+    // LDS accesses only), so the loads overlap them.
+    const int t = threadIdx.x;
+    const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
+    const int64_t p = sl.start + slot;
+    const bool mine = slot < sl.len && p < A.n;
+    ParticleIn<Elem<SPLIT>> in;
+    if (mine) in = load_particle<Elem<SPLIT>>(A, p);
 
     double2* wflat = reinterpret_cast<double2*>(&win[0][0][0]);
     static_assert((3 * kWinRows * kWinCols) % 2 == 0, "the window is cleared in pairs");
@@ -379,16 +418,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __syncthreads();
 
     Events ev = {0, 0, 0, 0, 0};
-    // one particle per thread; lane t takes particle (t % 8) * 32 + t / 8 of
-    // the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
-    // the slice's cells and their LDS atomics rarely hit one address
-    const int t = threadIdx.x;
-    const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
-    const int64_t p = sl.start + slot;
     int row_lo = kWinRows, row_hi = -1;                  // window rows this lane deposited on
-    if (slot < sl.len && p < A.n) {
+    if (mine) {
         Move mv;
-        if (advance<SPLIT>(A, p, mv, ev, &tab)) {
+        if (advance<SPLIT>(A, p, in, mv, ev, &tab)) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 esirkepov(mv, A.dt,
