@@ -131,7 +131,9 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     A.nr = g->nr; A.nth = g->nth; A.guard = g->guard; A.pitch = g->pitch;
     A.lnr0 = g->lnr0; A.dlnr = g->dlnr; A.dth = g->dth;
     A.idlnr = 1.0 / g->dlnr; A.idth = 1.0 / g->dth;
-    A.small_steps = (2.0 * g->dlnr <= grpic::kSmallArg && 2.0 * g->dth <= grpic::kSmallArg) ? 1 : 0;
+    A.small_steps = (2.0 * g->dlnr <= grpic::kTinyArg && 2.0 * g->dth <= grpic::kTinyArg)     ? 2
+                  : (2.0 * g->dlnr <= grpic::kSmallArg && 2.0 * g->dth <= grpic::kSmallArg) ? 1
+                                                                                             : 0;
     // split precision: FP64 where a step can reach r < 2M (the strong-field
     // region) and within a sin(theta) < kPoleSin band of the axis (+2 cells of reach)
     const double M = m ? m->M : 0.0;

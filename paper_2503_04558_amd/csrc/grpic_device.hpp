@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace grpic {
 
 constexpr int kMaxSpecies = 8;
@@ -20,7 +22,7 @@ struct StepArgs {
     int nr, nth, guard, pitch;
     double lnr0, dlnr, dth;
     double idlnr, idth;                     // 1/dlnr, 1/dth
-    int small_steps;                        // 2 dlnr and 2 dth <= kSmallArg: Taylor offsets
+    int small_steps;                        // Taylor offsets: 2 with 2 dlnr, 2 dth <= kTinyArg, 1 <= kSmallArg, else 0
     int fp64_rows;                          // split precision: rows i < fp64_rows run in FP64
     int pole_cols;                          // split precision: columns this close to the axis run in FP64
     double dt;
@@ -141,63 +143,71 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
 // two for |x|, |y| <= kSmallArg.  A point of a step is less than two cells
 // from its start cell's corner (a move is below one cell), so grids with
 // 2 dlnr and 2 dth <= kSmallArg use them; coarser grids use the library
-// functions (a grid-uniform choice).
+// functions (a grid-uniform choice).  Grids with 2 dlnr and 2 dth <=
+// kTinyArg take shorter series (exp to x^5, sin to y^5, cos to y^4; the
+// first omitted term is below a quarter ulp there).
 constexpr double kSmallArg = 0.07;
+constexpr double kTinyArg = 0.005;
 // Within ~5.7 degrees of a pole (anchor sin(theta) < kPoleSin) sin and cos
 // are taken from theta = eta * dth directly: there the centrifugal terms
 // (gamma^phph ~ 1/sin^2) amplify how sin(theta) is rounded, and this keeps
 // the rounding the same as in the plain formula.
 constexpr double kPoleSin = 0.1;
 
-template <class R>
+// SHORT selects the short series (a launch-uniform choice made once per
+// particle step, so that each variant is straight-line code).
+template <bool SHORT, class R>
 __device__ __forceinline__ R exp_small(R x) {
-    R p = R(1.0 / 3628800.0);
-    p = fma(p, x, R(1.0 / 362880.0));
-    p = fma(p, x, R(1.0 / 40320.0));
-    p = fma(p, x, R(1.0 / 5040.0));
-    p = fma(p, x, R(1.0 / 720.0));
-    p = fma(p, x, R(1.0 / 120.0));
-    p = fma(p, x, R(1.0 / 24.0));
-    p = fma(p, x, R(1.0 / 6.0));
-    p = fma(p, x, R(0.5));
-    p = fma(p, x, R(1.0));
-    return fma(p, x, R(1.0));
+    if constexpr (std::is_same<R, float>::value) {
+        // float: the series cut where the next term is below 1e-9 (|x| <= kSmallArg)
+        float p = 1.0f / 120.0f;
+        p = fmaf(p, x, 1.0f / 24.0f);
+        p = fmaf(p, x, 1.0f / 6.0f);
+        p = fmaf(p, x, 0.5f);
+        p = fmaf(p, x, 1.0f);
+        return fmaf(p, x, 1.0f);
+    } else {
+        R p = R(1.0 / 120.0);
+        if constexpr (!SHORT) {
+            p = R(1.0 / 3628800.0);
+            p = fma(p, x, R(1.0 / 362880.0));
+            p = fma(p, x, R(1.0 / 40320.0));
+            p = fma(p, x, R(1.0 / 5040.0));
+            p = fma(p, x, R(1.0 / 720.0));
+            p = fma(p, x, R(1.0 / 120.0));
+        }
+        p = fma(p, x, R(1.0 / 24.0));
+        p = fma(p, x, R(1.0 / 6.0));
+        p = fma(p, x, R(0.5));
+        p = fma(p, x, R(1.0));
+        return fma(p, x, R(1.0));
+    }
 }
 
-// float: the series cut where the next term is below 1e-9 (|x| <= kSmallArg).
-template <>
-__device__ __forceinline__ float exp_small<float>(float x) {
-    float p = 1.0f / 120.0f;
-    p = fmaf(p, x, 1.0f / 24.0f);
-    p = fmaf(p, x, 1.0f / 6.0f);
-    p = fmaf(p, x, 0.5f);
-    p = fmaf(p, x, 1.0f);
-    return fmaf(p, x, 1.0f);
-}
-
-template <class R>
+template <bool SHORT, class R>
 __device__ __forceinline__ void sincos_small(R y, R& sn, R& cs) {
     const R y2 = y * y;
-    R ps = R(1.0 / 362880.0);
-    ps = fma(ps, y2, R(-1.0 / 5040.0));
-    ps = fma(ps, y2, R(1.0 / 120.0));
-    ps = fma(ps, y2, R(-1.0 / 6.0));
-    sn = fma(ps * y2, y, y);
-    R pc = R(-1.0 / 3628800.0);
-    pc = fma(pc, y2, R(1.0 / 40320.0));
-    pc = fma(pc, y2, R(-1.0 / 720.0));
-    pc = fma(pc, y2, R(1.0 / 24.0));
-    pc = fma(pc, y2, R(-0.5));
-    cs = fma(pc, y2, R(1.0));
-}
-
-template <>
-__device__ __forceinline__ void sincos_small<float>(float y, float& sn, float& cs) {
-    const float y2 = y * y;
-    const float ps = fmaf(1.0f / 120.0f, y2, -1.0f / 6.0f);
-    sn = fmaf(ps * y2, y, y);
-    const float pc = fmaf(1.0f / 24.0f, y2, -0.5f);
-    cs = fmaf(pc, y2, 1.0f);
+    if constexpr (std::is_same<R, float>::value) {
+        const float ps = fmaf(1.0f / 120.0f, y2, -1.0f / 6.0f);
+        sn = fmaf(ps * y2, y, y);
+        const float pc = fmaf(1.0f / 24.0f, y2, -0.5f);
+        cs = fmaf(pc, y2, 1.0f);
+    } else {
+        R ps = R(1.0 / 120.0), pc = R(1.0 / 24.0);
+        if constexpr (!SHORT) {
+            ps = R(1.0 / 362880.0);
+            ps = fma(ps, y2, R(-1.0 / 5040.0));
+            ps = fma(ps, y2, R(1.0 / 120.0));
+            pc = R(-1.0 / 3628800.0);
+            pc = fma(pc, y2, R(1.0 / 40320.0));
+            pc = fma(pc, y2, R(-1.0 / 720.0));
+            pc = fma(pc, y2, R(1.0 / 24.0));
+        }
+        ps = fma(ps, y2, R(-1.0 / 6.0));
+        sn = fma(ps * y2, y, y);
+        pc = fma(pc, y2, R(-0.5));
+        cs = fma(pc, y2, R(1.0));
+    }
 }
 
 // r, sin(theta), cos(theta) at the corner (ci, cj) of a particle's start
@@ -237,13 +247,13 @@ __device__ __forceinline__ Anchor<R> make_anchor(const StepArgs& A, int ci, int 
 }
 
 // r, sin(theta), cos(theta) of the point (xi, eta) in grid units.
-template <class R>
+template <bool SHORT, class R>
 __device__ __forceinline__ void point_at(const StepArgs& A, const Anchor<R>& an, R xi, R eta, R& r, R& s, R& c) {
     if (A.small_steps) {
-        r = an.r * exp_small((xi - R(an.ci)) * R(A.dlnr));
+        r = an.r * exp_small<SHORT>((xi - R(an.ci)) * R(A.dlnr));
         if (an.s >= R(kPoleSin)) {
             R sy, cy;
-            sincos_small((eta - R(an.cj)) * R(A.dth), sy, cy);
+            sincos_small<SHORT>((eta - R(an.cj)) * R(A.dth), sy, cy);
             s = fma(an.s, cy, an.c * sy);
             c = fma(an.c, cy, -(an.s * sy));
         } else {
@@ -262,13 +272,13 @@ __device__ __forceinline__ void point_at(const StepArgs& A, const Anchor<R>& an,
 // Same from offsets (dxi, deta) relative to the anchor cell's corner (the
 // split-precision path integrates positions this way: in float an absolute
 // xi near 2000 would carry an ulp of 1e-4 cells).
-template <class R>
+template <bool SHORT, class R>
 __device__ __forceinline__ void point_rel(const StepArgs& A, const Anchor<R>& an, R dxi, R deta, R& r, R& s, R& c) {
     if (A.small_steps) {
-        r = an.r * exp_small(dxi * R(A.dlnr));
+        r = an.r * exp_small<SHORT>(dxi * R(A.dlnr));
         if (an.s >= R(kPoleSin)) {
             R sy, cy;
-            sincos_small(deta * R(A.dth), sy, cy);
+            sincos_small<SHORT>(deta * R(A.dth), sy, cy);
             s = fma(an.s, cy, an.c * sy);
             c = fma(an.c, cy, -(an.s * sy));
             return;
@@ -304,11 +314,11 @@ __device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, R r, c
 }
 
 // Same, evaluating the metric at (xi, eta) from the anchor.
-template <class R>
+template <bool SHORT, class R>
 __device__ __forceinline__ void geodesic_rhs(const StepArgs& A, const Anchor<R>& an, R eps, R xi, R eta,
                                              R ur, R ut, R up, R f[5]) {
     R r, s, c;
-    point_at(A, an, xi, eta, r, s, c);
+    point_at<SHORT>(A, an, xi, eta, r, s, c);
     Metric<R> k;
     MetricDeriv<R> d;
     ks_metric<R, true>(R(A.a), R(A.M), r, s, c, k, &d);

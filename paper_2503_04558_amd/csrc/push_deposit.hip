@@ -97,6 +97,7 @@ __device__ __forceinline__ ParticleIn<T> load_particle(const StepArgs& A, int64_
 // Advances live particle p by one step in place.  Returns true when the move
 // is to be deposited (mv filled), false when the particle was or became
 // removed without a deposit.
+template <bool SHORT>
 __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const ParticleIn<double>& in, Move& mv,
                                             Events& ev, const TileAnchors* T) {
     const int cell = in.cell;
@@ -133,7 +134,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const 
     {
         // metric and derivatives at x^n serve both the kick and the first RHS
         double r0, s0, c0;
-        point_at(A, an, xi0, eta0, r0, s0, c0);
+        point_at<SHORT>(A, an, xi0, eta0, r0, s0, c0);
         Metric<double> k0;
         MetricDeriv<double> d0;
         ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
@@ -144,7 +145,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const 
     const double y0[5] = {xi0, eta0, 0.0, u[0], u[1]};
     for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
     for (int it = 0; it < A.ncorr; ++it) {
-        geodesic_rhs(A, an, eps, yt[0], yt[1], yt[3], yt[4], u[2], f1);
+        geodesic_rhs<SHORT>(A, an, eps, yt[0], yt[1], yt[3], yt[4], u[2], f1);
         for (int c = 0; c < 5; ++c) yt[c] = y0[c] + 0.5 * dt * (f1[c] + f0[c]);
     }
     double xi1 = yt[0], eta1 = yt[1];
@@ -198,7 +199,7 @@ __device__ __forceinline__ float cic_f32(const float* __restrict__ F, const Step
 
 // Kick and predictor-corrector in precision R on offsets from the start
 // cell; y = (dxi, deta, phi, u_r, u_th) on return, u[2] = u_ph.
-template <class R>
+template <bool SHORT, class R>
 __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R dxr, R dxt, R eps, R qm,
                                            bool massless, const R D[3], const R B[3], R u[3], R yt[5],
                                            const TileAnchors* T) {
@@ -207,7 +208,7 @@ __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R 
     R f0[5], f1[5];
     {
         R r0, s0, c0;
-        point_rel(A, an, dxr, dxt, r0, s0, c0);
+        point_rel<SHORT>(A, an, dxr, dxt, r0, s0, c0);
         Metric<R> k0;
         MetricDeriv<R> d0;
         ks_metric<R, true>(R(A.a), R(A.M), r0, s0, c0, k0, &d0);
@@ -218,7 +219,7 @@ __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R 
     for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
     for (int it = 0; it < A.ncorr; ++it) {
         R r, sn, cs;
-        point_rel(A, an, yt[0], yt[1], r, sn, cs);
+        point_rel<SHORT>(A, an, yt[0], yt[1], r, sn, cs);
         Metric<R> k;
         MetricDeriv<R> d;
         ks_metric<R, true>(R(A.a), R(A.M), r, sn, cs, k, &d);
@@ -233,6 +234,7 @@ __device__ __forceinline__ float offset_f32(double x) {
     return f < 1.0f ? f : 0.99999994f;
 }
 
+template <bool SHORT>
 __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, const ParticleIn<float>& in, Move& mv,
                                               Events& ev, const TileAnchors* T) {
     const int cell = in.cell;
@@ -264,12 +266,12 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, cons
     if (fp64) {
         const double D[3] = {Df[0], Df[1], Df[2]}, B[3] = {Bf[0], Bf[1], Bf[2]};
         double u[3] = {in.u[0], in.u[1], in.u[2]};
-        split_core<double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y, T);
+        split_core<SHORT, double>(A, ci, cj, (double)fxr, (double)fxt, massless ? 0.0 : 1.0, qm, massless, D, B, u, y, T);
         uph1 = u[2];
     } else {
         float u[3] = {in.u[0], in.u[1], in.u[2]};
         float yf[5];
-        split_core<float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf, T);
+        split_core<SHORT, float>(A, ci, cj, fxr, fxt, massless ? 0.0f : 1.0f, (float)qm, massless, Df, Bf, u, yf, T);
         for (int c = 0; c < 5; ++c) y[c] = yf[c];
         uph1 = u[2];
     }
@@ -309,11 +311,13 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, cons
 template <bool SPLIT>
 using Elem = typename std::conditional<SPLIT, float, double>::type;
 
-template <bool SPLIT>
+// SHORT: the short Taylor series, for grids fine enough for them
+// (small_steps == 2); the launch picks the kernel variant.
+template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T = nullptr) {
-    if constexpr (SPLIT) return advance_split(A, p, in, mv, ev, T);
-    else return advance_f64(A, p, in, mv, ev, T);
+    if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T);
+    else return advance_f64<SHORT>(A, p, in, mv, ev, T);
 }
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
@@ -339,7 +343,7 @@ __device__ __forceinline__ void workgroup_events_to_global(const StepArgs& A, co
             if (cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
 }
 
-template <bool SPLIT>
+template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     __shared__ int cnt[5];
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
@@ -347,7 +351,7 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         Move mv;
-        if (advance<SPLIT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev)) scatter_global(A, mv);
+        if (advance<SPLIT, SHORT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev)) scatter_global(A, mv);
     }
     if (!A.counters) return;                                 // uniform
     __syncthreads();
@@ -356,10 +360,14 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     workgroup_events_to_global(A, cnt);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) { push_deposit_body<false>(A); }
-__global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { push_deposit_body<true>(A); }
+template <bool SHORT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) {
+    push_deposit_body<false, SHORT>(A);
+}
+template <bool SHORT>
+__global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { push_deposit_body<true, SHORT>(A); }
 
-template <bool SPLIT>
+template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
                                                         const Slice* __restrict__ slices, int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live) {
@@ -421,7 +429,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     int row_lo = kWinRows, row_hi = -1;                  // window rows this lane deposited on
     if (mine) {
         Move mv;
-        if (advance<SPLIT>(A, p, in, mv, ev, &tab)) {
+        if (advance<SPLIT, SHORT>(A, p, in, mv, ev, &tab)) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 esirkepov(mv, A.dt,
@@ -488,15 +496,17 @@ __global__ __launch_bounds__(256) void slice_live_sum(const TilingHeader* __rest
     }
 }
 
-__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(const StepArgs A, const TilingHeader* hdr,
-                                                                       const Slice* __restrict__ slices,
-                                                                       int64_t slice_cap, int32_t* slice_live) {
-    push_deposit_tiled_body<false>(A, hdr, slices, slice_cap, slice_live);
+template <bool SHORT>
+__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
+    const StepArgs A, const TilingHeader* hdr, const Slice* __restrict__ slices, int64_t slice_cap,
+    int32_t* slice_live) {
+    push_deposit_tiled_body<false, SHORT>(A, hdr, slices, slice_cap, slice_live);
 }
+template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A, const TilingHeader* hdr,
                                                                          const Slice* __restrict__ slices,
                                                                          int64_t slice_cap, int32_t* slice_live) {
-    push_deposit_tiled_body<true>(A, hdr, slices, slice_cap, slice_live);
+    push_deposit_tiled_body<true, SHORT>(A, hdr, slices, slice_cap, slice_live);
 }
 
 // Q_ij += q w S_ij(x_p) over live particles (FP64 or split offsets).
@@ -523,8 +533,11 @@ static inline dim3 blocks_for(int64_t n) { return dim3((unsigned)((n + 255) / 25
 
 hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream) {
     if (A.n <= 0) return hipSuccess;
-    if (split) hipLaunchKernelGGL(push_deposit_split, blocks_for(A.n), dim3(256), 0, stream, A);
-    else hipLaunchKernelGGL(push_deposit_f64, blocks_for(A.n), dim3(256), 0, stream, A);
+    const bool sh = A.small_steps == 2;
+    if (split && sh) hipLaunchKernelGGL(push_deposit_split<true>, blocks_for(A.n), dim3(256), 0, stream, A);
+    else if (split) hipLaunchKernelGGL(push_deposit_split<false>, blocks_for(A.n), dim3(256), 0, stream, A);
+    else if (sh) hipLaunchKernelGGL(push_deposit_f64<true>, blocks_for(A.n), dim3(256), 0, stream, A);
+    else hipLaunchKernelGGL(push_deposit_f64<false>, blocks_for(A.n), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
 
@@ -535,12 +548,12 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
     int32_t* live = tiling_slice_live(tiling, slice_cap);
     const int64_t grid = (slice_cap + 7) / 8 * 8;
-    if (split)
-        hipLaunchKernelGGL(push_deposit_split_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
-                           slices, slice_cap, live);
-    else
-        hipLaunchKernelGGL(push_deposit_f64_tiled, dim3((unsigned)grid), dim3(kPushThreads), 0, stream, A, hdr,
-                           slices, slice_cap, live);
+    const dim3 g((unsigned)grid), b(kPushThreads);
+    const bool sh = A.small_steps == 2;
+    if (split && sh) hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
+    else if (split) hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
+    else if (sh) hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
+    else hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
     if (A.counters)
         hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, hdr, live, slice_cap, A.counters);
     return hipGetLastError();

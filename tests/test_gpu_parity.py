@@ -128,6 +128,20 @@ def test_parity_photons_and_ions(tiled):
 
 
 @pytest.mark.parametrize("tiled", TILED)
+def test_parity_fine_grid_short_series(tiled):
+    """1600 x 1280, a = 0.99: twice the cell size is below 0.005 in ln r and
+    theta, so the kernels take their short Taylor series for the offsets of
+    the predictor-corrector points from the start cell (the 2048^2 workload
+    does too).  6e4 particles of that workload's recipe, 6 steps."""
+    _announce(f"parity fine grid short series tiled={tiled}")
+    g = wl.make_grid(1600, 1280, 0.99)
+    assert 2 * g.dlnr <= 0.005 and 2 * g.dth <= 0.005
+    parts = wl.pairs(g, 30_000, kind="mj", seed=11, params=dict(T=0.1, vphi=0.1))
+    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 6, TOL, tiled=tiled)
+    _announce(f"errors {e} counters {c}")
+
+
+@pytest.mark.parametrize("tiled", TILED)
 def test_parity_schwarzschild_full_crossing_dt(tiled):
     """a = 0 and the largest dt the library accepts (the full light-crossing
     time of the smallest cell): moves approach one cell per step."""

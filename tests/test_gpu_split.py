@@ -141,6 +141,20 @@ def test_split_error_report_1e6():
     assert rep["ill_conditioned"] <= 1e-3 * rep["n"], rep
 
 
+def test_split_error_report_fine_grid():
+    """1600 x 1280, a = 0.99 (short Taylor series for the point offsets),
+    6e4 particles of the 2048^2 workload's recipe, 10 steps, tiled."""
+    _announce("split 1600x1280 6e4 10 steps")
+    g = wl.make_grid(1600, 1280, 0.99)
+    assert 2 * g.dlnr <= 0.005 and 2 * g.dth <= 0.005
+    rep = split_report(g, wl.pairs(g, 30_000, kind="mj", seed=11, params=dict(T=0.1, vphi=0.1)), 10, tiled=True)
+    _announce(f"split report fine grid {rep}")
+    assert rep["status_mismatch"] <= rep["ill_conditioned"], rep
+    assert rep["mom_max"] <= MOM_TOL and rep["energy_max"] <= ENERGY_TOL, rep
+    assert rep["mom_violations"] == 0 and rep["energy_violations"] == 0, rep
+    assert rep["ill_conditioned"] <= 1e-3 * rep["n"], rep
+
+
 def test_split_continuity_on_gpu_outputs():
     _announce("split continuity 512x512 1e6")
     g = wl.make_grid(512, 512, 0.9)
