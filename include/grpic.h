@@ -155,10 +155,11 @@ typedef struct {
  *   that have drifted out of their tile's LDS window since the sort deposit
  *   straight to global memory, so results do not depend on how fresh the
  *   sort is.  Only particles live at the sort are pushed (the sort marks the
- *   rest removed); without a tiling any particle order works.  With
- *   counters, the push also writes each slice's live count into the tiling
- *   (pushes that share a tiling must be stream-ordered, as they share the
- *   particles anyway).
+ *   rest removed); without a tiling any particle order works.  A tiled
+ *   push also writes into the tiling: each launch first fills its table of
+ *   r, sin(theta) and cos(theta) at the cell corners its tiles start from,
+ *   and with counters each slice's live count (pushes that share a tiling
+ *   must be stream-ordered, as they share the particles anyway).
  * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
  * ckpt (optional, device, ckpt_bytes >= grpic_checkpoint_bytes(n, nsteps,
  *   ckpt_every)): the particle state is saved before every step k with

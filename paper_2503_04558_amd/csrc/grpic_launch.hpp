@@ -44,14 +44,27 @@ inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; 
 inline int64_t slice_capacity(int64_t n, int nr, int nth) {
     return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 1;
 }
-// Layout: header, slice table (capacity entries), then one int32 per slice
-// that a push with counters fills with the slice's live particle count (so
-// that the count needs no same-address atomics; a small kernel sums it).
+// Layout: header, slice table (capacity entries), one int32 per slice that
+// a push with counters fills with the slice's live particle count (so that
+// the count needs no same-address atomics; a small kernel sums it), then
+// (8-byte aligned) the anchor table that each tiled push fills before it
+// runs: r at the corners of rows -kMarginRows .. nr + kMarginRows - 1, then
+// sin and cos at columns -kMarginCols .. tiles_per_row * kTileCells +
+// kMarginCols, i.e. every anchor a tile's window can ask for.
+inline int anchor_table_rows(int nr) { return nr + 2 * kMarginRows; }
+inline int anchor_table_cols(int nth) { return tiles_per_row(nth) * kTileCells + 2 * kMarginCols + 1; }
+inline size_t tiling_anchor_offset(int64_t slice_cap) {
+    return (sizeof(TilingHeader) + (size_t)slice_cap * (sizeof(Slice) + sizeof(int32_t)) + 7) / 8 * 8;
+}
 inline size_t tiling_bytes(int64_t n, int nr, int nth) {
-    return sizeof(TilingHeader) + (size_t)slice_capacity(n, nr, nth) * (sizeof(Slice) + sizeof(int32_t));
+    return tiling_anchor_offset(slice_capacity(n, nr, nth)) +
+           sizeof(double) * ((size_t)anchor_table_rows(nr) + 2 * (size_t)anchor_table_cols(nth));
 }
 inline int32_t* tiling_slice_live(void* tiling, int64_t slice_cap) {
     return reinterpret_cast<int32_t*>(reinterpret_cast<Slice*>(static_cast<TilingHeader*>(tiling) + 1) + slice_cap);
+}
+inline double* tiling_anchors(void* tiling, int64_t slice_cap) {
+    return reinterpret_cast<double*>(static_cast<char*>(tiling) + tiling_anchor_offset(slice_cap));
 }
 
 // ---------------------------------------------------------------- launchers

@@ -21,6 +21,7 @@
 #include "grpic_device.hpp"
 #include "grpic_launch.hpp"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace grpic {
@@ -41,9 +42,9 @@ struct Events {
 
 // Anchors (r at a row's corner, sin and cos at a column's) of one tile and
 // the drift margin around it (rows ti - kMarginRows .. ti + kMarginRows,
-// columns j_lo - kMarginCols .. j_lo + kTileCells + kMarginCols), evaluated
-// once per workgroup into LDS; particles that have drifted further evaluate
-// their own.
+// columns j_lo - kMarginCols .. j_lo + kTileCells + kMarginCols), copied
+// once per workgroup into LDS from the launch's anchor table; particles that
+// have drifted further evaluate their own (same functions, same values).
 constexpr int kAnchorRows = 2 * kMarginRows + 1;
 constexpr int kAnchorCols = kTileCells + 2 * kMarginCols + 1;
 struct TileAnchors {
@@ -370,7 +371,8 @@ __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { pu
 template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
                                                         const Slice* __restrict__ slices, int64_t slice_cap,
-                                                        int32_t* __restrict__ slice_live) {
+                                                        int32_t* __restrict__ slice_live,
+                                                        const double* __restrict__ anchors) {
     __shared__ double win[3][kWinRows][kWinCols];
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
@@ -414,14 +416,21 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         touched[1] = -1;
     }
     if (A.small_steps) {
+        // table entry of row i is anchors[i + kMarginRows], of column j
+        // S[j + kMarginCols] and C[j + kMarginCols]
+        const double* S = anchors + (A.nr + 2 * kMarginRows);
+        const double* C = S + (tpr * kTileCells + 2 * kMarginCols + 1);
         const int t0 = threadIdx.x;
         if (t0 == 0) {
             tab.i_lo = ti - kMarginRows;
             tab.j_lo = j_lo - kMarginCols;
         }
-        if (t0 < kAnchorRows) tab.r[t0] = anchor_r(A, ti - kMarginRows + t0);
+        if (t0 < kAnchorRows) tab.r[t0] = anchors[ti + t0];
         const int k = t0 - 64;                                // columns: from the second wave on
-        if (k >= 0 && k < kAnchorCols) anchor_sc(A, j_lo - kMarginCols + k, tab.s[k], tab.c[k]);
+        if (k >= 0 && k < kAnchorCols) {
+            tab.s[k] = S[j_lo + k];
+            tab.c[k] = C[j_lo + k];
+        }
     }
     __syncthreads();
 
@@ -499,14 +508,28 @@ __global__ __launch_bounds__(256) void slice_live_sum(const TilingHeader* __rest
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
     const StepArgs A, const TilingHeader* hdr, const Slice* __restrict__ slices, int64_t slice_cap,
-    int32_t* slice_live) {
-    push_deposit_tiled_body<false, SHORT>(A, hdr, slices, slice_cap, slice_live);
+    int32_t* slice_live, const double* anchors) {
+    push_deposit_tiled_body<false, SHORT>(A, hdr, slices, slice_cap, slice_live, anchors);
 }
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A, const TilingHeader* hdr,
                                                                          const Slice* __restrict__ slices,
-                                                                         int64_t slice_cap, int32_t* slice_live) {
-    push_deposit_tiled_body<true, SHORT>(A, hdr, slices, slice_cap, slice_live);
+                                                                         int64_t slice_cap, int32_t* slice_live,
+                                                                         const double* anchors) {
+    push_deposit_tiled_body<true, SHORT>(A, hdr, slices, slice_cap, slice_live, anchors);
+}
+
+// The anchor table of a tiled launch (layout in grpic_launch.hpp).
+__global__ __launch_bounds__(256) void tile_anchor_table(const StepArgs A, double* __restrict__ anchors, int rows,
+                                                         int cols) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < rows) anchors[t] = anchor_r(A, t - kMarginRows);
+    if (t < cols) {
+        double s, c;
+        anchor_sc(A, t - kMarginCols, s, c);
+        anchors[rows + t] = s;
+        anchors[rows + cols + t] = c;
+    }
 }
 
 // Q_ij += q w S_ij(x_p) over live particles (FP64 or split offsets).
@@ -547,13 +570,23 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
     int32_t* live = tiling_slice_live(tiling, slice_cap);
+    double* anchors = tiling_anchors(tiling, slice_cap);
+    if (A.small_steps) {
+        const int rows = anchor_table_rows(A.nr), cols = anchor_table_cols(A.nth);
+        hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0,
+                           stream, A, anchors, rows, cols);
+    }
     const int64_t grid = (slice_cap + 7) / 8 * 8;
     const dim3 g((unsigned)grid), b(kPushThreads);
     const bool sh = A.small_steps == 2;
-    if (split && sh) hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
-    else if (split) hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
-    else if (sh) hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
-    else hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live);
+    if (split && sh)
+        hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+    else if (split)
+        hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+    else if (sh)
+        hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+    else
+        hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
     if (A.counters)
         hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, hdr, live, slice_cap, A.counters);
     return hipGetLastError();
