@@ -411,22 +411,34 @@ __device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
     // A move that stays in one cell row (column) touches vertex rows i0, i0+1
     // only, and its r-flux prefix sum is zero from the second row on (the
     // shape weights of both end points sum to 1 over those rows): those
-    // values are exactly zero and are not added.
+    // values are exactly zero and are not added.  The 21 entries fall into
+    // four groups by which of the two conditions they need (8 always, 5 with
+    // two_r, 5 with two_t, 3 with both), so a wave branches three times.
     const bool two_r = floor(m.xi0) != floor(m.xi1), two_t = floor(m.eta0) != floor(m.eta1);
-    double dx = 0.0, dy = 0.0;
-    for (int a = 0; a < 2; ++a) {
-        dx += wx1[a] - wx0[a];
-        dy += wy1[a] - wy0[a];
-        const double fx = hf * dx, fy = hf * dy;
-        for (int b = 0; b < 3; ++b) {
-            if ((a == 0 || two_r) && (b < 2 || two_t)) add(0, m.i0 + a, m.j0 + b, fx * (wy0[b] + wy1[b]));
-            if ((a == 0 || two_t) && (b < 2 || two_r)) add(1, m.i0 + b, m.j0 + a, fy * (wx0[b] + wx1[b]));
-        }
-    }
+    const double fx[2] = {hf * (wx1[0] - wx0[0]), hf * ((wx1[0] - wx0[0]) + (wx1[1] - wx0[1]))};
+    const double fy[2] = {hf * (wy1[0] - wy0[0]), hf * ((wy1[0] - wy0[0]) + (wy1[1] - wy0[1]))};
+    double p1[3], p0[3];
     for (int b = 0; b < 3; ++b) {
-        const double p1 = cp6 * fma(2.0, wy1[b], wy0[b]), p0 = cp6 * fma(2.0, wy0[b], wy1[b]);
-        for (int a = 0; a < 3; ++a)
-            if ((a < 2 || two_r) && (b < 2 || two_t)) add(2, m.i0 + a, m.j0 + b, fma(wx1[a], p1, wx0[a] * p0));
+        p1[b] = cp6 * fma(2.0, wy1[b], wy0[b]);
+        p0[b] = cp6 * fma(2.0, wy0[b], wy1[b]);
+    }
+    // F^r through (i0+a+1/2, j0+b), F^th through (i0+b, j0+a+1/2), G^ph at (i0+a, j0+b)
+    auto fr = [&](int a, int b) { add(0, m.i0 + a, m.j0 + b, fx[a] * (wy0[b] + wy1[b])); };
+    auto ft = [&](int a, int b) { add(1, m.i0 + b, m.j0 + a, fy[a] * (wx0[b] + wx1[b])); };
+    auto gp = [&](int a, int b) { add(2, m.i0 + a, m.j0 + b, fma(wx1[a], p1[b], wx0[a] * p0[b])); };
+    fr(0, 0); fr(0, 1); ft(0, 0); ft(0, 1);
+    gp(0, 0); gp(1, 0); gp(0, 1); gp(1, 1);
+    if (two_r) {
+        fr(1, 0); fr(1, 1); ft(0, 2);
+        gp(2, 0); gp(2, 1);
+    }
+    if (two_t) {
+        fr(0, 2); ft(1, 0); ft(1, 1);
+        gp(0, 2); gp(1, 2);
+    }
+    if (two_r && two_t) {
+        fr(1, 2); ft(1, 2);
+        gp(2, 2);
     }
 }
 
