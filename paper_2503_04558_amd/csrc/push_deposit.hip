@@ -376,7 +376,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __shared__ double win[3][kWinRows][kWinCols];
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
-    __shared__ int touched[2];                           // lowest and highest window row of a deposit
+    __shared__ int touched[4];                           // lowest, highest window row; lowest, highest column
     // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of slices so neighbouring tiles share its L2.
     const int64_t nslices = hdr->nslices;
@@ -414,6 +414,8 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (threadIdx.x == 0) {
         touched[0] = kWinRows;
         touched[1] = -1;
+        touched[2] = kWinCols;
+        touched[3] = -1;
     }
     if (A.small_steps) {
         // table entry of row i is anchors[i + kMarginRows], of column j
@@ -435,7 +437,8 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __syncthreads();
 
     Events ev = {0, 0, 0, 0, 0};
-    int row_lo = kWinRows, row_hi = -1;                  // window rows this lane deposited on
+    int row_lo = kWinRows, row_hi = -1;                  // window rows and columns this lane deposited on
+    int col_lo = kWinCols, col_hi = -1;
     if (mine) {
         Move mv;
         if (advance<SPLIT, SHORT>(A, p, in, mv, ev, &tab)) {
@@ -445,6 +448,8 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
                           [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
                 row_lo = li;
                 row_hi = li + 2;
+                col_lo = lj;
+                col_hi = lj + 2;
             } else {
                 scatter_global(A, mv);                   // drifted out of the window
                 ev.spill = 1;
@@ -454,10 +459,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     for (int off = 32; off > 0; off >>= 1) {
         row_lo = min(row_lo, __shfl_xor(row_lo, off));
         row_hi = max(row_hi, __shfl_xor(row_hi, off));
+        col_lo = min(col_lo, __shfl_xor(col_lo, off));
+        col_hi = max(col_hi, __shfl_xor(col_hi, off));
     }
     if ((threadIdx.x & 63) == 0 && row_hi >= 0) {
         atomicMin(&touched[0], row_lo);
         atomicMax(&touched[1], row_hi);
+        atomicMin(&touched[2], col_lo);
+        atomicMax(&touched[3], col_hi);
     }
     if (A.counters) wave_events_to_lds(ev, cnt);
     __syncthreads();
@@ -465,10 +474,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
     const int rows_lo = -A.guard, rows_hi = A.nr + A.guard;             // inclusive vertex rows
     const int cols_lo = -A.guard, cols_hi = A.pitch - A.guard - 1;      // inclusive vertex columns
-    // only the rows that received deposits
-    const int r0 = touched[0], nrow = touched[1] - touched[0] + 1;
-    for (int e = threadIdx.x; e < nrow * kWinCols; e += kPushThreads) {
-        const int rr = e / kWinCols, c = e - rr * kWinCols;
+    // only the rectangle of rows and columns that received deposits (a
+    // slice covers a few cells of its tile; empty when nothing was deposited)
+    const bool any = touched[1] >= 0;                    // then all four bounds are set
+    const int r0 = touched[0], nrow = any ? touched[1] - touched[0] + 1 : 0;
+    const int c0 = touched[2], ncol = any ? touched[3] - touched[2] + 1 : 1;
+    for (int e = threadIdx.x; e < nrow * ncol; e += kPushThreads) {
+        const int rr = e / ncol;
+        const int c = c0 + (e - rr * ncol);
         const int r = r0 + rr;
         const int gi = wi0 + r, gj = wj0 + c;
         if (gi < rows_lo || gi > rows_hi || gj < cols_lo || gj > cols_hi) continue;
