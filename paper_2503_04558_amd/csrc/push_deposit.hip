@@ -95,27 +95,45 @@ __device__ __forceinline__ ParticleIn<T> load_particle(const StepArgs& A, int64_
     return in;
 }
 
-// Advances live particle p by one step in place.  Returns true when the move
-// is to be deposited (mv filled), false when the particle was or became
-// removed without a deposit.
+// A particle's state after a step, for the caller to store: kind 0 nothing
+// (it was removed before the step), 1 removed now (cell = -1, the rest
+// unchanged), 2 the new cell, offsets and momenta in x = (xr, xth, ur, uth,
+// uph).
+template <class T>
+struct ParticleOut {
+    int kind, cell;
+    T x[5];
+};
+
+template <class T>
+__device__ __forceinline__ void store_particle(const StepArgs& A, int64_t p, const ParticleOut<T>& o) {
+    if (o.kind == 0) return;
+    A.cell[p] = o.kind == 2 ? o.cell : -1;
+    if (o.kind != 2) return;
+    static_cast<T*>(A.xr)[p] = o.x[0];
+    static_cast<T*>(A.xth)[p] = o.x[1];
+    static_cast<T*>(A.ur)[p] = o.x[2];
+    static_cast<T*>(A.uth)[p] = o.x[3];
+    static_cast<T*>(A.uph)[p] = o.x[4];
+}
+
+// Advances live particle p by one step; its new state goes to out.  Returns
+// true when the move is to be deposited (mv filled), false when the particle
+// was or became removed without a deposit.
 template <bool SHORT>
 __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const ParticleIn<double>& in, Move& mv,
-                                            Events& ev, const TileAnchors* T) {
+                                            Events& ev, const TileAnchors* T, ParticleOut<double>& out) {
+    out.kind = 0;
     const int cell = in.cell;
     if (cell < 0) return false;
     ev.live = 1;
-    double* xr = static_cast<double*>(A.xr);
-    double* xth = static_cast<double*>(A.xth);
-    double* ur = static_cast<double*>(A.ur);
-    double* uth = static_cast<double*>(A.uth);
-    double* uph = static_cast<double*>(A.uph);
+    out.kind = 1;
     const double* w = static_cast<const double*>(A.w);
     const double dxr = in.dxr, dxt = in.dxt;
     const int s = in.s;
     // Inputs that would index outside the grid arrays are removed as bad.
     if (cell >= A.nr * A.nth || s >= A.nsp || !(dxr >= 0.0 && dxr <= 1.0 && dxt >= 0.0 && dxt <= 1.0)) {
         ev.bad = 1;
-        A.cell[p] = -1;
         return false;
     }
     const int ci = cell / A.nth, cj = cell - ci * A.nth;
@@ -155,7 +173,6 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const 
                       && isfinite(yt[4]) && isfinite(u[2]);
     if (!finite || fabs(xi1 - xi0) >= 1.0 || fabs(eta1 - eta0) >= 1.0) {
         ev.bad = 1;
-        A.cell[p] = -1;
         return false;
     }
     if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
@@ -164,17 +181,17 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const 
     if (A.phi) static_cast<double*>(A.phi)[p] += yt[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
-        A.cell[p] = -1;
     } else {
         const int i1 = (int)floor(xi1);
         int j1 = (int)floor(eta1);
         if (j1 >= A.nth) j1 = A.nth - 1;
-        A.cell[p] = i1 * A.nth + j1;
-        xr[p] = xi1 - (double)i1;
-        xth[p] = eta1 - (double)j1;
-        ur[p] = yt[3];
-        uth[p] = u1t;
-        uph[p] = u[2];
+        out.kind = 2;
+        out.cell = i1 * A.nth + j1;
+        out.x[0] = xi1 - (double)i1;
+        out.x[1] = eta1 - (double)j1;
+        out.x[2] = yt[3];
+        out.x[3] = u1t;
+        out.x[4] = u[2];
     }
     return true;
 }
@@ -237,21 +254,17 @@ __device__ __forceinline__ float offset_f32(double x) {
 
 template <bool SHORT>
 __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, const ParticleIn<float>& in, Move& mv,
-                                              Events& ev, const TileAnchors* T) {
+                                              Events& ev, const TileAnchors* T, ParticleOut<float>& out) {
+    out.kind = 0;
     const int cell = in.cell;
     if (cell < 0) return false;
     ev.live = 1;
-    float* xr = static_cast<float*>(A.xr);
-    float* xth = static_cast<float*>(A.xth);
-    float* ur = static_cast<float*>(A.ur);
-    float* uth = static_cast<float*>(A.uth);
-    float* uph = static_cast<float*>(A.uph);
+    out.kind = 1;
     const float* w = static_cast<const float*>(A.w);
     const float fxr = in.dxr, fxt = in.dxt;
     const int s = in.s;
     if (cell >= A.nr * A.nth || s >= A.nsp || !(fxr >= 0.0f && fxr <= 1.0f && fxt >= 0.0f && fxt <= 1.0f)) {
         ev.bad = 1;
-        A.cell[p] = -1;
         return false;
     }
     const int ci = cell / A.nth, cj = cell - ci * A.nth;
@@ -283,7 +296,6 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, cons
                       && isfinite(uph1);
     if (!finite || fabs(xi1 - xi0) >= 1.0 || fabs(eta1 - eta0) >= 1.0) {
         ev.bad = 1;
-        A.cell[p] = -1;
         return false;
     }
     if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
@@ -297,14 +309,14 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, cons
     if (A.phi) static_cast<float*>(A.phi)[p] += (float)y[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
-        A.cell[p] = -1;
     } else {
-        A.cell[p] = i1 * A.nth + j1;
-        xr[p] = ox;
-        xth[p] = oy;
-        ur[p] = (float)y[3];
-        uth[p] = (float)u1t;
-        uph[p] = (float)uph1;
+        out.kind = 2;
+        out.cell = i1 * A.nth + j1;
+        out.x[0] = ox;
+        out.x[1] = oy;
+        out.x[2] = (float)y[3];
+        out.x[3] = (float)u1t;
+        out.x[4] = (float)uph1;
     }
     return true;
 }
@@ -316,9 +328,9 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 // (small_steps == 2); the launch picks the kernel variant.
 template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
-                                        Events& ev, const TileAnchors* T = nullptr) {
-    if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T);
-    else return advance_f64<SHORT>(A, p, in, mv, ev, T);
+                                        Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
+    if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T, out);
+    else return advance_f64<SHORT>(A, p, in, mv, ev, T, out);
 }
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
@@ -352,7 +364,10 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         Move mv;
-        if (advance<SPLIT, SHORT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev)) scatter_global(A, mv);
+        ParticleOut<Elem<SPLIT>> out;
+        const bool dep = advance<SPLIT, SHORT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev, nullptr, out);
+        store_particle(A, p, out);
+        if (dep) scatter_global(A, mv);
     }
     if (!A.counters) return;                                 // uniform
     __syncthreads();
@@ -377,6 +392,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
     __shared__ int touched[4];                           // lowest, highest window row; lowest, highest column
+    // the slice's new particle states, by slot (one pad element per 32 keeps
+    // the permuted lanes' writes on distinct banks): written back in slot
+    // order after the deposit, so that consecutive lanes store consecutive
+    // particles (the loads stay in the pushing lanes: staging them too would
+    // make each wave wait for its loads before the first barrier)
+    constexpr int kStage = kSliceMax + kSliceMax / 32;
+    __shared__ int st_kind[kStage], st_cell[kStage];
+    __shared__ Elem<SPLIT> st_x[5][kStage];
     // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of slices so neighbouring tiles share its L2.
     const int64_t nslices = hdr->nslices;
@@ -395,7 +418,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
-    // one particle per thread; lane t takes particle (t % 8) * 32 + t / 8 of
+    // one particle per thread; lane t pushes particle (t % 8) * 32 + t / 8 of
     // the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
     // the slice's cells and their LDS atomics rarely hit one address.  Its
     // state is loaded before the LDS set-up and the barrier (which waits for
@@ -441,7 +464,13 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     int col_lo = kWinCols, col_hi = -1;
     if (mine) {
         Move mv;
-        if (advance<SPLIT, SHORT>(A, p, in, mv, ev, &tab)) {
+        ParticleOut<Elem<SPLIT>> out;
+        const bool dep = advance<SPLIT, SHORT>(A, p, in, mv, ev, &tab, out);
+        const int si = slot + slot / 32;
+        st_kind[si] = out.kind;
+        st_cell[si] = out.cell;
+        for (int k = 0; k < 5; ++k) st_x[k][si] = out.x[k];
+        if (dep) {
             const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
             if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
                 esirkepov(mv, A.dt,
@@ -490,6 +519,15 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             const double v = win[a][r][c];
             if (v != 0.0) atomicAdd(J[a] + g, v);
         }
+    }
+    // the new particle states, thread t storing slot t
+    if (t < sl.len && sl.start + t < A.n) {
+        const int si = t + t / 32;
+        ParticleOut<Elem<SPLIT>> o;
+        o.kind = st_kind[si];
+        o.cell = st_cell[si];
+        for (int k = 0; k < 5; ++k) o.x[k] = st_x[k][si];
+        store_particle(A, sl.start + t, o);
     }
     if (A.counters && threadIdx.x == 0) {
         // the live count goes to the slice's own word (summed by slice_live_sum);
