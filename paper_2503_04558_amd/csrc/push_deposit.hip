@@ -499,6 +499,16 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     }
     if (A.counters) wave_events_to_lds(ev, cnt);
     __syncthreads();
+    // the new particle states, thread t storing slot t (before the flush, so
+    // that the stores' latency overlaps it)
+    if (t < sl.len && sl.start + t < A.n) {
+        const int si = t + t / 32;
+        ParticleOut<Elem<SPLIT>> o;
+        o.kind = st_kind[si];
+        o.cell = st_cell[si];
+        for (int k = 0; k < 5; ++k) o.x[k] = st_x[k][si];
+        store_particle(A, sl.start + t, o);
+    }
     // flush the window's non-zero entries that lie inside the grid arrays
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
     const int rows_lo = -A.guard, rows_hi = A.nr + A.guard;             // inclusive vertex rows
@@ -519,15 +529,6 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             const double v = win[a][r][c];
             if (v != 0.0) atomicAdd(J[a] + g, v);
         }
-    }
-    // the new particle states, thread t storing slot t
-    if (t < sl.len && sl.start + t < A.n) {
-        const int si = t + t / 32;
-        ParticleOut<Elem<SPLIT>> o;
-        o.kind = st_kind[si];
-        o.cell = st_cell[si];
-        for (int k = 0; k < 5; ++k) o.x[k] = st_x[k][si];
-        store_particle(A, sl.start + t, o);
     }
     if (A.counters && threadIdx.x == 0) {
         // the live count goes to the slice's own word (summed by slice_live_sum);
