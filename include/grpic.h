@@ -21,7 +21,9 @@
  * value at (i + s_r, j + s_th):
  *   D^r, B^th, F^r : (1/2, 0)     D^th, B^r, F^th : (0, 1/2)
  *   D^ph, G^ph     : (0, 0)       B^ph            : (1/2, 1/2)
- * guard >= 2 and pitch >= nth + 1 + 2*guard are required.
+ * guard >= 2 and pitch >= nth + 1 + 2*guard are required, and a grid array
+ * of (nr + 1 + 2*guard) x pitch doubles must stay below 4 GiB (the kernels
+ * address grid arrays with 32-bit offsets).
  *
  * Particles (structure of arrays, one element per particle):
  *   cell  int32   i*nth + j of the cell holding the particle, -1 = removed

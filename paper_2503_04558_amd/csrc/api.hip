@@ -47,6 +47,8 @@ int check_grid(const grpic_grid* g) {
     if (g->guard < 2) return fail(GRPIC_EINVAL, "grid: guard must be >= 2 (got %d)", g->guard);
     if (g->pitch < g->nth + 1 + 2 * g->guard)
         return fail(GRPIC_EINVAL, "grid: pitch %d < nth + 1 + 2*guard", g->pitch);
+    if ((int64_t)(g->nr + 1 + 2 * g->guard) * g->pitch * (int64_t)sizeof(double) > (int64_t)UINT32_MAX)
+        return fail(GRPIC_EINVAL, "grid: arrays of (nr + 1 + 2*guard) x pitch doubles must stay below 4 GiB");
     if (!isfinite(g->lnr0) || !(g->dlnr > 0.0) || !isfinite(g->dlnr))
         return fail(GRPIC_EINVAL, "grid: lnr0 must be finite and dlnr > 0");
     const double dth = M_PI / g->nth;

@@ -442,8 +442,19 @@ __device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
     }
 }
 
-__device__ __forceinline__ long grid_index(const StepArgs& A, int i, int j) {
-    return (long)(i + A.guard) * A.pitch + (j + A.guard);
+// Element index of vertex (i, j) in a grid array; every grid array is below
+// 4 GiB (checked at the boundary), so indices and byte offsets fit in 32 bits.
+__device__ __forceinline__ uint32_t grid_index(const StepArgs& A, int i, int j) {
+    return (uint32_t)((i + A.guard) * A.pitch + (j + A.guard));
+}
+
+// Element idx of an array from a workgroup-uniform base by a 32-bit byte
+// offset, which the loads and stores take as a scalar base register plus a
+// vector offset (no 64-bit address arithmetic per lane).
+template <class T>
+__device__ __forceinline__ T* elem(T* base, uint32_t idx) {
+    return reinterpret_cast<T*>(reinterpret_cast<typename std::conditional<std::is_const<T>::value, const char, char>::type*>(base) +
+                                idx * (uint32_t)sizeof(T));
 }
 
 }  // namespace grpic

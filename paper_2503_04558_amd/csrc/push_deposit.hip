@@ -28,12 +28,17 @@ namespace grpic {
 
 // Bilinear interpolation in index space of the grid array F at (f, h),
 // where (f, h) are grid coordinates already shifted by the stagger.
+// Two consecutive elements of a row as one vector load (8-byte aligned).
+typedef double double2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 __device__ __forceinline__ double cic_f64(const double* __restrict__ F, const StepArgs& A, double f, double h) {
     const int i = (int)floor(f), j = (int)floor(h);
     const double wf = f - (double)i, wh = h - (double)j;
-    const double* p = F + grid_index(A, i, j);
-    return (1.0 - wf) * (1.0 - wh) * p[0] + wf * (1.0 - wh) * p[A.pitch]
-         + (1.0 - wf) * wh * p[1] + wf * wh * p[A.pitch + 1];
+    const uint32_t o = grid_index(A, i, j);
+    const double2_a8 lo = *reinterpret_cast<const double2_a8*>(elem(F, o));
+    const double2_a8 hi = *reinterpret_cast<const double2_a8*>(elem(F, o + (uint32_t)A.pitch));
+    return (1.0 - wf) * (1.0 - wh) * lo.x + wf * (1.0 - wh) * hi.x + (1.0 - wf) * wh * lo.y + wf * wh * hi.y;
 }
 
 struct Events {
@@ -82,16 +87,30 @@ struct ParticleIn {
     T dxr, dxt, u[3];
 };
 
+// Particle base + k of the particle arrays: base is uniform across the
+// workgroup (its slice's or block's first particle), so each access is a
+// scalar base register plus a 32-bit lane offset.
+struct PIdx {
+    int64_t base;
+    uint32_t k;
+    template <class T>
+    __device__ __forceinline__ T* at(T* arr) const { return elem(arr + base, k); }
+    template <class T>
+    __device__ __forceinline__ T* at(void* arr) const { return at(static_cast<T*>(arr)); }
+    template <class T>
+    __device__ __forceinline__ const T* at(const void* arr) const { return at(static_cast<const T*>(arr)); }
+};
+
 template <class T>
-__device__ __forceinline__ ParticleIn<T> load_particle(const StepArgs& A, int64_t p) {
+__device__ __forceinline__ ParticleIn<T> load_particle(const StepArgs& A, const PIdx& p) {
     ParticleIn<T> in;
-    in.cell = A.cell[p];
-    in.s = A.sp[p];
-    in.dxr = static_cast<const T*>(A.xr)[p];
-    in.dxt = static_cast<const T*>(A.xth)[p];
-    in.u[0] = static_cast<const T*>(A.ur)[p];
-    in.u[1] = static_cast<const T*>(A.uth)[p];
-    in.u[2] = static_cast<const T*>(A.uph)[p];
+    in.cell = *p.at(A.cell);
+    in.s = *p.at(A.sp);
+    in.dxr = *p.at<T>(A.xr);
+    in.dxt = *p.at<T>(A.xth);
+    in.u[0] = *p.at<T>(A.ur);
+    in.u[1] = *p.at<T>(A.uth);
+    in.u[2] = *p.at<T>(A.uph);
     return in;
 }
 
@@ -106,22 +125,22 @@ struct ParticleOut {
 };
 
 template <class T>
-__device__ __forceinline__ void store_particle(const StepArgs& A, int64_t p, const ParticleOut<T>& o) {
+__device__ __forceinline__ void store_particle(const StepArgs& A, const PIdx& p, const ParticleOut<T>& o) {
     if (o.kind == 0) return;
-    A.cell[p] = o.kind == 2 ? o.cell : -1;
+    *p.at(A.cell) = o.kind == 2 ? o.cell : -1;
     if (o.kind != 2) return;
-    static_cast<T*>(A.xr)[p] = o.x[0];
-    static_cast<T*>(A.xth)[p] = o.x[1];
-    static_cast<T*>(A.ur)[p] = o.x[2];
-    static_cast<T*>(A.uth)[p] = o.x[3];
-    static_cast<T*>(A.uph)[p] = o.x[4];
+    *p.at<T>(A.xr) = o.x[0];
+    *p.at<T>(A.xth) = o.x[1];
+    *p.at<T>(A.ur) = o.x[2];
+    *p.at<T>(A.uth) = o.x[3];
+    *p.at<T>(A.uph) = o.x[4];
 }
 
 // Advances live particle p by one step; its new state goes to out.  Returns
 // true when the move is to be deposited (mv filled), false when the particle
 // was or became removed without a deposit.
 template <bool SHORT>
-__device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const ParticleIn<double>& in, Move& mv,
+__device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, const ParticleIn<double>& in, Move& mv,
                                             Events& ev, const TileAnchors* T, ParticleOut<double>& out) {
     out.kind = 0;
     const int cell = in.cell;
@@ -177,8 +196,8 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, int64_t p, const 
     }
     if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
     else if (eta1 > (double)A.nth) { eta1 = 2.0 * A.nth - eta1; u1t = -u1t; ev.refl = 1; }
-    mv = make_move(A.q[s] * w[p], xi0, eta0, xi1, eta1, yt[2]);
-    if (A.phi) static_cast<double*>(A.phi)[p] += yt[2];
+    mv = make_move(A.q[s] * *p.at(w), xi0, eta0, xi1, eta1, yt[2]);
+    if (A.phi) *p.at<double>(A.phi) += yt[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
     } else {
@@ -210,9 +229,10 @@ __device__ __forceinline__ float cic_f32(const float* __restrict__ F, const Step
                                          float fx, float fy) {
     const float fi = floorf(fx), fj = floorf(fy);
     const float wf = fx - fi, wh = fy - fj;
-    const float* q = F + grid_index(A, ci + (int)fi, cj + (int)fj);
-    return (1.0f - wf) * (1.0f - wh) * q[0] + wf * (1.0f - wh) * q[A.pitch]
-         + (1.0f - wf) * wh * q[1] + wf * wh * q[A.pitch + 1];
+    const uint32_t o = grid_index(A, ci + (int)fi, cj + (int)fj);
+    const float2_a4 lo = *reinterpret_cast<const float2_a4*>(elem(F, o));
+    const float2_a4 hi = *reinterpret_cast<const float2_a4*>(elem(F, o + (uint32_t)A.pitch));
+    return (1.0f - wf) * (1.0f - wh) * lo.x + wf * (1.0f - wh) * hi.x + (1.0f - wf) * wh * lo.y + wf * wh * hi.y;
 }
 
 // Kick and predictor-corrector in precision R on offsets from the start
@@ -253,7 +273,7 @@ __device__ __forceinline__ float offset_f32(double x) {
 }
 
 template <bool SHORT>
-__device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, const ParticleIn<float>& in, Move& mv,
+__device__ __forceinline__ bool advance_split(const StepArgs& A, const PIdx& p, const ParticleIn<float>& in, Move& mv,
                                               Events& ev, const TileAnchors* T, ParticleOut<float>& out) {
     out.kind = 0;
     const int cell = in.cell;
@@ -305,8 +325,8 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, int64_t p, cons
     int j1 = (int)floor(eta1);
     if (j1 >= A.nth) j1 = A.nth - 1;
     const float ox = offset_f32(xi1 - (double)i1), oy = offset_f32(eta1 - (double)j1);
-    mv = make_move(A.q[s] * (double)w[p], xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2]);
-    if (A.phi) static_cast<float*>(A.phi)[p] += (float)y[2];
+    mv = make_move(A.q[s] * (double)*p.at(w), xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2]);
+    if (A.phi) *p.at<float>(A.phi) += (float)y[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
     } else {
@@ -327,7 +347,7 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 // SHORT: the short Taylor series, for grids fine enough for them
 // (small_steps == 2); the launch picks the kernel variant.
 template <bool SPLIT, bool SHORT>
-__device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
+__device__ __forceinline__ bool advance(const StepArgs& A, const PIdx& p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
     if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T, out);
     else return advance_f64<SHORT>(A, p, in, mv, ev, T, out);
@@ -335,7 +355,7 @@ __device__ __forceinline__ bool advance(const StepArgs& A, int64_t p, const Part
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
-    esirkepov(mv, A.dt, [&](int c, int i, int j, double v) { atomicAdd(J[c] + grid_index(A, i, j), v); });
+    esirkepov(mv, A.dt, [&](int c, int i, int j, double v) { atomicAdd(elem(J[c], grid_index(A, i, j)), v); });
 }
 
 // Event counts of a workgroup: each wave adds its ballot counts to five LDS
@@ -360,13 +380,14 @@ template <bool SPLIT, bool SHORT>
 __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     __shared__ int cnt[5];
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const PIdx pi{(int64_t)blockIdx.x * blockDim.x, threadIdx.x};
+    const int64_t p = pi.base + pi.k;
     Events ev = {0, 0, 0, 0, 0};
     if (p < A.n) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT>(A, p, load_particle<Elem<SPLIT>>(A, p), mv, ev, nullptr, out);
-        store_particle(A, p, out);
+        const bool dep = advance<SPLIT, SHORT>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
+        store_particle(A, pi, out);
         if (dep) scatter_global(A, mv);
     }
     if (!A.counters) return;                                 // uniform
@@ -425,10 +446,11 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     // LDS accesses only), so the loads overlap them.
     const int t = threadIdx.x;
     const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
+    const PIdx pi{sl.start, (uint32_t)slot};
     const int64_t p = sl.start + slot;
     const bool mine = slot < sl.len && p < A.n;
     ParticleIn<Elem<SPLIT>> in;
-    if (mine) in = load_particle<Elem<SPLIT>>(A, p);
+    if (mine) in = load_particle<Elem<SPLIT>>(A, pi);
 
     double2* wflat = reinterpret_cast<double2*>(&win[0][0][0]);
     static_assert((3 * kWinRows * kWinCols) % 2 == 0, "the window is cleared in pairs");
@@ -465,7 +487,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (mine) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT>(A, p, in, mv, ev, &tab, out);
+        const bool dep = advance<SPLIT, SHORT>(A, pi, in, mv, ev, &tab, out);
         const int si = slot + slot / 32;
         st_kind[si] = out.kind;
         st_cell[si] = out.cell;
@@ -507,7 +529,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         o.kind = st_kind[si];
         o.cell = st_cell[si];
         for (int k = 0; k < 5; ++k) o.x[k] = st_x[k][si];
-        store_particle(A, sl.start + t, o);
+        store_particle(A, PIdx{sl.start, (uint32_t)t}, o);
     }
     // flush the window's non-zero entries that lie inside the grid arrays
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
@@ -524,10 +546,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         const int r = r0 + rr;
         const int gi = wi0 + r, gj = wj0 + c;
         if (gi < rows_lo || gi > rows_hi || gj < cols_lo || gj > cols_hi) continue;
-        const long g = grid_index(A, gi, gj);
+        const uint32_t g = grid_index(A, gi, gj);
         for (int a = 0; a < 3; ++a) {
             const double v = win[a][r][c];
-            if (v != 0.0) atomicAdd(J[a] + g, v);
+            if (v != 0.0) atomicAdd(elem(J[a], g), v);
         }
     }
     if (A.counters && threadIdx.x == 0) {

@@ -37,6 +37,21 @@ def test_crossing_time_matches_generator():
     assert bad < 0
 
 
+def test_grid_arrays_above_4gib_are_rejected():
+    """Grid arrays are addressed with 32-bit byte offsets: (nr + 1 + 2 guard)
+    x pitch doubles must stay below 4 GiB."""
+    g = wl.make_grid(64, 32, 0.5)
+    ok = grpic.make_grid(g)
+    assert grpic.grpic_crossing_time(grpic.make_metric(0.5, 1.0), g) > 0
+    rows = ok.nr + 1 + 2 * ok.guard
+    big = grpic.grpic_grid(ok.nr, ok.nth, ok.guard, (2 ** 32) // (8 * rows) + 1, ok.lnr0, ok.dlnr, ok.dth)
+    assert rows * big.pitch * 8 > 2 ** 32 - 1
+    assert grpic.lib().grpic_crossing_time(ctypes.byref(grpic.make_metric(0.5, 1.0)), ctypes.byref(big)) < 0
+    assert "4 GiB" in grpic.lib().grpic_last_error().decode()
+    fits = grpic.grpic_grid(ok.nr, ok.nth, ok.guard, (2 ** 32 - 1) // (8 * rows), ok.lnr0, ok.dlnr, ok.dth)
+    assert grpic.lib().grpic_crossing_time(ctypes.byref(grpic.make_metric(0.5, 1.0)), ctypes.byref(fits)) > 0
+
+
 def _call_push(metric, grid, species, nsp, parts, fields, cur, dt, nsteps=1, ncorr=3):
     L = grpic.lib()
     return L.grpic_push_deposit(
