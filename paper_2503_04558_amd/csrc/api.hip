@@ -133,6 +133,8 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     A.nr = g->nr; A.nth = g->nth; A.guard = g->guard; A.pitch = g->pitch;
     A.lnr0 = g->lnr0; A.dlnr = g->dlnr; A.dth = g->dth;
     A.idlnr = 1.0 / g->dlnr; A.idth = 1.0 / g->dth;
+    A.inv_nth = 1.0 / g->nth;
+    A.inv_tpr = 1.0 / grpic::tiles_per_row(g->nth);
     A.small_steps = (2.0 * g->dlnr <= grpic::kTinyArg && 2.0 * g->dth <= grpic::kTinyArg)     ? 2
                   : (2.0 * g->dlnr <= grpic::kSmallArg && 2.0 * g->dth <= grpic::kSmallArg) ? 1
                                                                                              : 0;

@@ -22,6 +22,7 @@ struct StepArgs {
     int nr, nth, guard, pitch;
     double lnr0, dlnr, dth;
     double idlnr, idth;                     // 1/dlnr, 1/dth
+    double inv_nth, inv_tpr;                // 1/nth, 1/tiles per row (integer quotients)
     int small_steps;                        // Taylor offsets: 2 with 2 dlnr, 2 dth <= kTinyArg, 1 <= kSmallArg, else 0
     int fp64_rows;                          // split precision: rows i < fp64_rows run in FP64
     int pole_cols;                          // split precision: columns this close to the axis run in FP64
@@ -440,6 +441,17 @@ __device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
         fr(1, 2); ft(1, 2);
         gp(2, 2);
     }
+}
+
+// n / d for 0 <= n < 2^31 and d > 0, from the double product n * (1/d)
+// (within 2^-21 of the quotient, so truncation is off by at most one) and
+// one correction on the remainder; cheaper than the integer division
+// sequence, for a divisor known only at run time.
+__device__ __forceinline__ int div_by(int n, int d, double inv_d) {
+    int q = (int)((double)n * inv_d);
+    const int64_t r = (int64_t)n - (int64_t)q * d;
+    q += (r >= d) - (r < 0);
+    return q;
 }
 
 // Element index of vertex (i, j) in a grid array; every grid array is below

@@ -155,7 +155,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         ev.bad = 1;
         return false;
     }
-    const int ci = cell / A.nth, cj = cell - ci * A.nth;
+    const int ci = div_by(cell, A.nth, A.inv_nth), cj = cell - ci * A.nth;
     const double xi0 = (double)ci + dxr, eta0 = (double)cj + dxt;
     double u[3] = {in.u[0], in.u[1], in.u[2]};
     const double* const* F = reinterpret_cast<const double* const*>(A.F);
@@ -287,7 +287,7 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, const PIdx& p, 
         ev.bad = 1;
         return false;
     }
-    const int ci = cell / A.nth, cj = cell - ci * A.nth;
+    const int ci = div_by(cell, A.nth, A.inv_nth), cj = cell - ci * A.nth;
     const float* const* F = reinterpret_cast<const float* const*>(A.F);
     const float Df[3] = {cic_f32(F[0], A, ci, cj, fxr - 0.5f, fxt), cic_f32(F[1], A, ci, cj, fxr, fxt - 0.5f),
                          cic_f32(F[2], A, ci, cj, fxr, fxt)};
@@ -435,7 +435,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         return;
     }
     const int tpr = (A.nth + kTileCells - 1) / kTileCells;
-    const int ti = sl.tile / tpr;
+    const int ti = div_by(sl.tile, tpr, A.inv_tpr);
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
@@ -540,16 +540,17 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const bool any = touched[1] >= 0;                    // then all four bounds are set
     const int r0 = touched[0], nrow = any ? touched[1] - touched[0] + 1 : 0;
     const int c0 = touched[2], ncol = any ? touched[3] - touched[2] + 1 : 1;
-    for (int e = threadIdx.x; e < nrow * ncol; e += kPushThreads) {
-        const int rr = e / ncol;
-        const int c = c0 + (e - rr * ncol);
-        const int r = r0 + rr;
-        const int gi = wi0 + r, gj = wj0 + c;
-        if (gi < rows_lo || gi > rows_hi || gj < cols_lo || gj > cols_hi) continue;
-        const uint32_t g = grid_index(A, gi, gj);
-        for (int a = 0; a < 3; ++a) {
-            const double v = win[a][r][c];
-            if (v != 0.0) atomicAdd(elem(J[a], g), v);
+    // rows to groups of 32 threads, columns to the threads of a group
+    for (int rr = threadIdx.x >> 5; rr < nrow; rr += kPushThreads >> 5) {
+        for (int cc = threadIdx.x & 31; cc < ncol; cc += 32) {
+            const int r = r0 + rr, c = c0 + cc;
+            const int gi = wi0 + r, gj = wj0 + c;
+            if (gi < rows_lo || gi > rows_hi || gj < cols_lo || gj > cols_hi) continue;
+            const uint32_t g = grid_index(A, gi, gj);
+            for (int a = 0; a < 3; ++a) {
+                const double v = win[a][r][c];
+                if (v != 0.0) atomicAdd(elem(J[a], g), v);
+            }
         }
     }
     if (A.counters && threadIdx.x == 0) {
