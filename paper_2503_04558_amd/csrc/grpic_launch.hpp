@@ -34,6 +34,10 @@ struct TilingHeader {
     int32_t nr, nth, tiles_per_row, tile_cells;
 };
 
+// The slice table is in dispatch order: entry b holds the slice that
+// workgroup b of a tiled push runs (b runs on XCD b % 8, so each XCD gets a
+// contiguous band of slices in tile order, and neighbouring tiles share its
+// L2); entries without a slice have len = 0.
 struct Slice {
     int64_t start;            // first particle
     int32_t len;              // particles in the slice (<= kSliceMax)
@@ -41,8 +45,10 @@ struct Slice {
 };
 
 inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; }
+// At most n / kSliceMax + ntiles slices; 8 more entries because the table
+// is kept in dispatch order (below), which rounds each XCD's band up.
 inline int64_t slice_capacity(int64_t n, int nr, int nth) {
-    return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 1;
+    return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 8;
 }
 // Layout: header, slice table (capacity entries), one int32 per slice that
 // a push with counters fills with the slice's live particle count (so that

@@ -405,8 +405,8 @@ template <bool SHORT>
 __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { push_deposit_body<true, SHORT>(A); }
 
 template <bool SPLIT, bool SHORT>
-__device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const TilingHeader* hdr,
-                                                        const Slice* __restrict__ slices, int64_t slice_cap,
+__device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const Slice* __restrict__ slices,
+                                                        int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live,
                                                         const double* __restrict__ anchors) {
     __shared__ double win[3][kWinRows][kWinCols];
@@ -421,14 +421,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     constexpr int kStage = kSliceMax + kSliceMax / 32;
     __shared__ int st_kind[kStage], st_cell[kStage];
     __shared__ Elem<SPLIT> st_x[5][kStage];
-    // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
-    // contiguous band of slices so neighbouring tiles share its L2.
-    const int64_t nslices = hdr->nslices;
-    const int64_t per_xcd = (nslices + 7) / 8;
-    // (workgroups past 8 * per_xcd would alias the next XCD's band: they exit)
-    if ((int64_t)(blockIdx.x / 8) >= per_xcd) return;          // uniform across the workgroup
-    const int64_t logical = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (logical >= nslices || logical >= slice_cap) return;
+    // the slice table is in dispatch order (XCD-aware bands, written so by
+    // the sort): one load finds this workgroup's slice
+    const int64_t logical = blockIdx.x;
+    if (logical >= slice_cap) return;
     const Slice sl = slices[logical];
     if (sl.start < 0 || sl.len <= 0) {
         if (A.counters && threadIdx.x == 0) slice_live[logical] = 0;
@@ -563,10 +559,9 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
 }
 
 // counters[LIVE] += sum of the per-slice live counts of one tiled push.
-__global__ __launch_bounds__(256) void slice_live_sum(const TilingHeader* __restrict__ hdr,
-                                                      const int32_t* __restrict__ live, int64_t slice_cap,
+__global__ __launch_bounds__(256) void slice_live_sum(const int32_t* __restrict__ live, int64_t slice_cap,
                                                       unsigned long long* __restrict__ counters) {
-    const int64_t n = min(hdr->nslices, slice_cap);
+    const int64_t n = slice_cap;                         // every entry is written by the push
     unsigned long long v = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         v += (unsigned long long)live[i];
@@ -582,16 +577,16 @@ __global__ __launch_bounds__(256) void slice_live_sum(const TilingHeader* __rest
 
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
-    const StepArgs A, const TilingHeader* hdr, const Slice* __restrict__ slices, int64_t slice_cap,
+    const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap,
     int32_t* slice_live, const double* anchors) {
-    push_deposit_tiled_body<false, SHORT>(A, hdr, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<false, SHORT>(A, slices, slice_cap, slice_live, anchors);
 }
 template <bool SHORT>
-__global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A, const TilingHeader* hdr,
+__global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
                                                                          const Slice* __restrict__ slices,
                                                                          int64_t slice_cap, int32_t* slice_live,
                                                                          const double* anchors) {
-    push_deposit_tiled_body<true, SHORT>(A, hdr, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<true, SHORT>(A, slices, slice_cap, slice_live, anchors);
 }
 
 // The anchor table of a tiled launch (layout in grpic_launch.hpp).
@@ -655,15 +650,15 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     const dim3 g((unsigned)grid), b(kPushThreads);
     const bool sh = A.small_steps == 2;
     if (split && sh)
-        hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     else if (split)
-        hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     else if (sh)
-        hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     else
-        hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, hdr, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     if (A.counters)
-        hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, hdr, live, slice_cap, A.counters);
+        hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, live, slice_cap, A.counters);
     return hipGetLastError();
 }
 

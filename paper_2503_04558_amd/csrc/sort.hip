@@ -210,10 +210,18 @@ __global__ __launch_bounds__(256) void tile_slice_counts(const unsigned long lon
     ns[t] = (cnt + kSliceMax - 1) / kSliceMax;
 }
 
-// Slice table: tile t's particles cut into ns balanced slices.
+__global__ __launch_bounds__(256) void slices_empty(Slice* __restrict__ out, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) out[i] = Slice{-1, 0, 0};
+}
+
+// Slice table: tile t's particles cut into ns balanced slices; slice L (in
+// tile order) goes to entry (L % per_xcd) * 8 + L / per_xcd, the workgroup
+// that runs the L % per_xcd-th slice of XCD L / per_xcd's band.
 __global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __restrict__ offs,
                                                    const unsigned long long* __restrict__ base, int nr, int nth,
-                                                   int tpr, int64_t n, TilingHeader* hdr, Slice* __restrict__ out) {
+                                                   int tpr, int64_t n, int64_t cap, TilingHeader* hdr,
+                                                   Slice* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ntiles = (int64_t)nr * tpr;
     if (t == 0) {
@@ -233,6 +241,7 @@ __global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __r
     const int64_t b = (int64_t)base[t];
     const int64_t ns = (int64_t)base[t + 1] - b;
     if (ns <= 0) return;
+    const int64_t per_xcd = ((int64_t)base[ntiles] + 7) / 8;
     const int64_t each = (cnt + ns - 1) / ns;
     for (int64_t s = 0; s < ns; ++s) {
         const int64_t s0 = s * each;
@@ -240,7 +249,9 @@ __global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __r
         sl.start = start + s0;
         sl.len = (int32_t)(cnt - s0 < each ? cnt - s0 : each);
         sl.tile = (int32_t)t;
-        out[b + s] = sl;
+        const int64_t L = b + s;
+        const int64_t e = (L % per_xcd) * 8 + L / per_xcd;
+        if (e < cap) out[e] = sl;                        // always: cap >= nslices + 8
     }
 }
 
@@ -314,8 +325,10 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
         hipLaunchKernelGGL(tile_slice_counts, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.nr, S.nth,
                            tpr, S.tile_slices);
         scan_exclusive(S.tile_slices, ntiles + 1, S.blocksums, stream);
+        const int64_t cap = slice_capacity(S.n, S.nr, S.nth);
+        hipLaunchKernelGGL(slices_empty, dim3(nblk(cap)), dim3(256), 0, stream, slices, cap);
         hipLaunchKernelGGL(tile_slices, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.tile_slices, S.nr,
-                           S.nth, tpr, S.n, hdr, slices);
+                           S.nth, tpr, S.n, cap, hdr, slices);
     }
     hipLaunchKernelGGL(sort_offsets_out, dim3(nblk(len)), dim3(256), 0, stream, S.counts, S.ncell,
                        S.cell_offsets, S.n_alive);
