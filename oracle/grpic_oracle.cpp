@@ -742,3 +742,316 @@ int orc_has_openmp(void) {
 }
 
 }  /* extern "C" */
+
+/* ================================================================== */
+/* Field solver (Sec. 2.1, eqs. integral-form, fld-predictor,          */
+/* fld-corrector, Dr-axis; App. B, eqs. D-update, auxH, B-update,      */
+/* auxE), plain and slow.                                              */
+/*                                                                     */
+/* Locations (Fig. Yee), array element (i, j) of each component:       */
+/*   D^r, B^th, E_r, H_th at (i+1/2, j)    D^th, B^r, E_th, H_r at     */
+/*   (i, j+1/2)    D^ph, E_ph at (i, j)    B^ph, H_ph at (i+1/2, j+1/2) */
+/* with r_x = exp(lnr0 + x dlnr), theta_y = y dth.  Areas and volumes  */
+/* are per unit phi, so the flux-form currents of the deposit are       */
+/* J^r A^D_r, J^th A^D_th, J^ph A^D_ph.                                */
+/*                                                                     */
+/* Readings (also in the design notes):                                */
+/*   - corrector: X^{n+1} = X^n + dt (w0 C(X^n) + w1 C(X~)) - dt J with */
+/*     w0 + w1 = 1 (the printed dt/2 in front would not give Heun's    */
+/*     method at w0 = w1 = 1/2, as the text says it does);             */
+/*   - auxE: the sqrt(gamma) beta^r B^th term of E_ph is averaged with  */
+/*     a factor 1/2 like every other interpolated term;                */
+/*   - Dr-axis: D^r on an axis gains dt (+-H_ph / A^D_r - J^r); H_ph    */
+/*     beyond the axis is zero (the phi loop there has no length);     */
+/*   - inner and outer guard rows copy the nearest physical row (zero   */
+/*     gradient; the outer one under the damping layer);               */
+/*   - damping layer: after each step every component at radial grid    */
+/*     position x >= nr - L is multiplied by 1 - d ((x - nr + L)/L)^2.  */
+/* ================================================================== */
+namespace {
+
+/* 10-point Gauss-Legendre nodes and weights on [-1, 1]: roots of P_10
+ * by Newton's method from the Chebyshev guesses, w = 2/((1-x^2) P'^2). */
+struct Gauss10 {
+    double x[10], w[10];
+    Gauss10() {
+        const int n = 10;
+        for (int k = 0; k < n; ++k) {
+            double z = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = z;
+                for (int m = 2; m <= n; ++m) {
+                    const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+                const double dz = p1 / dp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-16) break;
+            }
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            x[k] = z;
+            w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+};
+
+struct FieldGeo {
+    Geom g;
+    double r(double x) const { return std::exp(g.lnr0 + x * g.dlnr); }
+    double th(double y) const { return y * g.dth; }
+    KS<double> at(double x, double y) const {
+        KS<double> k;
+        ks_metric<double>(g.a, g.M, r(x), th(y), k);
+        return k;
+    }
+    double sqrtg(double rr, double t) const {
+        KS<double> k;
+        ks_metric<double>(g.a, g.M, rr, t, k);
+        return k.sqrtg;
+    }
+    /* int_{t0}^{t1} sqrt(gamma)(r, theta) dtheta */
+    double int_th(double rr, double t0, double t1) const {
+        static const Gauss10 G;
+        double s = 0.0;
+        for (int k = 0; k < 10; ++k) {
+            const double t = 0.5 * (t0 + t1) + 0.5 * (t1 - t0) * G.x[k];
+            s += G.w[k] * sqrtg(rr, t);
+        }
+        return 0.5 * (t1 - t0) * s;
+    }
+    /* int_{r0}^{r1} sqrt(gamma)(r, theta) dr */
+    double int_r(double t, double r0, double r1) const {
+        static const Gauss10 G;
+        double s = 0.0;
+        for (int k = 0; k < 10; ++k) {
+            const double rr = 0.5 * (r0 + r1) + 0.5 * (r1 - r0) * G.x[k];
+            s += G.w[k] * sqrtg(rr, t);
+        }
+        return 0.5 * (r1 - r0) * s;
+    }
+    /* int int sqrt(gamma) dr dtheta over [r0, r1] x [t0, t1] */
+    double int_rth(double r0, double r1, double t0, double t1) const {
+        static const Gauss10 G;
+        double s = 0.0;
+        for (int k = 0; k < 10; ++k) {
+            const double rr = 0.5 * (r0 + r1) + 0.5 * (r1 - r0) * G.x[k];
+            s += G.w[k] * int_th(rr, t0, t1);
+        }
+        return 0.5 * (r1 - r0) * s;
+    }
+    double clamp_th(double y) const { return std::min(std::max(y, 0.0), (double)g.nth) * g.dth; }
+
+    /* Area elements per unit phi, at the locations of the six components. */
+    double AD_r(int i, int j) const {      /* r = r_{i+1/2}, theta over [j-1/2, j+1/2] within [0, pi] */
+        return int_th(r(i + 0.5), clamp_th(j - 0.5), clamp_th(j + 0.5));
+    }
+    double AD_th(int i, int j) const {     /* theta_{j+1/2}, r over [i-1/2, i+1/2] */
+        return int_r(th(j + 0.5), r(i - 0.5), r(i + 0.5));
+    }
+    double AD_ph(int i, int j) const {
+        return int_rth(r(i - 0.5), r(i + 0.5), clamp_th(j - 0.5), clamp_th(j + 0.5));
+    }
+    double AB_r(int i, int j) const { return int_th(r(i), th(j), th(j + 1)); }
+    double AB_th(int i, int j) const { return int_r(th(j), r(i), r(i + 1)); }
+    double AB_ph(int i, int j) const { return int_rth(r(i), r(i + 1), th(j), th(j + 1)); }
+};
+
+/* Grid arrays of the solver: three D, three B components. */
+struct FieldState {
+    std::vector<double> c[6];   /* D^r, D^th, D^ph, B^r, B^th, B^ph */
+};
+
+/* Rows of a component that are updated; half: located at i + 1/2.      */
+inline bool half_r(int comp) { return comp == 0 || comp == 4 || comp == 5; }
+
+/* Zero-gradient guard rows; D^ph and B^th are zero on the axes. */
+void fill_guards(const Geom& g, std::vector<double>* c) {
+    for (int comp = 0; comp < 6; ++comp) {
+        const int last = half_r(comp) ? g.nr - 1 : g.nr;
+        for (int j = -g.guard; j < g.pitch - g.guard; ++j) {
+            for (int i = -g.guard; i < 0; ++i) c[comp][idx(g, i, j)] = c[comp][idx(g, 0, j)];
+            for (int i = last + 1; i <= g.nr + g.guard; ++i) c[comp][idx(g, i, j)] = c[comp][idx(g, last, j)];
+        }
+    }
+    for (int i = -g.guard; i <= g.nr + g.guard; ++i) {
+        c[2][idx(g, i, 0)] = c[2][idx(g, i, g.nth)] = 0.0;
+        c[4][idx(g, i, 0)] = c[4][idx(g, i, g.nth)] = 0.0;
+    }
+}
+
+/* Auxiliary fields (eqs. auxE, auxH), metric coefficients formed first,
+ * then averaged to the auxiliary field's location.  E[0..2] = E_r, E_th,
+ * E_ph; H[0..2] = H_r, H_th, H_ph; each over the rows its circulations
+ * use (-1 .. nr).                                                      */
+void aux_fields(const FieldGeo& fg, const std::vector<double>* c, std::vector<double>* E, std::vector<double>* H) {
+    const Geom& g = fg.g;
+    const std::vector<double>&Dr = c[0], &Dt = c[1], &Dp = c[2], &Br = c[3], &Bt = c[4], &Bp = c[5];
+    auto aG_rr = [&](double x, double y) { const KS<double> k = fg.at(x, y); return k.alpha * k.g_rr; };
+    auto aG_rp = [&](double x, double y) { const KS<double> k = fg.at(x, y); return k.alpha * k.g_rp; };
+    auto aG_tt = [&](double x, double y) { const KS<double> k = fg.at(x, y); return k.alpha * k.g_tt; };
+    auto aG_pp = [&](double x, double y) { const KS<double> k = fg.at(x, y); return k.alpha * k.g_pp; };
+    auto sgB = [&](double x, double y) { const KS<double> k = fg.at(x, y); return k.sqrtg * k.beta; };
+    for (int i = -1; i <= g.nr; ++i) {
+        for (int j = 0; j <= g.nth; ++j) {
+            const long e = idx(g, i, j);
+            const long em = idx(g, i - 1, j), ep = idx(g, i + 1, j);
+            /* E_r at (i+1/2, j) */
+            E[0][e] = aG_rr(i + 0.5, j) * Dr[e] + 0.5 * (aG_rp(i, j) * Dp[e] + aG_rp(i + 1, j) * Dp[ep]);
+            /* E_th at (i, j+1/2) */
+            if (j < g.nth)
+                E[1][e] = aG_tt(i, j + 0.5) * Dt[e] -
+                          0.5 * (sgB(i + 0.5, j + 0.5) * Bp[e] + sgB(i - 0.5, j + 0.5) * Bp[em]);
+            /* E_ph at (i, j) */
+            E[2][e] = aG_pp(i, j) * Dp[e] + 0.5 * (aG_rp(i + 0.5, j) * Dr[e] + aG_rp(i - 0.5, j) * Dr[em]) +
+                      0.5 * (sgB(i + 0.5, j) * Bt[e] + sgB(i - 0.5, j) * Bt[em]);
+            /* H_r at (i, j+1/2) */
+            if (j < g.nth)
+                H[0][e] = aG_rr(i, j + 0.5) * Br[e] +
+                          0.5 * (aG_rp(i + 0.5, j + 0.5) * Bp[e] + aG_rp(i - 0.5, j + 0.5) * Bp[em]);
+            /* H_th at (i+1/2, j) */
+            H[1][e] = aG_tt(i + 0.5, j) * Bt[e] + 0.5 * (sgB(i, j) * Dp[e] + sgB(i + 1, j) * Dp[ep]);
+            /* H_ph at (i+1/2, j+1/2) */
+            if (j < g.nth)
+                H[2][e] = aG_pp(i + 0.5, j + 0.5) * Bp[e] +
+                          0.5 * (aG_rp(i, j + 0.5) * Br[e] + aG_rp(i + 1, j + 0.5) * Br[ep]) -
+                          0.5 * (sgB(i, j + 0.5) * Dt[e] + sgB(i + 1, j + 0.5) * Dt[ep]);
+        }
+    }
+}
+
+/* Circulations C (eqs. D-update, B-update, Dr-axis) of the state c:
+ * C[0..2] for D^r, D^th, D^ph (C_H, current not included), C[3..5] for
+ * B^r, B^th, B^ph (C_E); zero outside the updated ranges.              */
+void circulations(const FieldGeo& fg, const std::vector<double>* c, std::vector<double>* C) {
+    const Geom& g = fg.g;
+    const long n = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
+    std::vector<double> E[3], H[3];
+    for (int k = 0; k < 3; ++k) { E[k].assign(n, 0.0); H[k].assign(n, 0.0); }
+    aux_fields(fg, c, E, H);
+    for (int k = 0; k < 6; ++k) C[k].assign(n, 0.0);
+    const double dth = g.dth;
+    for (int i = 0; i <= g.nr; ++i) {
+        const double dr_dual = fg.r(i + 0.5) - fg.r(i - 0.5), dr = fg.r(i + 1) - fg.r(i);
+        for (int j = 0; j <= g.nth; ++j) {
+            const long e = idx(g, i, j), em = idx(g, i - 1, j), ep = idx(g, i + 1, j);
+            const long ejm = idx(g, i, j - 1), ejp = idx(g, i, j + 1);
+            if (i < g.nr) {        /* D^r at (i+1/2, j), the axes included */
+                const double hp = j < g.nth ? H[2][e] : 0.0, hm = j > 0 ? H[2][ejm] : 0.0;
+                C[0][e] = (hp - hm) / fg.AD_r(i, j);
+            }
+            if (j < g.nth)         /* D^th at (i, j+1/2) */
+                C[1][e] = (H[2][em] - H[2][e]) / fg.AD_th(i, j);
+            if (j > 0 && j < g.nth)   /* D^ph at (i, j) */
+                C[2][e] = ((H[1][e] - H[1][em]) * dth + (H[0][ejm] - H[0][e]) * dr_dual) / fg.AD_ph(i, j);
+            if (j < g.nth)         /* B^r at (i, j+1/2) */
+                C[3][e] = -(E[2][ejp] - E[2][e]) / fg.AB_r(i, j);
+            if (i < g.nr && j > 0 && j < g.nth)   /* B^th at (i+1/2, j) */
+                C[4][e] = -(E[2][e] - E[2][ep]) / fg.AB_th(i, j);
+            if (i < g.nr && j < g.nth)            /* B^ph at (i+1/2, j+1/2) */
+                C[5][e] = -((E[1][ep] - E[1][e]) * dth + (E[0][e] - E[0][ejp]) * dr) / fg.AB_ph(i, j);
+        }
+    }
+}
+
+/* Current per unit area (flux form / area) at the D locations. */
+void current_density(const FieldGeo& fg, const double* const* F, std::vector<double>* J) {
+    const Geom& g = fg.g;
+    const long n = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
+    for (int k = 0; k < 3; ++k) J[k].assign(n, 0.0);
+    if (!F) return;
+    for (int i = 0; i <= g.nr; ++i)
+        for (int j = 0; j <= g.nth; ++j) {
+            const long e = idx(g, i, j);
+            if (i < g.nr && F[0]) J[0][e] = F[0][e] / fg.AD_r(i, j);
+            if (j < g.nth && F[1]) J[1][e] = F[1][e] / fg.AD_th(i, j);
+            if (j > 0 && j < g.nth && F[2]) J[2][e] = F[2][e] / fg.AD_ph(i, j);
+        }
+}
+
+}  /* namespace */
+
+extern "C" {
+
+/* Area elements per unit phi at the six component locations (arrays of
+ * the grid's shape, zero where the component does not live).          */
+void orc_field_areas(const Geom* gp, double* const* A) {
+    const FieldGeo fg{*gp};
+    const Geom& g = *gp;
+    for (int i = 0; i <= g.nr; ++i)
+        for (int j = 0; j <= g.nth; ++j) {
+            const long e = idx(g, i, j);
+            if (i < g.nr) A[0][e] = fg.AD_r(i, j);
+            if (j < g.nth) A[1][e] = fg.AD_th(i, j);
+            A[2][e] = fg.AD_ph(i, j);
+            if (j < g.nth) A[3][e] = fg.AB_r(i, j);
+            if (i < g.nr) A[4][e] = fg.AB_th(i, j);
+            if (i < g.nr && j < g.nth) A[5][e] = fg.AB_ph(i, j);
+        }
+}
+
+/* Circulations of the state (arrays D^r..B^ph) into C[6] (guard rows of
+ * the state are filled first; D^ph, B^th are zeroed on the axes).      */
+void orc_field_circulations(const Geom* gp, double* const* X, double* const* C) {
+    const FieldGeo fg{*gp};
+    const long n = (long)(gp->nr + 1 + 2 * gp->guard) * gp->pitch;
+    std::vector<double> c[6], out[6];
+    for (int k = 0; k < 6; ++k) c[k].assign(X[k], X[k] + n);
+    fill_guards(*gp, c);
+    circulations(fg, c, out);
+    for (int k = 0; k < 6; ++k) std::copy(out[k].begin(), out[k].end(), C[k]);
+}
+
+/* One field step in place: X[6] = D^r, D^th, D^ph, B^r, B^th, B^ph (grid
+ * arrays); F[3] = flux-form currents of the step (NULL = none); predictor
+ * and ncorr corrector passes with weights w0 = 1 - w1, w1; then the
+ * damping layer over the last damp_cells rows (0 = none).              */
+void orc_field_step(const Geom* gp, double* const* X, const double* const* F, double dt, double w1,
+                    int ncorr, int damp_cells, double damp_max) {
+    const Geom& g = *gp;
+    const FieldGeo fg{g};
+    const long n = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
+    std::vector<double> x0[6], xt[6], C0[6], C1[6], J[3];
+    for (int k = 0; k < 6; ++k) x0[k].assign(X[k], X[k] + n);
+    fill_guards(g, x0);
+    circulations(fg, x0, C0);
+    current_density(fg, F, J);
+    const double w0 = 1.0 - w1;
+    /* updated ranges: the circulations are zero elsewhere, so x0 + dt C
+     * leaves guard rows and the axis zeros of D^ph, B^th unchanged, and
+     * the guards are refilled after every pass                          */
+    for (int k = 0; k < 6; ++k) {
+        xt[k] = x0[k];
+        for (long e = 0; e < n; ++e) xt[k][e] = x0[k][e] + dt * (C0[k][e] - (k < 3 ? J[k][e] : 0.0));
+    }
+    fill_guards(g, xt);
+    for (int it = 0; it < ncorr; ++it) {
+        circulations(fg, xt, C1);
+        for (int k = 0; k < 6; ++k)
+            for (long e = 0; e < n; ++e)
+                xt[k][e] = x0[k][e] + dt * (w0 * C0[k][e] + w1 * C1[k][e]) - dt * (k < 3 ? J[k][e] : 0.0);
+        fill_guards(g, xt);
+    }
+    if (damp_cells > 0) {
+        const double x_in = (double)(g.nr - damp_cells);
+        for (int k = 0; k < 6; ++k)
+            for (int i = 0; i <= g.nr; ++i) {
+                const double x = i + (half_r(k) ? 0.5 : 0.0);
+                if (x < x_in) continue;
+                const double s = (x - x_in) / damp_cells;
+                const double f = 1.0 - damp_max * s * s;
+                for (int j = 0; j <= g.nth; ++j) xt[k][idx(g, i, j)] *= f;
+            }
+        fill_guards(g, xt);
+    }
+    for (int k = 0; k < 6; ++k) std::copy(xt[k].begin(), xt[k].end(), X[k]);
+}
+
+}  /* extern "C" */

@@ -286,3 +286,50 @@ def loss_particle(grid, species_row, xi, eta, u, w, fields, lam, dt, nsteps, nco
     if trajectory:
         return float(out.value), int(st), traj
     return float(out.value), int(st)
+
+
+# ---------------------------------------------------------------- field solver
+
+FIELD_KEYS = ("Dr", "Dth", "Dph", "Br", "Bth", "Bph")
+
+
+def _grid_arrays(grid, arrays):
+    shape = (grid.nr + 1 + 2 * grid.guard, grid.pitch)
+    out = [np.ascontiguousarray(np.array(a, dtype=np.float64)).reshape(shape) for a in arrays]
+    return out, shape
+
+
+def _field_ptrs(arrays):
+    return (ctypes.c_void_p * len(arrays))(*[_p(a) for a in arrays])
+
+
+def field_areas(grid) -> list:
+    """Area elements per unit phi at the locations of D^r, D^th, D^ph,
+    B^r, B^th, B^ph (10-point Gauss quadrature of sqrt(gamma))."""
+    shape = (grid.nr + 1 + 2 * grid.guard, grid.pitch)
+    A = [np.zeros(shape) for _ in range(6)]
+    lib().orc_field_areas(ctypes.byref(geom(grid)), _field_ptrs(A))
+    return A
+
+
+def field_circulations(grid, X) -> list:
+    """C_H for D^r, D^th, D^ph and C_E for B^r, B^th, B^ph of the state X
+    (six grid arrays; guard rows are filled from it first)."""
+    Xs, shape = _grid_arrays(grid, X)
+    C = [np.zeros(shape) for _ in range(6)]
+    lib().orc_field_circulations(ctypes.byref(geom(grid)), _field_ptrs(Xs), _field_ptrs(C))
+    return C
+
+
+def field_step(grid, X, F=None, dt=0.0, w1=0.53, ncorr=7, damp_cells=0, damp_max=0.0) -> list:
+    """One field step (predictor + ncorr correctors, weights 1 - w1, w1) of
+    the state X with the flux-form currents F (three grid arrays or None);
+    returns the new state (six arrays)."""
+    Xs, shape = _grid_arrays(grid, X)
+    Fs = None
+    if F is not None:
+        Fs, _ = _grid_arrays(grid, F)
+    lib().orc_field_step(ctypes.byref(geom(grid)), _field_ptrs(Xs), _field_ptrs(Fs) if Fs is not None else None,
+                         ctypes.c_double(dt), ctypes.c_double(w1), ctypes.c_int(ncorr), ctypes.c_int(damp_cells),
+                         ctypes.c_double(damp_max))
+    return Xs

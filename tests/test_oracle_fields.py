@@ -1,0 +1,233 @@
+"""Pins of the oracle's field solver (Sec. 2.1, App. B) against what the
+mathematics fixes, independently of the oracle's own formulas:
+
+* area elements: the closed forms of flat space (sqrt(gamma) = r^2 sin),
+  and an independent adaptive integrator in the Kerr metric;
+* a stationary exact solution (the rotating Wald field, App. C) has
+  circulations that vanish at second order in the cell size;
+* the Yee structure: the discrete divergence of B through the B faces is
+  invariant to rounding, and div D - Q is invariant when J and Q come from
+  the charge-conserving deposit of a particle step;
+* the corrector: its fixed point is the implicit trapezoidal step
+  X1 = X0 + dt (w0 C(X0) + w1 C(X1)) - dt J;
+* the axis values of D^ph, B^th stay zero, and the damping layer scales
+  by its stated profile.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import oracle as orc
+from paper_2503_04558_amd import workload as wl
+
+
+def _r(g, x):
+    return np.exp(g.lnr0 + x * g.dlnr)
+
+
+def _th(g, y):
+    return np.clip(y, 0.0, g.nth) * g.dth
+
+
+def test_areas_flat_space_closed_form():
+    g = wl.make_grid(12, 10, 0.0, M=0.0, r_in=2.0, r_out=20.0)
+    A = orc.field_areas(g)
+    G = g.guard
+    r3 = lambda a, b: (b ** 3 - a ** 3) / 3.0
+    worst = 0.0
+    for i in range(g.nr + 1):
+        for j in range(g.nth + 1):
+            e = (G + i, G + j)
+            ri = lambda x: _r(g, i + x)
+            tj = lambda y: _th(g, j + y)
+            want = {}
+            if i < g.nr:
+                want[0] = ri(0.5) ** 2 * (np.cos(tj(-0.5)) - np.cos(tj(0.5)))
+            if j < g.nth:
+                want[1] = np.sin(tj(0.5)) * r3(ri(-0.5), ri(0.5))
+                want[3] = ri(0) ** 2 * (np.cos(tj(0)) - np.cos(tj(1)))
+            want[2] = r3(ri(-0.5), ri(0.5)) * (np.cos(tj(-0.5)) - np.cos(tj(0.5)))
+            if i < g.nr:
+                want[4] = np.sin(tj(0)) * r3(ri(0), ri(1))
+            if i < g.nr and j < g.nth:
+                want[5] = r3(ri(0), ri(1)) * (np.cos(tj(0)) - np.cos(tj(1)))
+            for k, v in want.items():
+                worst = max(worst, abs(A[k][e] - v) / max(abs(v), 1e-300) if v != 0 else abs(A[k][e]))
+    assert worst < 1e-13
+
+
+def test_areas_kerr_against_adaptive_quadrature():
+    g = wl.make_grid(16, 16, 0.95)
+    A = orc.field_areas(g)
+    G = g.guard
+
+    def sqrtg(r, th):
+        return orc.metric(g.a, g.M, r, th)["sqrtg"]
+
+    for (i, j) in ((0, 0), (3, 7), (15, 15), (8, 1)):
+        r0, r1 = _r(g, i), _r(g, i + 1)
+        t0, t1 = _th(g, j), _th(g, j + 1)
+        want_bph = integrate.dblquad(lambda t, r: sqrtg(r, t), r0, r1, t0, t1, epsabs=0, epsrel=1e-13)[0]
+        assert A[5][G + i, G + j] == pytest.approx(want_bph, rel=1e-12)
+        want_dr = integrate.quad(lambda t: sqrtg(_r(g, i + 0.5), t), _th(g, j - 0.5), _th(g, j + 0.5),
+                                 epsabs=0, epsrel=1e-13)[0]
+        assert A[0][G + i, G + j] == pytest.approx(want_dr, rel=1e-12)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9])
+def test_stationary_wald_circulations_vanish_at_second_order(a):
+    """The rotating Wald field (App. C; D from eq. E-H-B-D) is an exact
+    stationary vacuum solution: every discrete d/dt of the interior must
+    fall as the cell size squared (a sign or index slip in any E_i, H_i or
+    circulation term leaves an O(1) residual)."""
+    worst = []
+    for n in (32, 64, 128):
+        g = wl.make_grid(n, n, a)
+        C = orc.field_circulations(g, wl.wald_fields(g))
+        G = g.guard
+        worst.append([np.abs(c[G + n // 4: G + 3 * n // 4, G + n // 8: G + 7 * n // 8]).max() for c in C])
+    worst = np.array(worst)
+    assert np.all(worst[-1] < 1e-5)
+    live = worst.min(axis=0) > 1e-13          # at a = 0, D, B^ph and their rates vanish exactly
+    assert live.sum() >= (3 if a == 0.0 else 6)
+    assert np.all(worst[:, ~live] < 1e-13)
+    ratios = worst[:-1, live] / worst[1:, live]
+    assert np.all(ratios > 3.5), ratios
+
+
+def _random_state(g, seed, B_from_potential=True):
+    """Smooth-ish random D, B; B^r and B^th from a vertex potential A_ph so
+    that their discrete divergence through the B faces is zero."""
+    rng = np.random.default_rng(seed)
+    shape = (g.nr + 1 + 2 * g.guard, g.pitch)
+    X = [rng.normal(size=shape) * 0.1 for _ in range(6)]
+    if B_from_potential:
+        A = orc.field_areas(g)
+        G = g.guard
+        Aph = rng.normal(size=shape) * 0.1
+        Aph[:, G] = 0.0
+        Aph[:, G + g.nth] = 0.0
+        Br = np.zeros(shape)
+        Bt = np.zeros(shape)
+        for i in range(g.nr + 1):
+            for j in range(g.nth):
+                Br[G + i, G + j] = (Aph[G + i, G + j + 1] - Aph[G + i, G + j]) / A[3][G + i, G + j]
+        for i in range(g.nr):
+            for j in range(1, g.nth):
+                Bt[G + i, G + j] = -(Aph[G + i + 1, G + j] - Aph[G + i, G + j]) / A[4][G + i, G + j]
+        X[3], X[4] = Br, Bt
+    G = g.guard
+    for k in (2, 4):                         # D^ph and B^th vanish on the axes
+        X[k][:, G] = 0.0
+        X[k][:, G + g.nth] = 0.0
+    return X
+
+
+def _div_B(g, X, A):
+    G = g.guard
+    fr = X[3] * A[3]
+    ft = X[4] * A[4]
+    d = np.zeros((g.nr, g.nth))
+    for i in range(g.nr):
+        for j in range(g.nth):
+            d[i, j] = (fr[G + i + 1, G + j] - fr[G + i, G + j]) + (ft[G + i, G + j + 1] - ft[G + i, G + j])
+    return d, np.abs(fr).max() + np.abs(ft).max()
+
+
+def test_div_B_is_invariant():
+    g = wl.make_grid(20, 16, 0.9)
+    A = orc.field_areas(g)
+    X = _random_state(g, 1)
+    d0, scale = _div_B(g, X, A)
+    assert np.abs(d0).max() < 1e-14 * scale
+    rng = np.random.default_rng(2)
+    F = [rng.normal(size=X[0].shape) * 0.01 for _ in range(3)]
+    for _ in range(3):
+        X = orc.field_step(g, X, F, wl.crossing_dt(g), 0.53, 7)
+    d1, scale1 = _div_B(g, X, A)
+    assert np.abs(d1).max() < 1e-13 * scale1
+
+
+def _div_D(g, X, A):
+    G = g.guard
+    fr = X[0] * A[0]
+    ft = X[1] * A[1]
+    d = np.zeros((g.nr + 1, g.nth + 1))
+    for i in range(1, g.nr):
+        for j in range(g.nth + 1):
+            s = fr[G + i, G + j] - fr[G + i - 1, G + j]
+            if j < g.nth:
+                s += ft[G + i, G + j]
+            if j > 0:
+                s -= ft[G + i, G + j - 1]
+            d[i, j] = s
+    return d
+
+
+def test_gauss_law_holds_with_the_deposit():
+    """div D - Q is invariant over a step whose J and Q come from the
+    oracle's charge-conserving deposit (interior dual cells and the axis)."""
+    g = wl.make_grid(24, 20, 0.9)
+    A = orc.field_areas(g)
+    X = _random_state(g, 3)
+    parts = wl.pairs(g, 4000, kind="mj", seed=4, params=dict(T=0.5))
+    sp = wl.species_table()
+    dt = wl.crossing_dt(g)
+    Q0 = orc.charge(g, sp, parts)
+    p1, J, _, _ = orc.run(g, sp, parts, wl.wald_fields(g), dt, 1)
+    Q1 = orc.charge(g, sp, p1)
+    X1 = orc.field_step(g, X, J, dt, 0.53, 7)
+    G = g.guard
+    before = _div_D(g, X, A)[1:g.nr] - Q0[G + 1: G + g.nr, G: G + g.nth + 1]
+    after = _div_D(g, X1, A)[1:g.nr] - Q1[G + 1: G + g.nr, G: G + g.nth + 1]
+    scale = np.abs(Q1).max() + np.abs(_div_D(g, X1, A)).max()
+    assert np.abs(after - before).max() < 1e-13 * scale
+    # the currents are not negligible against that bar
+    assert dt * np.abs(J[0]).max() > 1e6 * 1e-13 * scale
+
+
+@pytest.mark.parametrize("w1", [0.5, 0.53])
+def test_corrector_fixed_point_is_the_trapezoid_step(w1):
+    g = wl.make_grid(12, 10, 0.9)
+    X0 = _random_state(g, 5)
+    rng = np.random.default_rng(6)
+    F = [rng.normal(size=X0[0].shape) * 0.01 for _ in range(3)]
+    dt = 0.5 * wl.crossing_dt(g)
+    X1 = orc.field_step(g, X0, F, dt, w1, 80)
+    C0 = orc.field_circulations(g, X0)
+    C1 = orc.field_circulations(g, X1)
+    A = orc.field_areas(g)
+    G = g.guard
+    for k in range(6):
+        J = np.zeros_like(X0[k])
+        if k < 3:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                J = np.where(A[k] != 0.0, F[k] / A[k], 0.0)
+            if k == 2:                     # D^ph is not updated on the axes
+                J[:, G] = 0.0
+                J[:, G + g.nth] = 0.0
+        sl = (slice(G, G + g.nr + 1), slice(G, G + g.nth + 1))
+        want = X0[k] + dt * ((1 - w1) * C0[k] + w1 * C1[k]) - dt * J
+        scale = np.abs(X1[k][sl]).max() + 1e-300
+        if k in (0, 4, 5):
+            sl = (slice(G, G + g.nr), sl[1])       # components at i + 1/2: rows 0 .. nr - 1
+        assert np.abs(X1[k][sl] - want[sl]).max() < 1e-12 * scale, k
+
+
+def test_axis_zeros_and_damping_profile():
+    g = wl.make_grid(20, 16, 0.9)
+    X = _random_state(g, 7)
+    dt = wl.crossing_dt(g)
+    a = orc.field_step(g, X, None, dt, 0.53, 3)
+    b = orc.field_step(g, X, None, dt, 0.53, 3, damp_cells=6, damp_max=0.1)
+    G = g.guard
+    for k in (2, 4):                         # D^ph, B^th on both axes
+        assert not a[k][:, G].any() and not a[k][:, G + g.nth].any()
+    x_in = g.nr - 6
+    for k in range(6):
+        half = k in (0, 4, 5)
+        for i in range(g.nr + (0 if half else 1)):
+            x = i + (0.5 if half else 0.0)
+            f = 1.0 - 0.1 * ((x - x_in) / 6) ** 2 if x >= x_in else 1.0
+            cols = slice(G, G + g.nth + 1)
+            np.testing.assert_array_equal(b[k][G + i, cols], a[k][G + i, cols] * f)
