@@ -252,6 +252,54 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
                int64_t* n_alive_dev, void* stream);
 
 /*
+ * Field solver (Sec. 2.1, eqs. integral-form, fld-predictor, fld-corrector,
+ * Dr-axis; App. B, eqs. D-update, auxH, B-update, auxE).  GRPIC_FP64 grid
+ * arrays of the layout above: the dynamic fields D^i, B^i at their Yee
+ * locations, advanced in place by one step of dt.
+ *
+ * grpic_field_tables: writes, on the device, the metric coefficients
+ * alpha gamma_ij and sqrt(gamma) beta^r at the six component locations and
+ * the inverse area elements (per unit phi; 10-point Gauss quadrature of
+ * sqrt(gamma) over each face) into `tables` (device, at least
+ * grpic_field_tables_bytes(grid) bytes, caller-owned).  The library records
+ * the metric and grid the tables describe; grpic_field_step checks them.
+ *
+ * grpic_field_step: one step of the generalized Maxwell equations.
+ *   state: the six dynamic field arrays (device, updated in place).
+ *   J: the step's currents in flux form, as grpic_push_deposit accumulates
+ *     them (F^r = J^r A^D_r, F^th = J^th A^D_th, G^ph = J^ph A^D_ph, areas per
+ *     unit phi); NULL for vacuum.
+ *   The auxiliary fields E_i, H_i are formed metric coefficients first and
+ *   then averaged to their location (eqs. auxE with the 1/2 on the last
+ *   term of E_ph, auxH).  A predictor X~ = X^n + dt (C(X^n) - J) is followed
+ *   by ncorr (0 .. 64) passes X~ = X^n + dt ((1 - w1) C(X^n) + w1 C(X~))
+ *   - dt J, w1 in [0, 1] (the paper's beta; 0.53 and 7 passes in its
+ *   production runs; w1 = 1/2 is Heun's method).  D^r on the axes takes
+ *   the half-cell area and only the H_ph of its own side (eq. Dr-axis, with
+ *   dt on J as well); D^ph = B^th = 0 on the axes; guard rows copy the
+ *   nearest physical row (zero gradient) at both radial edges.  After the
+ *   step, every component at radial grid position x >= nr - damp_cells is
+ *   multiplied by 1 - damp_max ((x - nr + damp_cells)/damp_cells)^2 (an
+ *   outer damping layer; damp_cells = 0: none; damp_max in [0, 1]).
+ *   ws: device workspace of at least grpic_field_workspace_bytes(grid)
+ *   bytes; its contents on entry do not matter.
+ *   Errors: GRPIC_EINVAL for NULL arrays, dt <= 0, parameters out of range
+ *   or tables not written for this metric and grid; GRPIC_ENOMEM for a small
+ *   workspace.
+ */
+typedef struct {
+    double *D[3], *B[3];                    /* D^r, D^th, D^ph; B^r, B^th, B^ph */
+} grpic_field_state;
+
+size_t grpic_field_tables_bytes(const grpic_grid* grid);
+size_t grpic_field_workspace_bytes(const grpic_grid* grid);
+int grpic_field_tables(const grpic_metric* metric, const grpic_grid* grid, void* tables, size_t tables_bytes,
+                       void* stream);
+int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const void* tables,
+                     const grpic_field_state* state, const grpic_current* J, double dt, double w1, int ncorr,
+                     int damp_cells, double damp_max, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * grpic_crossing_time -- minimum over cell centres of the time light needs to
  * cross one cell, from |dxi/dt| <= (alpha sqrt(gamma^rr) + |beta^r|)/(r dlnr)
  * and |deta/dt| <= alpha sqrt(gamma^thth)/dth.  Host computation.  Returns a

@@ -12,6 +12,7 @@
 #include <tuple>
 
 #include "grpic.h"
+#include "grpic_fields.hpp"
 #include "grpic_launch.hpp"
 
 namespace {
@@ -158,6 +159,53 @@ void fill_common(grpic::StepArgs& A, const grpic_metric* m, const grpic_grid* g,
     A.xr = p->xr; A.xth = p->xth; A.ur = p->ur; A.uth = p->uth; A.uph = p->uph; A.w = p->w;
     A.sp = p->sp;
     A.phi = p->phi;
+}
+
+// Host-side record of the field tables written by grpic_field_tables: the
+// metric and grid they describe, so that a step can check them.
+struct FieldTablesInfo {
+    double a, M, lnr0, dlnr, dth;
+    int nr, nth, guard, pitch;
+};
+std::mutex g_ftab_mu;
+std::map<const void*, FieldTablesInfo> g_ftabs;
+
+// 10-point Gauss-Legendre nodes and weights on [-1, 1] (Newton's method on
+// P_10 from the Chebyshev guesses; w = 2 / ((1 - x^2) P_10'(x)^2)).
+void gauss_legendre10(double* x, double* w) {
+    const int n = 10;
+    for (int k = 0; k < n; ++k) {
+        double z = cos(M_PI * (k + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double step = p1 / dp;
+            z -= step;
+            if (fabs(step) < 1e-16) break;
+        }
+        x[k] = z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+void fill_field_args(grpic::FieldArgs& F, const grpic_metric* m, const grpic_grid* g) {
+    memset(&F, 0, sizeof F);
+    F.a = m->a;
+    F.M = m->M;
+    F.lnr0 = g->lnr0;
+    F.dlnr = g->dlnr;
+    F.dth = g->dth;
+    F.nr = g->nr;
+    F.nth = g->nth;
+    F.guard = g->guard;
+    F.pitch = g->pitch;
+    F.plane = grpic::field_plane(g->nr, g->pitch, g->guard);
+    F.nrow = g->nr + 4;
 }
 
 }  // namespace
@@ -380,6 +428,89 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
         g_tilings[tiling] = TilingInfo{in->n, grid->nr, grid->nth};
     }
     return GRPIC_OK;
+}
+
+size_t grpic_field_tables_bytes(const grpic_grid* grid) {
+    if (check_grid(grid)) return 0;
+    return grpic::field_tables_bytes(grid->nr, grid->pitch, grid->guard);
+}
+
+size_t grpic_field_workspace_bytes(const grpic_grid* grid) {
+    if (check_grid(grid)) return 0;
+    return grpic::field_workspace_bytes(grid->nr, grid->pitch, grid->guard);
+}
+
+int grpic_field_tables(const grpic_metric* metric, const grpic_grid* grid, void* tables, size_t tables_bytes,
+                       void* stream) {
+    int rc;
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid))) return rc;
+    if (!tables) return fail(GRPIC_EINVAL, "tables is NULL");
+    const size_t need = grpic_field_tables_bytes(grid);
+    if (tables_bytes < need) return fail(GRPIC_ENOMEM, "field tables need %zu bytes, got %zu", need, tables_bytes);
+    grpic::FieldArgs F;
+    fill_field_args(F, metric, grid);
+    F.tab = static_cast<double*>(tables);
+    F.drow = F.tab + grpic::kTablePlanes * F.plane;
+    double gx[10], gw[10];
+    gauss_legendre10(gx, gw);
+    if ((rc = hip_status(grpic::launch_field_tables(F, gx, gw, static_cast<hipStream_t>(stream)), "field tables")))
+        return rc;
+    std::lock_guard<std::mutex> lk(g_ftab_mu);
+    g_ftabs[tables] = FieldTablesInfo{metric->a, metric->M, grid->lnr0, grid->dlnr, grid->dth,
+                                      grid->nr, grid->nth, grid->guard, grid->pitch};
+    return GRPIC_OK;
+}
+
+int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const void* tables,
+                     const grpic_field_state* state, const grpic_current* J, double dt, double w1, int ncorr,
+                     int damp_cells, double damp_max, void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid))) return rc;
+    if (!state) return fail(GRPIC_EINVAL, "state is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!state->D[c] || !state->B[c]) return fail(GRPIC_EINVAL, "state: NULL component");
+    if (J && (!J->Fr || !J->Fth || !J->Gph)) return fail(GRPIC_EINVAL, "current: NULL array");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(GRPIC_EINVAL, "dt must be positive and finite");
+    if (!(w1 >= 0.0 && w1 <= 1.0)) return fail(GRPIC_EINVAL, "w1 must lie in [0, 1]");
+    if (ncorr < 0 || ncorr > 64) return fail(GRPIC_EINVAL, "ncorr must be in [0, 64]");
+    if (damp_cells < 0 || damp_cells > grid->nr) return fail(GRPIC_EINVAL, "damp_cells must be in [0, nr]");
+    if (!(damp_max >= 0.0 && damp_max <= 1.0)) return fail(GRPIC_EINVAL, "damp_max must lie in [0, 1]");
+    {
+        std::lock_guard<std::mutex> lk(g_ftab_mu);
+        auto it = g_ftabs.find(tables);
+        const FieldTablesInfo want{metric->a, metric->M, grid->lnr0, grid->dlnr, grid->dth,
+                                   grid->nr, grid->nth, grid->guard, grid->pitch};
+        if (!tables || it == g_ftabs.end() || memcmp(&it->second, &want, sizeof want) != 0)
+            return fail(GRPIC_EINVAL, "tables were not written by grpic_field_tables for this metric and grid");
+    }
+    const size_t need = grpic_field_workspace_bytes(grid);
+    if (!ws || ws_bytes < need) return fail(GRPIC_ENOMEM, "field workspace needs %zu bytes, got %zu", need, ws_bytes);
+    grpic::FieldArgs F;
+    fill_field_args(F, metric, grid);
+    F.tab = const_cast<double*>(static_cast<const double*>(tables));
+    F.drow = F.tab + grpic::kTablePlanes * F.plane;
+    if (J) {
+        F.J[0] = J->Fr;
+        F.J[1] = J->Fth;
+        F.J[2] = J->Gph;
+    }
+    F.dt = dt;
+    F.w1 = w1;
+    F.w0 = 1.0 - w1;
+    grpic::FieldPtrs X, x0, C0, aux;
+    for (int c = 0; c < 3; ++c) {
+        X.c[c] = state->D[c];
+        X.c[3 + c] = state->B[c];
+    }
+    double* w = static_cast<double*>(ws);
+    for (int c = 0; c < 6; ++c) {
+        x0.c[c] = w + (size_t)c * F.plane;
+        C0.c[c] = w + (size_t)(6 + c) * F.plane;
+        aux.c[c] = w + (size_t)(12 + c) * F.plane;
+    }
+    return hip_status(grpic::launch_field_step(F, X, x0, C0, aux, ncorr, damp_cells, damp_max,
+                                               static_cast<hipStream_t>(stream)),
+                      "field step");
 }
 
 }  // extern "C"

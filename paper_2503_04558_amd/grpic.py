@@ -63,9 +63,14 @@ class grpic_field_grads(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
 
 
+class grpic_field_state(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
+
+
 EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
-            "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version")
+            "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
+            "grpic_field_tables_bytes", "grpic_field_workspace_bytes", "grpic_field_tables", "grpic_field_step")
 
 
 class GrpicError(RuntimeError):
@@ -105,6 +110,14 @@ def lib():
         L.grpic_sort.restype = ctypes.c_int
         L.grpic_crossing_time.argtypes = [vp, vp]
         L.grpic_crossing_time.restype = ctypes.c_double
+        L.grpic_field_tables_bytes.argtypes = [vp]
+        L.grpic_field_tables_bytes.restype = sz
+        L.grpic_field_workspace_bytes.argtypes = [vp]
+        L.grpic_field_workspace_bytes.restype = sz
+        L.grpic_field_tables.argtypes = [vp, vp, vp, sz, vp]
+        L.grpic_field_tables.restype = ctypes.c_int
+        L.grpic_field_step.argtypes = [vp, vp, vp, vp, vp, f64, f64, i32, i32, f64, vp, sz, vp]
+        L.grpic_field_step.restype = ctypes.c_int
         L.grpic_last_error.restype = ctypes.c_char_p
         L.grpic_version.restype = ctypes.c_char_p
         _lib = L
@@ -405,3 +418,59 @@ class PushDeposit(torch.autograd.Function):
         grpic_push_deposit_backward(metric, grid, species, start, F, lam, dt, nsteps, ncorr, ckpt, ckpt_every, ws,
                                     gu, gF)
         return (None,) * 8 + tuple(gu) + tuple(gF)
+
+
+# ---------------------------------------------------------------- field solver
+def grpic_field_tables_bytes(grid) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_field_tables_bytes(ctypes.byref(g)))
+
+
+def grpic_field_workspace_bytes(grid) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_field_workspace_bytes(ctypes.byref(g)))
+
+
+def grpic_field_tables(metric: grpic_metric, grid, tables: torch.Tensor, stream=None) -> None:
+    g = make_grid(grid)
+    if not tables.is_cuda or not tables.is_contiguous():
+        raise ValueError("tables: expected a contiguous device tensor")
+    _check(lib().grpic_field_tables(ctypes.byref(metric), ctypes.byref(g), _ptr(tables), _nbytes(tables),
+                                    _stream(stream)))
+
+
+def grpic_field_step(metric: grpic_metric, grid, tables: torch.Tensor, state, J, dt: float, w1: float = 0.53,
+                     ncorr: int = 7, damp_cells: int = 0, damp_max: float = 0.0, ws: torch.Tensor | None = None,
+                     stream=None) -> None:
+    """state: six float64 grid arrays D^r, D^th, D^ph, B^r, B^th, B^ph,
+    updated in place; J: the flux-form currents (three arrays) or None."""
+    g = make_grid(grid)
+    if len(state) != 6:
+        raise ValueError("state: need D^r, D^th, D^ph, B^r, B^th, B^ph")
+    for i, f in enumerate(state):
+        _need(f, torch.float64, _grid_numel(grid), f"state {i}")
+    st = grpic_field_state()
+    for c in range(3):
+        st.D[c] = state[c].data_ptr()
+        st.B[c] = state[3 + c].data_ptr()
+    C = make_current(grid, J) if J is not None else None
+    if ws is None or not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("ws: expected a contiguous device tensor")
+    _check(lib().grpic_field_step(ctypes.byref(metric), ctypes.byref(g), _ptr(tables), ctypes.byref(st),
+                                  ctypes.byref(C) if C is not None else None, float(dt), float(w1), int(ncorr),
+                                  int(damp_cells), float(damp_max), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+class FieldSolver:
+    """Tables and workspace of one metric and grid, allocated once."""
+
+    def __init__(self, metric: grpic_metric, grid, device="cuda"):
+        self.metric, self.grid = metric, grid
+        self.tables = torch.empty(grpic_field_tables_bytes(grid), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(grpic_field_workspace_bytes(grid), dtype=torch.uint8, device=device)
+        grpic_field_tables(metric, grid, self.tables)
+
+    def step(self, state, J, dt: float, w1: float = 0.53, ncorr: int = 7, damp_cells: int = 0,
+             damp_max: float = 0.0, stream=None) -> None:
+        grpic_field_step(self.metric, self.grid, self.tables, state, J, dt, w1, ncorr, damp_cells, damp_max,
+                         self.ws, stream)
