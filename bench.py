@@ -241,6 +241,51 @@ def run_adjoint(args):
             "dense_lambda_bwd_ms": min(bd), "dense_lambda_bwd_over_fwd": min(bd) / min(f_ck)}
 
 
+# Field step: grid planes one evaluation must move at least, with the
+# coefficient and inverse-area tables precomputed (20 planes): the
+# predictor reads the state, tables and currents (3) and writes the state
+# and its circulations; a corrector pass reads the iterate, the start state,
+# the start circulations, tables and currents and writes the iterate.
+FIELD_PLANES_PREDICTOR = 6 + 20 + 3 + 6 + 6
+FIELD_PLANES_CORRECTOR = 6 + 6 + 6 + 20 + 3 + 6
+
+
+def run_fields(args, g, F):
+    """Time field steps (predictor + args.field_ncorr correctors) of the
+    Wald state on the throughput grid, currents passed (zero), damping over
+    the outer 64 rows."""
+    import torch
+
+    from paper_2503_04558_amd import grpic
+
+    metric = grpic.make_metric(g.a, g.M)
+    dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+    solver = grpic.FieldSolver(metric, g)
+    state = [f.to(torch.float64).clone() for f in F]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    kw = dict(w1=args.field_w1, ncorr=args.field_ncorr, damp_cells=64, damp_max=0.05)
+    for _ in range(2):
+        solver.step(state, J, dt, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.field_steps):
+        solver.step(state, J, dt, stream=stream, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.field_steps
+    finite = all(bool(torch.isfinite(s).all()) for s in state)
+    plane = (g.nr + 1) * (g.nth + 1) * 8
+    nbytes = plane * (FIELD_PLANES_PREDICTOR + args.field_ncorr * FIELD_PLANES_CORRECTOR)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"fields: {args.field_steps} steps of ncorr={args.field_ncorr}: {ms:.3f} ms/step, finite={finite}")
+    return {"grid": [g.nr, g.nth], "ncorr": args.field_ncorr, "w1": args.field_w1, "steps": args.field_steps,
+            "ms_per_step": ms, "cell_updates_per_s": g.nr * g.nth / (ms * 1e-3), "finite": finite,
+            "roofline_hbm": dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, bytes_per_step=nbytes)}
+
+
 def run_cpu_baseline(args, grid):
     """The FP64 oracle (OpenMP over particles) on a bounded sample."""
     from oracle import oracle as orc
@@ -289,6 +334,10 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the backward / forward timing")
     ap.add_argument("--adj-pairs", type=int, default=500_000)
+    ap.add_argument("--no-fields", action="store_true", help="skip the field-solver timing")
+    ap.add_argument("--field-steps", type=int, default=10)
+    ap.add_argument("--field-ncorr", type=int, default=7)
+    ap.add_argument("--field-w1", type=float, default=0.53)
     ap.add_argument("--cpu-pairs", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -330,6 +379,7 @@ def main():
         F32 = [f.to(torch.float32) for f in F]
         rs = run_gpu(args, g, F32, split_parts, grpic.GRPIC_FP32_SPLIT)
     del split_parts
+    fld = None if args.no_fields else run_fields(args, g, F)
     adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
     # 1344 flop per 97 B = 13.9 flop/B, above the FP64 ridge (78.6 TFLOP/s / 8 TB/s =
@@ -384,6 +434,8 @@ def main():
         }
     if adj is not None:
         out["adjoint"] = adj
+    if fld is not None:
+        out["fields"] = fld
     print(json.dumps(out), flush=True)
 
 
