@@ -242,12 +242,13 @@ def run_adjoint(args):
 
 
 # Field step: grid planes one evaluation must move at least, with the
-# coefficient and inverse-area tables precomputed (20 planes): the
-# predictor reads the state, tables and currents (3) and writes the state
-# and its circulations; a corrector pass reads the iterate, the start state,
-# the start circulations, tables and currents and writes the iterate.
-FIELD_PLANES_PREDICTOR = 6 + 20 + 3 + 6 + 6
-FIELD_PLANES_CORRECTOR = 6 + 6 + 6 + 20 + 3 + 6
+# metric coefficients formed in registers and the six inverse areas
+# tabulated: the predictor reads the state, inverse areas and currents (3)
+# and writes the state and its circulations; a corrector pass reads the
+# iterate, the start state, the start circulations, inverse areas and
+# currents and writes the iterate.
+FIELD_PLANES_PREDICTOR = 6 + 6 + 3 + 6 + 6
+FIELD_PLANES_CORRECTOR = 6 + 6 + 6 + 6 + 3 + 6
 
 
 def run_fields(args, g, F):

@@ -257,10 +257,11 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
  * arrays of the layout above: the dynamic fields D^i, B^i at their Yee
  * locations, advanced in place by one step of dt.
  *
- * grpic_field_tables: writes, on the device, the metric coefficients
- * alpha gamma_ij and sqrt(gamma) beta^r at the six component locations and
- * the inverse area elements (per unit phi; 10-point Gauss quadrature of
- * sqrt(gamma) over each face) into `tables` (device, at least
+ * grpic_field_tables: writes, on the device, the inverse area elements of
+ * the six components (per unit phi; 10-point Gauss quadrature of sqrt(gamma)
+ * over each face), radial edge lengths, and r, sin theta, cos theta at
+ * half-cell steps (from which the step forms the metric coefficients
+ * alpha gamma_ij, sqrt(gamma) beta^r) into `tables` (device, at least
  * grpic_field_tables_bytes(grid) bytes, caller-owned).  The library records
  * the metric and grid the tables describe; grpic_field_step checks them.
  *

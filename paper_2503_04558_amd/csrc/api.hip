@@ -432,7 +432,7 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
 
 size_t grpic_field_tables_bytes(const grpic_grid* grid) {
     if (check_grid(grid)) return 0;
-    return grpic::field_tables_bytes(grid->nr, grid->pitch, grid->guard);
+    return grpic::field_tables_bytes(grid->nr, grid->nth, grid->pitch, grid->guard);
 }
 
 size_t grpic_field_workspace_bytes(const grpic_grid* grid) {
@@ -451,6 +451,8 @@ int grpic_field_tables(const grpic_metric* metric, const grpic_grid* grid, void*
     fill_field_args(F, metric, grid);
     F.tab = static_cast<double*>(tables);
     F.drow = F.tab + grpic::kTablePlanes * F.plane;
+    F.rad = F.drow + grpic::kDrRows * F.nrow;
+    F.sn = F.rad + grpic::field_nrad(F.nr);
     double gx[10], gw[10];
     gauss_legendre10(gx, gw);
     if ((rc = hip_status(grpic::launch_field_tables(F, gx, gw, static_cast<hipStream_t>(stream)), "field tables")))
@@ -489,6 +491,8 @@ int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const v
     fill_field_args(F, metric, grid);
     F.tab = const_cast<double*>(static_cast<const double*>(tables));
     F.drow = F.tab + grpic::kTablePlanes * F.plane;
+    F.rad = F.drow + grpic::kDrRows * F.nrow;
+    F.sn = F.rad + grpic::field_nrad(F.nr);
     if (J) {
         F.J[0] = J->Fr;
         F.J[1] = J->Fth;
@@ -497,18 +501,18 @@ int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const v
     F.dt = dt;
     F.w1 = w1;
     F.w0 = 1.0 - w1;
-    grpic::FieldPtrs X, x0, C0, aux;
+    grpic::FieldPtrs X, C0, W1, W2;
     for (int c = 0; c < 3; ++c) {
         X.c[c] = state->D[c];
         X.c[3 + c] = state->B[c];
     }
     double* w = static_cast<double*>(ws);
     for (int c = 0; c < 6; ++c) {
-        x0.c[c] = w + (size_t)c * F.plane;
-        C0.c[c] = w + (size_t)(6 + c) * F.plane;
-        aux.c[c] = w + (size_t)(12 + c) * F.plane;
+        C0.c[c] = w + (size_t)c * F.plane;
+        W1.c[c] = w + (size_t)(6 + c) * F.plane;
+        W2.c[c] = w + (size_t)(12 + c) * F.plane;
     }
-    return hip_status(grpic::launch_field_step(F, X, x0, C0, aux, ncorr, damp_cells, damp_max,
+    return hip_status(grpic::launch_field_step(F, X, C0, W1, W2, ncorr, damp_cells, damp_max,
                                                static_cast<hipStream_t>(stream)),
                       "field step");
 }

@@ -2,26 +2,33 @@
 // the integral form of the 3+1 Maxwell equations on the staggered Yee grid,
 // advanced by a predictor and ncorr semi-implicit corrector passes.
 //
-// One evaluation of the circulations is two stencil kernels over the grid
-// (HBM-bound, no matrix work): field_aux forms the auxiliary fields E_i, H_i
-// of eqs. auxE / auxH (metric coefficients first, then averaged to the
-// auxiliary field's location), field_update takes their circulations
-// (eqs. D-update, B-update; the axis rows of D^r by eq. Dr-axis) and writes
-// the predictor or corrector value.  Guard rows are refilled (zero
-// gradient) and the axis values of D^ph, B^th set to zero after every pass;
-// a damping layer scales the outer rows after the step.
+// One evaluation of the circulations is one stencil kernel (HBM-bound, no
+// matrix work), field_eval_kernel: a workgroup takes a tile of kTileR x
+// kTileC grid points, forms the auxiliary fields E_i, H_i of eqs. auxE /
+// auxH over the tile and a one-point halo in LDS -- metric coefficients
+// first (evaluated on the fly from tabulated r and sin, cos theta), then
+// averaged to the auxiliary field's location -- and then takes their
+// circulations (eqs. D-update, B-update; the axis rows of D^r by eq.
+// Dr-axis) and writes the predictor or corrector value of its points.
+// Guard rows are refilled (zero gradient) and the axis values of D^ph, B^th
+// set to zero after every pass; a damping layer scales the outer rows after
+// the step.
 //
 // Locations, array element (i, j) of each component (r_x = exp(lnr0 + x
 // dlnr), theta_y = y dth): D^r, B^th, E_r, H_th at (i+1/2, j); D^th, B^r,
 // E_th, H_r at (i, j+1/2); D^ph, E_ph at (i, j); B^ph, H_ph at (i+1/2, j+1/2).
 // Areas and volumes are per unit phi (the deposit's flux-form currents are
 // J^r A^D_r, J^th A^D_th, J^ph A^D_ph).
+#include "grpic_device.hpp"
 #include "grpic_fields.hpp"
 
 #include <algorithm>
 
 namespace grpic {
 namespace {
+
+constexpr int kTileR = 8, kTileC = 64;                  // grid points per workgroup (2 per thread)
+constexpr int kAuxR = kTileR + 2, kAuxC = kTileC + 2;   // with a one-point halo
 
 __device__ __forceinline__ double rad(const FieldArgs& F, double x) { return exp(F.lnr0 + x * F.dlnr); }
 
@@ -33,24 +40,36 @@ __device__ __forceinline__ double sqrt_gamma(double a, double M, double r, doubl
 }
 
 struct Coef {
-    double aGrr, aGrp, aGtt, aGpp, sgB;       // alpha gamma_ij, sqrt(gamma) beta^r
+    double aGrr, aGrp, aGtt, aGpp, sgB;                 // alpha gamma_ij, sqrt(gamma) beta^r
 };
 
-__device__ __forceinline__ Coef coef_at(double a, double M, double r, double th) {
-    const double s = sin(th), c = cos(th), s2 = s * s;
-    const double rho2 = r * r + a * a * c * c;
-    const double z = 2.0 * M * r / rho2;
-    const double opz = 1.0 + z;
-    const double alpha = 1.0 / sqrt(opz);
-    const double Delta = r * r + a * a - 2.0 * M * r;
-    const double Sigma = (r * r + a * a) * (r * r + a * a) - a * a * Delta * s2;
+// Coefficients at radius r and polar angle with sine s, cosine c, with
+// alpha = 1/sqrt(1 + z), z = 2 M r / rho^2: alpha gamma_rr = sqrt(1 + z),
+// alpha gamma_rph = -a sin^2 sqrt(1 + z), alpha gamma_thth = rho^2 alpha,
+// alpha gamma_phph = alpha Sigma sin^2 / rho^2, sqrt(gamma) beta^r =
+// rho^2 |sin| sqrt(1 + z) z / (1 + z) = 2 M r |sin| alpha.  One reciprocal
+// and one reciprocal square root per point.
+__device__ __forceinline__ Coef coef_at(double a, double M, double r, double s, double c) {
+    const double s2 = s * s, a2 = a * a, r2 = r * r;
+    const double rho2 = r2 + a2 * (c * c);
+    const double irho2 = rcp(rho2);
+    const double tMr = 2.0 * M * r;
+    double sq, alpha;
+    sqrt_rsqrt(1.0 + tMr * irho2, sq, alpha);
+    const double ra2 = r2 + a2;
+    const double Sigma = ra2 * ra2 - a2 * (ra2 - tMr) * s2;
     Coef k;
-    k.aGrr = alpha * opz;
-    k.aGrp = -alpha * a * s2 * opz;
+    k.aGrr = sq;
+    k.aGrp = -a * s2 * sq;
     k.aGtt = alpha * rho2;
-    k.aGpp = alpha * Sigma * s2 / rho2;
-    k.sgB = rho2 * fabs(s) * sqrt(opz) * (z / opz);
+    k.aGpp = alpha * Sigma * s2 * irho2;
+    k.sgB = tMr * fabs(s) * alpha;
     return k;
+}
+
+// At grid position (x, y) = (hx / 2, hy / 2), hx >= -4 (x = -2), hy >= 0.
+__device__ __forceinline__ Coef coef_grid(const FieldArgs& F, int hx, int hy) {
+    return coef_at(F.a, F.M, F.rad[hx + 4], F.sn[hy], F.sn[field_nang(F.nth) + hy]);
 }
 
 struct Quad {
@@ -76,39 +95,23 @@ __device__ __forceinline__ double int_rth(const FieldArgs& F, const Quad& Q, dou
 
 __device__ __forceinline__ double inv_or_zero(double v) { return v != 0.0 ? 1.0 / v : 0.0; }
 
-// Tables: coefficients at the six locations and inverse areas, for the
-// physical rows and columns (0 .. nr, 0 .. nth) and the guard rows -2, -1
-// and nr + 1 that the auxiliary fields of rows -1 and nr reach.
+// Tables: inverse areas of the six components over the physical rows and
+// columns (zero in the other rows -2, -1, nr + 1 that the table covers),
+// radial edge lengths per row, radii and sin, cos at half-integer steps.
 __global__ __launch_bounds__(256) void field_tables_kernel(FieldArgs F, Quad Q) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int ncol = F.nth + 1;
+    if (t < field_nrad(F.nr)) F.rad[t] = rad(F, -2.0 + 0.5 * (double)t);
+    if (t < field_nang(F.nth)) {
+        F.sn[t] = sin(0.5 * (double)t * F.dth);
+        F.sn[field_nang(F.nth) + t] = cos(0.5 * (double)t * F.dth);
+    }
     if (t >= (int64_t)ncol * F.nrow) return;
     const int i = (int)(t / ncol) + kTableRowLo, j = (int)(t % ncol);
     const uint32_t e = F.at(i, j);
     const double th_j = j * F.dth, th_h = (j + 0.5) * F.dth;
     const double r_i = rad(F, i), r_h = rad(F, i + 0.5);
     auto clamp_th = [&](double y) { return fmin(fmax(y, 0.0), (double)F.nth) * F.dth; };
-    // coefficients: D^r and B^th at (i+1/2, j), D^th and B^r at (i, j+1/2),
-    // D^ph at (i, j), B^ph at (i+1/2, j+1/2)
-    const Coef cDr = coef_at(F.a, F.M, r_h, th_j), cDt = coef_at(F.a, F.M, r_i, th_h);
-    const Coef cDp = coef_at(F.a, F.M, r_i, th_j), cBp = coef_at(F.a, F.M, r_h, th_h);
-    double* T = F.tab;
-    const size_t S = F.plane;
-    T[kT_Dr_aGrr * S + e] = cDr.aGrr;
-    T[kT_Dr_aGrp * S + e] = cDr.aGrp;
-    T[kT_Dr_sgB * S + e] = cDr.sgB;                // B^th shares the location
-    T[kT_Dr_aGtt * S + e] = cDr.aGtt;
-    T[kT_Dt_aGtt * S + e] = cDt.aGtt;
-    T[kT_Dt_sgB * S + e] = cDt.sgB;
-    T[kT_Dt_aGrr * S + e] = cDt.aGrr;              // B^r shares the location
-    T[kT_Dt_aGrp * S + e] = cDt.aGrp;
-    T[kT_Dp_aGpp * S + e] = cDp.aGpp;
-    T[kT_Dp_aGrp * S + e] = cDp.aGrp;
-    T[kT_Dp_sgB * S + e] = cDp.sgB;
-    T[kT_Bp_aGpp * S + e] = cBp.aGpp;
-    T[kT_Bp_aGrp * S + e] = cBp.aGrp;
-    T[kT_Bp_sgB * S + e] = cBp.sgB;
-    // inverse areas (per unit phi), zero where a component is not updated
     double iADr = 0.0, iADt = 0.0, iADp = 0.0, iABr = 0.0, iABt = 0.0, iABp = 0.0;
     if (i >= 0 && i <= F.nr) {
         const double r_m = rad(F, i - 0.5), r_p = rad(F, i + 1.0);
@@ -119,13 +122,15 @@ __global__ __launch_bounds__(256) void field_tables_kernel(FieldArgs F, Quad Q) 
         if (i < F.nr && j > 0 && j < F.nth) iABt = inv_or_zero(int_r(F, Q, th_j, r_i, r_p));
         if (i < F.nr && j < F.nth) iABp = inv_or_zero(int_rth(F, Q, r_i, r_p, th_j, (j + 1) * F.dth));
     }
+    double* T = F.tab;
+    const size_t S = F.plane;
     T[kT_iADr * S + e] = iADr;
     T[kT_iADt * S + e] = iADt;
     T[kT_iADp * S + e] = iADp;
     T[kT_iABr * S + e] = iABr;
     T[kT_iABt * S + e] = iABt;
     T[kT_iABp * S + e] = iABp;
-    if (j == 0) {                                   // radial edge lengths of row i
+    if (j == 0) {                                       // radial edge lengths of row i
         F.drow[kDrPrimal * F.nrow + (i - kTableRowLo)] = rad(F, i + 1.0) - r_i;
         F.drow[kDrDual * F.nrow + (i - kTableRowLo)] = r_h - rad(F, i - 0.5);
     }
@@ -146,108 +151,133 @@ __global__ __launch_bounds__(256) void field_axis_kernel(FieldArgs F, FieldPtrs 
 
 __global__ __launch_bounds__(256) void field_guard_rows_kernel(FieldArgs F, FieldPtrs X) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nrows = 2 * F.guard + 1;                 // -guard .. -1, nr .. nr + guard
+    const int nrows = 2 * F.guard + 1;                  // -guard .. -1, nr .. nr + guard
     if (t >= (int64_t)nrows * F.pitch) return;
     const int r = (int)(t / F.pitch), jj = (int)(t % F.pitch) - F.guard;
     const int i = r < F.guard ? r - F.guard : F.nr + (r - F.guard);
     for (int c = 0; c < 6; ++c) {
         const bool half = c == 0 || c == 4 || c == 5;
         const int last = half ? F.nr - 1 : F.nr;
-        if (i >= 0 && i <= last) continue;             // row nr of D^th, D^ph, B^r is physical
+        if (i >= 0 && i <= last) continue;              // row nr of D^th, D^ph, B^r is physical
         const int src = i < 0 ? 0 : last;
         X.c[c][F.at(i, jj)] = X.c[c][F.at(src, jj)];
     }
 }
 
-// Auxiliary fields of the state X (eqs. auxE, auxH) over rows -1 .. nr and
-// columns 0 .. nth: aux.c[0..2] = E_r, E_th, E_ph; aux.c[3..5] = H_r, H_th, H_ph.
-__global__ __launch_bounds__(256) void field_aux_kernel(FieldArgs F, FieldPtrs X, FieldPtrs aux) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncol = F.nth + 1;
-    if (t >= (int64_t)ncol * (F.nr + 2)) return;
-    const int i = (int)(t / ncol) - 1, j = (int)(t % ncol);
+// The six auxiliary fields at grid point (i, j), -1 <= i <= nr, 0 <= j <=
+// nth, from the state X (guard rows filled): o[0..2] = E_r, E_th, E_ph,
+// o[3..5] = H_r, H_th, H_ph (E_th, H_r, H_ph only for j < nth, else 0).
+__device__ __forceinline__ void aux_at(const FieldArgs& F, const FieldPtrs& X, int i, int j, double o[6]) {
     const uint32_t e = F.at(i, j), em = F.at(i - 1, j), ep = F.at(i + 1, j);
-    const double* T = F.tab;
-    const size_t S = F.plane;
     const double *Dr = X.c[0], *Dt = X.c[1], *Dp = X.c[2], *Br = X.c[3], *Bt = X.c[4], *Bp = X.c[5];
-    auto tb = [&](int k, uint32_t x) { return T[k * S + x]; };
-    // E_r at (i+1/2, j)
-    aux.c[0][e] = tb(kT_Dr_aGrr, e) * Dr[e] + 0.5 * (tb(kT_Dp_aGrp, e) * Dp[e] + tb(kT_Dp_aGrp, ep) * Dp[ep]);
-    // E_ph at (i, j)
-    aux.c[2][e] = tb(kT_Dp_aGpp, e) * Dp[e] + 0.5 * (tb(kT_Dr_aGrp, e) * Dr[e] + tb(kT_Dr_aGrp, em) * Dr[em]) +
-                  0.5 * (tb(kT_Dr_sgB, e) * Bt[e] + tb(kT_Dr_sgB, em) * Bt[em]);
-    // H_th at (i+1/2, j)
-    aux.c[4][e] = tb(kT_Dr_aGtt, e) * Bt[e] + 0.5 * (tb(kT_Dp_sgB, e) * Dp[e] + tb(kT_Dp_sgB, ep) * Dp[ep]);
+    const int hx = 2 * i, hy = 2 * j;
+    // coefficients at (i +- 1/2, j), (i, j), (i + 1, j)
+    const Coef cRh = coef_grid(F, hx + 1, hy), cRm = coef_grid(F, hx - 1, hy);
+    const Coef cP = coef_grid(F, hx, hy), cPp = coef_grid(F, hx + 2, hy);
+    o[0] = cRh.aGrr * Dr[e] + 0.5 * (cP.aGrp * Dp[e] + cPp.aGrp * Dp[ep]);
+    o[2] = cP.aGpp * Dp[e] + 0.5 * (cRh.aGrp * Dr[e] + cRm.aGrp * Dr[em]) +
+           0.5 * (cRh.sgB * Bt[e] + cRm.sgB * Bt[em]);
+    o[4] = cRh.aGtt * Bt[e] + 0.5 * (cP.sgB * Dp[e] + cPp.sgB * Dp[ep]);
     if (j < F.nth) {
-        // E_th at (i, j+1/2)
-        aux.c[1][e] = tb(kT_Dt_aGtt, e) * Dt[e] - 0.5 * (tb(kT_Bp_sgB, e) * Bp[e] + tb(kT_Bp_sgB, em) * Bp[em]);
-        // H_r at (i, j+1/2)
-        aux.c[3][e] = tb(kT_Dt_aGrr, e) * Br[e] + 0.5 * (tb(kT_Bp_aGrp, e) * Bp[e] + tb(kT_Bp_aGrp, em) * Bp[em]);
-        // H_ph at (i+1/2, j+1/2)
-        aux.c[5][e] = tb(kT_Bp_aGpp, e) * Bp[e] + 0.5 * (tb(kT_Dt_aGrp, e) * Br[e] + tb(kT_Dt_aGrp, ep) * Br[ep]) -
-                      0.5 * (tb(kT_Dt_sgB, e) * Dt[e] + tb(kT_Dt_sgB, ep) * Dt[ep]);
+        // coefficients at (i, j + 1/2), (i + 1, j + 1/2), (i +- 1/2, j + 1/2)
+        const Coef cT = coef_grid(F, hx, hy + 1), cTp = coef_grid(F, hx + 2, hy + 1);
+        const Coef cBh = coef_grid(F, hx + 1, hy + 1), cBm = coef_grid(F, hx - 1, hy + 1);
+        o[1] = cT.aGtt * Dt[e] - 0.5 * (cBh.sgB * Bp[e] + cBm.sgB * Bp[em]);
+        o[3] = cT.aGrr * Br[e] + 0.5 * (cBh.aGrp * Bp[e] + cBm.aGrp * Bp[em]);
+        o[5] = cBh.aGpp * Bp[e] + 0.5 * (cT.aGrp * Br[e] + cTp.aGrp * Br[ep]) -
+               0.5 * (cT.sgB * Dt[e] + cTp.sgB * Dt[ep]);
+    } else {
+        o[1] = o[3] = o[5] = 0.0;
     }
 }
 
-// Circulations of the auxiliary fields and the pass's update, rows 0 .. nr,
-// columns 0 .. nth.  first: C0 <- C and out = x0 + dt (C - J); else
-// out = x0 + dt (w0 C0 + w1 C) - dt J.  Elements a component does not
-// update are left alone.
-__global__ __launch_bounds__(256) void field_update_kernel(FieldArgs F, FieldPtrs aux, FieldPtrs x0, FieldPtrs C0,
-                                                           FieldPtrs out, int first) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncol = F.nth + 1;
-    if (t >= (int64_t)ncol * (F.nr + 1)) return;
-    const int i = (int)(t / ncol), j = (int)(t % ncol);
-    const uint32_t e = F.at(i, j), em = F.at(i - 1, j), ep = F.at(i + 1, j);
-    const uint32_t ejm = F.at(i, j - 1), ejp = F.at(i, j + 1);
+// One evaluation: the auxiliary fields of X over the tile and its halo in
+// LDS, then for each point of the tile the circulations and the pass's
+// value of all six components.  FIRST: C0 <- C and the value is x0 + dt (C
+// - J); else x0 + dt (w0 C0 + w1 C) - dt J.  Elements a component does not
+// update take x0 (zero on the axes for D^ph, B^th); with L > 0 the values
+// at radial position x >= nr - L are scaled by 1 - d ((x - nr + L) / L)^2
+// (the damping layer, on the step's last pass).  The zero-gradient guard
+// rows of out are written from the rows they copy.  out must not alias X
+// (other workgroups read X in their halo); it may alias x0, which is read
+// only at the point being written.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs X, FieldPtrs x0, FieldPtrs C0,
+                                                         FieldPtrs out, int L, double d) {
+    __shared__ double aux[6][kAuxR][kAuxC];
+    const int tiles_c = (F.nth + kTileC) / kTileC;      // columns 0 .. nth
+    const int i0 = (int)(blockIdx.x / tiles_c) * kTileR, j0 = (int)(blockIdx.x % tiles_c) * kTileC;
+    for (int e = threadIdx.x; e < kAuxR * kAuxC; e += blockDim.x) {
+        const int li = e / kAuxC, lj = e - li * kAuxC;
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        double o[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (i >= -1 && i <= F.nr && j >= 0 && j <= F.nth) aux_at(F, X, i, j, o);
+        for (int c = 0; c < 6; ++c) aux[c][li][lj] = o[c];
+    }
+    __syncthreads();
     const double* T = F.tab;
     const size_t S = F.plane;
-    const double *Er = aux.c[0], *Et = aux.c[1], *Ep = aux.c[2], *Hr = aux.c[3], *Ht = aux.c[4], *Hp = aux.c[5];
-    const double dth = F.dth;
-    const double dr = F.drow[kDrPrimal * F.nrow + (i - kTableRowLo)];
-    const double drd = F.drow[kDrDual * F.nrow + (i - kTableRowLo)];
-    auto apply = [&](int c, double C, double J) {
-        if (first) {
-            C0.c[c][e] = C;
-            out.c[c][e] = x0.c[c][e] + F.dt * (C - J);
-        } else {
-            out.c[c][e] = x0.c[c][e] + F.dt * (F.w0 * C0.c[c][e] + F.w1 * C) - F.dt * J;
+    for (int k = threadIdx.x; k < kTileR * kTileC; k += blockDim.x) {
+        const int li = k / kTileC, lj = k - li * kTileC;
+        const int i = i0 + li, j = j0 + lj;
+        if (i > F.nr || j > F.nth) continue;
+        const int a = li + 1, b = lj + 1;                // this point in the aux tile
+        const uint32_t e = F.at(i, j);
+        const double dr = F.drow[kDrPrimal * F.nrow + (i - kTableRowLo)];
+        const double drd = F.drow[kDrDual * F.nrow + (i - kTableRowLo)];
+        double f_i = 1.0, f_h = 1.0;                     // damping at x = i, i + 1/2
+        if (L > 0) {
+            const double x_in = (double)(F.nr - L);
+            auto damp = [&](double x) {
+                const double s = (x - x_in) / L;
+                return x < x_in ? 1.0 : 1.0 - d * s * s;
+            };
+            f_i = damp((double)i);
+            f_h = damp(i + 0.5);
         }
-    };
-    auto cur = [&](int c, int k) { return F.J[c] ? F.J[c][e] * T[k * S + e] : 0.0; };
-    if (i < F.nr) {                                       // D^r at (i+1/2, j), axes included
-        const double hp = j < F.nth ? Hp[e] : 0.0, hm = j > 0 ? Hp[ejm] : 0.0;
-        apply(0, (hp - hm) * T[kT_iADr * S + e], cur(0, kT_iADr));
-    }
-    if (j < F.nth) {                                      // D^th at (i, j+1/2)
-        apply(1, (Hp[em] - Hp[e]) * T[kT_iADt * S + e], cur(1, kT_iADt));
-        apply(3, -(Ep[ejp] - Ep[e]) * T[kT_iABr * S + e], 0.0);   // B^r at (i, j+1/2)
-    }
-    if (j > 0 && j < F.nth) {                             // D^ph at (i, j)
-        apply(2, ((Ht[e] - Ht[em]) * dth + (Hr[ejm] - Hr[e]) * drd) * T[kT_iADp * S + e], cur(2, kT_iADp));
-        if (i < F.nr) apply(4, -(Ep[e] - Ep[ep]) * T[kT_iABt * S + e], 0.0);   // B^th at (i+1/2, j)
-    }
-    if (i < F.nr && j < F.nth)                            // B^ph at (i+1/2, j+1/2)
-        apply(5, -((Et[ep] - Et[e]) * dth + (Er[e] - Er[ejp]) * dr) * T[kT_iABp * S + e], 0.0);
-}
-
-// Damping layer: component values at radial position x >= nr - L scaled
-// by 1 - d ((x - nr + L) / L)^2.
-__global__ __launch_bounds__(256) void field_damp_kernel(FieldArgs F, FieldPtrs X, int L, double d) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncol = F.nth + 1;
-    if (t >= (int64_t)ncol * (L + 1)) return;
-    const int i = F.nr - L + (int)(t / ncol), j = (int)(t % ncol);
-    if (i < 0) return;
-    const double x_in = (double)(F.nr - L);
-    for (int c = 0; c < 6; ++c) {
-        const bool half = c == 0 || c == 4 || c == 5;
-        if (half && i >= F.nr) continue;
-        const double x = i + (half ? 0.5 : 0.0);
-        if (x < x_in) continue;
-        const double s = (x - x_in) / L;
-        X.c[c][F.at(i, j)] *= 1.0 - d * s * s;
+        auto put = [&](int c, double v) {
+            const bool half = c == 0 || c == 4 || c == 5;
+            const int last = half ? F.nr - 1 : F.nr;
+            v *= half ? f_h : f_i;
+            out.c[c][e] = v;
+            if (i == 0)
+                for (int g = 1; g <= F.guard; ++g) out.c[c][F.at(-g, j)] = v;
+            if (i == last)
+                for (int r = last + 1; r <= F.nr + F.guard; ++r) out.c[c][F.at(r, j)] = v;
+        };
+        auto next = [&](int c, double C, double J) {
+            if (FIRST) {
+                C0.c[c][e] = C;
+                return x0.c[c][e] + F.dt * (C - J);
+            }
+            return x0.c[c][e] + F.dt * (F.w0 * C0.c[c][e] + F.w1 * C) - F.dt * J;
+        };
+        auto cur = [&](int c, int t) { return F.J[c] ? F.J[c][e] * T[t * S + e] : 0.0; };
+        const bool axis = j == 0 || j == F.nth;
+        if (i < F.nr) {                                  // D^r at (i+1/2, j), axes included
+            const double hp = j < F.nth ? aux[5][a][b] : 0.0, hm = j > 0 ? aux[5][a][b - 1] : 0.0;
+            put(0, next(0, (hp - hm) * T[kT_iADr * S + e], cur(0, kT_iADr)));
+        }
+        // D^th at (i, j+1/2), B^r at (i, j+1/2)
+        put(1, j < F.nth ? next(1, (aux[5][a - 1][b] - aux[5][a][b]) * T[kT_iADt * S + e], cur(1, kT_iADt))
+                         : x0.c[1][e]);
+        put(3, j < F.nth ? next(3, -(aux[2][a][b + 1] - aux[2][a][b]) * T[kT_iABr * S + e], 0.0) : x0.c[3][e]);
+        // D^ph at (i, j), B^th at (i+1/2, j)
+        put(2, axis ? 0.0
+                    : next(2,
+                           ((aux[4][a][b] - aux[4][a - 1][b]) * F.dth + (aux[3][a][b - 1] - aux[3][a][b]) * drd) *
+                               T[kT_iADp * S + e],
+                           cur(2, kT_iADp)));
+        if (i < F.nr) {
+            put(4, axis ? 0.0 : next(4, -(aux[2][a][b] - aux[2][a + 1][b]) * T[kT_iABt * S + e], 0.0));
+            // B^ph at (i+1/2, j+1/2)
+            put(5, j < F.nth ? next(5,
+                                    -((aux[1][a + 1][b] - aux[1][a][b]) * F.dth +
+                                      (aux[0][a][b] - aux[0][a][b + 1]) * dr) *
+                                        T[kT_iABp * S + e],
+                                    0.0)
+                             : x0.c[5][e]);
+        }
     }
 }
 
@@ -267,33 +297,39 @@ hipError_t launch_field_tables(const FieldArgs& F, const double* gx, const doubl
         Q.x[k] = gx[k];
         Q.w[k] = gw[k];
     }
-    hipLaunchKernelGGL(field_tables_kernel, dim3(nb((int64_t)(F.nth + 1) * F.nrow)), dim3(256), 0, stream, F, Q);
+    const int64_t n = std::max<int64_t>((int64_t)(F.nth + 1) * F.nrow,
+                                        std::max(field_nrad(F.nr), field_nang(F.nth)));
+    hipLaunchKernelGGL(field_tables_kernel, dim3(nb(n)), dim3(256), 0, stream, F, Q);
     return hipGetLastError();
 }
 
-hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs x0, FieldPtrs C0, FieldPtrs aux, int ncorr,
+// The step.  X's guard rows and axis values are set first; the predictor
+// reads X (iterate and start state) and writes W1 and the start
+// circulations C0; corrector passes alternate between W1 and W2 (a pass's
+// workgroups read their neighbours' halo of the previous iterate) and the
+// last writes X, which it reads only point by point as the start state, with
+// the damping layer applied.  With no corrector the predictor writes X from
+// a copy of it in W2.
+hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs C0, FieldPtrs W1, FieldPtrs W2, int ncorr,
                              int damp_cells, double damp_max, hipStream_t stream) {
     const int64_t n_all = (int64_t)(F.nr + 1 + 2 * F.guard) * F.pitch;
-    const int64_t n_aux = (int64_t)(F.nth + 1) * (F.nr + 2), n_upd = (int64_t)(F.nth + 1) * (F.nr + 1);
     const int64_t n_axis = (int64_t)(F.nr + 1 + 2 * F.guard) * 2, n_grow = (int64_t)(2 * F.guard + 1) * F.pitch;
-    auto guards = [&](FieldPtrs P) {
-        hipLaunchKernelGGL(field_axis_kernel, dim3(nb(n_axis)), dim3(256), 0, stream, F, P);
-        hipLaunchKernelGGL(field_guard_rows_kernel, dim3(nb(n_grow)), dim3(256), 0, stream, F, P);
-    };
-    guards(X);
-    hipLaunchKernelGGL(field_copy_kernel, dim3(nb(n_all)), dim3(256), 0, stream, x0, X, n_all);
-    hipLaunchKernelGGL(field_aux_kernel, dim3(nb(n_aux)), dim3(256), 0, stream, F, x0, aux);
-    hipLaunchKernelGGL(field_update_kernel, dim3(nb(n_upd)), dim3(256), 0, stream, F, aux, x0, C0, X, 1);
-    guards(X);
-    for (int it = 0; it < ncorr; ++it) {
-        hipLaunchKernelGGL(field_aux_kernel, dim3(nb(n_aux)), dim3(256), 0, stream, F, X, aux);
-        hipLaunchKernelGGL(field_update_kernel, dim3(nb(n_upd)), dim3(256), 0, stream, F, aux, x0, C0, X, 0);
-        guards(X);
+    const unsigned tiles = (unsigned)(((F.nr + kTileR) / kTileR) * ((F.nth + kTileC) / kTileC));
+    hipLaunchKernelGGL(field_axis_kernel, dim3(nb(n_axis)), dim3(256), 0, stream, F, X);
+    hipLaunchKernelGGL(field_guard_rows_kernel, dim3(nb(n_grow)), dim3(256), 0, stream, F, X);
+    if (ncorr == 0) {
+        hipLaunchKernelGGL(field_copy_kernel, dim3(nb(n_all)), dim3(256), 0, stream, W2, X, n_all);
+        hipLaunchKernelGGL(field_eval_kernel<true>, dim3(tiles), dim3(256), 0, stream, F, W2, W2, C0, X, damp_cells,
+                           damp_max);
+        return hipGetLastError();
     }
-    if (damp_cells > 0) {
-        hipLaunchKernelGGL(field_damp_kernel, dim3(nb((int64_t)(F.nth + 1) * (damp_cells + 1))), dim3(256), 0, stream,
-                           F, X, damp_cells, damp_max);
-        guards(X);
+    hipLaunchKernelGGL(field_eval_kernel<true>, dim3(tiles), dim3(256), 0, stream, F, X, X, C0, W1, 0, 0.0);
+    for (int it = 0; it < ncorr; ++it) {
+        const bool last = it == ncorr - 1;
+        const FieldPtrs cur = it % 2 == 0 ? W1 : W2;
+        const FieldPtrs nxt = last ? X : (it % 2 == 0 ? W2 : W1);
+        hipLaunchKernelGGL(field_eval_kernel<false>, dim3(tiles), dim3(256), 0, stream, F, cur, X, C0, nxt,
+                           last ? damp_cells : 0, damp_max);
     }
     return hipGetLastError();
 }
