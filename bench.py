@@ -242,13 +242,13 @@ def run_adjoint(args):
 
 
 # Field step: grid planes one evaluation must move at least, with the
-# metric coefficients formed in registers and the six inverse areas
-# tabulated: the predictor reads the state, inverse areas and currents (3)
-# and writes the state and its circulations; a corrector pass reads the
-# iterate, the start state, the start circulations, inverse areas and
-# currents and writes the iterate.
+# metric coefficients formed in registers, the six inverse areas tabulated
+# and the corrector's constant part R = X^n + dt (w0 C(X^n) - J) formed once:
+# the predictor reads the state, inverse areas and currents (3) and writes
+# the predicted state and R; a corrector pass reads the iterate, R and the
+# inverse areas and writes the iterate.
 FIELD_PLANES_PREDICTOR = 6 + 6 + 3 + 6 + 6
-FIELD_PLANES_CORRECTOR = 6 + 6 + 6 + 6 + 3 + 6
+FIELD_PLANES_CORRECTOR = 6 + 6 + 6 + 6
 
 
 def run_fields(args, g, F):

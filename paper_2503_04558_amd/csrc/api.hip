@@ -501,18 +501,18 @@ int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const v
     F.dt = dt;
     F.w1 = w1;
     F.w0 = 1.0 - w1;
-    grpic::FieldPtrs X, C0, W1, W2;
+    grpic::FieldPtrs X, R, W1, W2;
     for (int c = 0; c < 3; ++c) {
         X.c[c] = state->D[c];
         X.c[3 + c] = state->B[c];
     }
     double* w = static_cast<double*>(ws);
     for (int c = 0; c < 6; ++c) {
-        C0.c[c] = w + (size_t)c * F.plane;
+        R.c[c] = w + (size_t)c * F.plane;
         W1.c[c] = w + (size_t)(6 + c) * F.plane;
         W2.c[c] = w + (size_t)(12 + c) * F.plane;
     }
-    return hip_status(grpic::launch_field_step(F, X, C0, W1, W2, ncorr, damp_cells, damp_max,
+    return hip_status(grpic::launch_field_step(F, X, R, W1, W2, ncorr, damp_cells, damp_max,
                                                static_cast<hipStream_t>(stream)),
                       "field step");
 }

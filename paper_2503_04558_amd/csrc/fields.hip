@@ -192,21 +192,30 @@ __device__ __forceinline__ void aux_at(const FieldArgs& F, const FieldPtrs& X, i
 }
 
 // One evaluation: the auxiliary fields of X over the tile and its halo in
-// LDS, then for each point of the tile the circulations and the pass's
-// value of all six components.  FIRST: C0 <- C and the value is x0 + dt (C
-// - J); else x0 + dt (w0 C0 + w1 C) - dt J.  Elements a component does not
-// update take x0 (zero on the axes for D^ph, B^th); with L > 0 the values
-// at radial position x >= nr - L are scaled by 1 - d ((x - nr + L) / L)^2
-// (the damping layer, on the step's last pass).  The zero-gradient guard
-// rows of out are written from the rows they copy.  out must not alias X
-// (other workgroups read X in their halo); it may alias x0, which is read
-// only at the point being written.
+// LDS, then for each point of the tile the circulations C and the pass's
+// value of all six components.  The terms of a corrector that do not change
+// between passes are formed once: FIRST (the predictor, X = x0) writes
+// R = x0 + dt (w0 C - J) and the value x0 + dt (C - J); a corrector's value
+// is R + dt w1 C.  Elements a component does not update take x0 (R holds
+// it for the correctors; zero on the axes for D^ph, B^th); with L > 0 the
+// values at radial position x >= nr - L are scaled by 1 - d ((x - nr + L) /
+// L)^2 (the damping layer, on the step's last pass).  The zero-gradient
+// guard rows of out are written from the rows they copy.  out must not
+// alias X (other workgroups read X in their halo).
+//
+// Tile order: workgroup w runs on XCD w mod 8 (the dispatcher's round
+// robin), so logical tile (w mod 8) per + w / 8 gives each XCD a contiguous
+// band of tile rows in row-major order; the halo rows a tile shares with its
+// neighbours are then read through the same L2.
 template <bool FIRST>
-__global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs X, FieldPtrs x0, FieldPtrs C0,
-                                                         FieldPtrs out, int L, double d) {
+__global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs X, FieldPtrs x0, FieldPtrs R,
+                                                         FieldPtrs out, int L, double d, unsigned ntiles,
+                                                         unsigned per_xcd) {
     __shared__ double aux[6][kAuxR][kAuxC];
+    const unsigned tile = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (tile >= ntiles) return;                          // whole workgroup: before any barrier
     const int tiles_c = (F.nth + kTileC) / kTileC;      // columns 0 .. nth
-    const int i0 = (int)(blockIdx.x / tiles_c) * kTileR, j0 = (int)(blockIdx.x % tiles_c) * kTileC;
+    const int i0 = (int)(tile / tiles_c) * kTileR, j0 = (int)(tile % tiles_c) * kTileC;
     for (int e = threadIdx.x; e < kAuxR * kAuxC; e += blockDim.x) {
         const int li = e / kAuxC, lj = e - li * kAuxC;
         const int i = i0 - 1 + li, j = j0 - 1 + lj;
@@ -247,12 +256,21 @@ __global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs 
         };
         auto next = [&](int c, double C, double J) {
             if (FIRST) {
-                C0.c[c][e] = C;
-                return x0.c[c][e] + F.dt * (C - J);
+                const double x = x0.c[c][e];
+                R.c[c][e] = x + F.dt * (F.w0 * C - J);
+                return x + F.dt * (C - J);
             }
-            return x0.c[c][e] + F.dt * (F.w0 * C0.c[c][e] + F.w1 * C) - F.dt * J;
+            return R.c[c][e] + F.dt * F.w1 * C;
         };
-        auto cur = [&](int c, int t) { return F.J[c] ? F.J[c][e] * T[t * S + e] : 0.0; };
+        auto keep = [&](int c) {                         // an element the component does not update
+            if (FIRST) {
+                const double x = x0.c[c][e];
+                R.c[c][e] = x;
+                return x;
+            }
+            return R.c[c][e];
+        };
+        auto cur = [&](int c, int t) { return FIRST && F.J[c] ? F.J[c][e] * T[t * S + e] : 0.0; };
         const bool axis = j == 0 || j == F.nth;
         if (i < F.nr) {                                  // D^r at (i+1/2, j), axes included
             const double hp = j < F.nth ? aux[5][a][b] : 0.0, hm = j > 0 ? aux[5][a][b - 1] : 0.0;
@@ -260,8 +278,8 @@ __global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs 
         }
         // D^th at (i, j+1/2), B^r at (i, j+1/2)
         put(1, j < F.nth ? next(1, (aux[5][a - 1][b] - aux[5][a][b]) * T[kT_iADt * S + e], cur(1, kT_iADt))
-                         : x0.c[1][e]);
-        put(3, j < F.nth ? next(3, -(aux[2][a][b + 1] - aux[2][a][b]) * T[kT_iABr * S + e], 0.0) : x0.c[3][e]);
+                         : keep(1));
+        put(3, j < F.nth ? next(3, -(aux[2][a][b + 1] - aux[2][a][b]) * T[kT_iABr * S + e], 0.0) : keep(3));
         // D^ph at (i, j), B^th at (i+1/2, j)
         put(2, axis ? 0.0
                     : next(2,
@@ -276,7 +294,7 @@ __global__ __launch_bounds__(256) void field_eval_kernel(FieldArgs F, FieldPtrs 
                                       (aux[0][a][b] - aux[0][a][b + 1]) * dr) *
                                         T[kT_iABp * S + e],
                                     0.0)
-                             : x0.c[5][e]);
+                             : keep(5));
         }
     }
 }
@@ -304,32 +322,33 @@ hipError_t launch_field_tables(const FieldArgs& F, const double* gx, const doubl
 }
 
 // The step.  X's guard rows and axis values are set first; the predictor
-// reads X (iterate and start state) and writes W1 and the start
-// circulations C0; corrector passes alternate between W1 and W2 (a pass's
+// reads X (iterate and start state) and writes W1 and the corrector's
+// constant part R; corrector passes alternate between W1 and W2 (a pass's
 // workgroups read their neighbours' halo of the previous iterate) and the
-// last writes X, which it reads only point by point as the start state, with
-// the damping layer applied.  With no corrector the predictor writes X from
-// a copy of it in W2.
-hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs C0, FieldPtrs W1, FieldPtrs W2, int ncorr,
+// last writes X with the damping layer applied.  With no corrector the
+// predictor writes X from a copy of it in W2.
+hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs R, FieldPtrs W1, FieldPtrs W2, int ncorr,
                              int damp_cells, double damp_max, hipStream_t stream) {
     const int64_t n_all = (int64_t)(F.nr + 1 + 2 * F.guard) * F.pitch;
     const int64_t n_axis = (int64_t)(F.nr + 1 + 2 * F.guard) * 2, n_grow = (int64_t)(2 * F.guard + 1) * F.pitch;
     const unsigned tiles = (unsigned)(((F.nr + kTileR) / kTileR) * ((F.nth + kTileC) / kTileC));
-    hipLaunchKernelGGL(field_axis_kernel, dim3(nb(n_axis)), dim3(256), 0, stream, F, X);
-    hipLaunchKernelGGL(field_guard_rows_kernel, dim3(nb(n_grow)), dim3(256), 0, stream, F, X);
+    const unsigned per = (tiles + 7) / 8;
+    const dim3 grid(8 * per), block(256);
+    hipLaunchKernelGGL(field_axis_kernel, dim3(nb(n_axis)), block, 0, stream, F, X);
+    hipLaunchKernelGGL(field_guard_rows_kernel, dim3(nb(n_grow)), block, 0, stream, F, X);
     if (ncorr == 0) {
-        hipLaunchKernelGGL(field_copy_kernel, dim3(nb(n_all)), dim3(256), 0, stream, W2, X, n_all);
-        hipLaunchKernelGGL(field_eval_kernel<true>, dim3(tiles), dim3(256), 0, stream, F, W2, W2, C0, X, damp_cells,
-                           damp_max);
+        hipLaunchKernelGGL(field_copy_kernel, dim3(nb(n_all)), block, 0, stream, W2, X, n_all);
+        hipLaunchKernelGGL(field_eval_kernel<true>, grid, block, 0, stream, F, W2, W2, R, X, damp_cells, damp_max,
+                           tiles, per);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(field_eval_kernel<true>, dim3(tiles), dim3(256), 0, stream, F, X, X, C0, W1, 0, 0.0);
+    hipLaunchKernelGGL(field_eval_kernel<true>, grid, block, 0, stream, F, X, X, R, W1, 0, 0.0, tiles, per);
     for (int it = 0; it < ncorr; ++it) {
         const bool last = it == ncorr - 1;
         const FieldPtrs cur = it % 2 == 0 ? W1 : W2;
         const FieldPtrs nxt = last ? X : (it % 2 == 0 ? W2 : W1);
-        hipLaunchKernelGGL(field_eval_kernel<false>, dim3(tiles), dim3(256), 0, stream, F, cur, X, C0, nxt,
-                           last ? damp_cells : 0, damp_max);
+        hipLaunchKernelGGL(field_eval_kernel<false>, grid, block, 0, stream, F, cur, X, R, nxt,
+                           last ? damp_cells : 0, damp_max, tiles, per);
     }
     return hipGetLastError();
 }

@@ -43,14 +43,14 @@ inline size_t field_tables_bytes(int nr, int nth, int pitch, int guard) {
     return sizeof(double) * (kTablePlanes * field_plane(nr, pitch, guard) + (size_t)kDrRows * (nr + 4) +
                              field_nrad(nr) + 2 * (size_t)field_nang(nth));
 }
-// Workspace: the start circulations and two buffers of corrector
-// iterates: 18 grid arrays.
+// Workspace: the corrector's constant part X^n + dt (w0 C(X^n) - J) and two
+// buffers of corrector iterates: 18 grid arrays.
 inline size_t field_workspace_bytes(int nr, int pitch, int guard) {
     return sizeof(double) * 18 * field_plane(nr, pitch, guard);
 }
 
 hipError_t launch_field_tables(const FieldArgs& F, const double* gx, const double* gw, hipStream_t stream);
-hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs C0, FieldPtrs W1, FieldPtrs W2, int ncorr,
+hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs R, FieldPtrs W1, FieldPtrs W2, int ncorr,
                              int damp_cells, double damp_max, hipStream_t stream);
 
 }  // namespace grpic
