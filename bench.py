@@ -46,20 +46,23 @@ FP64_OPS_PER_PARTICLE_STEP = 1344
 
 KERNEL_SOURCES = ("push_deposit.hip", "grpic_device.hpp", "grpic_launch.hpp")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "push_deposit_tiled_2048x2048_2e8.md")
+FIELD_SOURCES = ("fields.hip", "grpic_fields.hpp", "grpic_device.hpp")
+FIELD_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "field_step_2048x2048.md")
 
 
-def measured_traffic() -> dict:
-    """HBM bytes per launch of the tiled push kernels from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if the kernel sources are still
-    the ones it was measured on (else empty: the figure is stale)."""
+def measured_traffic(profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES) -> dict:
+    """HBM bytes per launch (or per step) from the `traffic_bytes_per_launch`
+    line of a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if the
+    kernel sources are still the ones it was measured on (else empty: the
+    figure is stale)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2503_04558_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(profile) as fh:
             line = next(ln for ln in fh if ln.startswith("traffic_bytes_per_launch"))
     except (OSError, StopIteration):
         return {}
@@ -284,7 +287,9 @@ def run_fields(args, g, F):
     return {"grid": [g.nr, g.nth], "ncorr": args.field_ncorr, "w1": args.field_w1, "steps": args.field_steps,
             "ms_per_step": ms, "cell_updates_per_s": g.nr * g.nth / (ms * 1e-3), "finite": finite,
             "roofline_hbm": dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, bytes_per_step=nbytes)}
+                                 frac=round(gbs / HBM_PEAK_GBS, 4),
+                                 traffic=measured_traffic(FIELD_TRAFFIC_PROFILE, FIELD_SOURCES).get("step"),
+                                 bytes_per_step=nbytes)}
 
 
 def run_cpu_baseline(args, grid):
