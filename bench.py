@@ -50,12 +50,15 @@ FIELD_SOURCES = ("fields.hip", "grpic_fields.hpp", "grpic_device.hpp")
 FIELD_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "field_step_2048x2048.md")
 
 
-def measured_traffic(profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES) -> dict:
+def measured_traffic(profile=None, sources=None) -> dict:
     """HBM bytes per launch (or per step) from the `traffic_bytes_per_launch`
     line of a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if the
     kernel sources are still the ones it was measured on (else empty: the
-    figure is stale)."""
+    figure is stale).  Defaults: the tiled push kernels."""
     import hashlib
+
+    profile = profile or TRAFFIC_PROFILE
+    sources = sources or KERNEL_SOURCES
 
     h = hashlib.sha256()
     for f in sources:

@@ -31,3 +31,19 @@ def test_traffic_figure_tracks_kernel_sources(tmp_path, monkeypatch):
     stale.write_text("traffic_bytes_per_launch f64=1e10 split=5e9 sources=0000\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(stale))
     assert bench.measured_traffic() == {}
+
+
+def test_field_traffic_figure_tracks_field_sources(tmp_path):
+    """The field leg's measured traffic is keyed to the field kernel sources
+    and is within a few percent above the algorithmic bytes of a step."""
+    import bench
+
+    t = bench.measured_traffic(bench.FIELD_TRAFFIC_PROFILE, bench.FIELD_SOURCES)
+    if t:
+        plane = 2049 * 2049 * 8
+        alg = plane * (bench.FIELD_PLANES_PREDICTOR + 7 * bench.FIELD_PLANES_CORRECTOR)
+        assert 1.0 <= t["step"] / alg < 1.2
+        assert abs(t["predictor"] + 7 * t["corrector"] - t["step"]) < 1e-3 * t["step"]
+    stale = tmp_path / "f.md"
+    stale.write_text("traffic_bytes_per_launch step=1e9 sources=0000\n")
+    assert bench.measured_traffic(str(stale), bench.FIELD_SOURCES) == {}
