@@ -295,6 +295,94 @@ def run_fields(args, g, F):
                                  bytes_per_step=nbytes)}
 
 
+def run_pic(args):
+    """The full-step batch in the FP32-split form: on a pic_grid^2 grid
+    (a = 0.99), 2 * pic_pairs e+- with dN/dgamma ~ gamma^-2 on [1, 1e3]
+    (seed 0) and the Wald field B0 = 1 as the initial state, each step is a
+    tiled split push + deposit against a float copy of the fields, then the
+    field step (predictor + 7 correctors, w1 = 0.53, damping over the outer
+    32 rows) with that step's currents; re-sorted every sort_every steps.
+    Prints one JSON line with the time per PIC step and its parts."""
+    import torch
+
+    from paper_2503_04558_amd import grpic
+    from paper_2503_04558_amd import workload as wl
+
+    t0 = time.time()
+    g = wl.make_grid(args.pic_grid, args.pic_grid, 0.99)
+    n = 2 * args.pic_pairs
+    parts = grpic.empty_particles(n, grpic.GRPIC_FP32_SPLIT)
+
+    def sink(start, arrs):
+        m = len(arrs["cell"])
+        for k, v in arrs.items():
+            parts[k][start:start + m].copy_(torch.from_numpy(np.ascontiguousarray(v)))
+
+    wl.pairs(g, args.pic_pairs, kind="powerlaw", seed=0, params=dict(gmax=1e3), workers=args.workers, sink=sink)
+    state = [torch.as_tensor(f).cuda() for f in wl.wald_fields(g, B0=1.0)]
+    torch.cuda.synchronize()
+    log(f"pic: inputs ready in {time.time() - t0:.1f}s: grid {g.nr}x{g.nth}, {n} split particles")
+    sp = wl.species_table()
+    metric = grpic.make_metric(g.a, g.M)
+    dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+    sorter = grpic.Sorter(g, n, grpic.GRPIC_FP32_SPLIT)
+    solver = grpic.FieldSolver(metric, g)
+    F32 = [s.float() for s in state]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
+    cur = {"p": parts}
+    marks = []
+
+    def step(k, timed):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if timed else None
+        if timed:
+            ev[0].record()
+        if k % args.sort_every == 0:
+            cur["p"] = sorter.sort(cur["p"])
+        if timed:
+            ev[1].record()
+        for j in J:
+            j.zero_()
+        for f32, s in zip(F32, state):
+            f32.copy_(s)
+        if timed:
+            ev[2].record()
+        grpic.grpic_push_deposit(metric, g, sp, cur["p"], F32, J, dt, 1, args.ncorr, tiling=sorter.tiling,
+                                 counters=counters if timed else None)
+        if timed:
+            ev[3].record()
+        solver.step(state, J, dt, 0.53, 7, damp_cells=32, damp_max=0.1)
+        if timed:
+            ev[4].record()
+            marks.append(ev)
+
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0.record()
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k, True)
+    w1.record()
+    torch.cuda.synchronize()
+    total = w0.elapsed_time(w1)
+    part = np.array([[m[i].elapsed_time(m[i + 1]) for i in range(4)] for m in marks])
+    cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
+    finite = all(bool(torch.isfinite(s).all()) for s in state)
+    live = cnt["live_steps"] / args.steps
+    out = {"metric": "full PIC step (split push + deposit + field step) particle-steps/s", "unit": "particle-steps/s",
+           "value": cnt["live_steps"] / (total * 1e-3), "ms_per_step": total / args.steps, "steps": args.steps,
+           "warmup": args.warmup, "dtype": "f32 particles and fields for the push (f64 in r < 2M, near the axis, "
+           "and for the deposit); f64 field solver",
+           "config": {"workload": f"{g.nr}x{g.nth} Kerr-Schild log-r grid, a=0.99, {n} e+- (dN/dgamma ~ gamma^-2 "
+                                  f"on [1, 1e3]), Wald B0=1 initial fields, field step N=7 w1=0.53, sort every "
+                                  f"{args.sort_every} steps, ncorr={args.ncorr}", "dt": dt},
+           "parts_ms": {"sort_avg_per_step": float(part[:, 0].mean()), "zero_J_and_float_fields": float(part[:, 1].mean()),
+                        "push_deposit": float(part[:, 2].mean()), "field_step": float(part[:, 3].mean())},
+           "live_particles_per_step": live, "counters": cnt, "fields_finite": finite}
+    print(json.dumps(out), flush=True)
+
+
 def run_cpu_baseline(args, grid):
     """The FP64 oracle (OpenMP over particles) on a bounded sample."""
     from oracle import oracle as orc
@@ -349,6 +437,10 @@ def main():
     ap.add_argument("--field-w1", type=float, default=0.53)
     ap.add_argument("--cpu-pairs", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--pic", action="store_true",
+                    help="only time the full PIC step of the split-form batch (push + deposit + field step)")
+    ap.add_argument("--pic-grid", type=int, default=4096)
+    ap.add_argument("--pic-pairs", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -369,6 +461,10 @@ def main():
         print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not supported",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.pic:
+        run_pic(args)
+        return
 
     import torch
 
