@@ -281,7 +281,13 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
  *   nearest physical row (zero gradient) at both radial edges.  After the
  *   step, every component at radial grid position x >= nr - damp_cells is
  *   multiplied by 1 - damp_max ((x - nr + damp_cells)/damp_cells)^2 (an
- *   outer damping layer; damp_cells = 0: none; damp_max in [0, 1]).
+ *   outer damping layer; damp_cells = 0: none; damp_max in [0, 1]).  Last,
+ *   the guard columns beyond each axis (read by the particle gather near
+ *   the axis) are set from the mirrored columns by axisymmetry: (r, -theta,
+ *   phi) is (r, theta, phi + pi), so the r and phi components are even and
+ *   D^th, B^th odd across the axis (integer columns -m <-> m, nth + m <->
+ *   nth - m; columns at j + 1/2: -m <-> m - 1, nth - 1 + m <-> nth - m).
+ *   Requires nth >= 2 * guard.
  *   ws: device workspace of at least grpic_field_workspace_bytes(grid)
  *   bytes; its contents on entry do not matter.
  *   Errors: GRPIC_EINVAL for NULL arrays, dt <= 0, parameters out of range

@@ -766,7 +766,10 @@ int orc_has_openmp(void) {
 /*   - inner and outer guard rows copy the nearest physical row (zero   */
 /*     gradient; the outer one under the damping layer);               */
 /*   - damping layer: after each step every component at radial grid    */
-/*     position x >= nr - L is multiplied by 1 - d ((x - nr + L)/L)^2.  */
+/*     position x >= nr - L is multiplied by 1 - d ((x - nr + L)/L)^2;  */
+/*   - columns beyond the axes (read by the particle gather) are set     */
+/*     after each step from the mirrored columns by axisymmetry, the    */
+/*     theta components negated.                                        */
 /* ================================================================== */
 namespace {
 
@@ -884,6 +887,31 @@ void fill_guards(const Geom& g, std::vector<double>* c) {
     for (int i = -g.guard; i <= g.nr + g.guard; ++i) {
         c[2][idx(g, i, 0)] = c[2][idx(g, i, g.nth)] = 0.0;
         c[4][idx(g, i, 0)] = c[4][idx(g, i, g.nth)] = 0.0;
+    }
+}
+
+/* Columns beyond the axes, which the particles' CIC gather reads within
+ * half a cell of an axis.  The extended chart's point (r, -theta, phi) is
+ * (r, theta, phi + pi): the theta basis vector is reversed there and the r
+ * and phi ones are not, so by axisymmetry a component beyond the axis is
+ * its value at the mirrored location, negated for D^th and B^th.  Mirror
+ * pairs: integer columns -m <-> m and nth + m <-> nth - m; columns at
+ * j + 1/2 (D^th, B^r, B^ph) -m <-> m - 1 and nth - 1 + m <-> nth - m.   */
+void fill_axis_ghosts(const Geom& g, std::vector<double>* c) {
+    for (int comp = 0; comp < 6; ++comp) {
+        const double p = (comp == 1 || comp == 4) ? -1.0 : 1.0;
+        const bool half_th = comp == 1 || comp == 3 || comp == 5;
+        for (int i = -g.guard; i <= g.nr + g.guard; ++i)
+            for (int m = 1; m <= g.guard; ++m) {
+                auto& v = c[comp];
+                if (half_th) {
+                    v[idx(g, i, -m)] = p * v[idx(g, i, m - 1)];
+                    v[idx(g, i, g.nth - 1 + m)] = p * v[idx(g, i, g.nth - m)];
+                } else {
+                    v[idx(g, i, -m)] = p * v[idx(g, i, m)];
+                    v[idx(g, i, g.nth + m)] = p * v[idx(g, i, g.nth - m)];
+                }
+            }
     }
 }
 
@@ -1012,7 +1040,8 @@ void orc_field_circulations(const Geom* gp, double* const* X, double* const* C) 
 /* One field step in place: X[6] = D^r, D^th, D^ph, B^r, B^th, B^ph (grid
  * arrays); F[3] = flux-form currents of the step (NULL = none); predictor
  * and ncorr corrector passes with weights w0 = 1 - w1, w1; then the
- * damping layer over the last damp_cells rows (0 = none).              */
+ * damping layer over the last damp_cells rows (0 = none) and the columns
+ * beyond the axes.                                                     */
 void orc_field_step(const Geom* gp, double* const* X, const double* const* F, double dt, double w1,
                     int ncorr, int damp_cells, double damp_max) {
     const Geom& g = *gp;
@@ -1051,6 +1080,7 @@ void orc_field_step(const Geom* gp, double* const* X, const double* const* F, do
             }
         fill_guards(g, xt);
     }
+    fill_axis_ghosts(g, xt);
     for (int k = 0; k < 6; ++k) std::copy(xt[k].begin(), xt[k].end(), X[k]);
 }
 

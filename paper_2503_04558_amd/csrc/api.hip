@@ -469,6 +469,9 @@ int grpic_field_step(const grpic_metric* metric, const grpic_grid* grid, const v
     int rc;
     if ((rc = check_metric(metric)) || (rc = check_grid(grid))) return rc;
     if (!state) return fail(GRPIC_EINVAL, "state is NULL");
+    if (grid->nth < 2 * grid->guard)
+        return fail(GRPIC_EINVAL, "field step: nth (%d) must be at least 2*guard (the columns beyond the axes mirror "
+                                  "physical ones)", grid->nth);
     for (int c = 0; c < 3; ++c)
         if (!state->D[c] || !state->B[c]) return fail(GRPIC_EINVAL, "state: NULL component");
     if (J && (!J->Fr || !J->Fth || !J->Gph)) return fail(GRPIC_EINVAL, "current: NULL array");

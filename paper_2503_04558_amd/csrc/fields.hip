@@ -11,8 +11,8 @@
 // circulations (eqs. D-update, B-update; the axis rows of D^r by eq.
 // Dr-axis) and writes the predictor or corrector value of its points.
 // Guard rows are refilled (zero gradient) and the axis values of D^ph, B^th
-// set to zero after every pass; a damping layer scales the outer rows after
-// the step.
+// set to zero by every pass; a damping layer scales the outer rows on the
+// last pass, and the columns beyond the axes are refreshed after the step.
 //
 // Locations, array element (i, j) of each component (r_x = exp(lnr0 + x
 // dlnr), theta_y = y dth): D^r, B^th, E_r, H_th at (i+1/2, j); D^th, B^r,
@@ -161,6 +161,30 @@ __global__ __launch_bounds__(256) void field_guard_rows_kernel(FieldArgs F, Fiel
         if (i >= 0 && i <= last) continue;              // row nr of D^th, D^ph, B^r is physical
         const int src = i < 0 ? 0 : last;
         X.c[c][F.at(i, jj)] = X.c[c][F.at(src, jj)];
+    }
+}
+
+// Columns beyond the axes, which the particles' CIC gather reads within
+// half a cell of an axis.  By axisymmetry (the extended chart's point
+// (r, -theta, phi) is (r, theta, phi + pi), where only the theta basis
+// vector is reversed) a component there is its value at the mirrored
+// location, negated for D^th and B^th.  Mirror pairs: integer columns
+// -m <-> m and nth + m <-> nth - m; columns at j + 1/2 (D^th, B^r, B^ph)
+// -m <-> m - 1 and nth - 1 + m <-> nth - m; every row, m = 1 .. guard.
+// Written columns and read columns are disjoint (nth > guard).
+__global__ __launch_bounds__(256) void field_axis_ghosts_kernel(FieldArgs F, FieldPtrs X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int rows = F.nr + 1 + 2 * F.guard;
+    if (t >= (int64_t)rows * F.guard * 2) return;
+    const bool far = (t & 1) != 0;
+    const int m = (int)((t >> 1) % F.guard) + 1;
+    const int i = (int)((t >> 1) / F.guard) - F.guard;
+    for (int c = 0; c < 6; ++c) {
+        const double p = (c == 1 || c == 4) ? -1.0 : 1.0;
+        const bool half = c == 1 || c == 3 || c == 5;
+        const int dst = far ? (half ? F.nth - 1 + m : F.nth + m) : -m;
+        const int src = far ? F.nth - m : (half ? m - 1 : m);
+        X.c[c][F.at(i, dst)] = p * X.c[c][F.at(i, src)];
     }
 }
 
@@ -325,12 +349,14 @@ hipError_t launch_field_tables(const FieldArgs& F, const double* gx, const doubl
 // reads X (iterate and start state) and writes W1 and the corrector's
 // constant part R; corrector passes alternate between W1 and W2 (a pass's
 // workgroups read their neighbours' halo of the previous iterate) and the
-// last writes X with the damping layer applied.  With no corrector the
-// predictor writes X from a copy of it in W2.
+// last writes X with the damping layer applied; then X's columns beyond the
+// axes are refreshed.  With no corrector the predictor writes X from a copy
+// of it in W2.
 hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs R, FieldPtrs W1, FieldPtrs W2, int ncorr,
                              int damp_cells, double damp_max, hipStream_t stream) {
     const int64_t n_all = (int64_t)(F.nr + 1 + 2 * F.guard) * F.pitch;
     const int64_t n_axis = (int64_t)(F.nr + 1 + 2 * F.guard) * 2, n_grow = (int64_t)(2 * F.guard + 1) * F.pitch;
+    const int64_t n_ghost = (int64_t)(F.nr + 1 + 2 * F.guard) * F.guard * 2;
     const unsigned tiles = (unsigned)(((F.nr + kTileR) / kTileR) * ((F.nth + kTileC) / kTileC));
     const unsigned per = (tiles + 7) / 8;
     const dim3 grid(8 * per), block(256);
@@ -340,6 +366,7 @@ hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs R, Field
         hipLaunchKernelGGL(field_copy_kernel, dim3(nb(n_all)), block, 0, stream, W2, X, n_all);
         hipLaunchKernelGGL(field_eval_kernel<true>, grid, block, 0, stream, F, W2, W2, R, X, damp_cells, damp_max,
                            tiles, per);
+        hipLaunchKernelGGL(field_axis_ghosts_kernel, dim3(nb(n_ghost)), block, 0, stream, F, X);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(field_eval_kernel<true>, grid, block, 0, stream, F, X, X, R, W1, 0, 0.0, tiles, per);
@@ -350,6 +377,7 @@ hipError_t launch_field_step(const FieldArgs& F, FieldPtrs X, FieldPtrs R, Field
         hipLaunchKernelGGL(field_eval_kernel<false>, grid, block, 0, stream, F, cur, X, R, nxt,
                            last ? damp_cells : 0, damp_max, tiles, per);
     }
+    hipLaunchKernelGGL(field_axis_ghosts_kernel, dim3(nb(n_ghost)), block, 0, stream, F, X);
     return hipGetLastError();
 }
 
