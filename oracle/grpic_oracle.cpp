@@ -289,13 +289,60 @@ void boris_kick(const KS<T>& k, double qm, double dt, const T D[3], const T B[3]
     for (int c = 0; c < 3; ++c) u[c] = up[c] + h * Dl[c];
 }
 
+/* Vay's momentum update (Vay 2008) carried out in the FIDO frame, the
+ * alternative the paper mentions in Sec. 2.2.  The FIDO measures D, B and
+ * the spatial momentum u_i, and its clock advances alpha dt, so Vay's
+ * flat-space step applies with dt -> alpha dt; written with the spatial
+ * metric (dot products as gamma contractions, cross products with
+ * e_ijk = sqrt(gamma) eps_ijk) it needs no explicit triad.  Vay's steps,
+ * with h = (q/m) alpha dt / 2 and gamma = sqrt(1 + u^2):
+ *   1. u_half = u + h (D + (u / gamma) x B)       explicit first half
+ *   2. u'     = u_half + h D
+ *   3. tau    = h B,  sigma = 1 + u'^2 - tau^2,  w = u'.tau,
+ *      gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + w^2))) / 2
+ *      (the Lorentz factor that solves u_new = u' + (u_new/gamma_new) x tau)
+ *   4. t = tau / gamma_new,  s = 1 / (1 + t^2),
+ *      u_new = s (u' + (u'.t) t + u' x t).                              */
+template <class T>
+void vay_kick(const KS<T>& k, double qm, double dt, const T D[3], const T B[3], T u[3]) {
+    const T Dl[3] = {k.g_rr * D[0] + k.g_rp * D[2], k.g_tt * D[1], k.g_rp * D[0] + k.g_pp * D[2]};
+    const T h = qm * k.alpha * dt * 0.5;
+    const T uu = k.h_rr * u[0] * u[0] + 2.0 * k.h_rp * u[0] * u[2]
+               + k.h_tt * u[1] * u[1] + k.h_pp * u[2] * u[2];
+    const T gam = sqrt(1.0 + uu);
+    T v[3], vxB[3], up[3];
+    for (int c = 0; c < 3; ++c) v[c] = u[c] / gam;
+    cross_lower(k, v, B, vxB);
+    for (int c = 0; c < 3; ++c) up[c] = (u[c] + h * (Dl[c] + vxB[c])) + h * Dl[c];
+    T tau[3];
+    for (int c = 0; c < 3; ++c) tau[c] = h * B[c];
+    const T tau2 = k.g_rr * tau[0] * tau[0] + 2.0 * k.g_rp * tau[0] * tau[2]
+                 + k.g_tt * tau[1] * tau[1] + k.g_pp * tau[2] * tau[2];
+    const T w = up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2];
+    const T upup = k.h_rr * up[0] * up[0] + 2.0 * k.h_rp * up[0] * up[2]
+                 + k.h_tt * up[1] * up[1] + k.h_pp * up[2] * up[2];
+    const T sigma = 1.0 + upup - tau2;
+    const T gnew = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + w * w))));
+    T t[3];
+    for (int c = 0; c < 3; ++c) t[c] = tau[c] / gnew;
+    const T s = 1.0 / (1.0 + tau2 / (gnew * gnew));
+    const T ut = w / gnew;                                   /* u'_k t^k */
+    const T tl[3] = {k.g_rr * t[0] + k.g_rp * t[2], k.g_tt * t[1], k.g_rp * t[0] + k.g_pp * t[2]};
+    T x[3];
+    cross_lower(k, up, t, x);
+    for (int c = 0; c < 3; ++c) u[c] = s * (up[c] + ut * tl[c] + x[c]);
+}
+
+enum { KICK_BORIS = 0, KICK_VAY = 1 };
+
 /* ------------------------------------------------------------------ */
 /* 3+4. Kick at x^n, then the geodesic predictor-corrector.            */
 /* Returns the raw end point y1 = (xi, eta, phi, u_r, u_th, u_ph).     */
 /* ------------------------------------------------------------------ */
 template <class T>
 void push_with_fields(const Geom& g, const Species& sp, double dt, int ncorr,
-                      const T& xi, const T& eta, const T u[3], const T D[3], const T B[3], T y1[6]) {
+                      const T& xi, const T& eta, const T u[3], const T D[3], const T B[3], T y1[6],
+                      int kick = KICK_BORIS) {
     T uk[3] = {u[0], u[1], u[2]};
     const double eps = sp.massless ? 0.0 : 1.0;
     if (!sp.massless) {                 /* photons skip the Boris step */
@@ -303,7 +350,8 @@ void push_with_fields(const Geom& g, const Species& sp, double dt, int ncorr,
         const T th = eta * g.dth;
         KS<T> k;
         ks_metric(g.a, g.M, r, th, k);
-        boris_kick(k, sp.q / sp.m, dt, D, B, uk);
+        if (kick == KICK_VAY) vay_kick(k, sp.q / sp.m, dt, D, B, uk);
+        else boris_kick(k, sp.q / sp.m, dt, D, B, uk);
     }
     const T y0[6] = {xi, eta, T(0.0), uk[0], uk[1], uk[2]};
     T f0[6], f1[6], yt[6];
@@ -414,7 +462,7 @@ struct Outcome {
 };
 
 Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], double w, double dt, int ncorr,
-                 int32_t cell, double xr, double xth, const double u[3]) {
+                 int32_t cell, double xr, double xth, const double u[3], int kick = KICK_BORIS) {
     Outcome o;
     o.reflected = 0;
     o.status = ST_DEAD;
@@ -434,7 +482,7 @@ Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], dou
         B[c] = cic_gather(g, F[3 + c], kStagR[3 + c], kStagT[3 + c], xi0, eta0);
     }
     double y1[6];
-    push_with_fields(g, sp, dt, ncorr, xi0, eta0, u, D, B, y1);
+    push_with_fields(g, sp, dt, ncorr, xi0, eta0, u, D, B, y1, kick);
 
     double xi1 = y1[0], eta1 = y1[1];
     double u1[3] = {y1[3], y1[4], y1[5]};
@@ -555,10 +603,20 @@ void orc_boris(const Geom* g, double qm, double dt, double xi, double eta,
     for (int c = 0; c < 3; ++c) out[c] = uk[c];
 }
 
+void orc_vay(const Geom* g, double qm, double dt, double xi, double eta,
+             const double* u, const double* D, const double* B, double* out) {
+    const double r = std::exp(g->lnr0 + xi * g->dlnr), th = eta * g->dth;
+    KS<double> k;
+    ks_metric(g->a, g->M, r, th, k);
+    double uk[3] = {u[0], u[1], u[2]};
+    vay_kick(k, qm, dt, D, B, uk);
+    for (int c = 0; c < 3; ++c) out[c] = uk[c];
+}
+
 /* Kick with the given fields at x^n, then the geodesic PC; no boundaries. */
 void orc_push_point(const Geom* g, const Species* sp, double dt, int ncorr, double xi, double eta,
-                    const double* u, const double* D, const double* B, double* y1) {
-    push_with_fields(*g, *sp, dt, ncorr, xi, eta, u, D, B, y1);
+                    const double* u, const double* D, const double* B, double* y1, int kick) {
+    push_with_fields(*g, *sp, dt, ncorr, xi, eta, u, D, B, y1, kick);
 }
 
 void orc_gather(const Geom* g, const double* const* F, double xi, double eta, double* out) {
@@ -596,13 +654,14 @@ void orc_charge(const Geom* g, const Species* sp, int nsp, int64_t n, const int3
  * scales (|q w|/dt for F^r and F^th, |q w dphi|/dt for G^ph).  nthreads > 1: OpenMP over particles
  * with thread-private J reduced in thread order (timing mode).
  * stats[4] (+=): particles removed at the radial edges, removed as
- * non-finite or moving >= 1 cell, axis reflections, live particle-steps.  */
+ * non-finite or moving >= 1 cell, axis reflections, live particle-steps.
+ * kick: KICK_BORIS (the generalised Boris kick) or KICK_VAY.           */
 void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
              int32_t* cell, double* xr, double* xth, double* ur, double* uth, double* uph,
              const double* w, const uint8_t* spi, double* phi,
              const double* const* F, double* Fr, double* Fth, double* Gph,
              double* Afr, double* Afth, double* Agph,
-             double dt, int nsteps, int ncorr, int nthreads, int64_t* stats) {
+             double dt, int nsteps, int ncorr, int nthreads, int64_t* stats, int kick) {
     const Geom& g = *gp;
     const long ncell = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
     int64_t st_out = 0, st_bad = 0, st_refl = 0, st_live = 0;
@@ -614,7 +673,7 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
             for (int64_t p = 0; p < n; ++p) {
                 const double u[3] = {ur[p], uth[p], uph[p]};
                 if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
-                Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
+                Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick);
                 if (o.status == ST_DEAD) continue;
                 ++st_live;
                 if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
@@ -640,7 +699,7 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
                 for (int64_t p = 0; p < n; ++p) {
                     const double u[3] = {ur[p], uth[p], uph[p]};
                     if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
-                    Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u);
+                    Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick);
                     if (o.status == ST_DEAD) continue;
                     ++st_live;
                     if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }

@@ -100,7 +100,21 @@ def boris(grid, qm, dt, xi, eta, u, D, B) -> np.ndarray:
     return out
 
 
-def push_point(grid, q, m, dt, xi, eta, u, D, B, ncorr: int = 3, massless: bool = False) -> np.ndarray:
+def vay(grid, qm, dt, xi, eta, u, D, B) -> np.ndarray:
+    """Vay's momentum update in the FIDO frame (the alternative kick)."""
+    g = geom(grid)
+    u, D, B = _f64(u), _f64(D), _f64(B)
+    out = np.zeros(3)
+    lib().orc_vay(ctypes.byref(g), ctypes.c_double(qm), ctypes.c_double(dt), ctypes.c_double(xi),
+                  ctypes.c_double(eta), _p(u), _p(D), _p(B), _p(out))
+    return out
+
+
+KICKS = {"boris": 0, "vay": 1}
+
+
+def push_point(grid, q, m, dt, xi, eta, u, D, B, ncorr: int = 3, massless: bool = False,
+               kick: str = "boris") -> np.ndarray:
     """Kick with point fields D, B at x^n, then the geodesic PC (no boundaries).
 
     Returns y1 = (xi, eta, dphi, u_r, u_th, u_ph)."""
@@ -109,7 +123,8 @@ def push_point(grid, q, m, dt, xi, eta, u, D, B, ncorr: int = 3, massless: bool 
     u, D, B = _f64(u), _f64(D), _f64(B)
     y1 = np.zeros(6)
     lib().orc_push_point(ctypes.byref(g), ctypes.byref(sp), ctypes.c_double(dt), ctypes.c_int(ncorr),
-                         ctypes.c_double(xi), ctypes.c_double(eta), _p(u), _p(D), _p(B), _p(y1))
+                         ctypes.c_double(xi), ctypes.c_double(eta), _p(u), _p(D), _p(B), _p(y1),
+                         ctypes.c_int(KICKS[kick]))
     return y1
 
 
@@ -157,13 +172,15 @@ PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
 
 
 def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int = 1,
-        with_abs: bool = False, track_phi: bool = False, J=None):
+        with_abs: bool = False, track_phi: bool = False, J=None, kick: str = "boris"):
     """Advance copies of the particle arrays nsteps steps.
 
     Returns (parts_out, J, A, stats): J = [Fr, Fth, Gph] (added to the given
     J if any); A (with_abs, serial only) = per element, the sum over the
     contributions of their magnitude scale, |q w|/dt for F^r and F^th and
     |q w dphi|/dt for G^ph; stats = dict(out, bad, reflected, live_steps).
+    kick: "boris" (the generalised Boris kick) or "vay" (Vay's update in the
+    FIDO frame).
     """
     g = geom(grid)
     sp = _species_array(species)
@@ -194,7 +211,7 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
                   fptr, _p(J[0]), _p(J[1]), _p(J[2]),
                   _p(A[0]) if A else null, _p(A[1]) if A else null, _p(A[2]) if A else null,
                   ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(ncorr),
-                  ctypes.c_int(nthreads), _p(stats))
+                  ctypes.c_int(nthreads), _p(stats), ctypes.c_int(KICKS[kick]))
     st = dict(out=int(stats[0]), bad=int(stats[1]), reflected=int(stats[2]), live_steps=int(stats[3]))
     return p, J, A, st
 
