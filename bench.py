@@ -99,8 +99,9 @@ def make_workload(npairs: int, nr: int, nth: int, a: float, device: str = "cuda"
     return g, F, parts
 
 
-def run_gpu(args, g, F, parts, precision):
-    """Warm up, then time args.steps push + deposit steps of one precision."""
+def run_gpu(args, g, F, parts, precision, kick="boris"):
+    """Warm up, then time args.steps push + deposit steps of one precision
+    (and kick: the generalised Boris kick, or Vay's in the FIDO frame)."""
     import torch
 
     from paper_2503_04558_amd import grpic
@@ -136,7 +137,7 @@ def run_gpu(args, g, F, parts, precision):
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
         grpic.grpic_push_deposit(metric, g, sp, state["p"], F, J, dt, 1, args.ncorr, tiling=sorter.tiling,
-                                 counters=counters if timed else None)
+                                 counters=counters if timed else None, kick=kick)
         if timed:
             e1.record()
             ev_push.append((e0, e1))
@@ -432,6 +433,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the backward / forward timing")
     ap.add_argument("--adj-pairs", type=int, default=500_000)
     ap.add_argument("--no-fields", action="store_true", help="skip the field-solver timing")
+    ap.add_argument("--no-vay", action="store_true", help="skip the timing of the push with Vay's kick")
     ap.add_argument("--field-steps", type=int, default=10)
     ap.add_argument("--field-ncorr", type=int, default=7)
     ap.add_argument("--field-w1", type=float, default=0.53)
@@ -475,6 +477,7 @@ def main():
     split_parts = None
     if not args.no_split:      # the same initial particles in split form
         split_parts = {k: (v.clone() if k in ("cell", "sp") else v.to(torch.float32)) for k, v in parts.items()}
+    vay_parts = None if args.no_vay else {k: v.clone() for k, v in parts.items()}
     torch.cuda.synchronize()
     log(f"inputs ready in {time.time() - t0:.1f}s: grid {g.nr}x{g.nth}, {2 * args.pairs} particles")
     r = run_gpu(args, g, F, parts, grpic.GRPIC_FP64)
@@ -484,6 +487,10 @@ def main():
         F32 = [f.to(torch.float32) for f in F]
         rs = run_gpu(args, g, F32, split_parts, grpic.GRPIC_FP32_SPLIT)
     del split_parts
+    rv = None
+    if vay_parts is not None:
+        rv = run_gpu(args, g, F, vay_parts, grpic.GRPIC_FP64, kick="vay")
+    del vay_parts
     fld = None if args.no_fields else run_fields(args, g, F)
     adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
@@ -536,6 +543,14 @@ def main():
                                  frac=round(rs["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic.get("split"),
                                  bytes_per_launch=rs["bytes_per_launch"]),
             "counters": rs["counters"],
+        }
+    if rv is not None:
+        out["vay"] = {
+            "value": rv["value"], "unit": "particle-steps/s", "dtype": "f64",
+            "ms_per_step": rv["total_ms"] / args.steps, "vs_boris": rv["value"] / r["value"],
+            "kernel": {"name": "push_deposit_f64_tiled<kVay>", "avg_ms": rv["avg_push_ms"],
+                       "min_ms": float(np.min(rv["push_ms"]))},
+            "counters": rv["counters"],
         }
     if adj is not None:
         out["adjoint"] = adj

@@ -176,6 +176,27 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        void* ckpt, size_t ckpt_bytes, int ckpt_every,
                        int64_t* counters, void* stream);
 
+/*
+ * grpic_push_deposit_vay -- grpic_push_deposit with Vay's momentum update
+ * (Vay 2008) in the FIDO frame in place of the generalised Boris kick: the
+ * alternative pusher of Sec. 2.2.  With h = (q/m) alpha dt / 2, v = u/gamma,
+ * dot products as gamma_ij contractions and cross products with
+ * e_ijk = sqrt(gamma) eps_ijk:  u' = u + h (D + v x B) + h D,  tau = h B,
+ * gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + (u'.tau)^2)))/2 with
+ * sigma = 1 + u'^2 - tau^2,  t = tau/gamma_new,
+ * u_new = (u' + (u'.t) t + u' x t)/(1 + t^2).  It keeps u exactly when
+ * D = -v x B (the force-free drift), which the Boris kick does not.
+ * Everything else (gather, geodesic predictor-corrector, boundaries,
+ * deposit, tiling, counters, arguments and errors) is as in
+ * grpic_push_deposit.  GRPIC_FP64 particles only (GRPIC_EINVAL otherwise);
+ * no checkpoints (the adjoint differentiates the Boris kick).
+ */
+int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
+                           const grpic_species* species, int nsp,
+                           grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                           void* tiling, double dt, int nsteps, int ncorr,
+                           int64_t* counters, void* stream);
+
 /* Gradient outputs of grpic_push_deposit_backward (device, double). */
 typedef struct {
     double *ur, *uth, *uph;          /* per particle, overwritten */

@@ -221,12 +221,10 @@ double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid) {
     return crossing_time_cached(metric, grid);
 }
 
-int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
-                       const grpic_species* species, int nsp,
-                       grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                       void* tiling, double dt, int nsteps, int ncorr,
-                       void* ckpt, size_t ckpt_bytes, int ckpt_every,
-                       int64_t* counters, void* stream) {
+static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, const grpic_species* species, int nsp,
+                        grpic_particles* parts, const grpic_fields* fields, grpic_current* J, void* tiling, double dt,
+                        int nsteps, int ncorr, void* ckpt, size_t ckpt_bytes, int ckpt_every, int64_t* counters,
+                        void* stream, int kick) {
     int rc;
     if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
         (rc = check_particles(parts, "parts")))
@@ -274,11 +272,32 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
             if ((rc = hip_status(grpic::launch_save_state(A, dst, s), "checkpoint launch"))) return rc;
         }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
-        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s)
-                                    : grpic::launch_push_deposit(A, split, s);
+        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick)
+                                    : grpic::launch_push_deposit(A, split, s, kick);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
     return GRPIC_OK;
+}
+
+int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
+                       const grpic_species* species, int nsp,
+                       grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                       void* tiling, double dt, int nsteps, int ncorr,
+                       void* ckpt, size_t ckpt_bytes, int ckpt_every,
+                       int64_t* counters, void* stream) {
+    return push_deposit(metric, grid, species, nsp, parts, fields, J, tiling, dt, nsteps, ncorr, ckpt, ckpt_bytes,
+                        ckpt_every, counters, stream, grpic::kBoris);
+}
+
+int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
+                           const grpic_species* species, int nsp,
+                           grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                           void* tiling, double dt, int nsteps, int ncorr,
+                           int64_t* counters, void* stream) {
+    if (parts && parts->precision != GRPIC_FP64)
+        return fail(GRPIC_EINVAL, "grpic_push_deposit_vay: GRPIC_FP64 particles only");
+    return push_deposit(metric, grid, species, nsp, parts, fields, J, tiling, dt, nsteps, ncorr, nullptr, 0, 0,
+                        counters, stream, grpic::kVay);
 }
 
 size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every) {

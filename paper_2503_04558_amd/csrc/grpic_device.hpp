@@ -361,6 +361,55 @@ __device__ __forceinline__ void boris_kick(const Metric<R>& k, R qm, R dt, const
     for (int i = 0; i < 3; ++i) u[i] = um[i] + x[i] + h * Dl[i];
 }
 
+// Momentum kick variants of the particle step.
+enum Kick { kBoris = 0, kVay = 1 };
+
+// Vay's momentum update (Vay 2008) in the FIDO frame, the alternative
+// kick of Sec. 2.2: the FIDO measures D, B and u_i and its clock advances
+// alpha dt, so with h = (q/m) alpha dt / 2, dot products as gamma
+// contractions and cross products with e_ijk:
+//   u' = u + h (D + (u / gamma) x B) + h D;  tau = h B;
+//   gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + (u'.tau)^2))) / 2,
+//   sigma = 1 + u'^2 - tau^2 (the Lorentz factor that makes
+//   u_new = u' + (u_new / gamma_new) x tau solvable);
+//   t = tau / gamma_new, u_new = (u' + (u'.t) t + u' x t) / (1 + t^2).
+template <class R>
+__device__ __forceinline__ void vay_kick(const Metric<R>& k, R qm, R dt, const R D[3], const R B[3], R u[3]) {
+    const R Dl[3] = {k.g_rr * D[0] + k.g_rp * D[2], k.g_tt * D[1], k.g_rp * D[0] + k.g_pp * D[2]};
+    const R h = qm * k.alpha * dt * R(0.5);
+    const R uu = k.h_rr * u[0] * u[0] + R(2) * k.h_rp * u[0] * u[2]
+               + k.h_tt * u[1] * u[1] + k.h_pp * u[2] * u[2];
+    R gam, rgam;
+    sqrt_rsqrt(R(1) + uu, gam, rgam);
+    const R v[3] = {u[0] * rgam, u[1] * rgam, u[2] * rgam};
+    R x[3], up[3];
+    cross_lower(k, v, B, x);
+    for (int i = 0; i < 3; ++i) up[i] = (u[i] + h * (Dl[i] + x[i])) + h * Dl[i];
+    const R tau[3] = {h * B[0], h * B[1], h * B[2]};
+    const R tau2 = k.g_rr * tau[0] * tau[0] + R(2) * k.g_rp * tau[0] * tau[2]
+                 + k.g_tt * tau[1] * tau[1] + k.g_pp * tau[2] * tau[2];
+    const R w = up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2];
+    const R upup = k.h_rr * up[0] * up[0] + R(2) * k.h_rp * up[0] * up[2]
+                 + k.h_tt * up[1] * up[1] + k.h_pp * up[2] * up[2];
+    const R sigma = R(1) + upup - tau2;
+    R sd, rsd;
+    sqrt_rsqrt(sigma * sigma + R(4) * (tau2 + w * w), sd, rsd);   // > 0: sigma >= 1 when tau = 0
+    R gn, rgn;
+    sqrt_rsqrt(R(0.5) * (sigma + sd), gn, rgn);                     // gamma_new >= 1
+    const R t[3] = {tau[0] * rgn, tau[1] * rgn, tau[2] * rgn};
+    const R s = rcp(R(1) + tau2 * rgn * rgn);
+    const R ut = w * rgn;                                          // u'_k t^k
+    const R tl[3] = {k.g_rr * t[0] + k.g_rp * t[2], k.g_tt * t[1], k.g_rp * t[0] + k.g_pp * t[2]};
+    cross_lower(k, up, t, x);
+    for (int i = 0; i < 3; ++i) u[i] = s * (up[i] + ut * tl[i] + x[i]);
+}
+
+template <int KICK, class R>
+__device__ __forceinline__ void kick(const Metric<R>& k, R qm, R dt, const R D[3], const R B[3], R u[3]) {
+    if constexpr (KICK == kVay) vay_kick(k, qm, dt, D, B, u);
+    else boris_kick(k, qm, dt, D, B, u);
+}
+
 // CIC weight W(x) = max(0, 1 - |x|).
 template <class R>
 __device__ __forceinline__ R shape1(R x) {

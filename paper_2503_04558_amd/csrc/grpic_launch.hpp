@@ -74,9 +74,10 @@ inline double* tiling_anchors(void* tiling, int64_t slice_cap) {
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream);
+// kick: kBoris (the generalised Boris kick) or kVay (FP64 only).
+hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick = kBoris);
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream);
+                                     hipStream_t stream, int kick = kBoris);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream);
 
 struct SortArgs {

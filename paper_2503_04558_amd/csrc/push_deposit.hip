@@ -139,7 +139,7 @@ __device__ __forceinline__ void store_particle(const StepArgs& A, const PIdx& p,
 // Advances live particle p by one step; its new state goes to out.  Returns
 // true when the move is to be deposited (mv filled), false when the particle
 // was or became removed without a deposit.
-template <bool SHORT>
+template <bool SHORT, int KICK>
 __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, const ParticleIn<double>& in, Move& mv,
                                             Events& ev, const TileAnchors* T, ParticleOut<double>& out) {
     out.kind = 0;
@@ -176,7 +176,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         Metric<double> k0;
         MetricDeriv<double> d0;
         ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
-        if (!massless) boris_kick(k0, A.qm[s], dt, D, B, u);
+        if (!massless) kick<KICK>(k0, A.qm[s], dt, D, B, u);
         geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
     }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
@@ -346,11 +346,13 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 
 // SHORT: the short Taylor series, for grids fine enough for them
 // (small_steps == 2); the launch picks the kernel variant.
-template <bool SPLIT, bool SHORT>
+// KICK: the momentum kick (kBoris, or kVay for the FP64 path only).
+template <bool SPLIT, bool SHORT, int KICK>
 __device__ __forceinline__ bool advance(const StepArgs& A, const PIdx& p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
+    static_assert(!SPLIT || KICK == kBoris, "the split form runs the Boris kick only");
     if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T, out);
-    else return advance_f64<SHORT>(A, p, in, mv, ev, T, out);
+    else return advance_f64<SHORT, KICK>(A, p, in, mv, ev, T, out);
 }
 
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
@@ -376,7 +378,7 @@ __device__ __forceinline__ void workgroup_events_to_global(const StepArgs& A, co
             if (cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
 }
 
-template <bool SPLIT, bool SHORT>
+template <bool SPLIT, bool SHORT, int KICK>
 __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     __shared__ int cnt[5];
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
@@ -386,7 +388,7 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     if (p < A.n) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
+        const bool dep = advance<SPLIT, SHORT, KICK>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
         store_particle(A, pi, out);
         if (dep) scatter_global(A, mv);
     }
@@ -397,14 +399,16 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     workgroup_events_to_global(A, cnt);
 }
 
-template <bool SHORT>
+template <bool SHORT, int KICK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) {
-    push_deposit_body<false, SHORT>(A);
+    push_deposit_body<false, SHORT, KICK>(A);
 }
 template <bool SHORT>
-__global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) { push_deposit_body<true, SHORT>(A); }
+__global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) {
+    push_deposit_body<true, SHORT, kBoris>(A);
+}
 
-template <bool SPLIT, bool SHORT>
+template <bool SPLIT, bool SHORT, int KICK>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const Slice* __restrict__ slices,
                                                         int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live,
@@ -483,7 +487,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (mine) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT>(A, pi, in, mv, ev, &tab, out);
+        const bool dep = advance<SPLIT, SHORT, KICK>(A, pi, in, mv, ev, &tab, out);
         const int si = slot + slot / 32;
         st_kind[si] = out.kind;
         st_cell[si] = out.cell;
@@ -575,18 +579,18 @@ __global__ __launch_bounds__(256) void slice_live_sum(const int32_t* __restrict_
     }
 }
 
-template <bool SHORT>
+template <bool SHORT, int KICK>
 __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap,
     int32_t* slice_live, const double* anchors) {
-    push_deposit_tiled_body<false, SHORT>(A, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
 }
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
                                                                          const Slice* __restrict__ slices,
                                                                          int64_t slice_cap, int32_t* slice_live,
                                                                          const double* anchors) {
-    push_deposit_tiled_body<true, SHORT>(A, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<true, SHORT, kBoris>(A, slices, slice_cap, slice_live, anchors);
 }
 
 // The anchor table of a tiled launch (layout in grpic_launch.hpp).
@@ -624,18 +628,21 @@ __global__ __launch_bounds__(256) void charge_kernel(const StepArgs A, double* _
 
 static inline dim3 blocks_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream) {
+hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick) {
     if (A.n <= 0) return hipSuccess;
     const bool sh = A.small_steps == 2;
-    if (split && sh) hipLaunchKernelGGL(push_deposit_split<true>, blocks_for(A.n), dim3(256), 0, stream, A);
-    else if (split) hipLaunchKernelGGL(push_deposit_split<false>, blocks_for(A.n), dim3(256), 0, stream, A);
-    else if (sh) hipLaunchKernelGGL(push_deposit_f64<true>, blocks_for(A.n), dim3(256), 0, stream, A);
-    else hipLaunchKernelGGL(push_deposit_f64<false>, blocks_for(A.n), dim3(256), 0, stream, A);
+    const dim3 g = blocks_for(A.n), b(256);
+    if (split && sh) hipLaunchKernelGGL(push_deposit_split<true>, g, b, 0, stream, A);
+    else if (split) hipLaunchKernelGGL(push_deposit_split<false>, g, b, 0, stream, A);
+    else if (kick == kVay && sh) hipLaunchKernelGGL((push_deposit_f64<true, kVay>), g, b, 0, stream, A);
+    else if (kick == kVay) hipLaunchKernelGGL((push_deposit_f64<false, kVay>), g, b, 0, stream, A);
+    else if (sh) hipLaunchKernelGGL((push_deposit_f64<true, kBoris>), g, b, 0, stream, A);
+    else hipLaunchKernelGGL((push_deposit_f64<false, kBoris>), g, b, 0, stream, A);
     return hipGetLastError();
 }
 
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream) {
+                                     hipStream_t stream, int kick) {
     if (A.n <= 0) return hipSuccess;
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
@@ -653,10 +660,17 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
         hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     else if (split)
         hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
+    else if (kick == kVay && sh)
+        hipLaunchKernelGGL((push_deposit_f64_tiled<true, kVay>), g, b, 0, stream, A, slices, slice_cap, live, anchors);
+    else if (kick == kVay)
+        hipLaunchKernelGGL((push_deposit_f64_tiled<false, kVay>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
     else if (sh)
-        hipLaunchKernelGGL(push_deposit_f64_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL((push_deposit_f64_tiled<true, kBoris>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
     else
-        hipLaunchKernelGGL(push_deposit_f64_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
+        hipLaunchKernelGGL((push_deposit_f64_tiled<false, kBoris>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
     if (A.counters)
         hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, live, slice_cap, A.counters);
     return hipGetLastError();

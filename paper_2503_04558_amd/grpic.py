@@ -67,7 +67,7 @@ class grpic_field_state(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
 
 
-EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
+EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
             "grpic_field_tables_bytes", "grpic_field_workspace_bytes", "grpic_field_tables", "grpic_field_step")
@@ -100,6 +100,8 @@ def lib():
         L.grpic_backward_workspace_bytes.argtypes = [vp, i64, i32]
         L.grpic_backward_workspace_bytes.restype = sz
         L.grpic_push_deposit.restype = ctypes.c_int
+        L.grpic_push_deposit_vay.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
+        L.grpic_push_deposit_vay.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge.restype = ctypes.c_int
         L.grpic_sort_workspace_bytes.argtypes = [vp, i64]
@@ -220,7 +222,13 @@ def _nbytes(t: torch.Tensor | None) -> int:
 def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float,
                        nsteps: int, ncorr: int = 3, tiling: torch.Tensor | None = None,
                        ckpt: torch.Tensor | None = None, ckpt_every: int = 0,
-                       counters: torch.Tensor | None = None, stream=None) -> None:
+                       counters: torch.Tensor | None = None, stream=None, kick: str = "boris") -> None:
+    """kick: "boris" (grpic_push_deposit) or "vay" (grpic_push_deposit_vay:
+    FP64 particles, no checkpoints)."""
+    if kick not in ("boris", "vay"):
+        raise ValueError(f"kick: expected 'boris' or 'vay', got {kick!r}")
+    if kick == "vay" and ckpt is not None:
+        raise ValueError("kick='vay' takes no checkpoints (the adjoint differentiates the Boris kick)")
     g = make_grid(grid)
     sp = make_species(species)
     P = make_particles(parts)
@@ -232,6 +240,11 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
     for t, name in ((tiling, "tiling"), (ckpt, "ckpt")):
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name}: expected a contiguous device tensor")
+    if kick == "vay":
+        _check(lib().grpic_push_deposit_vay(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
+                                            ctypes.byref(P), ctypes.byref(F), ctypes.byref(C), _ptr(tiling),
+                                            float(dt), int(nsteps), int(ncorr), _ptr(counters), _stream(stream)))
+        return
     _check(lib().grpic_push_deposit(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
                                     ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(nsteps),
                                     int(ncorr), _ptr(ckpt), _nbytes(ckpt), int(ckpt_every), _ptr(counters),
