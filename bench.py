@@ -549,7 +549,7 @@ def main():
             "value": rv["value"], "unit": "particle-steps/s", "dtype": "f64",
             "ms_per_step": rv["total_ms"] / args.steps, "vs_boris": rv["value"] / r["value"],
             "kernel": {"name": "push_deposit_f64_tiled<kVay>", "avg_ms": rv["avg_push_ms"],
-                       "min_ms": float(np.min(rv["push_ms"]))},
+                       "min_ms": float(np.min(rv["push_ms"])), "traffic": traffic.get("vay")},
             "counters": rv["counters"],
         }
     if adj is not None:

@@ -26,7 +26,7 @@ def test_traffic_figure_tracks_kernel_sources(tmp_path, monkeypatch):
 
     t = bench.measured_traffic()
     if t:
-        assert set(t) == {"f64", "split"} and all(v > 1e9 for v in t.values())
+        assert {"f64", "split"} <= set(t) and all(v > 1e9 for v in t.values())
     stale = tmp_path / "p.md"
     stale.write_text("traffic_bytes_per_launch f64=1e10 split=5e9 sources=0000\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(stale))
