@@ -113,8 +113,14 @@ def test_full_step_batch_split_4096_1e9():
     solver = grpic.FieldSolver(metric, g)
     plane = g.shape[0] * g.shape[1]
     inv = solver.tables.view(torch.float64)[: 6 * plane].view(6, *g.shape)
-    area = [torch.where(inv[k] != 0, 1.0 / inv[k], torch.zeros_like(inv[k])) for k in (0, 1, 3, 4)]
     G = g.guard
+    cols = slice(G, G + g.nth + 1)              # the table is written over columns 0..nth only
+    area = []
+    for k in (0, 1, 3, 4):
+        a = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+        v = inv[k][:, cols]
+        a[:, cols] = torch.where(v != 0, 1.0 / v, torch.zeros_like(v))
+        area.append(a)
 
     def div_D(X):
         fr, ft = X[0] * area[0], X[1] * area[1]
@@ -162,7 +168,9 @@ def test_full_step_batch_split_4096_1e9():
         gauss = div_D(state) - Q1[G + 1: G + g.nr, G: G + g.nth + 1]
         scale = gauss.abs().max().item() + div_D(state).abs().max().item()
         gerr = (gauss - gauss0)[inner].abs().max().item() / scale
-        bscale = (state[3] * area[2]).abs().max().item() + (state[4] * area[3]).abs().max().item()
+        # over the faces div B reads: the table's columns outside 0..nth are not written
+        bscale = ((state[3] * area[2])[G: G + g.nr + 1, G: G + g.nth].abs().max().item()
+                  + (state[4] * area[3])[G: G + g.nr, G: G + g.nth + 1].abs().max().item())
         berr = (div_B(state) - divB0)[: g.nr - DAMP - 1].abs().max().item() / bscale
         finite = all(bool(torch.isfinite(s).all()) for s in state)
         _announce(f"step {k}: continuity {cont:.3e} of bound, Gauss {gerr:.3e}, div B {berr:.3e}, finite {finite}")
