@@ -233,3 +233,31 @@ def test_pic_loop_gauss_law_and_field_parity():
         inner = slice(0, g.nr - 1 - 6 - 1)
         assert (gauss - gauss0)[inner].abs().max().item() <= 1e-12 * scale, k
         _compare(g, [s.cpu().numpy() for s in state], host)
+
+
+@pytest.mark.parametrize("ncorr", [0, 3])
+def test_field_step_smallest_theta_grid_with_damping(ncorr):
+    """nth = 2 * guard (the smallest the columns beyond the axes allow: every
+    column is an axis neighbour), an odd nr (a partial last row of tiles),
+    damping over 3 rows, with and without correctors (the predictor writes
+    the caller's arrays itself when ncorr = 0)."""
+    _announce(f"field step 9x4 ncorr={ncorr} damping")
+    g = wl.make_grid(9, 4, 0.9)
+    assert g.nth == 2 * g.guard
+    X = _state(g, 4)
+    rng = np.random.default_rng(5)
+    F = [rng.normal(size=X[0].shape) * 0.01 for _ in range(3)]
+    dt = wl.crossing_dt(g)
+    got, _ = _gpu_step(g, X, F, dt, 0.53, ncorr, damp_cells=3, damp_max=0.3, nsteps=2)
+    want = X
+    for _ in range(2):
+        want = orc.field_step(g, want, F, dt, 0.53, ncorr, damp_cells=3, damp_max=0.3)
+    _compare(g, got, want)
+
+
+def test_field_step_rejects_theta_grid_below_two_guards():
+    g = wl.make_grid(9, 3, 0.9)
+    solver = grpic.FieldSolver(grpic.make_metric(0.9, 1.0), g)
+    state = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(6)]
+    with pytest.raises(grpic.GrpicError, match="nth"):
+        solver.step(state, None, 0.01, 0.53, 3)
