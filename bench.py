@@ -145,7 +145,8 @@ def run_gpu(args, g, F, parts, precision, kick="boris"):
     for k in range(args.warmup):
         step(k, False)
     torch.cuda.synchronize()
-    log(f"{'split' if precision else 'fp64'}: warmup {args.warmup} steps done")
+    label = ('split' if precision else 'fp64') + ('' if kick == 'boris' else f' ({kick} kick)')
+    log(f"{label}: warmup {args.warmup} steps done")
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -160,7 +161,7 @@ def run_gpu(args, g, F, parts, precision, kick="boris"):
     push_ms = [a.elapsed_time(b) for a, b in ev_push]
     sort_ms = [a.elapsed_time(b) for a, b in ev_sort]
     cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist()))
-    log(f"{'split' if precision else 'fp64'}: timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), "
+    log(f"{label}: timed {args.steps} steps: {total_ms:.2f} ms (wall {t_wall:.2f}s), "
         f"counters {cnt}")
     live = cnt["live_steps"]
     value = live / (total_ms * 1e-3)
@@ -294,6 +295,23 @@ def run_fields(args, g, F):
                                  frac=round(gbs / HBM_PEAK_GBS, 4),
                                  traffic=measured_traffic(FIELD_TRAFFIC_PROFILE, FIELD_SOURCES).get("step"),
                                  bytes_per_step=nbytes)}
+
+
+# A re-sort reads each particle's cell for the histogram (4 B), then its
+# cell and state (FP64: 5 x 8 B + weight 8 B + species 1 B + cell 4 B =
+# 53 B) and writes them at their sorted position (53 B).
+SORT_BYTES_PER_PARTICLE_F64 = 4 + 53 + 53
+
+
+def _sort_roofline(sort_ms, n, per_particle):
+    """HBM roofline of the timed re-sorts (the drifted order of a running
+    simulation; the first sort of the generator's random order is untimed)."""
+    if not sort_ms:
+        return None
+    ms = float(np.mean(sort_ms))
+    gbs = n * per_particle / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None, bytes_per_sort=n * per_particle, avg_ms=ms)
 
 
 def run_pic(args):
@@ -527,6 +545,7 @@ def main():
         "roofline": alu,
         "roofline_hbm": hbm,
         "sort_ms": r["sort_ms"],
+        "sort_roofline_hbm": _sort_roofline(r["sort_ms"], 2 * args.pairs, SORT_BYTES_PER_PARTICLE_F64),
         "kernel": {"name": "push_deposit_f64_tiled", "avg_ms": r["avg_push_ms"],
                    "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
                    "live_particles_per_launch": r["live_per_launch"]},
