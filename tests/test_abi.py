@@ -179,3 +179,66 @@ def test_checkpoint_and_backward_validation():
     bad = list(args)
     bad[7] = 2.01 * dt
     assert L.grpic_push_deposit_backward(*bad) == grpic.GRPIC_ERANGE
+
+
+def test_vay_entry_validation():
+    """grpic_push_deposit_vay shares the push's checks and takes FP64
+    particles only; every call here returns before any launch."""
+    g = wl.make_grid(32, 32, 0.9)
+    G = grpic.make_grid(g)
+    m = grpic.make_metric(0.9, 1.0)
+    sp = grpic.make_species(wl.species_table())
+    parts, fields, cur = _fake_args(g)
+    dt = wl.crossing_dt(g)
+    L = grpic.lib()
+
+    def call(parts, dt, ncorr=3):
+        return L.grpic_push_deposit_vay(ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts),
+                                        ctypes.byref(fields), ctypes.byref(cur), None, dt, 1, ncorr, None, None)
+
+    split = grpic.grpic_particles(10, *([0x1000] * 8), None, grpic.GRPIC_FP32_SPLIT, 0)
+    assert call(split, dt) == grpic.GRPIC_EINVAL
+    assert b"FP64" in L.grpic_last_error()
+    assert call(parts, -dt) == grpic.GRPIC_EINVAL
+    assert call(parts, dt, ncorr=17) == grpic.GRPIC_EINVAL
+    assert call(parts, 2.01 * dt) == grpic.GRPIC_ERANGE
+    empty = grpic.grpic_particles(0, *([None] * 9), grpic.GRPIC_FP64, 0)
+    assert call(empty, dt) == grpic.GRPIC_OK
+    with pytest.raises(ValueError, match="checkpoints"):
+        grpic.grpic_push_deposit(m, g, wl.species_table(), {}, [], [], dt, 1, kick="vay", ckpt=object())
+    with pytest.raises(ValueError, match="kick"):
+        grpic.grpic_push_deposit(m, g, wl.species_table(), {}, [], [], dt, 1, kick="leapfrog")
+
+
+def test_field_step_validation():
+    """The field step's host-side checks, before any device work: a theta
+    grid narrower than 2 * guard (the columns beyond the axes mirror physical
+    ones), tables not written for this metric and grid, a small workspace."""
+    L = grpic.lib()
+    m = grpic.make_metric(0.9, 1.0)
+    fake = 0x1000
+    state = grpic.grpic_field_state()
+    for c in range(3):
+        state.D[c] = fake
+        state.B[c] = fake
+    narrow = grpic.make_grid(wl.make_grid(9, 3, 0.9))
+    ok = grpic.make_grid(wl.make_grid(9, 8, 0.9))
+
+    def call(grid, tables, ws_bytes, dt=0.01):
+        return L.grpic_field_step(ctypes.byref(m), ctypes.byref(grid), tables, ctypes.byref(state), None, dt, 0.53,
+                                  7, 0, 0.0, fake, ws_bytes, None)
+
+    assert call(narrow, fake, 1 << 30) == grpic.GRPIC_EINVAL
+    assert b"nth" in L.grpic_last_error()
+    assert call(ok, fake, 1 << 30) == grpic.GRPIC_EINVAL            # tables never written
+    assert b"tables" in L.grpic_last_error()
+    assert call(ok, fake, 1 << 30, dt=-1.0) == grpic.GRPIC_EINVAL
+    assert L.grpic_field_workspace_bytes(ctypes.byref(ok)) == 18 * (9 + 1 + 2 * ok.guard) * ok.pitch * 8
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback: with libgrpic.so absent the binding raises."""
+    monkeypatch.setattr(grpic, "_lib", None)
+    monkeypatch.setattr(grpic, "LIB_PATH", str(tmp_path / "libgrpic.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        grpic.lib()
