@@ -402,6 +402,35 @@ def run_pic(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_ceiling_gbs(gib: int = 4, reps: int = 5) -> dict:
+    """A STREAM ceiling measured on this GPU over a gib-GiB FP64 array (read +
+    write counted): the runtime's device-to-device copy, and STREAM's scale
+    (b = 1.0 * a, torch's vectorised elementwise kernel); HIP events around
+    reps passes after two warm-ups.  The ceiling is the faster of the two."""
+    import torch
+
+    a = torch.ones(gib * (1 << 30) // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    nbytes = 2 * a.numel() * 8
+    out = {}
+    for name, op in (("copy", lambda: b.copy_(a)), ("scale", lambda: torch.mul(a, 1.0, out=b))):
+        for _ in range(2):
+            op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    best = max(out.values())
+    return {"achieved": best, "unit": "GB/s", "frac_of_peak": round(best / HBM_PEAK_GBS, 4),
+            "bytes_per_pass": nbytes, **{f"{k}_gbs": v for k, v in out.items()}}
+
+
 def run_cpu_baseline(args, grid):
     """The FP64 oracle (OpenMP over particles) on a bounded sample."""
     from oracle import oracle as orc
@@ -510,6 +539,8 @@ def main():
         rv = run_gpu(args, g, F, vay_parts, grpic.GRPIC_FP64, kick="vay")
     del vay_parts
     fld = None if args.no_fields else run_fields(args, g, F)
+    copy_ceiling = copy_ceiling_gbs()
+    log(f"STREAM ceiling: copy {copy_ceiling['copy_gbs']} GB/s, scale {copy_ceiling['scale_gbs']} GB/s")
     adj = None if args.no_adjoint else run_adjoint(args)
     cpu = None if args.no_cpu else run_cpu_baseline(args, g)
     # 1344 flop per 97 B = 13.9 flop/B, above the FP64 ridge (78.6 TFLOP/s / 8 TB/s =
@@ -546,6 +577,7 @@ def main():
         "roofline_hbm": hbm,
         "sort_ms": r["sort_ms"],
         "sort_roofline_hbm": _sort_roofline(r["sort_ms"], 2 * args.pairs, SORT_BYTES_PER_PARTICLE_F64),
+        "hbm_copy_ceiling": copy_ceiling,
         "kernel": {"name": "push_deposit_f64_tiled", "avg_ms": r["avg_push_ms"],
                    "min_ms": float(np.min(r["push_ms"])), "bytes_per_launch": r["bytes_per_launch"],
                    "live_particles_per_launch": r["live_per_launch"]},
