@@ -449,6 +449,106 @@ void scatter_move(const Geom& g, const Move<double>& mv, AccT& Fr, AccT& Ft, Acc
 }
 
 /* ------------------------------------------------------------------ */
+/* Third-order spline shape (the option Sec. 2.3 names beside CIC):    */
+/* the cubic B-spline, W(d) = (4 - 6 d^2 + 3 |d|^3)/6 for |d| < 1,     */
+/* (2 - |d|)^3 / 6 for 1 <= |d| < 2, zero beyond; support 4 vertices.  */
+/* ------------------------------------------------------------------ */
+template <class T>
+T shape3(const T& x) {
+    const T ax = fabs(x);
+    if (val(ax) >= 2.0) return T(0.0);
+    if (val(ax) >= 1.0) {
+        const T y = 2.0 - ax;
+        return y * y * y / 6.0;
+    }
+    return (4.0 - 6.0 * ax * ax + 3.0 * ax * ax * ax) / 6.0;
+}
+
+/* Gather with the cubic shape: the 4 x 4 vertices of the component's
+ * own stagger around the point (rows and columns beyond the grid are the
+ * guard rows and the columns beyond the axes).                         */
+template <class T, class Arr>
+T spline3_gather(const Geom& g, const Arr& arr, double sr, double st, const T& xi, const T& eta) {
+    const T f = xi - sr, h = eta - st;
+    const int i = (int)std::floor(val(f)), j = (int)std::floor(val(h));
+    T sum(0.0);
+    for (int a = -1; a <= 2; ++a)
+        for (int b = -1; b <= 2; ++b) sum = sum + shape3(f - (double)(i + a)) * shape3(h - (double)(j + b)) * arr[idx(g, i + a, j + b)];
+    return sum;
+}
+
+/* Esirkepov deposit of one move with the cubic shape: the same
+ * decomposition as for CIC on the 5 x 5 vertex window that holds both
+ * supports (moves are under one cell), lower corner (floor(min xi) - 1,
+ * floor(min eta) - 1).                                                  */
+struct Move3 {
+    int i0, j0;
+    double Fr[4][5];     /* flux through (i0+a+1/2, j0+b) */
+    double Ft[5][4];     /* flux through (i0+a, j0+b+1/2) */
+    double Gp[5][5];     /* J^ph dV at (i0+a, j0+b)       */
+    double scale_f, scale_p;
+};
+
+void esirkepov3(double qw, double dt, double xi0, double eta0, double xi1, double eta1, double dphi, Move3& mv) {
+    mv.i0 = (int)std::floor(std::min(xi0, xi1)) - 1;
+    mv.j0 = (int)std::floor(std::min(eta0, eta1)) - 1;
+    double Wr[5][5], Wt[5][5];
+    for (int a = 0; a < 5; ++a) {
+        const double wx0 = shape3(xi0 - (double)(mv.i0 + a)), wx1 = shape3(xi1 - (double)(mv.i0 + a));
+        for (int b = 0; b < 5; ++b) {
+            const double wy0 = shape3(eta0 - (double)(mv.j0 + b)), wy1 = shape3(eta1 - (double)(mv.j0 + b));
+            const double S00 = wx0 * wy0, S01 = wx0 * wy1, S10 = wx1 * wy0, S11 = wx1 * wy1;
+            Wr[a][b] = 0.5 * (S11 - S01 + S10 - S00);
+            Wt[a][b] = 0.5 * (S11 - S10 + S01 - S00);
+            mv.Gp[a][b] = qw * dphi / dt * (S11 / 3.0 + S10 / 6.0 + S01 / 6.0 + S00 / 3.0);
+        }
+    }
+    mv.scale_f = std::fabs(qw) / dt;
+    mv.scale_p = std::fabs(qw * dphi) / dt;
+    for (int b = 0; b < 5; ++b) {
+        double run = 0.0;
+        for (int a = 0; a < 4; ++a) { run += Wr[a][b]; mv.Fr[a][b] = -qw / dt * run; }
+    }
+    for (int a = 0; a < 5; ++a) {
+        double run = 0.0;
+        for (int b = 0; b < 4; ++b) { run += Wt[a][b]; mv.Ft[a][b] = -qw / dt * run; }
+    }
+}
+
+/* Folding across the axes: a deposit at a vertex column beyond an axis
+ * belongs to its mirror (axisymmetry maps (r, -theta, phi) to (r, theta,
+ * phi + pi)); vertex columns j < 0 -> -j, j > nth -> 2 nth - j, values
+ * kept (charge, J^r, J^ph are even); theta-face columns (j + 1/2) < 0 ->
+ * -j - 1, > nth -> 2 nth - 1 - j, values negated (J^th is odd).  Each
+ * vertex's discrete continuity is kept: the folded faces carry the
+ * divergence of the folded vertices.                                    */
+inline int fold_vertex(const Geom& g, int j) { return j < 0 ? -j : (j > g.nth ? 2 * g.nth - j : j); }
+inline int fold_face(const Geom& g, int j, double& sign) {
+    sign = 1.0;
+    if (j < 0) { sign = -1.0; return -j - 1; }
+    if (j >= g.nth) { sign = -1.0; return 2 * g.nth - 1 - j; }
+    return j;
+}
+
+template <class AccT>
+void scatter_move3(const Geom& g, const Move3& mv, AccT& Fr, AccT& Ft, AccT& Gp) {
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 5; ++b)
+            Fr.add(idx(g, mv.i0 + a, fold_vertex(g, mv.j0 + b)), mv.Fr[a][b], mv.scale_f);
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 4; ++b) {
+            double sgn;
+            const int jf = fold_face(g, mv.j0 + b, sgn);
+            Ft.add(idx(g, mv.i0 + a, jf), sgn * mv.Ft[a][b], mv.scale_f);
+        }
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b)
+            Gp.add(idx(g, mv.i0 + a, fold_vertex(g, mv.j0 + b)), mv.Gp[a][b], mv.scale_p);
+}
+
+enum { SHAPE_CIC = 1, SHAPE_SPLINE3 = 3 };
+
+/* ------------------------------------------------------------------ */
 /* One particle, one step: gather, push, boundaries, deposit, store.   */
 /* ------------------------------------------------------------------ */
 enum { ST_ALIVE = 0, ST_OUT = 1, ST_BAD = 2, ST_DEAD = 3 };
@@ -457,12 +557,14 @@ struct Outcome {
     int status;
     int reflected;
     Move<double> mv;
+    Move3 mv3;          /* the cubic shape's move (order 3) */
     int32_t cell;
     double xr, xth, u[3], dphi;
 };
 
 Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], double w, double dt, int ncorr,
-                 int32_t cell, double xr, double xth, const double u[3], int kick = KICK_BORIS) {
+                 int32_t cell, double xr, double xth, const double u[3], int kick = KICK_BORIS,
+                 int order = SHAPE_CIC) {
     Outcome o;
     o.reflected = 0;
     o.status = ST_DEAD;
@@ -478,8 +580,13 @@ Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], dou
 
     double D[3], B[3];
     for (int c = 0; c < 3; ++c) {
-        D[c] = cic_gather(g, F[c], kStagR[c], kStagT[c], xi0, eta0);
-        B[c] = cic_gather(g, F[3 + c], kStagR[3 + c], kStagT[3 + c], xi0, eta0);
+        if (order == SHAPE_SPLINE3) {
+            D[c] = spline3_gather(g, F[c], kStagR[c], kStagT[c], xi0, eta0);
+            B[c] = spline3_gather(g, F[3 + c], kStagR[3 + c], kStagT[3 + c], xi0, eta0);
+        } else {
+            D[c] = cic_gather(g, F[c], kStagR[c], kStagT[c], xi0, eta0);
+            B[c] = cic_gather(g, F[3 + c], kStagR[3 + c], kStagT[3 + c], xi0, eta0);
+        }
     }
     double y1[6];
     push_with_fields(g, sp, dt, ncorr, xi0, eta0, u, D, B, y1, kick);
@@ -497,7 +604,8 @@ Outcome step_one(const Geom& g, const Species& sp, const double* const F[6], dou
     if (eta1 < 0.0) { eta1 = -eta1; u1[1] = -u1[1]; o.reflected = 1; }
     else if (eta1 > (double)g.nth) { eta1 = 2.0 * g.nth - eta1; u1[1] = -u1[1]; o.reflected = 1; }
 
-    esirkepov(sp.q * w, dt, xi0, eta0, xi1, eta1, y1[2], o.mv);
+    if (order == SHAPE_SPLINE3) esirkepov3(sp.q * w, dt, xi0, eta0, xi1, eta1, y1[2], o.mv3);
+    else esirkepov(sp.q * w, dt, xi0, eta0, xi1, eta1, y1[2], o.mv);
     o.dphi = y1[2];
     if (xi1 < 0.0 || xi1 >= (double)g.nr) {     /* radial outflow: removed after depositing */
         o.status = ST_OUT;
@@ -632,6 +740,35 @@ void orc_deposit_move(const Geom* g, double qw, double dt, double xi0, double et
     scatter_move(*g, mv, a, b, c);
 }
 
+void orc_gather3(const Geom* g, const double* const* F, double xi, double eta, double* out) {
+    for (int c = 0; c < 6; ++c) out[c] = spline3_gather(*g, F[c], kStagR[c], kStagT[c], xi, eta);
+}
+
+/* Deposit one move with the cubic shape, folded across the axes (+=). */
+void orc_deposit_move3(const Geom* g, double qw, double dt, double xi0, double eta0,
+                       double xi1, double eta1, double dphi, double* Fr, double* Fth, double* Gph) {
+    Move3 mv;
+    esirkepov3(qw, dt, xi0, eta0, xi1, eta1, dphi, mv);
+    PlainAcc a{Fr}, b{Fth}, c{Gph};
+    scatter_move3(*g, mv, a, b, c);
+}
+
+/* Charge with the cubic shape, folded across the axes (Q is +=). */
+void orc_charge3(const Geom* g, const Species* sp, int nsp, int64_t n, const int32_t* cell,
+                 const double* xr, const double* xth, const double* w, const uint8_t* spi, double* Q) {
+    (void)nsp;
+    for (int64_t p = 0; p < n; ++p) {
+        if (cell[p] < 0) continue;
+        const int i = cell[p] / g->nth, j = cell[p] % g->nth;
+        const double qw = sp[spi[p]].q * w[p];
+        const double xi = i + xr[p], eta = j + xth[p];
+        for (int a = -1; a <= 2; ++a)
+            for (int b = -1; b <= 2; ++b)
+                Q[idx(*g, i + a, fold_vertex(*g, j + b))] +=
+                    qw * shape3(xi - (double)(i + a)) * shape3(eta - (double)(j + b));
+    }
+}
+
 /* Charge Q_ij = sum_p q w S_ij(x_p) over live particles (Q is +=). */
 void orc_charge(const Geom* g, const Species* sp, int nsp, int64_t n, const int32_t* cell,
                 const double* xr, const double* xth, const double* w, const uint8_t* spi, double* Q) {
@@ -655,13 +792,15 @@ void orc_charge(const Geom* g, const Species* sp, int nsp, int64_t n, const int3
  * with thread-private J reduced in thread order (timing mode).
  * stats[4] (+=): particles removed at the radial edges, removed as
  * non-finite or moving >= 1 cell, axis reflections, live particle-steps.
- * kick: KICK_BORIS (the generalised Boris kick) or KICK_VAY.           */
+ * kick: KICK_BORIS (the generalised Boris kick) or KICK_VAY.  order:
+ * SHAPE_CIC or SHAPE_SPLINE3 (the cubic shape for gather and deposit,
+ * folded across the axes; needs guard >= 3).                           */
 void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
              int32_t* cell, double* xr, double* xth, double* ur, double* uth, double* uph,
              const double* w, const uint8_t* spi, double* phi,
              const double* const* F, double* Fr, double* Fth, double* Gph,
              double* Afr, double* Afth, double* Agph,
-             double dt, int nsteps, int ncorr, int nthreads, int64_t* stats, int kick) {
+             double dt, int nsteps, int ncorr, int nthreads, int64_t* stats, int kick, int order) {
     const Geom& g = *gp;
     const long ncell = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
     int64_t st_out = 0, st_bad = 0, st_refl = 0, st_live = 0;
@@ -673,12 +812,13 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
             for (int64_t p = 0; p < n; ++p) {
                 const double u[3] = {ur[p], uth[p], uph[p]};
                 if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
-                Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick);
+                Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick, order);
                 if (o.status == ST_DEAD) continue;
                 ++st_live;
                 if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
                 st_refl += o.reflected;
-                scatter_move(g, o.mv, A_r, A_t, A_p);
+                if (order == SHAPE_SPLINE3) scatter_move3(g, o.mv3, A_r, A_t, A_p);
+                else scatter_move(g, o.mv, A_r, A_t, A_p);
                 if (phi) phi[p] += o.dphi;
                 if (o.status == ST_OUT) { ++st_out; cell[p] = -1; continue; }
                 cell[p] = o.cell; xr[p] = o.xr; xth[p] = o.xth;
@@ -699,12 +839,13 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
                 for (int64_t p = 0; p < n; ++p) {
                     const double u[3] = {ur[p], uth[p], uph[p]};
                     if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
-                    Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick);
+                    Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u, kick, order);
                     if (o.status == ST_DEAD) continue;
                     ++st_live;
                     if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
                     st_refl += o.reflected;
-                    scatter_move(g, o.mv, A_r, A_t, A_p);
+                    if (order == SHAPE_SPLINE3) scatter_move3(g, o.mv3, A_r, A_t, A_p);
+                    else scatter_move(g, o.mv, A_r, A_t, A_p);
                     if (phi) phi[p] += o.dphi;
                     if (o.status == ST_OUT) { ++st_out; cell[p] = -1; continue; }
                     cell[p] = o.cell; xr[p] = o.xr; xth[p] = o.xth;

@@ -148,6 +148,40 @@ def deposit_move(grid, qw, dt, xi0, eta0, xi1, eta1, dphi, J=None):
     return J
 
 
+def gather3(grid, fields, xi, eta) -> np.ndarray:
+    """The six components at (xi, eta) with the cubic spline shape."""
+    g = geom(grid)
+    fl = [_f64(f) for f in fields]
+    ptrs = (ctypes.c_void_p * 6)(*[f.ctypes.data for f in fl])
+    out = np.zeros(6)
+    lib().orc_gather3(ctypes.byref(g), ptrs, ctypes.c_double(xi), ctypes.c_double(eta), _p(out))
+    return out
+
+
+def deposit_move3(grid, qw, dt, xi0, eta0, xi1, eta1, dphi, J=None):
+    """Deposit of one move with the cubic shape, folded across the axes."""
+    g = geom(grid)
+    if J is None:
+        J = [np.zeros((grid.nr + 1 + 2 * grid.guard, grid.pitch)) for _ in range(3)]
+    lib().orc_deposit_move3(ctypes.byref(g), ctypes.c_double(qw), ctypes.c_double(dt),
+                            ctypes.c_double(xi0), ctypes.c_double(eta0), ctypes.c_double(xi1),
+                            ctypes.c_double(eta1), ctypes.c_double(dphi), _p(J[0]), _p(J[1]), _p(J[2]))
+    return J
+
+
+def charge3(grid, species, parts) -> np.ndarray:
+    """Q with the cubic spline shape, folded across the axes."""
+    g = geom(grid)
+    sp = _species_array(species)
+    cell = np.ascontiguousarray(parts["cell"], dtype=np.int32)
+    xr, xth, w = _f64(parts["xr"]), _f64(parts["xth"]), _f64(parts["w"])
+    spi = np.ascontiguousarray(parts["sp"], dtype=np.uint8)
+    Q = np.zeros((grid.nr + 1 + 2 * grid.guard, grid.pitch))
+    lib().orc_charge3(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(len(cell)),
+                      _p(cell), _p(xr), _p(xth), _p(w), _p(spi), _p(Q))
+    return Q
+
+
 def _species_array(species):
     arr = (Species * len(species))()
     for i, s in enumerate(species):
@@ -172,7 +206,7 @@ PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
 
 
 def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int = 1,
-        with_abs: bool = False, track_phi: bool = False, J=None, kick: str = "boris"):
+        with_abs: bool = False, track_phi: bool = False, J=None, kick: str = "boris", order: int = 1):
     """Advance copies of the particle arrays nsteps steps.
 
     Returns (parts_out, J, A, stats): J = [Fr, Fth, Gph] (added to the given
@@ -180,8 +214,13 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
     contributions of their magnitude scale, |q w|/dt for F^r and F^th and
     |q w dphi|/dt for G^ph; stats = dict(out, bad, reflected, live_steps).
     kick: "boris" (the generalised Boris kick) or "vay" (Vay's update in the
-    FIDO frame).
+    FIDO frame).  order: 1 (CIC) or 3 (the cubic spline shape for gather and
+    deposit, folded across the axes; the grid needs guard >= 3).
     """
+    if order not in (1, 3):
+        raise ValueError(f"order: expected 1 or 3, got {order}")
+    if order == 3 and grid.guard < 3:
+        raise ValueError("the cubic shape needs guard >= 3")
     g = geom(grid)
     sp = _species_array(species)
     p = {
@@ -211,7 +250,7 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
                   fptr, _p(J[0]), _p(J[1]), _p(J[2]),
                   _p(A[0]) if A else null, _p(A[1]) if A else null, _p(A[2]) if A else null,
                   ctypes.c_double(dt), ctypes.c_int(nsteps), ctypes.c_int(ncorr),
-                  ctypes.c_int(nthreads), _p(stats), ctypes.c_int(KICKS[kick]))
+                  ctypes.c_int(nthreads), _p(stats), ctypes.c_int(KICKS[kick]), ctypes.c_int(order))
     st = dict(out=int(stats[0]), bad=int(stats[1]), reflected=int(stats[2]), live_steps=int(stats[3]))
     return p, J, A, st
 
