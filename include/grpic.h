@@ -197,6 +197,34 @@ int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
                            void* tiling, double dt, int nsteps, int ncorr,
                            int64_t* counters, void* stream);
 
+/*
+ * grpic_push_deposit_spline3 -- grpic_push_deposit with the third-order
+ * shape (the spline option of Sec. 2.3) in place of CIC for both the field
+ * gather and the Esirkepov deposit: the cubic B-spline W(d) = 2/3 - d^2 +
+ * |d|^3/2 (|d| < 1), (2 - |d|)^3/6 (1 <= |d| < 2), 0 beyond, on the 4 x 4
+ * vertices of each component's own stagger for the gather (guard rows and
+ * the columns beyond the axes, which grpic_field_step keeps, are read) and
+ * the 5 x 5 vertex window (lower corner floor(min xi) - 1, floor(min eta) -
+ * 1) for the deposit.  Deposits beyond an axis are folded onto the mirror
+ * vertex (F^r, G^ph, values kept) or theta face (F^th, sign changed), by
+ * axisymmetry, so discrete charge continuity holds at every vertex with the
+ * cubic charge of grpic_charge3.  Generalised Boris kick, FP64 particles,
+ * no tiling (one thread per particle, global atomics), no checkpoints;
+ * grid->guard >= 3 (the window's radial reach), nth >= 4; otherwise
+ * arguments, errors and counters as in grpic_push_deposit.
+ */
+int grpic_push_deposit_spline3(const grpic_metric* metric, const grpic_grid* grid,
+                               const grpic_species* species, int nsp,
+                               grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                               double dt, int nsteps, int ncorr, int64_t* counters, void* stream);
+
+/*
+ * grpic_charge3 -- grpic_charge with the cubic spline shape, folded across
+ * the axes like grpic_push_deposit_spline3's deposit (guard >= 3).
+ */
+int grpic_charge3(const grpic_grid* grid, const grpic_species* species, int nsp,
+                  const grpic_particles* parts, double* Q, void* stream);
+
 /* Gradient outputs of grpic_push_deposit_backward (device, double). */
 typedef struct {
     double *ur, *uth, *uph;          /* per particle, overwritten */

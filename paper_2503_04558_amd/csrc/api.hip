@@ -224,7 +224,7 @@ double grpic_crossing_time(const grpic_metric* metric, const grpic_grid* grid) {
 static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, const grpic_species* species, int nsp,
                         grpic_particles* parts, const grpic_fields* fields, grpic_current* J, void* tiling, double dt,
                         int nsteps, int ncorr, void* ckpt, size_t ckpt_bytes, int ckpt_every, int64_t* counters,
-                        void* stream, int kick) {
+                        void* stream, int kick, int order = 1) {
     int rc;
     if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
         (rc = check_particles(parts, "parts")))
@@ -273,7 +273,7 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
         }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
         const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick)
-                                    : grpic::launch_push_deposit(A, split, s, kick);
+                                    : grpic::launch_push_deposit(A, split, s, kick, order);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
     return GRPIC_OK;
@@ -287,6 +287,19 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
                        int64_t* counters, void* stream) {
     return push_deposit(metric, grid, species, nsp, parts, fields, J, tiling, dt, nsteps, ncorr, ckpt, ckpt_bytes,
                         ckpt_every, counters, stream, grpic::kBoris);
+}
+
+int grpic_push_deposit_spline3(const grpic_metric* metric, const grpic_grid* grid,
+                               const grpic_species* species, int nsp,
+                               grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                               double dt, int nsteps, int ncorr, int64_t* counters, void* stream) {
+    if (parts && parts->precision != GRPIC_FP64)
+        return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: GRPIC_FP64 particles only");
+    if (grid && grid->guard < 3) return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: the cubic shape needs guard >= 3");
+    if (grid && grid->nth < 4)     // the folded 5 x 5 window stays inside columns 0 .. nth
+        return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: nth must be >= 4");
+    return push_deposit(metric, grid, species, nsp, parts, fields, J, nullptr, dt, nsteps, ncorr, nullptr, 0, 0,
+                        counters, stream, grpic::kBoris, 3);
 }
 
 int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
@@ -376,8 +389,8 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
     return hip_status(grpic::launch_push_deposit_backward(B, aux, static_cast<hipStream_t>(stream)), "backward launch");
 }
 
-int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
-                 const grpic_particles* parts, double* Q, void* stream) {
+static int charge(const grpic_grid* grid, const grpic_species* species, int nsp,
+                 const grpic_particles* parts, double* Q, void* stream, int order) {
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_species(species, nsp)) || (rc = check_particles(parts, "parts")))
         return rc;
@@ -385,7 +398,18 @@ int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
     grpic::StepArgs A;
     fill_common(A, nullptr, grid, species, nsp, parts);
     return hip_status(grpic::launch_charge(A, parts->precision == GRPIC_FP32_SPLIT, Q,
-                                           static_cast<hipStream_t>(stream)), "charge launch");
+                                           static_cast<hipStream_t>(stream), order), "charge launch");
+}
+
+int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp, const grpic_particles* parts,
+                 double* Q, void* stream) {
+    return charge(grid, species, nsp, parts, Q, stream, 1);
+}
+
+int grpic_charge3(const grpic_grid* grid, const grpic_species* species, int nsp, const grpic_particles* parts,
+                  double* Q, void* stream) {
+    if (grid && grid->guard < 3) return fail(GRPIC_EINVAL, "grpic_charge3: the cubic shape needs guard >= 3");
+    return charge(grid, species, nsp, parts, Q, stream, 3);
 }
 
 size_t grpic_sort_workspace_bytes(const grpic_grid* grid, int64_t n) {

@@ -492,6 +492,65 @@ __device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
     }
 }
 
+// Third-order shape (the spline option of Sec. 2.3): the cubic B-spline,
+// W(d) = 2/3 - d^2 + |d|^3 / 2 for |d| < 1, (2 - |d|)^3 / 6 for 1 <= |d| < 2,
+// zero beyond; four vertices carry a particle.
+__device__ __forceinline__ double shape3(double x) {
+    const double a = fabs(x);
+    const double y = 2.0 - a;
+    const double outer = y * y * y * (1.0 / 6.0);
+    const double inner = fma(a * a, fma(0.5, a, -1.0), 2.0 / 3.0);
+    return a >= 2.0 ? 0.0 : (a >= 1.0 ? outer : inner);
+}
+
+// Columns beyond an axis fold onto their mirror (axisymmetry: (r, -theta,
+// phi) is (r, theta, phi + pi)).  Vertex columns keep the value (charge,
+// J^r, J^ph are even); theta-face columns (j + 1/2) change sign (J^th is
+// odd).  Every vertex keeps its discrete continuity.
+__device__ __forceinline__ int fold_vertex(int j, int nth) { return j < 0 ? -j : (j > nth ? 2 * nth - j : j); }
+__device__ __forceinline__ int fold_face(int j, int nth, double& sign) {
+    sign = (j < 0 || j >= nth) ? -1.0 : 1.0;
+    return j < 0 ? -j - 1 : (j >= nth ? 2 * nth - 1 - j : j);
+}
+
+// Esirkepov fluxes of a move with the cubic shape on the 5 x 5 vertex window
+// (lower corner floor(min xi) - 1, floor(min eta) - 1) that holds both
+// supports, in the factorised form of the CIC version, folded across the
+// axes and handed to add(component, i, j, value): 20 F^r, 20 F^th, 25 G^ph.
+template <class Add>
+__device__ __forceinline__ void esirkepov3(const Move& m, double dt, int nth, Add&& add) {
+    const int i0 = (int)floor(fmin(m.xi0, m.xi1)) - 1, j0 = (int)floor(fmin(m.eta0, m.eta1)) - 1;
+    double wx0[5], wx1[5], wy0[5], wy1[5];
+    for (int a = 0; a < 5; ++a) {
+        wx0[a] = shape3(m.xi0 - (double)(i0 + a));
+        wx1[a] = shape3(m.xi1 - (double)(i0 + a));
+        wy0[a] = shape3(m.eta0 - (double)(j0 + a));
+        wy1[a] = shape3(m.eta1 - (double)(j0 + a));
+    }
+    const double idt = rcp(dt);
+    const double hf = -0.5 * m.qw * idt;
+    const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);
+    double fx[4], fy[4], runx = 0.0, runy = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        runx += wx1[a] - wx0[a];
+        runy += wy1[a] - wy0[a];
+        fx[a] = hf * runx;
+        fy[a] = hf * runy;
+    }
+    for (int b = 0; b < 5; ++b) {
+        const int jv = fold_vertex(j0 + b, nth);
+        const double sy = wy0[b] + wy1[b];
+        const double p1 = cp6 * fma(2.0, wy1[b], wy0[b]), p0 = cp6 * fma(2.0, wy0[b], wy1[b]);
+        for (int a = 0; a < 4; ++a) add(0, i0 + a, jv, fx[a] * sy);
+        for (int a = 0; a < 5; ++a) add(2, i0 + a, jv, fma(wx1[a], p1, wx0[a] * p0));
+    }
+    for (int b = 0; b < 4; ++b) {
+        double sg;
+        const int jf = fold_face(j0 + b, nth, sg);
+        for (int a = 0; a < 5; ++a) add(1, i0 + a, jf, sg * fy[b] * (wx0[a] + wx1[a]));
+    }
+}
+
 // n / d for 0 <= n < 2^31 and d > 0, from the double product n * (1/d)
 // (within 2^-21 of the quotient, so truncation is off by at most one) and
 // one correction on the remainder; cheaper than the integer division

@@ -41,6 +41,26 @@ __device__ __forceinline__ double cic_f64(const double* __restrict__ F, const St
     return (1.0 - wf) * (1.0 - wh) * lo.x + wf * (1.0 - wh) * hi.x + (1.0 - wf) * wh * lo.y + wf * wh * hi.y;
 }
 
+// Gather with the cubic shape: the 4 x 4 vertices around (f, h) =
+// (xi - sr, eta - st) of the component's own stagger (guard rows and the
+// columns beyond the axes included; the grid has guard >= 3).
+__device__ __forceinline__ double spline3_f64(const double* __restrict__ F, const StepArgs& A, double f, double h) {
+    const int i = (int)floor(f), j = (int)floor(h);
+    double wx[4], wy[4];
+    for (int a = 0; a < 4; ++a) {
+        wx[a] = shape3(f - (double)(i - 1 + a));
+        wy[a] = shape3(h - (double)(j - 1 + a));
+    }
+    double sum = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const uint32_t o = grid_index(A, i - 1 + a, j - 1);
+        double row = 0.0;
+        for (int b = 0; b < 4; ++b) row = fma(wy[b], *elem(F, o + (uint32_t)b), row);
+        sum = fma(wx[a], row, sum);
+    }
+    return sum;
+}
+
 struct Events {
     int live, out, bad, refl, spill;
 };
@@ -139,7 +159,7 @@ __device__ __forceinline__ void store_particle(const StepArgs& A, const PIdx& p,
 // Advances live particle p by one step; its new state goes to out.  Returns
 // true when the move is to be deposited (mv filled), false when the particle
 // was or became removed without a deposit.
-template <bool SHORT, int KICK>
+template <bool SHORT, int KICK, int ORDER>
 __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, const ParticleIn<double>& in, Move& mv,
                                             Events& ev, const TileAnchors* T, ParticleOut<double>& out) {
     out.kind = 0;
@@ -159,10 +179,12 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
     const double xi0 = (double)ci + dxr, eta0 = (double)cj + dxt;
     double u[3] = {in.u[0], in.u[1], in.u[2]};
     const double* const* F = reinterpret_cast<const double* const*>(A.F);
-    const double D[3] = {cic_f64(F[0], A, xi0 - 0.5, eta0), cic_f64(F[1], A, xi0, eta0 - 0.5),
-                         cic_f64(F[2], A, xi0, eta0)};
-    const double B[3] = {cic_f64(F[3], A, xi0, eta0 - 0.5), cic_f64(F[4], A, xi0 - 0.5, eta0),
-                         cic_f64(F[5], A, xi0 - 0.5, eta0 - 0.5)};
+    auto gather = [&](int c, double f, double h) {
+        if constexpr (ORDER == 3) return spline3_f64(F[c], A, f, h);
+        else return cic_f64(F[c], A, f, h);
+    };
+    const double D[3] = {gather(0, xi0 - 0.5, eta0), gather(1, xi0, eta0 - 0.5), gather(2, xi0, eta0)};
+    const double B[3] = {gather(3, xi0, eta0 - 0.5), gather(4, xi0 - 0.5, eta0), gather(5, xi0 - 0.5, eta0 - 0.5)};
     const bool massless = A.massless[s] != 0;
     const double dt = A.dt;
     const double eps = massless ? 0.0 : 1.0;
@@ -347,17 +369,21 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 // SHORT: the short Taylor series, for grids fine enough for them
 // (small_steps == 2); the launch picks the kernel variant.
 // KICK: the momentum kick (kBoris, or kVay for the FP64 path only).
-template <bool SPLIT, bool SHORT, int KICK>
+// ORDER: the shape, 1 (CIC) or 3 (cubic spline, FP64 untiled only).
+template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
 __device__ __forceinline__ bool advance(const StepArgs& A, const PIdx& p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
-    static_assert(!SPLIT || KICK == kBoris, "the split form runs the Boris kick only");
+    static_assert(!SPLIT || (KICK == kBoris && ORDER == 1), "the split form runs the Boris kick and CIC only");
     if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T, out);
-    else return advance_f64<SHORT, KICK>(A, p, in, mv, ev, T, out);
+    else return advance_f64<SHORT, KICK, ORDER>(A, p, in, mv, ev, T, out);
 }
 
+template <int ORDER = 1>
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
-    esirkepov(mv, A.dt, [&](int c, int i, int j, double v) { atomicAdd(elem(J[c], grid_index(A, i, j)), v); });
+    auto add = [&](int c, int i, int j, double v) { atomicAdd(elem(J[c], grid_index(A, i, j)), v); };
+    if constexpr (ORDER == 3) esirkepov3(mv, A.dt, A.nth, add);
+    else esirkepov(mv, A.dt, add);
 }
 
 // Event counts of a workgroup: each wave adds its ballot counts to five LDS
@@ -378,7 +404,7 @@ __device__ __forceinline__ void workgroup_events_to_global(const StepArgs& A, co
             if (cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
 }
 
-template <bool SPLIT, bool SHORT, int KICK>
+template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
 __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     __shared__ int cnt[5];
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
@@ -388,9 +414,10 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     if (p < A.n) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT, KICK>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
+        const bool dep =
+            advance<SPLIT, SHORT, KICK, ORDER>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
         store_particle(A, pi, out);
-        if (dep) scatter_global(A, mv);
+        if (dep) scatter_global<ORDER>(A, mv);
     }
     if (!A.counters) return;                                 // uniform
     __syncthreads();
@@ -399,9 +426,15 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
     workgroup_events_to_global(A, cnt);
 }
 
-template <bool SHORT, int KICK>
+template <bool SHORT, int KICK, int ORDER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) {
-    push_deposit_body<false, SHORT, KICK>(A);
+    push_deposit_body<false, SHORT, KICK, ORDER>(A);
+}
+// The cubic shape's kernel (96 gather loads, a 5 x 5 deposit): no waves
+// per SIMD target, so that its larger register set does not spill.
+template <bool SHORT>
+__global__ __launch_bounds__(256) void push_deposit_f64_spline3(const StepArgs A) {
+    push_deposit_body<false, SHORT, kBoris, 3>(A);
 }
 template <bool SHORT>
 __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) {
@@ -626,18 +659,43 @@ __global__ __launch_bounds__(256) void charge_kernel(const StepArgs A, double* _
     atomicAdd(q + A.pitch + 1, qw * fx * fy);
 }
 
+// Charge with the cubic shape, folded across the axes like the deposit.
+template <class T>
+__global__ __launch_bounds__(256) void charge3_kernel(const StepArgs A, double* __restrict__ Q) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    const int cell = A.cell[p];
+    const int s = A.sp[p];
+    if (cell < 0 || cell >= A.nr * A.nth || s >= A.nsp) return;
+    const double fx = (double)static_cast<const T*>(A.xr)[p];
+    const double fy = (double)static_cast<const T*>(A.xth)[p];
+    if (!(fx >= 0.0 && fx <= 1.0 && fy >= 0.0 && fy <= 1.0)) return;
+    const double qw = A.q[s] * (double)static_cast<const T*>(A.w)[p];
+    const int ci = cell / A.nth, cj = cell - ci * A.nth;
+    for (int a = -1; a <= 2; ++a) {
+        const double wx = qw * shape3(fx - (double)a);
+        for (int b = -1; b <= 2; ++b)
+            atomicAdd(elem(Q, grid_index(A, ci + a, fold_vertex(cj + b, A.nth))), wx * shape3(fy - (double)b));
+    }
+}
+
 static inline dim3 blocks_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick) {
+hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick, int order) {
     if (A.n <= 0) return hipSuccess;
     const bool sh = A.small_steps == 2;
     const dim3 g = blocks_for(A.n), b(256);
+    if (order == 3) {                                    // FP64, Boris kick (checked by the caller)
+        if (sh) hipLaunchKernelGGL(push_deposit_f64_spline3<true>, g, b, 0, stream, A);
+        else hipLaunchKernelGGL(push_deposit_f64_spline3<false>, g, b, 0, stream, A);
+        return hipGetLastError();
+    }
     if (split && sh) hipLaunchKernelGGL(push_deposit_split<true>, g, b, 0, stream, A);
     else if (split) hipLaunchKernelGGL(push_deposit_split<false>, g, b, 0, stream, A);
-    else if (kick == kVay && sh) hipLaunchKernelGGL((push_deposit_f64<true, kVay>), g, b, 0, stream, A);
-    else if (kick == kVay) hipLaunchKernelGGL((push_deposit_f64<false, kVay>), g, b, 0, stream, A);
-    else if (sh) hipLaunchKernelGGL((push_deposit_f64<true, kBoris>), g, b, 0, stream, A);
-    else hipLaunchKernelGGL((push_deposit_f64<false, kBoris>), g, b, 0, stream, A);
+    else if (kick == kVay && sh) hipLaunchKernelGGL((push_deposit_f64<true, kVay, 1>), g, b, 0, stream, A);
+    else if (kick == kVay) hipLaunchKernelGGL((push_deposit_f64<false, kVay, 1>), g, b, 0, stream, A);
+    else if (sh) hipLaunchKernelGGL((push_deposit_f64<true, kBoris, 1>), g, b, 0, stream, A);
+    else hipLaunchKernelGGL((push_deposit_f64<false, kBoris, 1>), g, b, 0, stream, A);
     return hipGetLastError();
 }
 
@@ -676,9 +734,11 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     return hipGetLastError();
 }
 
-hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream) {
+hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream, int order) {
     if (A.n <= 0) return hipSuccess;
-    if (split) hipLaunchKernelGGL(charge_kernel<float>, blocks_for(A.n), dim3(256), 0, stream, A, Q);
+    if (order == 3 && split) hipLaunchKernelGGL(charge3_kernel<float>, blocks_for(A.n), dim3(256), 0, stream, A, Q);
+    else if (order == 3) hipLaunchKernelGGL(charge3_kernel<double>, blocks_for(A.n), dim3(256), 0, stream, A, Q);
+    else if (split) hipLaunchKernelGGL(charge_kernel<float>, blocks_for(A.n), dim3(256), 0, stream, A, Q);
     else hipLaunchKernelGGL(charge_kernel<double>, blocks_for(A.n), dim3(256), 0, stream, A, Q);
     return hipGetLastError();
 }

@@ -67,7 +67,8 @@ class grpic_field_state(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
 
 
-EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
+EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_spline3", "grpic_charge3",
+            "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
             "grpic_field_tables_bytes", "grpic_field_workspace_bytes", "grpic_field_tables", "grpic_field_step")
@@ -102,6 +103,10 @@ def lib():
         L.grpic_push_deposit.restype = ctypes.c_int
         L.grpic_push_deposit_vay.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
         L.grpic_push_deposit_vay.restype = ctypes.c_int
+        L.grpic_push_deposit_spline3.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, vp]
+        L.grpic_push_deposit_spline3.restype = ctypes.c_int
+        L.grpic_charge3.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.grpic_charge3.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge.restype = ctypes.c_int
         L.grpic_sort_workspace_bytes.argtypes = [vp, i64]
@@ -222,11 +227,18 @@ def _nbytes(t: torch.Tensor | None) -> int:
 def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float,
                        nsteps: int, ncorr: int = 3, tiling: torch.Tensor | None = None,
                        ckpt: torch.Tensor | None = None, ckpt_every: int = 0,
-                       counters: torch.Tensor | None = None, stream=None, kick: str = "boris") -> None:
+                       counters: torch.Tensor | None = None, stream=None, kick: str = "boris",
+                       order: int = 1) -> None:
     """kick: "boris" (grpic_push_deposit) or "vay" (grpic_push_deposit_vay:
-    FP64 particles, no checkpoints)."""
+    FP64 particles, no checkpoints).  order: 1 (CIC) or 3 (the cubic spline
+    shape, grpic_push_deposit_spline3: FP64, Boris kick, no tiling or
+    checkpoints, grid guard >= 3)."""
     if kick not in ("boris", "vay"):
         raise ValueError(f"kick: expected 'boris' or 'vay', got {kick!r}")
+    if order not in (1, 3):
+        raise ValueError(f"order: expected 1 or 3, got {order!r}")
+    if order == 3 and (kick != "boris" or tiling is not None or ckpt is not None):
+        raise ValueError("order=3 runs the Boris kick untiled and takes no checkpoints")
     if kick == "vay" and ckpt is not None:
         raise ValueError("kick='vay' takes no checkpoints (the adjoint differentiates the Boris kick)")
     g = make_grid(grid)
@@ -240,6 +252,11 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
     for t, name in ((tiling, "tiling"), (ckpt, "ckpt")):
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name}: expected a contiguous device tensor")
+    if order == 3:
+        _check(lib().grpic_push_deposit_spline3(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
+                                                ctypes.byref(P), ctypes.byref(F), ctypes.byref(C), float(dt),
+                                                int(nsteps), int(ncorr), _ptr(counters), _stream(stream)))
+        return
     if kick == "vay":
         _check(lib().grpic_push_deposit_vay(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
                                             ctypes.byref(P), ctypes.byref(F), ctypes.byref(C), _ptr(tiling),
@@ -291,12 +308,17 @@ def grpic_push_deposit_backward(metric: grpic_metric, grid, species, parts: dict
                                              ctypes.byref(GFg), _stream(stream)))
 
 
-def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None) -> None:
+def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None, order: int = 1) -> None:
+    """Q += the charge at the vertices with the CIC (order 1) or the cubic
+    spline shape (order 3, grpic_charge3)."""
+    if order not in (1, 3):
+        raise ValueError(f"order: expected 1 or 3, got {order!r}")
     g = make_grid(grid)
     sp = make_species(species)
     P = make_particles(parts)
     _need(Q, torch.float64, _grid_numel(grid), "Q")
-    _check(lib().grpic_charge(ctypes.byref(g), sp, len(species), ctypes.byref(P), Q.data_ptr(), _stream(stream)))
+    fn = lib().grpic_charge3 if order == 3 else lib().grpic_charge
+    _check(fn(ctypes.byref(g), sp, len(species), ctypes.byref(P), Q.data_ptr(), _stream(stream)))
 
 
 def grpic_sort_workspace_bytes(grid, n: int) -> int:

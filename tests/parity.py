@@ -35,7 +35,7 @@ from paper_2503_04558_amd import workload as wl
 
 
 def gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, precision=grpic.GRPIC_FP64,
-            J0=None, tiled=False, kick="boris"):
+            J0=None, tiled=False, kick="boris", order=1):
     """Push on the GPU.  tiled: sort on the GPU first (grpic_sort with a
     tiling; phi carries each particle's index through the sort) and push with
     the tiling; the result is returned in the input order."""
@@ -61,7 +61,7 @@ def gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, precision=g
         parts = {k: v for k, v in parts.items() if k != "phi"}
         tiling = sorter.tiling
     grpic.grpic_push_deposit(grpic.make_metric(grid.a, grid.M), grid, species, parts, F, J, dt, nsteps,
-                             ncorr, tiling=tiling, counters=counters, kick=kick)
+                             ncorr, tiling=tiling, counters=counters, kick=kick, order=order)
     torch.cuda.synchronize()
     cnt = dict(zip(grpic.COUNTER_NAMES, counters.cpu().numpy().tolist()))
     out = grpic.to_host(parts)
@@ -91,13 +91,15 @@ def perturbed(parts_np, seed=20250306):
     return q
 
 
-def oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, sensitivity=True, kick="boris"):
+def oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=3, sensitivity=True, kick="boris", order=1):
     """Oracle result (p, J, A, stats) and, with sensitivity, the oracle on
     the perturbed particles (p, J)."""
-    p, J, A, st = orc.run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=ncorr, with_abs=True, kick=kick)
+    p, J, A, st = orc.run(grid, species, parts_np, fields_np, dt, nsteps, ncorr=ncorr, with_abs=True, kick=kick,
+                          order=order)
     pert = None
     if sensitivity:
-        pp, Jp, _, _ = orc.run(grid, species, perturbed(parts_np), fields_np, dt, nsteps, ncorr=ncorr, kick=kick)
+        pp, Jp, _, _ = orc.run(grid, species, perturbed(parts_np), fields_np, dt, nsteps, ncorr=ncorr, kick=kick,
+                               order=order)
         pert = (pp, Jp)
     return p, J, A, st, pert
 
@@ -156,12 +158,12 @@ def compare_current(Jg, Jo, Ao, tol, Jp=None):
 
 
 def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, ncorr=3, tiled=False,
-                  max_ill_fraction=1e-3, kick="boris"):
+                  max_ill_fraction=1e-3, kick="boris", order=1):
     """max_ill_fraction bounds the share of ill-conditioned particles, a
     property of the oracle runs alone (0.1 % for representative workloads;
     stress tests that place every particle at the axis set their own)."""
-    pg, Jg, cg = gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, tiled=tiled, kick=kick)
-    po, Jo, Ao, so, pert = oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, kick=kick)
+    pg, Jg, cg = gpu_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, tiled=tiled, kick=kick, order=order)
+    po, Jo, Ao, so, pert = oracle_run(grid, species, parts_np, fields_np, dt, nsteps, ncorr, kick=kick, order=order)
     e = compare_particles(grid, pg, po, tol, pert)
     assert e["status_mismatch"] == 0, e
     assert e["violations"] == 0, e

@@ -242,3 +242,30 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(grpic, "LIB_PATH", str(tmp_path / "libgrpic.so"))
     with pytest.raises(RuntimeError, match="not built"):
         grpic.lib()
+
+
+def test_spline3_entry_validation():
+    """grpic_push_deposit_spline3 and grpic_charge3: FP64 only, guard >= 3,
+    nth >= 4; every call here returns before any launch."""
+    L = grpic.lib()
+    m = grpic.make_metric(0.9, 1.0)
+    sp = grpic.make_species(wl.species_table())
+    g3 = wl.make_grid(32, 32, 0.9, guard=3)
+    parts, fields, cur = _fake_args(g3)
+    dt = wl.crossing_dt(g3)
+
+    def call(grid, parts, dt):
+        G = grpic.make_grid(grid)
+        return L.grpic_push_deposit_spline3(ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts),
+                                            ctypes.byref(fields), ctypes.byref(cur), dt, 1, 3, None, None)
+
+    assert call(wl.make_grid(32, 32, 0.9), parts, dt) == grpic.GRPIC_EINVAL        # guard 2
+    assert b"guard" in L.grpic_last_error()
+    assert call(wl.make_grid(32, 3, 0.9, guard=3), parts, dt) == grpic.GRPIC_EINVAL  # nth 3
+    split = grpic.grpic_particles(10, *([0x1000] * 8), None, grpic.GRPIC_FP32_SPLIT, 0)
+    assert call(g3, split, dt) == grpic.GRPIC_EINVAL
+    assert call(g3, parts, 2.01 * dt) == grpic.GRPIC_ERANGE
+    empty = grpic.grpic_particles(0, *([None] * 9), grpic.GRPIC_FP64, 0)
+    assert call(g3, empty, dt) == grpic.GRPIC_OK
+    G2 = grpic.make_grid(wl.make_grid(16, 16, 0.5))
+    assert L.grpic_charge3(ctypes.byref(G2), sp, 2, ctypes.byref(parts), 0x1000, None) == grpic.GRPIC_EINVAL
