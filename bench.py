@@ -402,6 +402,46 @@ def run_pic(args):
     print(json.dumps(out), flush=True)
 
 
+def run_spline3(args) -> dict:
+    """The third-order (cubic spline) shape against CIC, both untiled (the
+    cubic path has no tiled kernel yet): 2 * spline_pairs e+- of the
+    throughput recipe on the 2048^2 grid with guard 3, generator order, the
+    same particles and fields for both; 1 warm-up and args.spline_steps
+    timed steps each, HIP events on the launch stream."""
+    import torch
+
+    from paper_2503_04558_amd import grpic
+    from paper_2503_04558_amd import workload as wl
+
+    g = wl.make_grid(args.nr, args.nth, args.spin, guard=3)
+    host = wl.pairs(g, args.spline_pairs, kind="mj", seed=0, params=dict(T=0.1, vphi=0.1), workers=args.workers)
+    F = [torch.as_tensor(f).cuda() for f in wl.wald_fields(g, B0=1.0)]
+    sp = wl.species_table()
+    metric = grpic.make_metric(g.a, g.M)
+    dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+    out = {}
+    for order in (3, 1):
+        parts = grpic.to_device(host)
+        J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
+        grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, 1, args.ncorr, order=order)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, args.spline_steps, args.ncorr, counters=counters,
+                                 order=order)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.spline_steps
+        live = counters.cpu().tolist()[grpic.COUNTER_NAMES.index("live_steps")] / args.spline_steps
+        out[order] = dict(ms_per_step=ms, value=live / (ms * 1e-3))
+        del parts, J
+    log(f"spline3: {out[3]['ms_per_step']:.2f} ms/step untiled (CIC untiled {out[1]['ms_per_step']:.2f})")
+    return {"value": out[3]["value"], "unit": "particle-steps/s", "dtype": "f64", "ms_per_step": out[3]["ms_per_step"],
+            "kernel": "push_deposit_f64_spline3 (untiled)", "particles": 2 * args.spline_pairs,
+            "cic_untiled_same_particles": out[1], "vs_cic_untiled": out[3]["value"] / out[1]["value"]}
+
+
 def copy_ceiling_gbs(gib: int = 4, reps: int = 5) -> dict:
     """A STREAM ceiling measured on this GPU over a gib-GiB FP64 array (read +
     write counted): the runtime's device-to-device copy, and STREAM's scale
@@ -481,6 +521,9 @@ def main():
     ap.add_argument("--adj-pairs", type=int, default=500_000)
     ap.add_argument("--no-fields", action="store_true", help="skip the field-solver timing")
     ap.add_argument("--no-vay", action="store_true", help="skip the timing of the push with Vay's kick")
+    ap.add_argument("--no-spline3", action="store_true", help="skip the timing of the cubic spline shape")
+    ap.add_argument("--spline-pairs", type=int, default=10_000_000)
+    ap.add_argument("--spline-steps", type=int, default=5)
     ap.add_argument("--field-steps", type=int, default=10)
     ap.add_argument("--field-ncorr", type=int, default=7)
     ap.add_argument("--field-w1", type=float, default=0.53)
@@ -539,6 +582,7 @@ def main():
         rv = run_gpu(args, g, F, vay_parts, grpic.GRPIC_FP64, kick="vay")
     del vay_parts
     fld = None if args.no_fields else run_fields(args, g, F)
+    sp3 = None if args.no_spline3 else run_spline3(args)
     copy_ceiling = copy_ceiling_gbs()
     log(f"STREAM ceiling: copy {copy_ceiling['copy_gbs']} GB/s, scale {copy_ceiling['scale_gbs']} GB/s")
     adj = None if args.no_adjoint else run_adjoint(args)
@@ -603,6 +647,8 @@ def main():
                        "min_ms": float(np.min(rv["push_ms"])), "traffic": traffic.get("vay")},
             "counters": rv["counters"],
         }
+    if sp3 is not None:
+        out["spline3"] = sp3
     if adj is not None:
         out["adjoint"] = adj
     if fld is not None:
