@@ -209,14 +209,16 @@ int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
  * vertex (F^r, G^ph, values kept) or theta face (F^th, sign changed), by
  * axisymmetry, so discrete charge continuity holds at every vertex with the
  * cubic charge of grpic_charge3.  Generalised Boris kick, FP64 particles,
- * no tiling (one thread per particle, global atomics), no checkpoints;
- * grid->guard >= 3 (the window's radial reach), nth >= 4; otherwise
+ * no checkpoints; grid->guard >= 3 (the window's radial reach), nth >= 4.
+ * tiling: NULL (one thread per particle, global atomics) or a grpic_sort
+ * tiling as in grpic_push_deposit (the LDS window holds the folded 5 x 5
+ * windows; moves outside it deposit to global memory).  Otherwise
  * arguments, errors and counters as in grpic_push_deposit.
  */
 int grpic_push_deposit_spline3(const grpic_metric* metric, const grpic_grid* grid,
                                const grpic_species* species, int nsp,
                                grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                               double dt, int nsteps, int ncorr, int64_t* counters, void* stream);
+                               void* tiling, double dt, int nsteps, int ncorr, int64_t* counters, void* stream);
 
 /*
  * grpic_charge3 -- grpic_charge with the cubic spline shape, folded across

@@ -272,7 +272,7 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
             if ((rc = hip_status(grpic::launch_save_state(A, dst, s), "checkpoint launch"))) return rc;
         }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
-        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick)
+        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick, order)
                                     : grpic::launch_push_deposit(A, split, s, kick, order);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }
@@ -292,13 +292,13 @@ int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
 int grpic_push_deposit_spline3(const grpic_metric* metric, const grpic_grid* grid,
                                const grpic_species* species, int nsp,
                                grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
-                               double dt, int nsteps, int ncorr, int64_t* counters, void* stream) {
+                               void* tiling, double dt, int nsteps, int ncorr, int64_t* counters, void* stream) {
     if (parts && parts->precision != GRPIC_FP64)
         return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: GRPIC_FP64 particles only");
     if (grid && grid->guard < 3) return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: the cubic shape needs guard >= 3");
     if (grid && grid->nth < 4)     // the folded 5 x 5 window stays inside columns 0 .. nth
         return fail(GRPIC_EINVAL, "grpic_push_deposit_spline3: nth must be >= 4");
-    return push_deposit(metric, grid, species, nsp, parts, fields, J, nullptr, dt, nsteps, ncorr, nullptr, 0, 0,
+    return push_deposit(metric, grid, species, nsp, parts, fields, J, tiling, dt, nsteps, ncorr, nullptr, 0, 0,
                         counters, stream, grpic::kBoris, 3);
 }
 

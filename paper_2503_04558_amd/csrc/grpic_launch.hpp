@@ -75,10 +75,10 @@ inline double* tiling_anchors(void* tiling, int64_t slice_cap) {
 
 // ---------------------------------------------------------------- launchers
 // kick: kBoris (the generalised Boris kick) or kVay (FP64 only).  order:
-// the shape, 1 (CIC) or 3 (cubic spline: FP64, Boris kick, untiled only).
+// the shape, 1 (CIC) or 3 (cubic spline: FP64, Boris kick).
 hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick = kBoris, int order = 1);
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream, int kick = kBoris);
+                                     hipStream_t stream, int kick = kBoris, int order = 1);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream, int order = 1);
 
 struct SortArgs {

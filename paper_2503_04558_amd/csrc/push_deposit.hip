@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) {
     push_deposit_body<true, SHORT, kBoris>(A);
 }
 
-template <bool SPLIT, bool SHORT, int KICK>
+template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const Slice* __restrict__ slices,
                                                         int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live,
@@ -520,23 +520,48 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (mine) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT, KICK>(A, pi, in, mv, ev, &tab, out);
+        const bool dep = advance<SPLIT, SHORT, KICK, ORDER>(A, pi, in, mv, ev, &tab, out);
         const int si = slot + slot / 32;
         st_kind[si] = out.kind;
         st_cell[si] = out.cell;
         for (int k = 0; k < 5; ++k) st_x[k][si] = out.x[k];
         if (dep) {
-            const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
-            if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
-                esirkepov(mv, A.dt,
-                          [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
-                row_lo = li;
-                row_hi = li + 2;
-                col_lo = lj;
-                col_hi = lj + 2;
+            if constexpr (ORDER == 3) {
+                // the cubic window: rows i3 .. i3 + 4, columns j3 .. j3 + 4
+                // folded across the axes (vertex and face columns)
+                const int i3 = (int)floor(fmin(mv.xi0, mv.xi1)) - 1, j3 = (int)floor(fmin(mv.eta0, mv.eta1)) - 1;
+                int jlo = kWinCols + wj0, jhi = wj0 - 1;
+                for (int b = 0; b < 5; ++b) {
+                    double sg;
+                    const int jv = fold_vertex(j3 + b, A.nth), jf = fold_face(j3 + b, A.nth, sg);
+                    jlo = min(jlo, min(jv, jf));
+                    jhi = max(jhi, max(jv, jf));
+                }
+                const int li = i3 - wi0, ljl = jlo - wj0, ljh = jhi - wj0;
+                if (li >= 0 && li + 4 < kWinRows && ljl >= 0 && ljh < kWinCols) {
+                    esirkepov3(mv, A.dt, A.nth,
+                               [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
+                    row_lo = li;
+                    row_hi = li + 4;
+                    col_lo = ljl;
+                    col_hi = ljh;
+                } else {
+                    scatter_global<3>(A, mv);            // drifted out of the window
+                    ev.spill = 1;
+                }
             } else {
-                scatter_global(A, mv);                   // drifted out of the window
-                ev.spill = 1;
+                const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
+                if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
+                    esirkepov(mv, A.dt,
+                              [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
+                    row_lo = li;
+                    row_hi = li + 2;
+                    col_lo = lj;
+                    col_hi = lj + 2;
+                } else {
+                    scatter_global(A, mv);               // drifted out of the window
+                    ev.spill = 1;
+                }
             }
         }
     }
@@ -617,6 +642,15 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3)
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap,
     int32_t* slice_live, const double* anchors) {
     push_deposit_tiled_body<false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
+}
+// The cubic shape's tiled kernel: no waves per SIMD target (its register
+// set does not fit the FP64 CIC kernel's).
+template <bool SHORT>
+__global__ __launch_bounds__(kPushThreads) void push_deposit_f64_tiled_spline3(const StepArgs A,
+                                                                               const Slice* __restrict__ slices,
+                                                                               int64_t slice_cap, int32_t* slice_live,
+                                                                               const double* anchors) {
+    push_deposit_tiled_body<false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);
 }
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
@@ -700,7 +734,7 @@ hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream
 }
 
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream, int kick) {
+                                     hipStream_t stream, int kick, int order) {
     if (A.n <= 0) return hipSuccess;
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
@@ -714,7 +748,12 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     const int64_t grid = (slice_cap + 7) / 8 * 8;
     const dim3 g((unsigned)grid), b(kPushThreads);
     const bool sh = A.small_steps == 2;
-    if (split && sh)
+    if (order == 3 && sh)                                // FP64, Boris kick (checked by the caller)
+        hipLaunchKernelGGL(push_deposit_f64_tiled_spline3<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
+    else if (order == 3)
+        hipLaunchKernelGGL(push_deposit_f64_tiled_spline3<false>, g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
+    else if (split && sh)
         hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
     else if (split)
         hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);

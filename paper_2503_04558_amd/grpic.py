@@ -103,7 +103,7 @@ def lib():
         L.grpic_push_deposit.restype = ctypes.c_int
         L.grpic_push_deposit_vay.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
         L.grpic_push_deposit_vay.restype = ctypes.c_int
-        L.grpic_push_deposit_spline3.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, vp]
+        L.grpic_push_deposit_spline3.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
         L.grpic_push_deposit_spline3.restype = ctypes.c_int
         L.grpic_charge3.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge3.restype = ctypes.c_int
@@ -231,14 +231,14 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
                        order: int = 1) -> None:
     """kick: "boris" (grpic_push_deposit) or "vay" (grpic_push_deposit_vay:
     FP64 particles, no checkpoints).  order: 1 (CIC) or 3 (the cubic spline
-    shape, grpic_push_deposit_spline3: FP64, Boris kick, no tiling or
-    checkpoints, grid guard >= 3)."""
+    shape, grpic_push_deposit_spline3: FP64, Boris kick, no checkpoints,
+    grid guard >= 3)."""
     if kick not in ("boris", "vay"):
         raise ValueError(f"kick: expected 'boris' or 'vay', got {kick!r}")
     if order not in (1, 3):
         raise ValueError(f"order: expected 1 or 3, got {order!r}")
-    if order == 3 and (kick != "boris" or tiling is not None or ckpt is not None):
-        raise ValueError("order=3 runs the Boris kick untiled and takes no checkpoints")
+    if order == 3 and (kick != "boris" or ckpt is not None):
+        raise ValueError("order=3 runs the Boris kick and takes no checkpoints")
     if kick == "vay" and ckpt is not None:
         raise ValueError("kick='vay' takes no checkpoints (the adjoint differentiates the Boris kick)")
     g = make_grid(grid)
@@ -254,8 +254,8 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
             raise ValueError(f"{name}: expected a contiguous device tensor")
     if order == 3:
         _check(lib().grpic_push_deposit_spline3(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
-                                                ctypes.byref(P), ctypes.byref(F), ctypes.byref(C), float(dt),
-                                                int(nsteps), int(ncorr), _ptr(counters), _stream(stream)))
+                                                ctypes.byref(P), ctypes.byref(F), ctypes.byref(C), _ptr(tiling),
+                                                float(dt), int(nsteps), int(ncorr), _ptr(counters), _stream(stream)))
         return
     if kick == "vay":
         _check(lib().grpic_push_deposit_vay(ctypes.byref(metric), ctypes.byref(g), sp, len(species),

@@ -257,7 +257,7 @@ def test_spline3_entry_validation():
     def call(grid, parts, dt):
         G = grpic.make_grid(grid)
         return L.grpic_push_deposit_spline3(ctypes.byref(m), ctypes.byref(G), sp, 2, ctypes.byref(parts),
-                                            ctypes.byref(fields), ctypes.byref(cur), dt, 1, 3, None, None)
+                                            ctypes.byref(fields), ctypes.byref(cur), None, dt, 1, 3, None, None)
 
     assert call(wl.make_grid(32, 32, 0.9), parts, dt) == grpic.GRPIC_EINVAL        # guard 2
     assert b"guard" in L.grpic_last_error()

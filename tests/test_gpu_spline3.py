@@ -1,6 +1,6 @@
 """GPU parity of the push + deposit with the third-order (cubic B-spline)
-shape (grpic_push_deposit_spline3 through the C ABI) against the oracle run
-with order=3, element by element at the FP64 bar and norms of
+shape (grpic_push_deposit_spline3 through the C ABI, untiled and tiled)
+against the oracle run with order=3, element by element at the FP64 bar and norms of
 tests/parity.py; the cubic charge (grpic_charge3) against the oracle's; and
 per-vertex continuity on the GPU's own outputs, including moves whose
 windows fold across the axes."""
@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 EPS = np.finfo(np.float64).eps
+TILED = [pytest.param(False, id="untiled"), pytest.param(True, id="tiled")]
 
 
 def _announce(msg):
@@ -40,35 +41,41 @@ def _axis_parts(g, n, seed):
                 ur=ur, uth=uth, uph=uph, w=rng.uniform(0.5, 2.0, n), sp=rng.integers(0, 2, n).astype(np.uint8))
 
 
-def test_spline3_parity_wald_config():
+@pytest.mark.parametrize("tiled", TILED)
+def test_spline3_parity_wald_config(tiled):
     """128^2, a = 0.99, guard 3, 2e4 e+- (|u| uniform in [0, 1]), Wald B0 = 1
-    (columns beyond the axes from the analytic field), 10 steps."""
-    _announce("spline3 parity 128x128 2e4 particles 10 steps")
+    (columns beyond the axes from the analytic field), 10 steps; untiled,
+    and through the GPU sort and the tiled kernel's LDS window."""
+    _announce(f"spline3 parity 128x128 2e4 particles 10 steps tiled={tiled}")
     g = wl.make_grid(128, 128, 0.99, guard=3)
     parts = wl.pairs(g, 10_000, kind="uniform", seed=0)
-    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 10, TOL, order=3)
+    e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 10, TOL, order=3,
+                         tiled=tiled)
     _announce(f"errors {e} counters {c}")
     assert c["out"] > 0 and c["reflected"] > 0
 
 
-def test_spline3_parity_axis_and_edges():
+@pytest.mark.parametrize("tiled", TILED)
+def test_spline3_parity_axis_and_edges(tiled):
     """Every particle within two cells of an axis (its 5 x 5 window folds)
     or at a radial edge, driven into it; 6 steps."""
-    _announce("spline3 parity axis/edges")
+    _announce(f"spline3 parity axis/edges tiled={tiled}")
     g = wl.make_grid(24, 24, 0.99, guard=3)
     parts = _axis_parts(g, 4000, 5)
     e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=2.0), wl.crossing_dt(g), 6, TOL,
-                         max_ill_fraction=1e-2, order=3)
+                         max_ill_fraction=1e-2, order=3, tiled=tiled)
     assert c["reflected"] > 20 and c["out"] > 100
 
 
+@pytest.mark.parametrize("tiled", TILED)
 @pytest.mark.parametrize("n", [1, 65, 1001])
-def test_spline3_parity_ragged(n):
-    _announce(f"spline3 parity ragged n={n}")
+def test_spline3_parity_ragged(n, tiled):
+    _announce(f"spline3 parity ragged n={n} tiled={tiled}")
     g = wl.make_grid(40, 100, 0.9, guard=3)
     parts = wl.pairs(g, (n + 1) // 2, kind="mj", seed=n, params=dict(T=0.5))
     parts = {k: v[:n] for k, v in parts.items()}
-    assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=3.0), wl.crossing_dt(g), 5, TOL, order=3)
+    assert_parity(g, wl.species_table(), parts, wl.wald_fields(g, B0=3.0), wl.crossing_dt(g), 5, TOL, order=3,
+                  tiled=tiled)
 
 
 def test_spline3_charge_and_continuity_on_gpu():
