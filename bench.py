@@ -403,11 +403,11 @@ def run_pic(args):
 
 
 def run_spline3(args) -> dict:
-    """The third-order (cubic spline) shape against CIC, both untiled (the
-    cubic path has no tiled kernel yet): 2 * spline_pairs e+- of the
-    throughput recipe on the 2048^2 grid with guard 3, generator order, the
-    same particles and fields for both; 1 warm-up and args.spline_steps
-    timed steps each, HIP events on the launch stream."""
+    """The third-order (cubic spline) shape against CIC on the same
+    particles and fields: 2 * spline_pairs e+- of the throughput recipe on
+    the 2048^2 grid with guard 3, untiled (generator order) and tiled (after
+    a GPU sort); 1 warm-up and args.spline_steps timed steps each, HIP
+    events on the launch stream."""
     import torch
 
     from paper_2503_04558_amd import grpic
@@ -419,27 +419,36 @@ def run_spline3(args) -> dict:
     sp = wl.species_table()
     metric = grpic.make_metric(g.a, g.M)
     dt = 0.5 * grpic.grpic_crossing_time(metric, g)
+    n = 2 * args.spline_pairs
     out = {}
-    for order in (3, 1):
-        parts = grpic.to_device(host)
-        J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
-        counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
-        grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, 1, args.ncorr, order=order)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, args.spline_steps, args.ncorr, counters=counters,
-                                 order=order)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.spline_steps
-        live = counters.cpu().tolist()[grpic.COUNTER_NAMES.index("live_steps")] / args.spline_steps
-        out[order] = dict(ms_per_step=ms, value=live / (ms * 1e-3))
-        del parts, J
-    log(f"spline3: {out[3]['ms_per_step']:.2f} ms/step untiled (CIC untiled {out[1]['ms_per_step']:.2f})")
-    return {"value": out[3]["value"], "unit": "particle-steps/s", "dtype": "f64", "ms_per_step": out[3]["ms_per_step"],
-            "kernel": "push_deposit_f64_spline3 (untiled)", "particles": 2 * args.spline_pairs,
-            "cic_untiled_same_particles": out[1], "vs_cic_untiled": out[3]["value"] / out[1]["value"]}
+    for tiled in (False, True):
+        for order in (3, 1):
+            parts = grpic.to_device(host)
+            tiling = None
+            if tiled:
+                sorter = grpic.Sorter(g, n, grpic.GRPIC_FP64)
+                parts = sorter.sort(parts)
+                tiling = sorter.tiling
+            J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+            counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
+            grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, 1, args.ncorr, tiling=tiling, order=order)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            grpic.grpic_push_deposit(metric, g, sp, parts, F, J, dt, args.spline_steps, args.ncorr, tiling=tiling,
+                                     counters=counters, order=order)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.spline_steps
+            live = counters.cpu().tolist()[grpic.COUNTER_NAMES.index("live_steps")] / args.spline_steps
+            out[(tiled, order)] = dict(ms_per_step=ms, value=live / (ms * 1e-3))
+            del parts, J
+    log(f"spline3: tiled {out[(True, 3)]['ms_per_step']:.2f} ms/step (CIC tiled {out[(True, 1)]['ms_per_step']:.2f}), "
+        f"untiled {out[(False, 3)]['ms_per_step']:.2f} (CIC untiled {out[(False, 1)]['ms_per_step']:.2f})")
+    t3, t1 = out[(True, 3)], out[(True, 1)]
+    return {"value": t3["value"], "unit": "particle-steps/s", "dtype": "f64", "ms_per_step": t3["ms_per_step"],
+            "kernel": "push_deposit_f64_tiled_spline3", "particles": n, "vs_cic_tiled": t3["value"] / t1["value"],
+            "cic_tiled_same_particles": t1, "untiled": out[(False, 3)], "cic_untiled_same_particles": out[(False, 1)]}
 
 
 def copy_ceiling_gbs(gib: int = 4, reps: int = 5) -> dict:
