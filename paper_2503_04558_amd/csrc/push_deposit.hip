@@ -369,7 +369,7 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 // SHORT: the short Taylor series, for grids fine enough for them
 // (small_steps == 2); the launch picks the kernel variant.
 // KICK: the momentum kick (kBoris, or kVay for the FP64 path only).
-// ORDER: the shape, 1 (CIC) or 3 (cubic spline, FP64 untiled only).
+// ORDER: the shape, 1 (CIC) or 3 (cubic spline, FP64 only).
 template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
 __device__ __forceinline__ bool advance(const StepArgs& A, const PIdx& p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
