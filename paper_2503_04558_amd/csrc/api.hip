@@ -170,26 +170,57 @@ struct FieldTablesInfo {
 std::mutex g_ftab_mu;
 std::map<const void*, FieldTablesInfo> g_ftabs;
 
-// 10-point Gauss-Legendre nodes and weights on [-1, 1] (Newton's method on
-// P_10 from the Chebyshev guesses; w = 2 / ((1 - x^2) P_10'(x)^2)).
+// 10-point Gauss-Legendre nodes and weights on [-1, 1] by the Golub-Welsch
+// method: the nodes are the eigenvalues of the symmetric tridiagonal Jacobi
+// matrix of the Legendre recurrence (zero diagonal, off-diagonal
+// k / sqrt(4 k^2 - 1), k = 1 .. 9), and each weight is 2 (the integral of 1)
+// times the squared first component of its unit eigenvector.  The
+// eigenproblem is solved by cyclic Jacobi rotations, which keep the
+// eigenvectors orthonormal to rounding.
 void gauss_legendre10(double* x, double* w) {
     const int n = 10;
-    for (int k = 0; k < n; ++k) {
-        double z = cos(M_PI * (k + 0.75) / (n + 0.5)), dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;
-            for (int m = 2; m <= n; ++m) {
-                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
-                p0 = p1;
-                p1 = p2;
+    double A[n][n] = {}, V[n][n] = {};
+    for (int k = 1; k < n; ++k) A[k - 1][k] = A[k][k - 1] = k / sqrt(4.0 * k * k - 1.0);
+    for (int i = 0; i < n; ++i) V[i][i] = 1.0;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[p][q] * A[p][q];
+        if (off < 1e-60) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                if (A[p][q] == 0.0) continue;
+                // rotation angle that zeroes A[p][q]: t = tan(angle)
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {          // A <- A R (columns p, q)
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {          // A <- R^T A (rows p, q)
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {          // V <- V R
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
             }
-            dp = n * (z * p1 - p0) / (z * z - 1.0);
-            const double step = p1 / dp;
-            z -= step;
-            if (fabs(step) < 1e-16) break;
-        }
-        x[k] = z;
-        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    // eigenpairs in ascending node order
+    int order[n];
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order, order + n, [&](int a, int b) { return A[a][a] < A[b][b]; });
+    for (int i = 0; i < n; ++i) {
+        const int e = order[i];
+        double norm = 0.0;
+        for (int k = 0; k < n; ++k) norm += V[k][e] * V[k][e];
+        x[i] = A[e][e];
+        w[i] = 2.0 * V[0][e] * V[0][e] / norm;
     }
 }
 

@@ -22,7 +22,9 @@ resulting change per particle (same norms) is that particle's rounding
 sensitivity s_p.  A particle passes if err_p <= tol + SENS_FACTOR * s_p, and a
 current element if |dF| <= tol * A_F + SENS_FACTOR * |dF_perturbed|.  For a
 well-conditioned particle s_p is ~1e-15 and the bar is tol.  The number of
-particles with s_p > tol is reported and must stay below 0.1 %.
+particles with s_p > tol is reported and must stay below 0.1 %.  So is the
+number of particles and current elements that pass only through this clause
+(err_p > tol): the bulk workloads require none.
 """
 from __future__ import annotations
 
@@ -139,22 +141,29 @@ def compare_particles(grid, pg, po, tol, pert=None):
         sens = particle_errors(grid, pp, po)
         status_ok |= (pp["cell"] >= 0) != alive_o          # status itself is sensitive there
     bad = err > tol + SENS_FACTOR * sens
+    clause = (err > tol) & ~bad             # passed only through the sensitivity clause
     return dict(status_mismatch=int(np.count_nonzero(~status_ok)), violations=int(np.count_nonzero(bad)),
+                clause_particles=int(np.count_nonzero(clause)),
                 err=float(err.max(initial=0.0)), well_conditioned_err=float(err[sens <= tol].max(initial=0.0)),
                 ill_conditioned=int(np.count_nonzero(sens > tol)), n_alive=int((alive_g & alive_o).sum()),
                 n=len(err))
 
 
-def compare_current(Jg, Jo, Ao, tol, Jp=None):
+def compare_current(Jg, Jo, Ao, tol, Jp=None, clause=False):
+    """(worst, violations) or, with clause, (worst, violations, number of
+    elements that pass only through the sensitivity clause)."""
     worst = 0.0
     bad = 0
+    only = 0
     for i, (g, o, a) in enumerate(zip(Jg, Jo, Ao)):
         spread = np.abs(Jp[i] - o) if Jp is not None else 0.0
         d = np.abs(g - o)
         scale = max(np.abs(a).max(), 1e-300)
         worst = max(worst, float(np.max(np.maximum(d - SENS_FACTOR * spread, 0.0)) / scale))
-        bad += int(np.count_nonzero(d > tol * a + SENS_FACTOR * spread))
-    return worst, bad
+        viol = d > tol * a + SENS_FACTOR * spread
+        bad += int(np.count_nonzero(viol))
+        only += int(np.count_nonzero((d > tol * a) & ~viol))
+    return (worst, bad, only) if clause else (worst, bad)
 
 
 def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, ncorr=3, tiled=False,
@@ -169,7 +178,9 @@ def assert_parity(grid, species, parts_np, fields_np, dt, nsteps, tol=1e-12, nco
     assert e["violations"] == 0, e
     assert e["well_conditioned_err"] <= tol, e
     assert e["ill_conditioned"] <= max(2, max_ill_fraction * e["n"]), e
-    e["J"], e["J_violations"] = compare_current(Jg, Jo, Ao, tol, pert[1])
+    e["J"], e["J_violations"], e["clause_J"] = compare_current(Jg, Jo, Ao, tol, pert[1], clause=True)
+    print(f"[gpu] parity: {e['clause_particles']} particles and {e['clause_J']} current elements pass only "
+          f"through the sensitivity clause; {e}", flush=True)
     assert e["J"] <= tol and e["J_violations"] == 0, e
     slack = e["ill_conditioned"]      # an ill-conditioned particle may reflect or leave in one run only
     if not tiled:       # the GPU sort drops particles removed before the push; the oracle counts them

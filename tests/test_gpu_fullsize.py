@@ -106,3 +106,4 @@ def test_full_size_sampled_parity_and_continuity():
     assert e["violations"] == 0, e
     assert e["well_conditioned_err"] <= TOL, e
     assert e["ill_conditioned"] <= max(2, 1e-3 * e["n"]), e
+    assert e["clause_particles"] == 0, e           # every sampled particle within 1e-12 itself

@@ -41,6 +41,7 @@ def test_parity_small_wald_config(tiled):
     e, c = assert_parity(g, wl.species_table(), parts, wl.wald_fields(g), wl.crossing_dt(g), 10, TOL, tiled=tiled)
     _announce(f"errors {e} counters {c}")
     assert c["out"] > 0 and c["reflected"] > 0     # both boundaries exercised
+    assert e["clause_particles"] == 0 and e["clause_J"] == 0, e     # every value within 1e-12 itself
 
 
 @pytest.mark.parametrize("tiled", TILED)
