@@ -679,6 +679,82 @@ bool valid_input(const Geom& g, int nsp, int32_t cell, double xr, double xth, ui
     return cell >= 0 && cell < g.nr * g.nth && xr >= 0.0 && xr <= 1.0 && xth >= 0.0 && xth <= 1.0 && s < nsp;
 }
 
+/* ------------------------------------------------------------------ */
+/* Photon emission and pair conversion (Sec. 4, the monopole spark-gap */
+/* application; eq. optical-depth).                                    */
+/*                                                                     */
+/* Readings (also in the design notes):                                */
+/*   - an e+- whose FIDO-frame Lorentz factor Gamma = sqrt(1 + u^2)     */
+/*     (u^2 = gamma^ij u_i u_j at the end point of its step) exceeds    */
+/*     gamma_thr emits one photon of FIDO energy eps_ph along its own   */
+/*     momentum, at its end point, with its weight; its momentum        */
+/*     magnitude drops by eps_ph (momentum conservation along the       */
+/*     common direction);                                              */
+/*   - a photon (FIDO energy eps = sqrt(gamma^ij u_i u_j)) converts     */
+/*     with probability P = 1 - exp(-tau dt) per step, drawn after its  */
+/*     push; the e- and e+ each get FIDO energy eps/2 along the        */
+/*     photon's direction, at its end point, with its weight, and the  */
+/*     photon is removed; photons below 2 m c^2 do not convert;        */
+/*   - particles created in a step are not pushed in that step, and    */
+/*     particles that left the grid in it neither emit nor convert;    */
+/*   - random numbers: Philox4x64-10 (Salmon et al. 2011) with counter */
+/*     (tag, step, 0, 0) and key (seed, 0): the first word gives the   */
+/*     uniform U = (x0 >> 11) 2^-53 of a photon's conversion, the      */
+/*     second the tag of an emitted photon or of the e-, the third     */
+/*     that of the e+.                                                  */
+/* ------------------------------------------------------------------ */
+struct Philox4x64 {
+    uint64_t x[4];
+};
+
+/* The high and low 64 bits of a * b. */
+inline void mul_hi_lo(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+    const unsigned __int128 p = (unsigned __int128)a * b;
+    hi = (uint64_t)(p >> 64);
+    lo = (uint64_t)p;
+}
+
+/* Ten rounds of the Philox 4x64 bijection of the counter under the key,
+ * the key advanced by the Weyl constants between rounds.                */
+Philox4x64 philox4x64_10(const uint64_t ctr[4], const uint64_t key[2]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_hi_lo(M0, x0, hi0, lo0);
+        mul_hi_lo(M1, x2, hi1, lo1);
+        const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    Philox4x64 r;
+    r.x[0] = x0; r.x[1] = x1; r.x[2] = x2; r.x[3] = x3;
+    return r;
+}
+
+struct Qed {
+    double gamma_thr, eps_ph, tau;
+    uint64_t seed;
+    int32_t electron_sp, positron_sp, photon_sp, pad;
+};
+
+/* gamma^ij u_i u_j at the grid point (xi, eta). */
+double u_squared(const Geom& g, double xi, double eta, const double u[3]) {
+    KS<double> k;
+    ks_metric(g.a, g.M, std::exp(g.lnr0 + xi * g.dlnr), eta * g.dth, k);
+    return k.h_rr * u[0] * u[0] + 2.0 * k.h_rp * u[0] * u[2] + k.h_tt * u[1] * u[1] + k.h_pp * u[2] * u[2];
+}
+
+struct Created {
+    int32_t cell;
+    double xr, xth, u[3], w;
+    uint8_t sp;
+    uint64_t tag;
+};
+
 }  // namespace
 
 /* ==================================================================== */
@@ -931,6 +1007,103 @@ void orc_count_ops(const Geom* g, const Species* sp, const double* const* F, dou
     esirkepov(sp->q * w, dt, cxi, ceta, y1[0], y1[1], y1[2], mv);
     const long v[7] = {g_ops.add, g_ops.mul, g_ops.div, g_ops.sqrt_, g_ops.exp_, g_ops.sin_, g_ops.cos_};
     for (int k = 0; k < 7; ++k) out[k] += v[k];
+}
+
+/* Philox4x64-10 of one counter under one key (for the pins). */
+void orc_philox(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+    const Philox4x64 r = philox4x64_10(ctr, key);
+    for (int k = 0; k < 4; ++k) out[k] = r.x[k];
+}
+
+/* One step of the monopole-workload particles: the push and deposit of
+ * orc_run (Boris kick for massive species, none for photons; serial,
+ * Neumaier-compensated J, optional scale arrays A), then photon emission
+ * by e+- above gamma_thr and pair conversion of photons (the readings
+ * above).  Particles are updated in place; created particles are appended
+ * to the c_* arrays (capacity cap, in particle order: an emitter's photon,
+ * a photon's e- then e+); *n_created receives their number (those beyond
+ * cap are dropped).  stats[4] (+=) as in orc_run; qstats[3] (+=): photons
+ * emitted, photons converted, created particles dropped.                */
+void orc_run_qed(const Geom* gp, const Species* sp, int nsp, int64_t n,
+                 int32_t* cell, double* xr, double* xth, double* ur, double* uth, double* uph,
+                 const double* w, uint8_t* spi, const uint64_t* tag,
+                 const double* const* F, double* Fr, double* Fth, double* Gph,
+                 double* Afr, double* Afth, double* Agph, double dt, int ncorr, int64_t step, const Qed* qed,
+                 int64_t cap, int32_t* c_cell, double* c_xr, double* c_xth, double* c_ur, double* c_uth,
+                 double* c_uph, double* c_w, uint8_t* c_sp, uint64_t* c_tag, int64_t* n_created,
+                 int64_t* stats, int64_t* qstats) {
+    const Geom& g = *gp;
+    const long ncell = (long)(g.nr + 1 + 2 * g.guard) * g.pitch;
+    std::vector<double> cr(ncell, 0.0), ct(ncell, 0.0), cp(ncell, 0.0);
+    Acc A_r{Fr, cr.data(), Afr}, A_t{Fth, ct.data(), Afth}, A_p{Gph, cp.data(), Agph};
+    const double P = 1.0 - std::exp(-qed->tau * dt);          /* eq. optical-depth */
+    int64_t st_out = 0, st_bad = 0, st_refl = 0, st_live = 0, emitted = 0, converted = 0, lost = 0, nc = 0;
+    auto append = [&](const Created& c) {
+        if (nc < cap) {
+            c_cell[nc] = c.cell; c_xr[nc] = c.xr; c_xth[nc] = c.xth;
+            c_ur[nc] = c.u[0]; c_uth[nc] = c.u[1]; c_uph[nc] = c.u[2];
+            c_w[nc] = c.w; c_sp[nc] = c.sp; c_tag[nc] = c.tag;
+            ++nc;
+        } else {
+            ++lost;
+        }
+    };
+    for (int64_t p = 0; p < n; ++p) {
+        const double u0[3] = {ur[p], uth[p], uph[p]};
+        if (cell[p] >= 0 && spi[p] >= nsp) { ++st_live; ++st_bad; cell[p] = -1; continue; }
+        const Outcome o = step_one(g, sp[spi[p]], F, w[p], dt, ncorr, cell[p], xr[p], xth[p], u0);
+        if (o.status == ST_DEAD) continue;
+        ++st_live;
+        if (o.status == ST_BAD) { ++st_bad; cell[p] = -1; continue; }
+        st_refl += o.reflected;
+        scatter_move(g, o.mv, A_r, A_t, A_p);
+        if (o.status == ST_OUT) { ++st_out; cell[p] = -1; continue; }
+        cell[p] = o.cell; xr[p] = o.xr; xth[p] = o.xth;
+        double u[3] = {o.u[0], o.u[1], o.u[2]};
+        const int s = spi[p];
+        const bool lepton = s == qed->electron_sp || s == qed->positron_sp;
+        const bool photon = s == qed->photon_sp;
+        if (lepton || photon) {
+            const double xi1 = (o.cell / g.nth) + o.xr, eta1 = (o.cell % g.nth) + o.xth;
+            const double uu = u_squared(g, xi1, eta1, u);
+            const uint64_t ctr[4] = {tag[p], (uint64_t)step, 0, 0}, key[2] = {qed->seed, 0};
+            if (lepton && std::sqrt(1.0 + uu) > qed->gamma_thr) {
+                const Philox4x64 rn = philox4x64_10(ctr, key);
+                const double umag = std::sqrt(uu);
+                Created ph;
+                ph.cell = o.cell; ph.xr = o.xr; ph.xth = o.xth; ph.w = w[p];
+                ph.sp = (uint8_t)qed->photon_sp; ph.tag = rn.x[1];
+                for (int c = 0; c < 3; ++c) ph.u[c] = u[c] * (qed->eps_ph / umag);
+                append(ph);
+                for (int c = 0; c < 3; ++c) u[c] = u[c] * ((umag - qed->eps_ph) / umag);
+                ++emitted;
+            } else if (photon) {
+                const Philox4x64 rn = philox4x64_10(ctr, key);
+                const double U = (double)(rn.x[0] >> 11) * (1.0 / 9007199254740992.0);
+                const double eps = std::sqrt(uu);
+                if (U < P && eps >= 2.0) {
+                    const double scale = std::sqrt(0.25 * eps * eps - 1.0) / eps;
+                    Created e[2];
+                    for (int k = 0; k < 2; ++k) {
+                        e[k].cell = o.cell; e[k].xr = o.xr; e[k].xth = o.xth; e[k].w = w[p];
+                        for (int c = 0; c < 3; ++c) e[k].u[c] = u[c] * scale;
+                    }
+                    e[0].sp = (uint8_t)qed->electron_sp; e[0].tag = rn.x[1];
+                    e[1].sp = (uint8_t)qed->positron_sp; e[1].tag = rn.x[2];
+                    append(e[0]);
+                    append(e[1]);
+                    cell[p] = -1;
+                    ++converted;
+                    continue;
+                }
+            }
+        }
+        ur[p] = u[0]; uth[p] = u[1]; uph[p] = u[2];
+    }
+    for (long e = 0; e < ncell; ++e) { Fr[e] += cr[e]; Fth[e] += ct[e]; Gph[e] += cp[e]; }
+    *n_created = nc;
+    if (stats) { stats[0] += st_out; stats[1] += st_bad; stats[2] += st_refl; stats[3] += st_live; }
+    if (qstats) { qstats[0] += emitted; qstats[1] += converted; qstats[2] += lost; }
 }
 
 int orc_has_openmp(void) {

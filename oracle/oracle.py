@@ -255,6 +255,70 @@ def run(grid, species, parts, fields, dt, nsteps, ncorr: int = 3, nthreads: int 
     return p, J, A, st
 
 
+def philox(counter, key) -> np.ndarray:
+    """Philox4x64-10 of one 4-word counter under a 2-word key (uint64)."""
+    c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+class Qed(ctypes.Structure):
+    _fields_ = [("gamma_thr", ctypes.c_double), ("eps_ph", ctypes.c_double), ("tau", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("electron_sp", ctypes.c_int32), ("positron_sp", ctypes.c_int32),
+                ("photon_sp", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+def run_qed(grid, species, parts, fields, dt, step, qed: dict, ncorr: int = 3, capacity=None, J=None):
+    """One step of photon emission and pair conversion around the push
+    (serial).  parts needs a uint64 "tag" array.  qed: gamma_thr, eps_ph,
+    tau, seed, electron_sp, positron_sp, photon_sp.  Returns (parts_out, J,
+    A, created, stats, qstats): created holds the new particles in creation
+    order; stats as in run; qstats = dict(emitted, converted, lost)."""
+    g = geom(grid)
+    sp = _species_array(species)
+    p = {
+        "cell": np.array(parts["cell"], dtype=np.int32, copy=True),
+        "xr": np.array(parts["xr"], dtype=np.float64, copy=True),
+        "xth": np.array(parts["xth"], dtype=np.float64, copy=True),
+        "ur": np.array(parts["ur"], dtype=np.float64, copy=True),
+        "uth": np.array(parts["uth"], dtype=np.float64, copy=True),
+        "uph": np.array(parts["uph"], dtype=np.float64, copy=True),
+        "w": np.array(parts["w"], dtype=np.float64, copy=True),
+        "sp": np.array(parts["sp"], dtype=np.uint8, copy=True),
+        "tag": np.array(parts["tag"], dtype=np.uint64, copy=True),
+    }
+    n = len(p["cell"])
+    cap = 2 * n if capacity is None else int(capacity)
+    c = {"cell": np.full(cap, -1, dtype=np.int32), "sp": np.zeros(cap, dtype=np.uint8),
+         "tag": np.zeros(cap, dtype=np.uint64)}
+    for k in ("xr", "xth", "ur", "uth", "uph", "w"):
+        c[k] = np.zeros(cap)
+    shape = (grid.nr + 1 + 2 * grid.guard, grid.pitch)
+    if J is None:
+        J = [np.zeros(shape) for _ in range(3)]
+    A = [np.zeros(shape) for _ in range(3)]
+    fl = [_f64(f) for f in fields]
+    fptr = (ctypes.c_void_p * 6)(*[f.ctypes.data for f in fl])
+    q = Qed(float(qed["gamma_thr"]), float(qed["eps_ph"]), float(qed["tau"]), int(qed["seed"]),
+            int(qed["electron_sp"]), int(qed["positron_sp"]), int(qed["photon_sp"]), 0)
+    nc = ctypes.c_int64(0)
+    stats = np.zeros(4, dtype=np.int64)
+    qstats = np.zeros(3, dtype=np.int64)
+    lib().orc_run_qed(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(n),
+                      _p(p["cell"]), _p(p["xr"]), _p(p["xth"]), _p(p["ur"]), _p(p["uth"]), _p(p["uph"]),
+                      _p(p["w"]), _p(p["sp"]), _p(p["tag"]), fptr, _p(J[0]), _p(J[1]), _p(J[2]),
+                      _p(A[0]), _p(A[1]), _p(A[2]), ctypes.c_double(dt), ctypes.c_int(ncorr),
+                      ctypes.c_int64(int(step)), ctypes.byref(q), ctypes.c_int64(cap),
+                      _p(c["cell"]), _p(c["xr"]), _p(c["xth"]), _p(c["ur"]), _p(c["uth"]), _p(c["uph"]),
+                      _p(c["w"]), _p(c["sp"]), _p(c["tag"]), ctypes.byref(nc), _p(stats), _p(qstats))
+    created = {k: v[: nc.value] for k, v in c.items()}
+    st = dict(out=int(stats[0]), bad=int(stats[1]), reflected=int(stats[2]), live_steps=int(stats[3]))
+    qs = dict(emitted=int(qstats[0]), converted=int(qstats[1]), lost=int(qstats[2]))
+    return p, J, A, created, st, qs
+
+
 def has_openmp() -> bool:
     return bool(lib().orc_has_openmp())
 

@@ -14,6 +14,9 @@ Contents
   wald-vector-potential and wald-solution-ks, with the mass M written back
   in) point-sampled at the Yee stagger of Fig. Yee, with D^i obtained from
   E_i by inverting eq. E-H-B-D.  On the axis D^ph = B^th = 0 (Sec. 2.1).
+* ``monopole_fields``: the vacuum monopole of App. C (the initial field of
+  the Sec. 4 spark-gap runs) on the same stagger, D^i again from eq.
+  E-H-B-D; ``qed_particles``: e+- and photons for that workload.
 * ``crossing_dt``: the cell crossing time at the coordinate speed of light,
   minimised over cell centres.
 * particle samplers: pairs placed per cell with uniform offsets; momenta
@@ -166,8 +169,49 @@ def wald_point(a, M, B0, r, th):
                 At=At, Aph=Aph)
 
 
-def wald_fields(grid: Grid, B0: float = 1.0, axis_bc: bool = True) -> list[np.ndarray]:
-    """The six field arrays D^r, D^th, D^ph, B^r, B^th, B^ph on the Yee stagger."""
+def monopole_point(a, M, B0, r, th):
+    """Vacuum monopole of App. C at points: dict of D^i, B^i, E_i, A_t, A_r, A_ph.
+
+    From the Kerr-Schild potential A = B0 (a cos/rho^2, a cos/rho^2, 0,
+    -cos (r^2 + a^2)/rho^2) (eq. for A_mu,monopole^KS; with the mass M
+    written back in only sqrt(gamma) changes): B^r = d_th A_ph / sqrt(g),
+    B^th = -d_r A_ph / sqrt(g), B^ph = -d_th A_r / sqrt(g), E_i = d_i A_t,
+    written with sin(theta) cancelled so the axis is regular; D^i from E_i by
+    inverting eq. E-H-B-D, as for the Wald field.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    th = np.asarray(th, dtype=np.float64)
+    k = _ks_pieces(a, M, r, th)
+    s, c, rho2 = k["s"], k["c"], k["rho2"]
+    rho4 = rho2 * rho2
+    sqz = np.sqrt(1.0 + k["z"])
+    q = r * r - a * a * c * c
+    # sqrt(gamma) B^i, sqrt(gamma) = rho^2 sin sqrt(1+z); sin cancelled in B^i
+    Br = B0 * (a * a + r * r) * q / (rho4 * rho2 * sqz)
+    Bth = -B0 * 2.0 * a * a * r * s * c / (rho4 * rho2 * sqz)
+    Bph = B0 * a * q / (rho4 * rho2 * sqz)
+    Er = -B0 * 2.0 * a * r * c / rho4
+    Eth = -B0 * a * q * s / rho4
+    sg_Bph = B0 * a * q * s / rho4
+    sg_Bth_over_s2 = -B0 * 2.0 * a * a * r * c / rho4
+    al, be = k["alpha"], k["beta"]
+    Dr = (k["h_rr"] * Er + k["h_rp"] * (-be * sg_Bth_over_s2 * s * s)) / al
+    Dth = k["h_tt"] * (Eth + be * sg_Bph) / al
+    Dph = (k["h_rp"] * Er - be * sg_Bth_over_s2 / rho2) / al
+    At = B0 * a * c / rho2
+    Aph = -B0 * c * (r * r + a * a) / rho2
+    return dict(Dr=Dr, Dth=Dth, Dph=Dph, Br=Br, Bth=Bth, Bph=Bph, Er=Er, Eth=Eth, At=At, Ar=At, Aph=Aph)
+
+
+def monopole_fields(grid: Grid, B0: float = 1.0, axis_bc: bool = True) -> list[np.ndarray]:
+    """The vacuum monopole (App. C) as the six field arrays on the Yee stagger."""
+    return wald_fields(grid, B0, axis_bc, point=monopole_point)
+
+
+def wald_fields(grid: Grid, B0: float = 1.0, axis_bc: bool = True, point=None) -> list[np.ndarray]:
+    """The six field arrays D^r, D^th, D^ph, B^r, B^th, B^ph on the Yee stagger
+    (of the rotating Wald field, or of the field that ``point`` gives)."""
+    point = wald_point if point is None else point
     rows, pitch, g = grid.rows, grid.pitch, grid.guard
     ii = np.arange(rows, dtype=np.float64)[:, None] - g
     jj = np.arange(pitch, dtype=np.float64)[None, :] - g
@@ -178,7 +222,7 @@ def wald_fields(grid: Grid, B0: float = 1.0, axis_bc: bool = True) -> list[np.nd
     for (sr, st), names in by_stagger.items():
         r = grid.r(ii + sr) * np.ones_like(jj)
         th = grid.theta(jj + st) * np.ones_like(ii)
-        vals = wald_point(grid.a, grid.M, B0, r, th)
+        vals = point(grid.a, grid.M, B0, r, th)
         for name in names:
             v = np.ascontiguousarray(vals[name], dtype=np.float64)
             if axis_bc and st == 0.0 and name in ("Dph", "Bth"):
@@ -345,6 +389,33 @@ def pairs(grid: Grid, npairs: int, kind: str = "uniform", seed: int = 0, params:
     with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
         parts = list(ex.map(run, jobs))
     return {k: np.concatenate([p[0][k] for p in parts]) for k in parts[0][0]}
+
+
+def qed_species_table():
+    """Species of the monopole workload: 0 = e-, 1 = e+, 2 = photon."""
+    return species_table() + [dict(q=0.0, m=0.0, massless=1)]
+
+
+def qed_particles(grid: Grid, npairs: int, photon_frac: float = 0.2, seed: int = 0, gmax: float = 1e3,
+                  eps_range=(1.0, 10.0), workers: int = 1):
+    """Inputs of the monopole workload: e+- pairs with dN/dgamma ~ gamma^-2 on
+    [1, gmax] (the pair recipe above), of which a fraction photon_frac of the
+    pairs' e- slots are turned into photons with FIDO energy uniform in
+    eps_range along an isotropic direction; uint64 tags 0 .. n-1."""
+    parts = pairs(grid, npairs, kind="powerlaw", seed=seed, params=dict(gmax=gmax), workers=workers)
+    n = len(parts["cell"])
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(1 << 30,))))
+    ph = np.flatnonzero((rng.uniform(0.0, 1.0, npairs) < photon_frac)) * 2
+    ci, cj = parts["cell"][ph] // grid.nth, parts["cell"][ph] % grid.nth
+    r = grid.r(ci + parts["xr"][ph])
+    th = grid.theta(cj + parts["xth"][ph])
+    eps = rng.uniform(eps_range[0], eps_range[1], len(ph))
+    uh = _isotropic_dirs(rng, len(ph)) * eps
+    ur, uth, uph = frame_to_covariant(grid.a, grid.M, r, th, uh)
+    parts["ur"][ph], parts["uth"][ph], parts["uph"][ph] = ur, uth, uph
+    parts["sp"][ph] = 2
+    parts["tag"] = np.arange(n, dtype=np.uint64)
+    return parts
 
 
 def species_table():

@@ -5,6 +5,8 @@
   A_r = -(2 M r A_t + a A_ph)/Delta from the Boyer-Lindquist -> Kerr-Schild
   change of coordinates (eq. BL_KS_diff), E_i = d_i A_t; and at M = 1 it equals
   the printed components of eq. wald-solution-ks.
+* The vacuum monopole of App. C is the curl of its potential, equals the
+  printed components at M = 1, and its D^i solves eq. E-H-B-D too.
 * D^i solves eq. E-H-B-D for the Wald E_i (checked with the oracle's metric,
   an independent implementation).
 * Orthonormal-frame momenta map to covariant u_i with gamma^ij u_i u_j = |u_hat|^2.
@@ -77,6 +79,60 @@ def test_wald_D_inverts_constitutive_relation():
     """E_i = alpha gamma_ij D^j + e_ijk beta^j B^k (eq. E-H-B-D)."""
     for a, M, r, th in _pts(seed=2):
         f = wl.wald_point(a, M, 1.0, r, th)
+        m = orc.metric(a, M, r, th)
+        D = np.array([f["Dr"], f["Dth"], f["Dph"]])
+        B = np.array([f["Br"], f["Bth"], f["Bph"]])
+        g = np.array([[m["g_rr"], 0, m["g_rph"]], [0, m["g_thth"], 0], [m["g_rph"], 0, m["g_phph"]]])
+        beta = np.array([m["beta"], 0.0, 0.0])
+        E = m["alpha"] * g @ D + m["sqrtg"] * np.cross(beta, B)
+        np.testing.assert_allclose(E, [f["Er"], f["Eth"], 0.0], atol=1e-12 * (1 + np.abs(E).max()))
+
+
+def test_monopole_field_is_curl_of_its_potential():
+    """App. C monopole: A = B0 (a cos/rho^2, a cos/rho^2, 0, -cos (r^2+a^2)/rho^2)
+    in Kerr-Schild coordinates; B^r = d_th A_ph / sqrt(g), B^th = -d_r A_ph /
+    sqrt(g), B^ph = -d_th A_r / sqrt(g), E_i = d_i A_t (finite differences of
+    the potential written out here)."""
+    B0 = 1.7
+    for a, M, r, th in _pts(seed=5):
+        f = wl.monopole_point(a, M, B0, r, th)
+        sg = orc.metric(a, M, r, th)["sqrtg"]
+        rho2 = lambda rr, tt: rr * rr + a * a * math.cos(tt) ** 2  # noqa: E731
+        At = lambda rr, tt: B0 * a * math.cos(tt) / rho2(rr, tt)  # noqa: E731
+        Aph = lambda rr, tt: -B0 * math.cos(tt) * (rr * rr + a * a) / rho2(rr, tt)  # noqa: E731
+        h_r, h_t = 1e-4 * r, 1e-4
+        assert f["Br"] == pytest.approx(_fd(lambda t: Aph(r, t), th, h_t) / sg, rel=1e-7, abs=1e-9)
+        assert f["Bth"] == pytest.approx(-_fd(lambda x: Aph(x, th), r, h_r) / sg, rel=1e-7, abs=1e-9)
+        assert f["Bph"] == pytest.approx(-_fd(lambda t: At(r, t), th, h_t) / sg, rel=1e-7, abs=1e-9)
+        assert f["Er"] == pytest.approx(_fd(lambda x: At(x, th), r, h_r), rel=1e-7, abs=1e-9)
+        assert f["Eth"] == pytest.approx(_fd(lambda t: At(r, t), th, h_t), rel=1e-7, abs=1e-9)
+        # the Kerr-Schild A_r is the coordinate change of the Boyer-Lindquist
+        # A_t, A_ph (A_r^BL = 0): A_r = -(2 M r A_t + a A_ph)/Delta
+        Delta = r * r + a * a - 2 * M * r
+        assert f["Ar"] == pytest.approx(-(2 * M * r * f["At"] + a * f["Aph"]) / Delta, rel=1e-12, abs=1e-14)
+
+
+def test_monopole_matches_printed_components():
+    """App. C's monopole B^i and E_i as printed."""
+    B0 = 2.0
+    for a, _, r, th in _pts(seed=6):
+        f = wl.monopole_point(a, 1.0, B0, r, th)
+        s, c = math.sin(th), math.cos(th)
+        rho2 = r * r + a * a * c * c
+        rho4 = rho2 * rho2
+        sg = orc.metric(a, 1.0, r, th)["sqrtg"]
+        Br = B0 / sg * (a * a + r * r) * (r * r - a * a * c * c) * s / rho4
+        Bth = -B0 / sg * 2 * a * a * r * s * s * c / rho4
+        Bph = B0 / sg * a * (r * r - a * a * c * c) * s / rho4
+        Er = -B0 * 2 * a * r * c / rho4
+        Eth = -B0 * a * (r * r - a * a * c * c) * s / rho4
+        np.testing.assert_allclose([f["Br"], f["Bth"], f["Bph"], f["Er"], f["Eth"]],
+                                   [Br, Bth, Bph, Er, Eth], rtol=1e-12, atol=1e-14)
+
+
+def test_monopole_D_inverts_constitutive_relation():
+    for a, M, r, th in _pts(seed=7):
+        f = wl.monopole_point(a, M, 1.0, r, th)
         m = orc.metric(a, M, r, th)
         D = np.array([f["Dr"], f["Dth"], f["Dph"]])
         B = np.array([f["Br"], f["Bth"], f["Bph"]])
