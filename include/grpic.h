@@ -32,6 +32,9 @@
  *   w             macro-particle weight
  *   sp    uint8   species index into the species table
  *   phi           optional accumulated azimuth (NULL: not tracked)
+ *   tag   uint64  optional identity of the particle (NULL: none); it keys
+ *                 the random numbers of grpic_push_deposit_qed, so that its
+ *                 draws do not depend on the order of the particles
  * Precision GRPIC_FP64: xr..w and phi are double.  GRPIC_FP32_SPLIT: xr..w are
  * float (the position keeps its integer cell exactly; fields are float too);
  * the kick and the predictor-corrector run in float on offsets from the start
@@ -108,6 +111,7 @@ typedef struct {
     void* phi;
     int32_t precision;   /* GRPIC_FP64 or GRPIC_FP32_SPLIT */
     int32_t reserved;
+    uint64_t* tag;       /* optional particle tags (NULL: none), moved by grpic_sort */
 } grpic_particles;
 
 /* Contravariant D^i and B^i, i = r, th, ph, on the Yee stagger; double for
@@ -227,6 +231,66 @@ int grpic_push_deposit_spline3(const grpic_metric* metric, const grpic_grid* gri
 int grpic_charge3(const grpic_grid* grid, const grpic_species* species, int nsp,
                   const grpic_particles* parts, double* Q, void* stream);
 
+/*
+ * grpic_push_deposit_qed -- one step of the monopole workload's particles
+ * (Sec. 4): the push and deposit of grpic_push_deposit (FP64, Boris kick,
+ * CIC; photons, the massless species, follow geodesics and carry no
+ * current), then, from each particle's end point:
+ *   - an e- or e+ whose FIDO Lorentz factor Gamma = sqrt(1 + gamma^ij u_i u_j)
+ *     exceeds gamma_thr emits one photon of FIDO energy eps_ph along its own
+ *     momentum, at its end point, with its weight; its FIDO momentum
+ *     magnitude drops by eps_ph (momentum kept along the common direction);
+ *   - a photon of FIDO energy eps = sqrt(gamma^ij u_i u_j) >= 2 (twice the
+ *     rest energy) converts with probability P = 1 - exp(-tau dt) (eq.
+ *     optical-depth) into an e- and an e+ of FIDO energy eps/2 each along its
+ *     direction, at its end point, with its weight, and is removed.
+ * Particles that left the grid in the step, or were removed as bad, neither
+ * emit nor convert; particles created in the step are not pushed in it.
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11) with counter (tag,
+ * step, 0, 0) and key (seed, 0), one block per particle and step: word 0
+ * gives a photon's uniform U = (x0 >> 11) 2^-53 (it converts iff U < P),
+ * word 1 the tag of the emitted photon or of the e-, word 2 that of the e+.
+ *
+ * parts: GRPIC_FP64 with tags; parts->n is the capacity of its arrays.
+ * n_used: device int64[2].  On entry n_used[0] is the number of array
+ *   elements in use (every element at or beyond it must have cell = -1);
+ *   the particles of [0, n_used[0]) are pushed and the created ones are
+ *   written to [n_used[0], n_used[0] + created) in no particular order, so
+ *   that on return n_used[0] counts them too (created particles beyond the
+ *   capacity are dropped and counted).  n_used[1] is working space (its
+ *   value on entry does not matter; 0 on return).  grpic_sort with
+ *   n_alive_dev = n_used leaves n_used[0] right for the next step.
+ * tiling: NULL, or the tiling of the grpic_sort call that produced the
+ *   current order; the particles appended since that sort are pushed
+ *   without the LDS window.
+ * step: the step number that keys the random numbers.
+ * qcounters: optional device int64[GRPIC_NQCOUNTERS], accumulated.
+ * Otherwise arguments and errors as in grpic_push_deposit, with nsteps = 1.
+ * GRPIC_EINVAL for non-FP64 particles, no tags, species indices outside
+ * the species table, a photon species that is not massless, an e- or e+
+ * species that is, gamma_thr <= 1, eps_ph <= 0 or
+ * eps_ph >= sqrt(gamma_thr^2 - 1) (the emitter's momentum must stay
+ * positive), tau < 0 or a NULL n_used.
+ */
+typedef struct {
+    double gamma_thr;                 /* emission threshold on Gamma               */
+    double eps_ph;                    /* FIDO energy of an emitted photon          */
+    double tau;                       /* conversion rate: P = 1 - exp(-tau dt)     */
+    uint64_t seed;                    /* key of the random stream                  */
+    int32_t electron_sp, positron_sp, photon_sp, reserved;
+} grpic_qed;
+
+#define GRPIC_QCNT_EMITTED 0          /* photons emitted                            */
+#define GRPIC_QCNT_CONVERTED 1        /* photons converted into pairs               */
+#define GRPIC_QCNT_DROPPED 2          /* created particles beyond the capacity      */
+#define GRPIC_NQCOUNTERS 3
+
+int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
+                           const grpic_species* species, int nsp,
+                           grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                           void* tiling, double dt, int64_t step, int ncorr, const grpic_qed* qed,
+                           int64_t* n_used, int64_t* counters, int64_t* qcounters, void* stream);
+
 /* Gradient outputs of grpic_push_deposit_backward (device, double). */
 typedef struct {
     double *ur, *uth, *uph;          /* per particle, overwritten */
@@ -292,7 +356,8 @@ int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
  * grpic_tiling_bytes(grid, in->n) bytes) receives the slice table that
  * grpic_push_deposit's tiled path runs on.  ws: device workspace of at least
  * grpic_sort_workspace_bytes() bytes.  n_alive_dev: device int64 receiving
- * the live count.
+ * the live count.  Tags move with their particles when in and out both
+ * carry them (GRPIC_EINVAL if only one does).
  * Not described by the paper: particles are kept ordered by cell so that a
  * workgroup's particles share field cache lines and one LDS current window.
  */

@@ -14,6 +14,7 @@
 #include "grpic.h"
 #include "grpic_fields.hpp"
 #include "grpic_launch.hpp"
+#include "grpic_qed.hpp"
 
 namespace {
 
@@ -344,6 +345,70 @@ int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
                         counters, stream, grpic::kVay);
 }
 
+int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
+                           const grpic_species* species, int nsp,
+                           grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
+                           void* tiling, double dt, int64_t step, int ncorr, const grpic_qed* qed,
+                           int64_t* n_used, int64_t* counters, int64_t* qcounters, void* stream) {
+    int rc;
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
+        (rc = check_particles(parts, "parts")))
+        return rc;
+    if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "grpic_push_deposit_qed: GRPIC_FP64 particles only");
+    if (parts->n > 0 && !parts->tag) return fail(GRPIC_EINVAL, "grpic_push_deposit_qed: the particles need tags");
+    if (!qed) return fail(GRPIC_EINVAL, "qed is NULL");
+    if (!n_used) return fail(GRPIC_EINVAL, "n_used is NULL");
+    const int sp_e = qed->electron_sp, sp_p = qed->positron_sp, sp_g = qed->photon_sp;
+    if (sp_e < 0 || sp_e >= nsp || sp_p < 0 || sp_p >= nsp || sp_g < 0 || sp_g >= nsp)
+        return fail(GRPIC_EINVAL, "qed: species indices must lie in [0, %d)", nsp);
+    if (!species[sp_g].massless) return fail(GRPIC_EINVAL, "qed: the photon species must be massless");
+    if (species[sp_e].massless || species[sp_p].massless)
+        return fail(GRPIC_EINVAL, "qed: the electron and positron species must be massive");
+    if (!(qed->gamma_thr > 1.0) || !isfinite(qed->gamma_thr)) return fail(GRPIC_EINVAL, "qed: gamma_thr must be > 1");
+    if (!(qed->eps_ph > 0.0) || !(qed->eps_ph < sqrt(qed->gamma_thr * qed->gamma_thr - 1.0)))
+        return fail(GRPIC_EINVAL, "qed: need 0 < eps_ph < sqrt(gamma_thr^2 - 1)");
+    if (!(qed->tau >= 0.0) || !isfinite(qed->tau)) return fail(GRPIC_EINVAL, "qed: tau must be >= 0 and finite");
+    if (step < 0) return fail(GRPIC_EINVAL, "step must be >= 0");
+    // the push's own checks (one step, no checkpoints); nothing is enqueued
+    // for an empty set
+    grpic_particles none = *parts;
+    none.n = 0;
+    if ((rc = push_deposit(metric, grid, species, nsp, &none, fields, J, nullptr, dt, 1, ncorr, nullptr, 0, 0,
+                           counters, stream, grpic::kBoris)))
+        return rc;
+    if (tiling) {
+        std::lock_guard<std::mutex> lk(g_tiling_mu);
+        auto it = g_tilings.find(tiling);
+        if (it == g_tilings.end() || it->second.n != parts->n || it->second.nr != grid->nr ||
+            it->second.nth != grid->nth)
+            return fail(GRPIC_EINVAL, "tiling was not written by grpic_sort for %lld particles on this grid",
+                        (long long)parts->n);
+    }
+    if (parts->n == 0) return GRPIC_OK;
+    grpic::StepArgs A;
+    fill_common(A, metric, grid, species, nsp, parts);
+    A.dt = dt;
+    A.ncorr = ncorr;
+    for (int c = 0; c < 3; ++c) { A.F[c] = fields->D[c]; A.F[3 + c] = fields->B[c]; }
+    A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;
+    A.counters = reinterpret_cast<unsigned long long*>(counters);
+    grpic::QedArgs Q;
+    memset(&Q, 0, sizeof Q);
+    Q.gamma_thr = qed->gamma_thr;
+    Q.eps_ph = qed->eps_ph;
+    Q.P = 1.0 - exp(-qed->tau * dt);                          // eq. optical-depth
+    Q.seed = qed->seed;
+    Q.step = (uint64_t)step;
+    Q.electron_sp = sp_e; Q.positron_sp = sp_p; Q.photon_sp = sp_g;
+    Q.tag = parts->tag;
+    Q.n_used = n_used;
+    Q.cap = parts->n;
+    Q.qcounters = reinterpret_cast<unsigned long long*>(qcounters);
+    const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
+    return hip_status(grpic::launch_push_deposit_qed(A, Q, tiling, cap, static_cast<hipStream_t>(stream)),
+                      "push_deposit_qed launch");
+}
+
 size_t grpic_checkpoint_bytes(int64_t n, int nsteps, int ckpt_every) {
     if (n < 0 || ckpt_every < 1 || nsteps < 0 || nsteps % ckpt_every != 0) return 0;
     return (size_t)(nsteps / ckpt_every) * grpic::checkpoint_slot_bytes(n);
@@ -465,6 +530,7 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
                       !out->sp))
         return fail(GRPIC_EINVAL, "out: NULL particle array");
     if ((in->phi == nullptr) != (out->phi == nullptr)) return fail(GRPIC_EINVAL, "phi given for only one of in/out");
+    if ((in->tag == nullptr) != (out->tag == nullptr)) return fail(GRPIC_EINVAL, "tag given for only one of in/out");
     if (in->n > 0 && (in->cell == out->cell || in->xr == out->xr)) return fail(GRPIC_EINVAL, "in and out alias");
     if (!n_alive_dev) return fail(GRPIC_EINVAL, "n_alive_dev is NULL");
     const size_t need = grpic_sort_workspace_bytes(grid, in->n);
@@ -489,6 +555,8 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
     S.cell_out = out->cell;
     S.sp_out = out->sp;
     S.phi_out = out->phi;
+    S.tag_in = in->tag;
+    S.tag_out = out->tag;
     S.counts = static_cast<unsigned long long*>(ws);
     S.blocksums = S.counts + (S.ncell + 1);
     S.tile_slices = S.blocksums + grpic::sort_scan_blocks((int64_t)S.ncell + 1) + 1;

@@ -31,6 +31,7 @@ constexpr int kWinCols = kTileCells + 2 * kMarginCols + 3; // vertex columns of 
 struct TilingHeader {
     int64_t nslices;          // written by the sort on the device
     int64_t n;                // particle count the tiling was built for
+    int64_t n_sorted;         // live particles at the sort (the slices cover [0, n_sorted))
     int32_t nr, nth, tiles_per_row, tile_cells;
 };
 
@@ -80,6 +81,10 @@ hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
                                      hipStream_t stream, int kick = kBoris, int order = 1);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream, int order = 1);
+struct QedArgs;
+// One QED step (FP64, Boris, CIC): the tiled slices if a tiling is given,
+// then the particles no slice covers; n_used updated on the device.
+hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap, hipStream_t stream);
 
 struct SortArgs {
     int64_t n;
@@ -89,10 +94,12 @@ struct SortArgs {
     const void* in[6];                // xr, xth, ur, uth, uph, w
     const uint8_t* sp_in;
     const void* phi_in;               // optional, same element size
+    const uint64_t* tag_in;           // optional
     int32_t* cell_out;
     void* out[6];
     uint8_t* sp_out;
     void* phi_out;
+    uint64_t* tag_out;
     unsigned long long* counts;       // ncell + 1 entries of workspace
     unsigned long long* blocksums;    // sort_scan_blocks(ncell + 1) + 1 entries of workspace
     unsigned long long* tile_slices;  // ntiles + 1 entries of workspace (tiling only)

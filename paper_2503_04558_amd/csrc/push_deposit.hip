@@ -20,6 +20,7 @@
 //                           registers: 256 VGPRs and one wave per SIMD.)
 #include "grpic_device.hpp"
 #include "grpic_launch.hpp"
+#include "grpic_qed.hpp"
 
 #include <algorithm>
 #include <type_traits>
@@ -441,11 +442,14 @@ __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) {
     push_deposit_body<true, SHORT, kBoris>(A);
 }
 
-template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
+// QED: photon emission and pair conversion after the push (FP64, Boris,
+// CIC), with the created particles appended after the elements in use.
+template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1, bool QED = false>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const Slice* __restrict__ slices,
                                                         int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live,
-                                                        const double* __restrict__ anchors) {
+                                                        const double* __restrict__ anchors,
+                                                        const QedArgs& Q = QedArgs{}) {
     __shared__ double win[3][kWinRows][kWinCols];
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
@@ -517,10 +521,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     Events ev = {0, 0, 0, 0, 0};
     int row_lo = kWinRows, row_hi = -1;                  // window rows and columns this lane deposited on
     int col_lo = kWinCols, col_hi = -1;
+    Created cr;
+    QedEvents qe = {0, 0};
+    cr.n = 0;
     if (mine) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
         const bool dep = advance<SPLIT, SHORT, KICK, ORDER>(A, pi, in, mv, ev, &tab, out);
+        if constexpr (QED) qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
         const int si = slot + slot / 32;
         st_kind[si] = out.kind;
         st_cell[si] = out.cell;
@@ -571,6 +579,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         col_lo = min(col_lo, __shfl_xor(col_lo, off));
         col_hi = max(col_hi, __shfl_xor(col_hi, off));
     }
+    if constexpr (QED) qed_append<double>(A, Q, Q.n_used[0], cr, qe);
     if ((threadIdx.x & 63) == 0 && row_hi >= 0) {
         atomicMin(&touched[0], row_lo);
         atomicMax(&touched[1], row_hi);
@@ -652,6 +661,83 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(2)
     push_deposit_tiled_body<false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);
 }
 template <bool SHORT>
+__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_qed(
+    const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
+    const double* anchors, const QedArgs Q) {
+    push_deposit_tiled_body<false, SHORT, kBoris, 1, true>(A, slices, slice_cap, slice_live, anchors, Q);
+}
+
+// The QED step of one block of particles b .. b + 255 below `end`: one
+// particle per thread, global atomics.
+template <bool SHORT>
+__device__ __forceinline__ void qed_block(const StepArgs& A, const QedArgs& Q, int64_t b, int64_t end, int* cnt) {
+    if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+    const PIdx pi{b, threadIdx.x};
+    Events ev = {0, 0, 0, 0, 0};
+    Created cr;
+    QedEvents qe = {0, 0};
+    cr.n = 0;
+    if (b + threadIdx.x < end) {
+        Move mv;
+        ParticleOut<double> out;
+        const ParticleIn<double> in = load_particle<double>(A, pi);
+        const bool dep = advance<false, SHORT, kBoris, 1>(A, pi, in, mv, ev, nullptr, out);
+        qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
+        store_particle(A, pi, out);
+        if (dep) scatter_global(A, mv);
+    }
+    qed_append<double>(A, Q, end, cr, qe);
+    if (A.counters) {                                       // uniform
+        __syncthreads();
+        wave_events_to_lds(ev, cnt);
+        __syncthreads();
+        workgroup_events_to_global(A, cnt);
+    }
+}
+
+// Without a tiling: block b takes particles 256 b .. 256 b + 255 of those in
+// use (the grid covers the capacity; blocks beyond the elements in use
+// return at once).
+template <bool SHORT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_qed(
+    const StepArgs A, const QedArgs Q) {
+    __shared__ int cnt[5];
+    const int64_t end = Q.n_used[0];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x;
+    if (b >= end) return;
+    qed_block<SHORT>(A, Q, b, end, cnt);
+}
+
+// With a tiling: the particles appended since the sort, [n_sorted,
+// n_used[0]), which no slice covers; a few blocks loop over them (a short
+// range, so the loop's register spills cost little).
+template <bool SHORT>
+__global__ __launch_bounds__(256) void push_deposit_f64_qed_tail(const StepArgs A, const QedArgs Q) {
+    __shared__ int cnt[5];
+    const int64_t end = Q.n_used[0];
+    const int64_t start = min(*Q.tail_start, end);
+    for (int64_t b = start + (int64_t)blockIdx.x * blockDim.x; b < end; b += (int64_t)gridDim.x * blockDim.x) {
+        qed_block<SHORT>(A, Q, b, end, cnt);
+        __syncthreads();                                    // cnt is cleared again next pass
+    }
+}
+
+// Before a QED step: the elements in use cover the tiling's sorted
+// particles, and the append counter starts at zero.
+__global__ void qed_begin(int64_t* n_used, const int64_t* tail_start, int64_t cap) {
+    int64_t n0 = n_used[0];
+    if (tail_start && *tail_start > n0) n0 = *tail_start;
+    n_used[0] = n0 < 0 ? 0 : (n0 > cap ? cap : n0);
+    n_used[1] = 0;
+}
+// After it: the appended particles join the elements in use.
+__global__ void qed_end(int64_t* n_used, int64_t cap) {
+    const int64_t n = n_used[0] + n_used[1];
+    n_used[0] = n > cap ? cap : n;
+    n_used[1] = 0;
+}
+
+template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
                                                                          const Slice* __restrict__ slices,
                                                                          int64_t slice_cap, int32_t* slice_live,
@@ -729,6 +815,44 @@ hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream
     else if (kick == kVay) hipLaunchKernelGGL((push_deposit_f64<false, kVay, 1>), g, b, 0, stream, A);
     else if (sh) hipLaunchKernelGGL((push_deposit_f64<true, kBoris, 1>), g, b, 0, stream, A);
     else hipLaunchKernelGGL((push_deposit_f64<false, kBoris, 1>), g, b, 0, stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap,
+                                   hipStream_t stream) {
+    const bool sh = A.small_steps == 2;
+    Q.tail_start = nullptr;
+    if (tiling) {
+        const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
+        Q.tail_start = &hdr->n_sorted;
+    }
+    hipLaunchKernelGGL(qed_begin, dim3(1), dim3(1), 0, stream, Q.n_used, Q.tail_start, Q.cap);
+    if (tiling) {
+        const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
+        const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
+        int32_t* live = tiling_slice_live(tiling, slice_cap);
+        double* anchors = tiling_anchors(tiling, slice_cap);
+        if (A.small_steps) {
+            const int rows = anchor_table_rows(A.nr), cols = anchor_table_cols(A.nth);
+            hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0,
+                               stream, A, anchors, rows, cols);
+        }
+        const dim3 g((unsigned)((slice_cap + 7) / 8 * 8)), b(kPushThreads);
+        if (sh) hipLaunchKernelGGL(push_deposit_f64_tiled_qed<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors, Q);
+        else hipLaunchKernelGGL(push_deposit_f64_tiled_qed<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors, Q);
+        if (A.counters)
+            hipLaunchKernelGGL(slice_live_sum, dim3(64), dim3(256), 0, stream, live, slice_cap, A.counters);
+    }
+    if (tiling) {                                        // the particles appended since the sort
+        const dim3 g((unsigned)std::min<int64_t>((A.n + 255) / 256, 1024));
+        if (sh) hipLaunchKernelGGL(push_deposit_f64_qed_tail<true>, g, dim3(256), 0, stream, A, Q);
+        else hipLaunchKernelGGL(push_deposit_f64_qed_tail<false>, g, dim3(256), 0, stream, A, Q);
+    } else {                                             // every element in use
+        const dim3 g((unsigned)((A.n + 255) / 256));
+        if (sh) hipLaunchKernelGGL(push_deposit_f64_qed<true>, g, dim3(256), 0, stream, A, Q);
+        else hipLaunchKernelGGL(push_deposit_f64_qed<false>, g, dim3(256), 0, stream, A, Q);
+    }
+    hipLaunchKernelGGL(qed_end, dim3(1), dim3(1), 0, stream, Q.n_used, Q.cap);
     return hipGetLastError();
 }
 

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __r
     if (t == 0) {
         hdr->nslices = (int64_t)base[ntiles];
         hdr->n = n;
+        hdr->n_sorted = (int64_t)offs[(int64_t)nr * nth];
         hdr->nr = nr;
         hdr->nth = nth;
         hdr->tiles_per_row = tpr;
@@ -284,12 +285,14 @@ __global__ __launch_bounds__(kChunkThreads) void sort_scatter(const SortArgs S) 
     // the particles' data is read first, so its latency overlaps the counting
     T v[kChunkItems][6], ph[kChunkItems];
     uint8_t spv[kChunkItems];
+    uint64_t tg[kChunkItems];
     for (int k = 0; k < kChunkItems; ++k) {
         const int64_t p = chunk_index(k);
         const bool valid = c[k] >= 0 && c[k] < S.ncell;
         for (int a = 0; a < 6; ++a) v[k][a] = valid ? static_cast<const T*>(S.in[a])[p] : T(0);
         spv[k] = valid ? S.sp_in[p] : 0;
         ph[k] = valid && S.phi_in ? static_cast<const T*>(S.phi_in)[p] : T(0);
+        tg[k] = valid && S.tag_in ? S.tag_in[p] : 0ull;
     }
     table_clear(Tb);
     __syncthreads();
@@ -306,6 +309,7 @@ __global__ __launch_bounds__(kChunkThreads) void sort_scatter(const SortArgs S) 
         for (int a = 0; a < 6; ++a) static_cast<T*>(S.out[a])[q] = v[k][a];
         S.sp_out[q] = spv[k];
         if (S.phi_in) static_cast<T*>(S.phi_out)[q] = ph[k];
+        if (S.tag_in) S.tag_out[q] = tg[k];
     }
 }
 

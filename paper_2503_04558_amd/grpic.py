@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -20,6 +21,8 @@ GRPIC_FP64, GRPIC_FP32_SPLIT = 0, 1
 GRPIC_MAX_SPECIES = 8
 GRPIC_NCOUNTERS = 5
 COUNTER_NAMES = ("out", "bad", "reflected", "live_steps", "spilled")
+GRPIC_NQCOUNTERS = 3
+QCOUNTER_NAMES = ("emitted", "converted", "dropped")
 
 PARTICLE_KEYS = ("cell", "xr", "xth", "ur", "uth", "uph", "w", "sp")
 REAL_KEYS = ("xr", "xth", "ur", "uth", "uph", "w")
@@ -44,7 +47,14 @@ class grpic_particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("cell", ctypes.c_void_p), ("xr", ctypes.c_void_p),
                 ("xth", ctypes.c_void_p), ("ur", ctypes.c_void_p), ("uth", ctypes.c_void_p),
                 ("uph", ctypes.c_void_p), ("w", ctypes.c_void_p), ("sp", ctypes.c_void_p),
-                ("phi", ctypes.c_void_p), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("phi", ctypes.c_void_p), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tag", ctypes.c_void_p)]
+
+
+class grpic_qed(ctypes.Structure):
+    _fields_ = [("gamma_thr", ctypes.c_double), ("eps_ph", ctypes.c_double), ("tau", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("electron_sp", ctypes.c_int32), ("positron_sp", ctypes.c_int32),
+                ("photon_sp", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class grpic_fields(ctypes.Structure):
@@ -68,6 +78,7 @@ class grpic_field_state(ctypes.Structure):
 
 
 EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_spline3", "grpic_charge3",
+            "grpic_push_deposit_qed",
             "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
@@ -105,6 +116,8 @@ def lib():
         L.grpic_push_deposit_vay.restype = ctypes.c_int
         L.grpic_push_deposit_spline3.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
         L.grpic_push_deposit_spline3.restype = ctypes.c_int
+        L.grpic_push_deposit_qed.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i64, i32, vp, vp, vp, vp, vp]
+        L.grpic_push_deposit_qed.restype = ctypes.c_int
         L.grpic_charge3.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge3.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -175,7 +188,7 @@ def particle_precision(parts: dict) -> int:
 
 def make_particles(parts: dict) -> grpic_particles:
     """dict of device tensors cell (int32), xr, xth, ur, uth, uph, w (float64 or
-    float32), sp (uint8), optional phi."""
+    float32), sp (uint8), optional phi, optional tag (int64, read as uint64)."""
     n = parts["cell"].numel()
     prec = particle_precision(parts)
     real = torch.float64 if prec == GRPIC_FP64 else torch.float32
@@ -186,7 +199,10 @@ def make_particles(parts: dict) -> grpic_particles:
     phi = parts.get("phi")
     if phi is not None:
         _need(phi, real, n, "phi")
-    return grpic_particles(n, *[_ptr(parts[k]) for k in PARTICLE_KEYS], _ptr(phi), prec, 0)
+    tag = parts.get("tag")
+    if tag is not None:
+        _need(tag, torch.int64, n, "tag")
+    return grpic_particles(n, *[_ptr(parts[k]) for k in PARTICLE_KEYS], _ptr(phi), prec, 0, _ptr(tag))
 
 
 def _grid_numel(g) -> int:
@@ -266,6 +282,37 @@ def grpic_push_deposit(metric: grpic_metric, grid, species, parts: dict, fields,
                                     ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(nsteps),
                                     int(ncorr), _ptr(ckpt), _nbytes(ckpt), int(ckpt_every), _ptr(counters),
                                     _stream(stream)))
+
+
+def make_qed(gamma_thr: float, eps_ph: float, tau: float, seed: int, electron_sp: int = 0, positron_sp: int = 1,
+             photon_sp: int = 2) -> grpic_qed:
+    return grpic_qed(float(gamma_thr), float(eps_ph), float(tau), int(seed) & ((1 << 64) - 1), int(electron_sp),
+                     int(positron_sp), int(photon_sp), 0)
+
+
+def grpic_push_deposit_qed(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float, step: int,
+                           qed: grpic_qed, n_used: torch.Tensor, ncorr: int = 3, tiling: torch.Tensor | None = None,
+                           counters: torch.Tensor | None = None, qcounters: torch.Tensor | None = None,
+                           stream=None) -> None:
+    """One step with photon emission and pair conversion.  parts: FP64 with a
+    "tag" tensor; its length is the capacity.  n_used: device int64 (2,),
+    n_used[0] the elements in use (updated on the device)."""
+    g = make_grid(grid)
+    sp = make_species(species)
+    P = make_particles(parts)
+    F = make_fields(grid, fields, torch.float64)
+    C = make_current(grid, J)
+    _need(n_used, torch.int64, 2, "n_used")
+    if counters is not None:
+        _need(counters, torch.int64, GRPIC_NCOUNTERS, "counters")
+    if qcounters is not None:
+        _need(qcounters, torch.int64, GRPIC_NQCOUNTERS, "qcounters")
+    if tiling is not None and (not tiling.is_cuda or not tiling.is_contiguous()):
+        raise ValueError("tiling: expected a contiguous device tensor")
+    _check(lib().grpic_push_deposit_qed(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
+                                        ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(step),
+                                        int(ncorr), ctypes.byref(qed), n_used.data_ptr(), _ptr(counters),
+                                        _ptr(qcounters), _stream(stream)))
 
 
 def grpic_checkpoint_bytes(n: int, nsteps: int, ckpt_every: int) -> int:
@@ -354,9 +401,10 @@ class Sorter:
     """Buffers for repeated grpic_sort calls on one grid and particle count:
     a spare particle set, the workspace, the tiling and the live count."""
 
-    def __init__(self, grid, n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda"):
+    def __init__(self, grid, n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda",
+                 with_tag: bool = False):
         self.grid = grid
-        self.spare = empty_particles(n, precision, with_phi, device)
+        self.spare = empty_particles(n, precision, with_phi, device, with_tag)
         self.ws = torch.empty(max(1, grpic_sort_workspace_bytes(grid, n)), dtype=torch.uint8, device=device)
         self.tiling = torch.empty(max(1, grpic_tiling_bytes(grid, n)), dtype=torch.uint8, device=device)
         self.n_alive = torch.zeros(1, dtype=torch.int64, device=device)
@@ -388,14 +436,22 @@ def to_device(parts_np: dict, precision: int = GRPIC_FP64, device="cuda") -> dic
         out[k] = torch.as_tensor(parts_np[k]).to(device=device, dtype=real)
     if "phi" in parts_np:
         out["phi"] = torch.as_tensor(parts_np["phi"]).to(device=device, dtype=real)
+    if "tag" in parts_np:
+        tag = np.ascontiguousarray(parts_np["tag"], dtype=np.uint64).view(np.int64)
+        out["tag"] = torch.as_tensor(tag).to(device)
     return out
 
 
 def to_host(parts: dict) -> dict:
-    return {k: v.detach().cpu().numpy() for k, v in parts.items()}
+    """Device particle tensors to numpy (tags back to uint64)."""
+    out = {k: v.detach().cpu().numpy() for k, v in parts.items()}
+    if "tag" in out:
+        out["tag"] = out["tag"].view(np.uint64)
+    return out
 
 
-def empty_particles(n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda") -> dict:
+def empty_particles(n: int, precision: int = GRPIC_FP64, with_phi: bool = False, device="cuda",
+                    with_tag: bool = False) -> dict:
     real = torch.float64 if precision == GRPIC_FP64 else torch.float32
     out = {"cell": torch.empty(n, dtype=torch.int32, device=device),
            "sp": torch.empty(n, dtype=torch.uint8, device=device)}
@@ -403,6 +459,8 @@ def empty_particles(n: int, precision: int = GRPIC_FP64, with_phi: bool = False,
         out[k] = torch.empty(n, dtype=real, device=device)
     if with_phi:
         out["phi"] = torch.empty(n, dtype=real, device=device)
+    if with_tag:
+        out["tag"] = torch.empty(n, dtype=torch.int64, device=device)
     return out
 
 

@@ -3,6 +3,7 @@ include/grpic.h declares, and its host-side logic (argument validation, the
 light-crossing bound) behaves as documented.  No device work is requested:
 every call here returns before any HIP call."""
 import ctypes
+import math
 import os
 import re
 
@@ -269,3 +270,47 @@ def test_spline3_entry_validation():
     assert call(g3, empty, dt) == grpic.GRPIC_OK
     G2 = grpic.make_grid(wl.make_grid(16, 16, 0.5))
     assert L.grpic_charge3(ctypes.byref(G2), sp, 2, ctypes.byref(parts), 0x1000, None) == grpic.GRPIC_EINVAL
+
+
+def test_qed_entry_validation():
+    """grpic_push_deposit_qed: FP64 particles with tags, a massless photon
+    species and massive leptons inside the species table, 1 < gamma_thr,
+    0 < eps_ph < sqrt(gamma_thr^2 - 1), tau >= 0, n_used given, and the
+    push's own checks; every call here returns before any launch."""
+    L = grpic.lib()
+    g = wl.make_grid(32, 32, 0.9)
+    G = grpic.make_grid(g)
+    m = grpic.make_metric(0.9, 1.0)
+    table = wl.qed_species_table()
+    sp = grpic.make_species(table)
+    fake = 0x1000
+    parts = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP64, 0, fake)
+    _, fields, cur = _fake_args(g)
+    dt = wl.crossing_dt(g)
+
+    def call(parts=parts, dt=dt, nsp=3, species=sp, n_used=fake, step=0, **kw):
+        q = dict(gamma_thr=100.0, eps_ph=4.0, tau=2.0, seed=1, electron_sp=0, positron_sp=1, photon_sp=2)
+        q.update(kw)
+        Q = grpic.make_qed(**q)
+        return L.grpic_push_deposit_qed(ctypes.byref(m), ctypes.byref(G), species, nsp, ctypes.byref(parts),
+                                        ctypes.byref(fields), ctypes.byref(cur), None, dt, step, 3,
+                                        ctypes.byref(Q), n_used, None, None, None)
+
+    notag = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP64, 0, None)
+    assert call(parts=notag) == grpic.GRPIC_EINVAL and b"tags" in L.grpic_last_error()
+    split = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP32_SPLIT, 0, fake)
+    assert call(parts=split) == grpic.GRPIC_EINVAL and b"FP64" in L.grpic_last_error()
+    assert call(n_used=None) == grpic.GRPIC_EINVAL and b"n_used" in L.grpic_last_error()
+    assert call(photon_sp=3) == grpic.GRPIC_EINVAL
+    assert call(photon_sp=1) == grpic.GRPIC_EINVAL and b"massless" in L.grpic_last_error()
+    assert call(electron_sp=2) == grpic.GRPIC_EINVAL and b"massive" in L.grpic_last_error()
+    assert call(gamma_thr=1.0) == grpic.GRPIC_EINVAL
+    assert call(eps_ph=0.0) == grpic.GRPIC_EINVAL
+    assert call(gamma_thr=3.0, eps_ph=math.sqrt(8.0)) == grpic.GRPIC_EINVAL       # eps_ph = |u| at threshold
+    assert call(tau=-1.0) == grpic.GRPIC_EINVAL
+    assert call(tau=float("nan")) == grpic.GRPIC_EINVAL
+    assert call(step=-1) == grpic.GRPIC_EINVAL
+    assert call(dt=-dt) == grpic.GRPIC_EINVAL
+    assert call(dt=2.01 * dt) == grpic.GRPIC_ERANGE
+    empty = grpic.grpic_particles(0, *([None] * 9), grpic.GRPIC_FP64, 0, None)
+    assert call(parts=empty) == grpic.GRPIC_OK
