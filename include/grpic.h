@@ -169,8 +169,9 @@ typedef struct {
  * dt > 0 must not exceed grpic_crossing_time(); ncorr in [0, 16].
  * ckpt (optional, device, ckpt_bytes >= grpic_checkpoint_bytes(n, nsteps,
  *   ckpt_every)): the particle state is saved before every step k with
- *   k % ckpt_every == 0, for grpic_push_deposit_backward (GRPIC_FP64 only;
- *   ckpt_every must divide nsteps).  NULL, 0, 0 when not needed.
+ *   k % ckpt_every == 0, for grpic_push_deposit_backward (in double; a
+ *   GRPIC_FP32_SPLIT state is promoted exactly; ckpt_every must divide
+ *   nsteps).  NULL, 0, 0 when not needed.
  * counters: optional device int64[GRPIC_NCOUNTERS], accumulated.
  */
 int grpic_push_deposit(const grpic_metric* metric, const grpic_grid* grid,
@@ -333,6 +334,46 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
                                 int ckpt_every, void* ws, size_t ws_bytes,
                                 const grpic_momentum_grads* grad_u, const grpic_field_grads* grad_fields,
                                 void* stream);
+
+/*
+ * grpic_push_deposit_backward_range -- grpic_push_deposit_backward for a
+ * range of the checkpointed particles and for fields that change from step
+ * to step (the push + deposit steps of a PIC loop whose field solver runs
+ * between them; the derivative does not pass through the field states,
+ * which are inputs here).
+ *
+ * range->first, range->count: the particles [first, first + count) of the
+ *   parts->n checkpointed ones are reversed; grad_u receives count entries
+ *   (entry k for particle first + k) and ws needs only
+ *   grpic_backward_workspace_bytes(grid, count, ckpt_every) bytes, so a
+ *   large set can be reversed in batches with one bounded workspace (field
+ *   gradients of successive batches add up).
+ * range->field_step_stride: 0 (every step gathers from `fields`) or the
+ *   distance in elements between the arrays of successive steps: step k of
+ *   the call gathers component c from fields->D[c] + k * stride (likewise
+ *   B), i.e. the fields the forward's step k saw.
+ * range->grad_step_stride: 0 (field gradients summed over the steps into
+ *   grad_fields) or the same distance for per-step gradient arrays.
+ * grad_fields: may be NULL (no field gradients).
+ * The checkpoints may come from a GRPIC_FP32_SPLIT forward (grpic_push_deposit
+ * saves the float states promoted exactly to double); the reverse then
+ * replays each segment in FP64 from its checkpoint, and parts must be a
+ * GRPIC_FP64 view of w and sp (the other arrays are not read).
+ * Otherwise arguments and errors as in grpic_push_deposit_backward; strides
+ * below one grid array are rejected (GRPIC_EINVAL).
+ */
+typedef struct {
+    int64_t first, count;
+    size_t field_step_stride;
+    size_t grad_step_stride;
+} grpic_backward_range;
+int grpic_push_deposit_backward_range(const grpic_metric* metric, const grpic_grid* grid,
+                                      const grpic_species* species, int nsp, const grpic_particles* parts,
+                                      const grpic_fields* fields, const grpic_current* lambda,
+                                      double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
+                                      int ckpt_every, const grpic_backward_range* range, void* ws,
+                                      size_t ws_bytes, const grpic_momentum_grads* grad_u,
+                                      const grpic_field_grads* grad_fields, void* stream);
 
 /*
  * grpic_charge -- Q_ij += sum over live particles of q w S_ij(x_p), the CIC

@@ -636,16 +636,21 @@ struct DualArray {                       /* value and tangent arrays as one Dual
     Dual operator[](long e) const { return Dual(v[e], d ? d[e] : 0.0); }
 };
 
+/* The field arrays of step n when each component's states of successive
+ * steps lie `stride` elements apart (stride 0: the same fields every step). */
+inline const double* at_step(const double* a, long off) { return a + off; }
+inline DualArray at_step(const DualArray& a, long off) { return DualArray{a.v + off, a.d ? a.d + off : nullptr}; }
+
 template <class T, class Arr>
 int particle_loss(const Geom& g, const Species& sp, const Arr* fld, const double* const* lam,
                   double w, double dt, int nsteps, int ncorr, T xi, T eta, T u[3], T& L,
-                  double* traj = nullptr) {
+                  double* traj = nullptr, long fstride = 0) {
     for (int n = 0; n < nsteps; ++n) {
         if (traj) { traj[2 * n] = val(xi); traj[2 * n + 1] = val(eta); }
         T D[3], B[3];
         for (int c = 0; c < 3; ++c) {
-            D[c] = cic_gather(g, fld[c], kStagR[c], kStagT[c], xi, eta);
-            B[c] = cic_gather(g, fld[3 + c], kStagR[3 + c], kStagT[3 + c], xi, eta);
+            D[c] = cic_gather(g, at_step(fld[c], n * fstride), kStagR[c], kStagT[c], xi, eta);
+            B[c] = cic_gather(g, at_step(fld[3 + c], n * fstride), kStagR[3 + c], kStagT[3 + c], xi, eta);
         }
         T y1[6];
         push_with_fields(g, sp, dt, ncorr, xi, eta, u, D, B, y1);
@@ -943,11 +948,32 @@ void orc_run(const Geom* gp, const Species* sp, int nsp, int64_t n,
  * out[0] = L, out[1] = dL/deps, Neumaier-summed over particles.
  * status (optional, per particle): 0 alive after nsteps, 1 left radially,
  * 2 removed as bad, -1 not taken (removed or invalid input).            */
+void orc_loss_dual_steps(const Geom* gp, const Species* sp, int nsp, int64_t n, const int32_t* cell,
+                         const double* xr, const double* xth, const double* ur, const double* uth,
+                         const double* uph, const double* w, const uint8_t* spi, const double* tur,
+                         const double* tuth, const double* tuph, const double* const* F, const double* const* tF,
+                         long fstride, const double* const* lam, double dt, int nsteps, int ncorr, double* out,
+                         int32_t* status);
+
 void orc_loss_dual(const Geom* gp, const Species* sp, int nsp, int64_t n, const int32_t* cell,
                    const double* xr, const double* xth, const double* ur, const double* uth, const double* uph,
                    const double* w, const uint8_t* spi, const double* tur, const double* tuth, const double* tuph,
                    const double* const* F, const double* const* tF, const double* const* lam,
                    double dt, int nsteps, int ncorr, double* out, int32_t* status) {
+    orc_loss_dual_steps(gp, sp, nsp, n, cell, xr, xth, ur, uth, uph, w, spi, tur, tuth, tuph, F, tF, 0, lam, dt,
+                        nsteps, ncorr, out, status);
+}
+
+/* orc_loss_dual with fields that change from step to step: component c of
+ * step k at F[c] + k * fstride (tangents likewise), as a field solver
+ * between the pushes would leave them; the derivative does not pass through
+ * the field states (they are inputs). */
+void orc_loss_dual_steps(const Geom* gp, const Species* sp, int nsp, int64_t n, const int32_t* cell,
+                         const double* xr, const double* xth, const double* ur, const double* uth,
+                         const double* uph, const double* w, const uint8_t* spi, const double* tur,
+                         const double* tuth, const double* tuph, const double* const* F, const double* const* tF,
+                         long fstride, const double* const* lam, double dt, int nsteps, int ncorr, double* out,
+                         int32_t* status) {
     const Geom& g = *gp;
     DualArray fd[6];
     for (int c = 0; c < 6; ++c) fd[c] = DualArray{F[c], tF ? tF[c] : nullptr};
@@ -967,7 +993,7 @@ void orc_loss_dual(const Geom* gp, const Species* sp, int nsp, int64_t n, const 
                      Dual(uph[p], tuph ? tuph[p] : 0.0)};
         Dual L(0.0, 0.0);
         const int st = particle_loss(g, sp[spi[p]], fd, lam, w[p], dt, nsteps, ncorr, Dual(ci + xr[p]),
-                                     Dual(cj + xth[p]), u, L);
+                                     Dual(cj + xth[p]), u, L, nullptr, fstride);
         nadd(s0, c0, L.v);
         nadd(s1, c1, L.d);
         if (status) status[p] = st;

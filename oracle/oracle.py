@@ -388,6 +388,42 @@ def loss_dual(grid, species, parts, fields, lam, dt, nsteps, ncorr: int = 3, tu=
     return float(out[0]), float(out[1]), status
 
 
+def loss_dual_steps(grid, species, parts, field_steps, lam, dt, ncorr: int = 3, tu=None):
+    """loss_dual over the steps of field_steps, whose fields change from step
+    to step: field_steps[k] holds the six arrays step k gathers from, or
+    field_steps is one float64 array of shape (6, nsteps, rows, pitch)
+    (inputs; the derivative is along tu only).  Returns (L, dL, status per
+    particle)."""
+    g = geom(grid)
+    sp = _species_array(species)
+    n = len(parts["cell"])
+    shape = (grid.nr + 1 + 2 * grid.guard, grid.pitch)
+    if isinstance(field_steps, np.ndarray):
+        if field_steps.ndim != 4 or field_steps.shape[0] != 6 or field_steps.shape[2:] != shape:
+            raise ValueError("field_steps: expected shape (6, nsteps, rows, pitch)")
+        nsteps = field_steps.shape[1]
+        stacked = [np.ascontiguousarray(field_steps[c], dtype=np.float64) for c in range(6)]
+    else:
+        nsteps = len(field_steps)
+        stacked = [np.ascontiguousarray(np.stack([np.asarray(fs[c], dtype=np.float64).reshape(shape)
+                                                  for fs in field_steps])) for c in range(6)]
+    fptr = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in stacked])
+    cell = np.ascontiguousarray(parts["cell"], dtype=np.int32)
+    arrs = {k: _f64(parts[k]) for k in ("xr", "xth", "ur", "uth", "uph", "w")}
+    spi = np.ascontiguousarray(parts["sp"], dtype=np.uint8)
+    tus = [None, None, None] if tu is None else [_f64(t) for t in tu]
+    L, keepL = _ptrs(lam)
+    out = np.zeros(2)
+    status = np.zeros(n, dtype=np.int32)
+    null = ctypes.c_void_p(0)
+    lib().orc_loss_dual_steps(ctypes.byref(g), sp, ctypes.c_int(len(species)), ctypes.c_int64(n), _p(cell),
+                              _p(arrs["xr"]), _p(arrs["xth"]), _p(arrs["ur"]), _p(arrs["uth"]), _p(arrs["uph"]),
+                              _p(arrs["w"]), _p(spi), *[null if t is None else _p(t) for t in tus],
+                              fptr, null, ctypes.c_long(shape[0] * shape[1]), L, ctypes.c_double(dt),
+                              ctypes.c_int(nsteps), ctypes.c_int(ncorr), _p(out), _p(status))
+    return float(out[0]), float(out[1]), status
+
+
 def loss_particle(grid, species_row, xi, eta, u, w, fields, lam, dt, nsteps, ncorr: int = 3, trajectory=False):
     """L of one particle on plain doubles; returns (L, status) or, with
     trajectory, (L, status, positions (nsteps + 1, 2), nan after removal)."""

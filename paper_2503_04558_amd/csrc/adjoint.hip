@@ -22,22 +22,25 @@ namespace grpic {
 size_t checkpoint_slot_bytes(int64_t n) { return slot_cell_bytes(n) + (size_t)n * 5 * 8; }
 int adj_max_corr() { return adj::kMaxCorr; }
 
+// The state before a step, in double whatever the particles' precision (a
+// float state is promoted exactly).
+template <class T>
 __global__ __launch_bounds__(256) void save_state(const StepArgs A, char* slot) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
     int32_t* cell = reinterpret_cast<int32_t*>(slot);
     double* d = reinterpret_cast<double*>(slot + slot_cell_bytes(A.n));
     cell[p] = A.cell[p];
-    const double* src[5] = {static_cast<const double*>(A.xr), static_cast<const double*>(A.xth),
-                            static_cast<const double*>(A.ur), static_cast<const double*>(A.uth),
-                            static_cast<const double*>(A.uph)};
-    for (int k = 0; k < 5; ++k) d[(int64_t)k * A.n + p] = src[k][p];
+    const T* src[5] = {static_cast<const T*>(A.xr), static_cast<const T*>(A.xth), static_cast<const T*>(A.ur),
+                       static_cast<const T*>(A.uth), static_cast<const T*>(A.uph)};
+    for (int k = 0; k < 5; ++k) d[(int64_t)k * A.n + p] = (double)src[k][p];
 }
 
-hipError_t launch_save_state(const StepArgs& A, void* slot, hipStream_t stream) {
+hipError_t launch_save_state(const StepArgs& A, bool split, void* slot, hipStream_t stream) {
     if (A.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(save_state, dim3((unsigned)((A.n + 255) / 256)), dim3(256), 0, stream, A,
-                       static_cast<char*>(slot));
+    const dim3 g((unsigned)((A.n + 255) / 256));
+    if (split) hipLaunchKernelGGL(save_state<float>, g, dim3(256), 0, stream, A, static_cast<char*>(slot));
+    else hipLaunchKernelGGL(save_state<double>, g, dim3(256), 0, stream, A, static_cast<char*>(slot));
     return hipGetLastError();
 }
 
@@ -94,18 +97,18 @@ __global__ __launch_bounds__(kBackThreads) void push_deposit_backward_f64(const 
     __shared__ double acc[6][4][kBackThreads];
     __shared__ long base[6][kBackThreads];
     const int t = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + t;
-    if (p >= B.n) return;                       // (no barrier below: the slots are per thread)
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + t;
+    if (q >= B.count) return;                   // (no barrier below: the slots are per thread)
     for (int c = 0; c < 6; ++c) base[c][t] = -1;
     auto flush = [&](int c) {
         const long e = base[c][t];
-        if (e < 0) return;
+        if (e < 0 || !B.gradF[c]) return;
         double* g = B.gradF[c];
         const long off[4] = {0, B.pitch, 1, B.pitch + 1};
         for (int k = 0; k < 4; ++k)
             if (acc[c][k][t] != 0.0) atomicAdd(g + e + off[k], acc[c][k][t]);
     };
-    backward_particle<NC>(B, p, [&](int c, long e, double g00, double g10, double g01, double g11) {
+    backward_particle<NC>(B, q, [&](int c, long e, double g00, double g10, double g01, double g11) {
         if (base[c][t] != e) {
             flush(c);
             base[c][t] = e;
@@ -128,7 +131,7 @@ size_t backward_aux_bytes(int rows, int pitch) {
 }
 
 hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t stream) {
-    if (B.n <= 0) return hipSuccess;
+    if (B.count <= 0) return hipSuccess;
     int* row_flag = static_cast<int*>(aux);
     int* col_flag = row_flag + B.rows;
     int* row_pre = col_flag + B.pitch;
@@ -138,7 +141,7 @@ hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t strea
     hipLaunchKernelGGL(lam_row_any, dim3((unsigned)B.rows), dim3(256), 0, stream, B, row_flag);
     hipLaunchKernelGGL(lam_col_any, dim3((unsigned)((B.pitch + 255) / 256)), dim3(256), 0, stream, B, col_flag);
     hipLaunchKernelGGL(lam_prefix, dim3(1), dim3(128), 0, stream, B, row_flag, col_flag, row_pre, col_pre);
-    const dim3 grid((unsigned)((B.n + kBackThreads - 1) / kBackThreads));
+    const dim3 grid((unsigned)((B.count + kBackThreads - 1) / kBackThreads));
     if (B.ncorr == kFastCorr)
         hipLaunchKernelGGL(push_deposit_backward_f64<kFastCorr>, grid, dim3(kBackThreads), 0, stream, B);
     else

@@ -269,7 +269,6 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
     if (nsteps < 0) return fail(GRPIC_EINVAL, "nsteps < 0");
     if (ncorr < 0 || ncorr > 16) return fail(GRPIC_EINVAL, "ncorr must be in [0, 16]");
     if (ckpt) {
-        if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "checkpoints need GRPIC_FP64 particles");
         if (ckpt_every < 1 || nsteps % ckpt_every != 0)
             return fail(GRPIC_EINVAL, "ckpt_every must be >= 1 and divide nsteps");
         const size_t need = grpic_checkpoint_bytes(parts->n, nsteps, ckpt_every);
@@ -301,7 +300,9 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
     for (int step = 0; step < nsteps; ++step) {
         if (ckpt && step % ckpt_every == 0) {
             void* dst = static_cast<char*>(ckpt) + (size_t)(step / ckpt_every) * slot;
-            if ((rc = hip_status(grpic::launch_save_state(A, dst, s), "checkpoint launch"))) return rc;
+            if ((rc = hip_status(grpic::launch_save_state(A, parts->precision == GRPIC_FP32_SPLIT, dst, s),
+                                 "checkpoint launch")))
+                return rc;
         }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
         const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick, order)
@@ -423,28 +424,38 @@ size_t grpic_backward_workspace_bytes(const grpic_grid* grid, int64_t n, int ckp
     return backward_state_bytes(n, ckpt_every) + grpic::backward_aux_bytes(grid->nr + 1 + 2 * grid->guard, grid->pitch);
 }
 
-int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
-                                const grpic_species* species, int nsp, const grpic_particles* parts,
-                                const grpic_fields* fields, const grpic_current* lambda,
-                                double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
-                                int ckpt_every, void* ws, size_t ws_bytes,
-                                const grpic_momentum_grads* grad_u, const grpic_field_grads* grad_fields,
-                                void* stream) {
+static int backward_checked(const grpic_metric* metric, const grpic_grid* grid, const grpic_species* species,
+                            int nsp, const grpic_particles* parts, const grpic_fields* fields,
+                            const grpic_current* lambda, double dt, int nsteps, int ncorr, const void* ckpt,
+                            size_t ckpt_bytes, int ckpt_every, const grpic_backward_range* range, void* ws,
+                            size_t ws_bytes, const grpic_momentum_grads* grad_u,
+                            const grpic_field_grads* grad_fields, void* stream) {
     int rc;
-    if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
-        (rc = check_particles(parts, "parts")))
+    if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)))
         return rc;
+    // the reverse reads w and sp of the particles (their states come from the checkpoints)
+    if (!parts) return fail(GRPIC_EINVAL, "parts is NULL");
+    if (parts->n < 0) return fail(GRPIC_EINVAL, "parts: n < 0");
     if (parts->precision != GRPIC_FP64) return fail(GRPIC_EINVAL, "the adjoint needs GRPIC_FP64 particles");
+    const int64_t first = range ? range->first : 0, count = range ? range->count : parts->n;
+    if (first < 0 || count < 0 || first > parts->n || count > parts->n - first)
+        return fail(GRPIC_EINVAL, "range: [first, first + count) must lie in [0, n)");
     if (!fields) return fail(GRPIC_EINVAL, "fields is NULL");
     for (int c = 0; c < 3; ++c)
         if (!fields->D[c] || !fields->B[c]) return fail(GRPIC_EINVAL, "fields: NULL component");
     if (!lambda || !lambda->Fr || !lambda->Fth || !lambda->Gph) return fail(GRPIC_EINVAL, "lambda: NULL array");
     if (!grad_u) return fail(GRPIC_EINVAL, "grad_u is NULL");
-    if (parts->n > 0 && (!grad_u->ur || !grad_u->uth || !grad_u->uph))
+    if (count > 0 && (!grad_u->ur || !grad_u->uth || !grad_u->uph))
         return fail(GRPIC_EINVAL, "grad_u: NULL array");
-    if (!grad_fields) return fail(GRPIC_EINVAL, "grad_fields is NULL");
-    for (int c = 0; c < 3; ++c)
-        if (!grad_fields->D[c] || !grad_fields->B[c]) return fail(GRPIC_EINVAL, "grad_fields: NULL component");
+    const bool want_fields = grad_fields != nullptr;
+    if (!range && !want_fields) return fail(GRPIC_EINVAL, "grad_fields is NULL");
+    if (want_fields)
+        for (int c = 0; c < 3; ++c)
+            if (!grad_fields->D[c] || !grad_fields->B[c]) return fail(GRPIC_EINVAL, "grad_fields: NULL component");
+    const size_t plane = (size_t)(grid->nr + 1 + 2 * grid->guard) * (size_t)grid->pitch;
+    if (range && ((range->field_step_stride != 0 && range->field_step_stride < plane) ||
+                  (range->grad_step_stride != 0 && range->grad_step_stride < plane)))
+        return fail(GRPIC_EINVAL, "range: step strides must be 0 or at least one grid array (%zu elements)", plane);
     if (!(dt > 0.0) || !isfinite(dt)) return fail(GRPIC_EINVAL, "dt must be positive and finite");
     if (ncorr < 0 || ncorr > grpic::adj_max_corr()) return fail(GRPIC_EINVAL, "ncorr must be in [0, %d] for the adjoint",
                                                                  grpic::adj_max_corr());
@@ -452,9 +463,9 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
         return fail(GRPIC_EINVAL, "need nsteps >= 1 and ckpt_every >= 1 dividing nsteps");
     if ((parts->n > 0 && !ckpt) || ckpt_bytes < grpic_checkpoint_bytes(parts->n, nsteps, ckpt_every))
         return fail(GRPIC_ENOMEM, "checkpoint buffer too small or NULL");
-    if ((parts->n > 0 && !ws) || ws_bytes < grpic_backward_workspace_bytes(grid, parts->n, ckpt_every))
+    if ((count > 0 && !ws) || ws_bytes < grpic_backward_workspace_bytes(grid, count, ckpt_every))
         return fail(GRPIC_ENOMEM, "backward workspace needs %zu bytes, got %zu",
-                    grpic_backward_workspace_bytes(grid, parts->n, ckpt_every), ws_bytes);
+                    grpic_backward_workspace_bytes(grid, count, ckpt_every), ws_bytes);
     const double tc = crossing_time_cached(metric, grid);
     if (dt > tc * (1.0 + 1e-12))
         return fail(GRPIC_ERANGE, "dt = %.17g exceeds the cell light-crossing time %.17g", dt, tc);
@@ -467,22 +478,49 @@ int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* gr
     B.dt = dt; B.ncorr = ncorr; B.nsteps = nsteps; B.ckpt_every = ckpt_every; B.nsp = nsp;
     for (int i = 0; i < nsp; ++i) { B.q[i] = species[i].q; B.m[i] = species[i].m; B.massless[i] = species[i].massless; }
     B.n = parts->n;
+    B.first = first;
+    B.count = count;
+    B.fstride = range ? range->field_step_stride : 0;
+    B.gstride = range ? range->grad_step_stride : 0;
     B.w = static_cast<const double*>(parts->w);
     B.sp = parts->sp;
     for (int c = 0; c < 3; ++c) {
         B.F[c] = static_cast<const double*>(fields->D[c]);
         B.F[3 + c] = static_cast<const double*>(fields->B[c]);
-        B.gradF[c] = grad_fields->D[c];
-        B.gradF[3 + c] = grad_fields->B[c];
+        B.gradF[c] = want_fields ? grad_fields->D[c] : nullptr;
+        B.gradF[3 + c] = want_fields ? grad_fields->B[c] : nullptr;
     }
     B.lam[0] = lambda->Fr; B.lam[1] = lambda->Fth; B.lam[2] = lambda->Gph;
     B.ckpt = ckpt;
     B.slot_bytes = grpic::checkpoint_slot_bytes(parts->n);
     B.ws = static_cast<double*>(ws);
     B.rows = grid->nr + 1 + 2 * grid->guard;
-    void* aux = static_cast<char*>(ws) + backward_state_bytes(parts->n, ckpt_every);
+    void* aux = static_cast<char*>(ws) + backward_state_bytes(count, ckpt_every);
     B.grad_u[0] = grad_u->ur; B.grad_u[1] = grad_u->uth; B.grad_u[2] = grad_u->uph;
     return hip_status(grpic::launch_push_deposit_backward(B, aux, static_cast<hipStream_t>(stream)), "backward launch");
+}
+
+int grpic_push_deposit_backward(const grpic_metric* metric, const grpic_grid* grid,
+                                const grpic_species* species, int nsp, const grpic_particles* parts,
+                                const grpic_fields* fields, const grpic_current* lambda,
+                                double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
+                                int ckpt_every, void* ws, size_t ws_bytes,
+                                const grpic_momentum_grads* grad_u, const grpic_field_grads* grad_fields,
+                                void* stream) {
+    return backward_checked(metric, grid, species, nsp, parts, fields, lambda, dt, nsteps, ncorr, ckpt, ckpt_bytes,
+                            ckpt_every, nullptr, ws, ws_bytes, grad_u, grad_fields, stream);
+}
+
+int grpic_push_deposit_backward_range(const grpic_metric* metric, const grpic_grid* grid,
+                                      const grpic_species* species, int nsp, const grpic_particles* parts,
+                                      const grpic_fields* fields, const grpic_current* lambda,
+                                      double dt, int nsteps, int ncorr, const void* ckpt, size_t ckpt_bytes,
+                                      int ckpt_every, const grpic_backward_range* range, void* ws,
+                                      size_t ws_bytes, const grpic_momentum_grads* grad_u,
+                                      const grpic_field_grads* grad_fields, void* stream) {
+    if (!range) return fail(GRPIC_EINVAL, "range is NULL");
+    return backward_checked(metric, grid, species, nsp, parts, fields, lambda, dt, nsteps, ncorr, ckpt, ckpt_bytes,
+                            ckpt_every, range, ws, ws_bytes, grad_u, grad_fields, stream);
 }
 
 static int charge(const grpic_grid* grid, const grpic_species* species, int nsp,

@@ -27,14 +27,18 @@ __host__ __device__ inline bool all_zero(const double a[5]) {
     return a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0 && a[3] == 0.0 && a[4] == 0.0;
 }
 
-// The reverse sweep of particle p (one thread per particle on the GPU).
+// The reverse sweep of particle p (one thread per particle on the GPU), the
+// q-th of the batch [first, first + count).
 // With a zero cotangent a step (or a whole segment)
 // whose deposit window(s) cannot touch a non-zero lambda contributes nothing
 // and is skipped: a move is below one cell per step, so a segment of C steps
 // from a checkpoint in cell (i, j) deposits only on vertices within C + 2 of it.
+// Step k gathers from the field arrays B.F[c] + k fstride and its field
+// cotangents go to element e + k gstride of the gradient arrays.
 template <int NC, class AddF>
-__host__ __device__ inline void backward_particle(const BackArgs& B, int64_t p, AddF addF) {
-    const int64_t n = B.n;
+__host__ __device__ inline void backward_particle(const BackArgs& B, int64_t q, AddF addF) {
+    const int64_t n = B.n, nb = B.count;
+    const int64_t p = B.first + q;
     const int ncorr = NC == kFastCorr ? kFastCorr : B.ncorr;
     const adj::Geo G{B.a, B.M, B.lnr0, B.dlnr, B.dth, B.nr, B.nth, B.guard, B.pitch, 1.0 / B.dlnr, 1.0 / B.dth};
     const int s = B.sp[p];
@@ -45,7 +49,7 @@ __host__ __device__ inline void backward_particle(const BackArgs& B, int64_t p, 
         const double qw = B.q[s] * B.w[p];
         const int C = B.ckpt_every;
         const int nseg = B.nsteps / C;
-        double* ws = B.ws;                                       // [m][component][particle]
+        double* ws = B.ws;                                       // [m][component][batch particle]
         for (int seg = nseg - 1; seg >= 0; --seg) {
             const char* slot = static_cast<const char*>(B.ckpt) + (size_t)seg * B.slot_bytes;
             const int32_t cell = reinterpret_cast<const int32_t*>(slot)[p];
@@ -60,15 +64,18 @@ __host__ __device__ inline void backward_particle(const BackArgs& B, int64_t p, 
             // start-of-step states of the segment (xi = NaN marks a removed particle)
             bool alive = true;
             for (int m = 0; m < C; ++m) {
-                double* w = ws + (size_t)m * 5 * n;
-                w[p] = alive ? xi : NAN;
-                w[n + p] = eta;
-                w[2 * n + p] = u[0];
-                w[3 * n + p] = u[1];
-                w[4 * n + p] = u[2];
+                double* w = ws + (size_t)m * 5 * nb;
+                w[q] = alive ? xi : NAN;
+                w[nb + q] = eta;
+                w[2 * nb + q] = u[0];
+                w[3 * nb + q] = u[1];
+                w[4 * nb + q] = u[2];
                 if (!alive) continue;
+                const size_t fo = (size_t)(seg * C + m) * B.fstride;
+                const double* const Fk[6] = {B.F[0] + fo, B.F[1] + fo, B.F[2] + fo,
+                                             B.F[3] + fo, B.F[4] + fo, B.F[5] + fo};
                 adj::StepTape<NC> T;
-                const int st = adj::replay_step(G, B.F, qm, massless, B.dt, ncorr, xi, eta, u, T);
+                const int st = adj::replay_step(G, Fk, qm, massless, B.dt, ncorr, xi, eta, u, T);
                 if (st != adj::ST_ALIVE) { alive = false; continue; }
                 xi = T.xi1;
                 eta = T.eta1;
@@ -77,22 +84,30 @@ __host__ __device__ inline void backward_particle(const BackArgs& B, int64_t p, 
                 u[2] = T.up[2];
             }
             for (int m = C - 1; m >= 0; --m) {
-                const double* w = ws + (size_t)m * 5 * n;
-                const double x0 = w[p];
+                const double* w = ws + (size_t)m * 5 * nb;
+                const double x0 = w[q];
                 if (isnan(x0)) continue;
-                const double e0 = w[n + p];
+                const double e0 = w[nb + q];
                 const int fi = (int)floor(x0), fj = (int)floor(e0);
                 if (all_zero(a) && !lam_in_box(B, fi - 1, fi + 2, fj - 1, fj + 2)) continue;
-                const double u0[3] = {w[2 * n + p], w[3 * n + p], w[4 * n + p]};
+                const double u0[3] = {w[2 * nb + q], w[3 * nb + q], w[4 * nb + q]};
+                const size_t k = (size_t)(seg * C + m);
+                const size_t fo = k * B.fstride;
+                const long go = (long)(k * B.gstride);
+                const double* const Fk[6] = {B.F[0] + fo, B.F[1] + fo, B.F[2] + fo,
+                                             B.F[3] + fo, B.F[4] + fo, B.F[5] + fo};
                 adj::StepTape<NC> T;
-                adj::replay_step(G, B.F, qm, massless, B.dt, ncorr, x0, e0, u0, T);
-                adj::reverse_step(G, B.F, B.lam, qm, massless, qw, B.dt, ncorr, T, a, addF);
+                adj::replay_step(G, Fk, qm, massless, B.dt, ncorr, x0, e0, u0, T);
+                adj::reverse_step(G, Fk, B.lam, qm, massless, qw, B.dt, ncorr, T, a,
+                                  [&](int c, long e, double g00, double g10, double g01, double g11) {
+                                      addF(c, e + go, g00, g10, g01, g11);
+                                  });
             }
         }
     }
-    B.grad_u[0][p] = a[2];
-    B.grad_u[1][p] = a[3];
-    B.grad_u[2][p] = a[4];
+    B.grad_u[0][q] = a[2];
+    B.grad_u[1][q] = a[3];
+    B.grad_u[2][q] = a[4];
 }
 
 }  // namespace grpic

@@ -123,9 +123,11 @@ struct BackArgs {
     const double* lam[3];             // dL/dF^r, dL/dF^th, dL/dG^ph
     const void* ckpt;
     size_t slot_bytes;
-    double* ws;                       // ckpt_every * 5 * n doubles
-    double* grad_u[3];                // out: dL/du_r, dL/du_th, dL/du_ph at step 0
-    double* gradF[6];                 // += dL/dD^i, dL/dB^i
+    int64_t first, count;             // the particles [first, first + count) of the checkpointed n
+    size_t fstride, gstride;          // elements between steps' field (gradient) arrays; 0: one set for all steps
+    double* ws;                       // ckpt_every * 5 * count doubles
+    double* grad_u[3];                // out: dL/du_r, dL/du_th, dL/du_ph at step 0 (count entries)
+    double* gradF[6];                 // += dL/dD^i, dL/dB^i (NULL: not wanted)
     int rows;                         // storage rows of the grid arrays (nr + 1 + 2 guard)
     const int* row_pre;               // lambda support, set by the launcher
     const int* col_pre;
@@ -133,12 +135,13 @@ struct BackArgs {
 
 size_t checkpoint_slot_bytes(int64_t n);
 int adj_max_corr();
-hipError_t launch_save_state(const StepArgs& A, void* slot, hipStream_t stream);
+hipError_t launch_save_state(const StepArgs& A, bool split, void* slot, hipStream_t stream);
 size_t backward_aux_bytes(int rows, int pitch);
 hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t stream);
 
 int64_t sort_scan_blocks(int64_t len);
 size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
+
 
 }  // namespace grpic

@@ -73,12 +73,17 @@ class grpic_field_grads(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
 
 
+class grpic_backward_range(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_int64), ("count", ctypes.c_int64), ("field_step_stride", ctypes.c_size_t),
+                ("grad_step_stride", ctypes.c_size_t)]
+
+
 class grpic_field_state(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3)]
 
 
 EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_spline3", "grpic_charge3",
-            "grpic_push_deposit_qed",
+            "grpic_push_deposit_qed", "grpic_push_deposit_backward_range",
             "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
@@ -107,6 +112,9 @@ def lib():
         L.grpic_push_deposit_backward.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, sz, i32, vp, sz,
                                                   vp, vp, vp]
         L.grpic_push_deposit_backward.restype = ctypes.c_int
+        L.grpic_push_deposit_backward_range.argtypes = [vp, vp, vp, i32, vp, vp, vp, f64, i32, i32, vp, sz, i32, vp,
+                                                        vp, sz, vp, vp, vp]
+        L.grpic_push_deposit_backward_range.restype = ctypes.c_int
         L.grpic_checkpoint_bytes.argtypes = [i64, i32, i32]
         L.grpic_checkpoint_bytes.restype = sz
         L.grpic_backward_workspace_bytes.argtypes = [vp, i64, i32]
@@ -353,6 +361,53 @@ def grpic_push_deposit_backward(metric: grpic_metric, grid, species, parts: dict
                                              int(nsteps), int(ncorr), ckpt.data_ptr(), _nbytes(ckpt),
                                              int(ckpt_every), ws.data_ptr(), _nbytes(ws), ctypes.byref(GU),
                                              ctypes.byref(GFg), _stream(stream)))
+
+
+def grpic_push_deposit_backward_range(metric: grpic_metric, grid, species, parts: dict, fields, lam, dt: float,
+                                      nsteps: int, ncorr: int, ckpt: torch.Tensor, ckpt_every: int, first: int,
+                                      count: int, ws: torch.Tensor, grad_u, grad_fields=None,
+                                      field_step_stride: int = 0, grad_step_stride: int = 0, stream=None) -> None:
+    """grpic_push_deposit_backward for particles [first, first + count) of the
+    checkpointed set (parts: float64 w and sp of all of them).  fields: the six
+    step-0 arrays; with field_step_stride > 0 each is the first of nsteps
+    arrays that far apart (e.g. views into a (nsteps, rows, pitch) tensor).
+    grad_u: three float64 tensors of count entries; grad_fields: None or six
+    arrays (per step with grad_step_stride > 0)."""
+    g = make_grid(grid)
+    sp = make_species(species)
+    n = parts["w"].numel()
+    _need(parts["w"], torch.float64, n, "w")
+    _need(parts["sp"], torch.uint8, n, "sp")
+    P = grpic_particles(n, None, None, None, None, None, None, parts["w"].data_ptr(), parts["sp"].data_ptr(), None,
+                        GRPIC_FP64, 0, None)
+    for i, f in enumerate(fields):
+        if not f.is_cuda or f.dtype != torch.float64 or not f.is_contiguous():
+            raise ValueError(f"field {i}: expected a contiguous float64 device tensor")
+    span = _grid_numel(grid) + (int(nsteps) - 1) * int(field_step_stride)
+    for i, f in enumerate(fields):
+        if f.untyped_storage().nbytes() - f.storage_offset() * 8 < span * 8:
+            raise ValueError(f"field {i}: storage shorter than nsteps arrays at the given stride")
+    F = grpic_fields()
+    for c in range(3):
+        F.D[c] = fields[c].data_ptr()
+        F.B[c] = fields[3 + c].data_ptr()
+    Lm = make_current(grid, lam)
+    for i, t in enumerate(grad_u):
+        _need(t, torch.float64, int(count), f"grad_u {i}")
+    GU = grpic_momentum_grads(*[t.data_ptr() for t in grad_u])
+    GFg = None
+    if grad_fields is not None:
+        GFg = grpic_field_grads()
+        for c in range(3):
+            GFg.D[c] = grad_fields[c].data_ptr()
+            GFg.B[c] = grad_fields[3 + c].data_ptr()
+    R = grpic_backward_range(int(first), int(count), int(field_step_stride), int(grad_step_stride))
+    _check(lib().grpic_push_deposit_backward_range(ctypes.byref(metric), ctypes.byref(g), sp, len(species),
+                                                   ctypes.byref(P), ctypes.byref(F), ctypes.byref(Lm), float(dt),
+                                                   int(nsteps), int(ncorr), ckpt.data_ptr(), _nbytes(ckpt),
+                                                   int(ckpt_every), ctypes.byref(R), ws.data_ptr(), _nbytes(ws),
+                                                   ctypes.byref(GU), None if GFg is None else ctypes.byref(GFg),
+                                                   _stream(stream)))
 
 
 def grpic_charge(grid, species, parts: dict, Q: torch.Tensor, stream=None, order: int = 1) -> None:

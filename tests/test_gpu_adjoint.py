@@ -298,3 +298,53 @@ def test_generic_corrector_count_and_mixed_species(ncorr):
     _, dL, _ = orc.loss_dual(g, species, parts, fields, lam, dt, nsteps, ncorr=ncorr, tF=tF)
     got = sum(float((a * t).sum()) for a, t in zip(gF, tF))
     assert got == pytest.approx(dL, rel=1e-9)
+
+
+def test_adjoint_full_set_sampled_against_oracle():
+    """The adjoint workload's whole set, the one bench.py times: 512^2,
+    a = 0.9, 1e6 Maxwell-Juttner e+- (T = 0.5), K = 32 steps with
+    checkpoints every 8, the shell loss at r = 5; sorted + tiled forward,
+    backward over all 1e6 particles.  2,000 sampled particles (1,000 of
+    those starting within reach of the shell, 1,000 from the whole set)
+    against the oracle's dual numbers run on each alone, at the bar of
+    test_momentum_gradient_matches_oracle_dual; a particle that never comes
+    near the shell must get exactly zero on both sides."""
+    _announce("adjoint full set 512x512 1e6: forward + backward, 2000 sampled")
+    g = wl.make_grid(512, 512, 0.9)
+    dt = wl.crossing_dt(g)
+    fields = wl.wald_fields(g, B0=1.0)
+    parts = wl.pairs(g, 500_000, kind="mj", seed=0, params=dict(T=0.5), workers=8)
+    sp = wl.species_table()
+    from adjoint_cases import shell_lambda
+    lam = shell_lambda(g, dt)
+    start, F, J, ck, order = forward(g, sp, parts, fields, dt, tiled=True)
+    gu, _ = backward(g, sp, start, F, lam, dt, ck)
+    cells = start["cell"].cpu().numpy()
+    n_alive = int((cells >= 0).sum())
+    from adjoint_cases import shell_face
+    i_star = shell_face(g)
+    # half of the sample within reach of the shell (K steps of at most half a
+    # cell), half from the whole set (rows of the sorted set)
+    rng = np.random.default_rng(21)
+    reach = np.flatnonzero(np.abs(cells[:n_alive] // g.nth - i_star) <= K // 2 + 2)
+    pick = np.unique(np.concatenate([rng.choice(reach, 1000, replace=False),
+                                     rng.choice(n_alive, 1000, replace=False)]))
+    src = order[pick]                                                # their input indices
+    sub = {k: v[src] for k, v in parts.items()}
+    c = dict(g=g, sp=sp, fields=fields, lam=lam, dt=dt)
+    ref = oracle_grad_u(c, sub)
+    pert = {k: np.array(v, copy=True) for k, v in sub.items()}
+    for k in ("ur", "uth", "uph"):
+        pert[k] *= 1.0 + 4 * EPS
+    sens = np.abs(oracle_grad_u(c, pert) - ref).max(axis=1)
+    got = gu[pick]
+    err = np.abs(got - ref).max(axis=1)
+    scale = np.abs(ref).max(axis=1)
+    bar = 1e-9 * scale + 1e-13 * max(scale.max(), 1e-300) + 64 * sens
+    zero_ref = scale == 0.0
+    _announce(f"sampled: {int((~zero_ref).sum())} with a non-zero gradient, {int(zero_ref.sum())} exactly zero; "
+              f"max err/bar {float((err / np.maximum(bar, 1e-300)).max()):.3e}")
+    assert np.all(np.isfinite(gu))
+    assert np.all(got[zero_ref] == 0.0)                   # skipped segments give exact zeros
+    assert (~zero_ref).sum() >= 40 and zero_ref.sum() >= 900
+    assert np.all(err <= bar), np.flatnonzero(err > bar)[:5]

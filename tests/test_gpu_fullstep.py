@@ -25,8 +25,16 @@ particle's rounding sensitivity).
 
 The field step itself is compared with the oracle element by element in the
 field tests; at 4096^2 the oracle's field step (tens of minutes on the host)
-is replaced here by the two conservation laws above.  The adjoint of the
-field-coupled loop is not built (the backward pass takes fixed fields).
+is replaced here by the two conservation laws above.
+
+Then the adjoint over the next 32 PIC steps (grpic_push_deposit_backward_range):
+the forward records the FP64 field state each push gathers from and one
+checkpoint (the split state promoted to FP64); the backward runs in batches
+of 2e7 particles with those per-step fields, for the charge carried through
+the shell r = 5.  Every gradient is finite; the sampled particles that cannot
+reach the shell in 32 steps get exactly zero, and those that can match the
+oracle's dual numbers fed the same per-step fields (FP64 from the same
+start), at the adjoint bar of test_gpu_adjoint.py.
 """
 import time
 
@@ -206,3 +214,77 @@ def test_full_step_batch_split_4096_1e9():
     assert rep["violations"] == 0, rep
     assert rep["mom_max"] <= MOM_TOL, rep
     assert rep["ill"] <= max(2, 1e-3 * NSAMPLE), rep
+
+    # ---- the adjoint over the next 32 PIC steps (the window's fields are
+    # inputs, recorded per step; one checkpoint, the split state promoted to
+    # FP64; the backward in batches of 2e7 particles)
+    K = 32
+    _announce(f"adjoint window: {K} PIC steps with the field history and a checkpoint")
+    slot = grpic.grpic_checkpoint_bytes(n, 1, 1)
+    ck = torch.empty(slot, dtype=torch.uint8, device="cuda")
+    hist = torch.empty((6, K) + tuple(g.shape), dtype=torch.float64, device="cuda")
+    i_star = int(np.argmin(np.abs(g.r(np.arange(g.nr) + 0.5) - 5.0)))
+    lam = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    lam[0][G + i_star, :] = dt
+    start_rows = {k: parts[k][rows].cpu().numpy() for k in KEYS}
+    Lwin = 0.0
+    for k in range(K):
+        for c in range(6):
+            hist[c, k].copy_(state[c])
+        F32fields = [s.float() for s in state]
+        J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        kw = dict(ckpt=ck, ckpt_every=1) if k == 0 else {}
+        grpic.grpic_push_deposit(metric, g, sp, parts, F32fields, J, dt, 1, 3, tiling=sorter.tiling, **kw)
+        del F32fields
+        Lwin += float((lam[0] * J[0]).sum())
+        solver.step(state, J, dt, 0.53, 7, damp_cells=DAMP, damp_max=0.1)
+        del J
+    view = {"w": parts["w"].double(), "sp": parts["sp"]}
+    batch = 20_000_000
+    ws = torch.empty(grpic.grpic_backward_workspace_bytes(g, batch, K), dtype=torch.uint8, device="cuda")
+    gu = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    plane = g.shape[0] * g.shape[1]
+    _announce(f"adjoint window: backward in {n // batch} batches")
+    for first in range(0, n, batch):
+        cnt_b = min(batch, n - first)
+        grpic.grpic_push_deposit_backward_range(metric, g, sp, view, [hist[c, 0] for c in range(6)], lam, dt, K, 3,
+                                                ck, K, first, cnt_b, ws, [gu[d, first:first + cnt_b] for d in range(3)],
+                                                field_step_stride=plane)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(gu).all())
+    got_g = gu[:, rows].cpu().numpy().T
+    del ws, view
+    _announce("adjoint window: oracle dual numbers on the sample with the recorded fields")
+    hist_np = hist.cpu().numpy()
+    del hist
+    lam_np = [l.cpu().numpy() for l in lam]
+    start64 = {k: np.asarray(v, dtype=np.float64) if k not in ("cell", "sp") else v for k, v in start_rows.items()}
+
+    def oracle_grads(p):
+        out = np.zeros((len(p["cell"]), 3))
+        for d in range(3):
+            t = [np.zeros(len(p["cell"])) for _ in range(3)]
+            t[d][:] = 1.0
+            # one particle per call: the directional derivative with a unit
+            # tangent on every particle is their sum
+            for i in range(len(p["cell"])):
+                one = {k: v[i:i + 1] for k, v in p.items()}
+                _, out[i, d], _ = orc.loss_dual_steps(g, sp, one, hist_np, lam_np, dt,
+                                                      tu=[t[0][i:i + 1], t[1][i:i + 1], t[2][i:i + 1]])
+        return out
+
+    near = np.flatnonzero(np.abs(start64["cell"] // g.nth - i_star) <= K // 2 + 2)
+    far = np.setdiff1d(np.arange(NSAMPLE), near)
+    assert np.all(got_g[far] == 0.0)                     # cannot reach the shell in the window: skipped, exact 0
+    ref = oracle_grads({k: v[near] for k, v in start64.items()})
+    pert = {k: np.array(v[near], copy=True) for k, v in start64.items()}
+    for k in ("ur", "uth", "uph"):
+        pert[k] *= 1.0 + 4 * EPS
+    sens = np.abs(oracle_grads(pert) - ref).max(axis=1)
+    err = np.abs(got_g[near] - ref).max(axis=1)
+    gscale = np.abs(ref).max(axis=1)
+    bar = 1e-9 * gscale + 1e-13 * max(gscale.max(), 1e-300) + 64 * sens
+    _announce(f"adjoint window: L = {Lwin:.6e}, {len(near)} sampled particles within reach of the shell "
+              f"({int((gscale > 0).sum())} non-zero), max err/bar {float((err / np.maximum(bar, 1e-300)).max()):.3e}")
+    assert (gscale > 0).sum() >= 20
+    assert np.all(err <= bar), np.flatnonzero(err > bar)[:5]

@@ -105,3 +105,40 @@ def test_field_gradient_matches_finite_differences(setup):
         if abs(dL - fd) <= 1e-5 * max(abs(dL), 1e-6):
             agree += 1
     assert agree >= 3          # a random field direction may move one particle across a kink
+
+
+def test_loss_with_per_step_fields_is_the_sum_over_field_epochs():
+    """loss_dual_steps takes step k's fields from field_steps[k]: with the same
+    fields every step it equals loss_dual bit for bit; with fields A for the
+    first k steps and B after, L equals the loss of k steps in A plus that of
+    the remaining steps in B from the state the first k steps reach (orc.run);
+    its u-derivative matches central differences of that split value."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2503_04558_amd import workload as wl
+    from adjoint_cases import shell_case
+
+    g, dt, fields, parts, lam = shell_case(60)
+    sp = wl.species_table()
+    K, k = 12, 5
+    tu = [np.ones(60), np.zeros(60), np.zeros(60)]
+    same = orc.loss_dual_steps(g, sp, parts, [fields] * K, lam, dt, tu=tu)
+    ref = orc.loss_dual(g, sp, parts, fields, lam, dt, K, tu=tu)
+    assert same[0] == ref[0] and same[1] == ref[1]
+    B = [1.7 * f for f in fields]                                   # a stronger field after step k
+    L, dL, _ = orc.loss_dual_steps(g, sp, parts, [fields] * k + [B] * (K - k), lam, dt, tu=tu)
+
+    def split(p):
+        L1, _, _ = orc.loss_dual(g, sp, p, fields, lam, dt, k)
+        mid, _, _, _ = orc.run(g, sp, p, fields, dt, k)
+        L2, _, _ = orc.loss_dual(g, sp, mid, B, lam, dt, K - k)
+        return L1 + L2
+
+    assert abs(L - split(parts)) <= 1e-13 * max(1.0, abs(L))
+    assert abs(L - ref[0]) > 1e-6                                     # the second epoch's fields matter
+    h = 1e-6
+    up = dict(parts, ur=parts["ur"] + h)
+    um = dict(parts, ur=parts["ur"] - h)
+    fd = (split(up) - split(um)) / (2 * h)
+    assert abs(fd - dL) <= 1e-5 * max(1.0, abs(dL))
