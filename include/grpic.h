@@ -409,6 +409,24 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
                int64_t* n_alive_dev, void* stream);
 
 /*
+ * grpic_sort_noalloc -- grpic_sort for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same sort, outputs and errors, with the workspace
+ * taken from a static device array of GRPIC_SORT_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends.  The call
+ * allocates nothing; its scratch is cleared by kernels, not memsets.
+ * GRPIC_ENOMEM if grpic_sort_workspace_bytes(grid, in->n) exceeds
+ * GRPIC_SORT_SCRATCH_BYTES (2048 x 2048 grids and smaller fit).  All calls
+ * on one GPU share that GPU's array: calls that overlap in time on one GPU
+ * (on different streams, or from different threads without ordering) race.
+ * The device is the calling thread's current device.
+ */
+#define GRPIC_SORT_SCRATCH_BYTES ((size_t)40 << 20)
+int grpic_sort_noalloc(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+                       int64_t* cell_offsets, void* tiling, size_t tiling_bytes, int64_t* n_alive_dev,
+                       void* stream);
+
+/*
  * Field solver (Sec. 2.1, eqs. integral-form, fld-predictor, fld-corrector,
  * Dr-axis; App. B, eqs. D-update, auxH, B-update, auxE).  GRPIC_FP64 grid
  * arrays of the layout above: the dynamic fields D^i, B^i at their Yee

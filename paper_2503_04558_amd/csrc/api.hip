@@ -557,9 +557,9 @@ size_t grpic_tiling_bytes(const grpic_grid* grid, int64_t n) {
     return grpic::tiling_bytes(n, grid->nr, grid->nth);
 }
 
-int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
-               int64_t* cell_offsets, void* tiling, size_t tiling_bytes, void* ws, size_t ws_bytes,
-               int64_t* n_alive_dev, void* stream) {
+static int sort_checked(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+                        int64_t* cell_offsets, void* tiling, size_t tiling_bytes, void* ws, size_t ws_bytes,
+                        int64_t* n_alive_dev, void* stream, bool noalloc) {
     int rc;
     if ((rc = check_grid(grid)) || (rc = check_particles(in, "in")) || (rc = check_particles(out, "out")))
         return rc;
@@ -572,6 +572,14 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
     if (in->n > 0 && (in->cell == out->cell || in->xr == out->xr)) return fail(GRPIC_EINVAL, "in and out alias");
     if (!n_alive_dev) return fail(GRPIC_EINVAL, "n_alive_dev is NULL");
     const size_t need = grpic_sort_workspace_bytes(grid, in->n);
+    if (noalloc) {
+        if (need > grpic::kSortScratchBytes)
+            return fail(GRPIC_ENOMEM, "grpic_sort_noalloc: this grid's sort needs %zu bytes of scratch, above its "
+                        "maximum of %zu (2048 x 2048 grids and smaller fit); use grpic_sort", need,
+                        grpic::kSortScratchBytes);
+        if ((rc = hip_status(grpic::sort_scratch(&ws), "sort scratch address"))) return rc;
+        ws_bytes = grpic::kSortScratchBytes;
+    }
     if (!ws || ws_bytes < need) return fail(GRPIC_ENOMEM, "sort workspace needs %zu bytes, got %zu", need, ws_bytes);
     if (tiling) {
         const size_t tneed = grpic_tiling_bytes(grid, in->n);
@@ -608,6 +616,18 @@ int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particle
         g_tilings[tiling] = TilingInfo{in->n, grid->nr, grid->nth};
     }
     return GRPIC_OK;
+}
+
+int grpic_sort(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+               int64_t* cell_offsets, void* tiling, size_t tiling_bytes, void* ws, size_t ws_bytes,
+               int64_t* n_alive_dev, void* stream) {
+    return sort_checked(grid, in, out, cell_offsets, tiling, tiling_bytes, ws, ws_bytes, n_alive_dev, stream, false);
+}
+
+int grpic_sort_noalloc(const grpic_grid* grid, const grpic_particles* in, grpic_particles* out,
+                       int64_t* cell_offsets, void* tiling, size_t tiling_bytes, int64_t* n_alive_dev,
+                       void* stream) {
+    return sort_checked(grid, in, out, cell_offsets, tiling, tiling_bytes, nullptr, 0, n_alive_dev, stream, true);
 }
 
 size_t grpic_field_tables_bytes(const grpic_grid* grid) {

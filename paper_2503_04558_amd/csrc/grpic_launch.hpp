@@ -143,5 +143,10 @@ int64_t sort_scan_blocks(int64_t len);
 size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
 
+// The sort workspace that grpic_sort_noalloc uses: a static device array of
+// kSortScratchBytes per GPU; sort_scratch returns its address on the current
+// device (looked up on the first call there).
+constexpr size_t kSortScratchBytes = size_t(40) << 20;
+hipError_t sort_scratch(void** ptr);
 
 }  // namespace grpic

@@ -12,6 +12,8 @@
 // order inside a cell is not specified.
 #include "grpic_launch.hpp"
 
+#include <mutex>
+
 namespace grpic {
 
 constexpr int kScanThreads = 256;
@@ -343,6 +345,36 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
         else hipLaunchKernelGGL(sort_scatter<float>, dim3(nchunk(S.n)), dim3(kChunkThreads), 0, stream, S);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- no-allocation sort
+// The workspace of grpic_sort_noalloc: a file-scope device array that every
+// GPU the library runs on holds until the process ends.  Host code never
+// passes its name to a kernel (on the host the name is only a stand-in):
+// its device address is looked up once per device, with that device
+// current, and kept.
+static __device__ __align__(256) unsigned char scratch[kSortScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t sort_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace grpic

@@ -83,7 +83,7 @@ class grpic_field_state(ctypes.Structure):
 
 
 EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_spline3", "grpic_charge3",
-            "grpic_push_deposit_qed", "grpic_push_deposit_backward_range",
+            "grpic_push_deposit_qed", "grpic_sort_noalloc", "grpic_push_deposit_backward_range",
             "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
@@ -133,6 +133,8 @@ def lib():
         L.grpic_sort_workspace_bytes.argtypes = [vp, i64]
         L.grpic_sort_workspace_bytes.restype = ctypes.c_size_t
         L.grpic_sort.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp]
+        L.grpic_sort_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, vp]
+        L.grpic_sort_noalloc.restype = ctypes.c_int
         L.grpic_tiling_bytes.argtypes = [vp, i64]
         L.grpic_tiling_bytes.restype = ctypes.c_size_t
         L.grpic_sort.restype = ctypes.c_int
@@ -450,6 +452,26 @@ def grpic_sort(grid, parts_in: dict, parts_out: dict, cell_offsets: torch.Tensor
     tbytes = 0 if tiling is None else tiling.numel() * tiling.element_size()
     _check(lib().grpic_sort(ctypes.byref(g), ctypes.byref(Pi), ctypes.byref(Po), _ptr(cell_offsets),
                             _ptr(tiling), tbytes, ws.data_ptr(), nbytes, n_alive.data_ptr(), _stream(stream)))
+
+
+GRPIC_SORT_SCRATCH_BYTES = 40 << 20
+
+
+def grpic_sort_noalloc(grid, parts_in: dict, parts_out: dict, cell_offsets: torch.Tensor | None,
+                       n_alive: torch.Tensor, tiling: torch.Tensor | None = None, stream=None) -> None:
+    """grpic_sort with the library's static scratch in place of a workspace."""
+    g = make_grid(grid)
+    Pi = make_particles(parts_in)
+    Po = make_particles(parts_out)
+    if Po.n < Pi.n:
+        raise ValueError("parts_out must hold as many particles as parts_in")
+    if cell_offsets is not None:
+        _need(cell_offsets, torch.int64, int(grid.nr) * int(grid.nth) + 1, "cell_offsets")
+    _need(n_alive, torch.int64, 1, "n_alive")
+    if tiling is not None and (not tiling.is_cuda or not tiling.is_contiguous()):
+        raise ValueError("tiling: expected a contiguous device tensor")
+    _check(lib().grpic_sort_noalloc(ctypes.byref(g), ctypes.byref(Pi), ctypes.byref(Po), _ptr(cell_offsets),
+                                    _ptr(tiling), _nbytes(tiling), n_alive.data_ptr(), _stream(stream)))
 
 
 class Sorter:

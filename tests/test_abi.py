@@ -314,3 +314,20 @@ def test_qed_entry_validation():
     assert call(dt=2.01 * dt) == grpic.GRPIC_ERANGE
     empty = grpic.grpic_particles(0, *([None] * 9), grpic.GRPIC_FP64, 0, None)
     assert call(parts=empty) == grpic.GRPIC_OK
+
+
+def test_sort_noalloc_rejects_grids_beyond_its_scratch():
+    """grpic_sort_noalloc: its fixed scratch holds the sort of a 2048^2 grid;
+    a 4096^2 grid is rejected with GRPIC_ENOMEM before any device work."""
+    L = grpic.lib()
+    fake = 0x1000
+    parts = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP64, 0, None)
+    out = grpic.grpic_particles(10, *([fake * 2] * 8), None, grpic.GRPIC_FP64, 0, None)
+    big = grpic.make_grid(wl.make_grid(4096, 4096, 0.9))
+    assert grpic.grpic_sort_workspace_bytes(wl.make_grid(2048, 2048, 0.9), 10) <= grpic.GRPIC_SORT_SCRATCH_BYTES
+    assert grpic.grpic_sort_workspace_bytes(wl.make_grid(4096, 4096, 0.9), 10) > grpic.GRPIC_SORT_SCRATCH_BYTES
+    rc = L.grpic_sort_noalloc(ctypes.byref(big), ctypes.byref(parts), ctypes.byref(out), None, None, 0, fake, None)
+    assert rc == grpic.GRPIC_ENOMEM and b"scratch" in L.grpic_last_error()
+    ok = grpic.make_grid(wl.make_grid(64, 64, 0.9))
+    rc = L.grpic_sort_noalloc(ctypes.byref(ok), ctypes.byref(parts), ctypes.byref(out), None, None, 0, None, None)
+    assert rc == grpic.GRPIC_EINVAL and b"n_alive" in L.grpic_last_error()
