@@ -517,37 +517,39 @@ __device__ __forceinline__ int fold_face(int j, int nth, double& sign) {
 // (lower corner floor(min xi) - 1, floor(min eta) - 1) that holds both
 // supports, in the factorised form of the CIC version, folded across the
 // axes and handed to add(component, i, j, value): 20 F^r, 20 F^th, 25 G^ph.
+// The theta-direction weights are formed one window column at a time (the
+// F^th prefix sum runs along with them), so only the five r-direction
+// weights of each end point and their prefix sums stay live.
 template <class Add>
 __device__ __forceinline__ void esirkepov3(const Move& m, double dt, int nth, Add&& add) {
     const int i0 = (int)floor(fmin(m.xi0, m.xi1)) - 1, j0 = (int)floor(fmin(m.eta0, m.eta1)) - 1;
-    double wx0[5], wx1[5], wy0[5], wy1[5];
+    double wx0[5], wx1[5];
     for (int a = 0; a < 5; ++a) {
         wx0[a] = shape3(m.xi0 - (double)(i0 + a));
         wx1[a] = shape3(m.xi1 - (double)(i0 + a));
-        wy0[a] = shape3(m.eta0 - (double)(j0 + a));
-        wy1[a] = shape3(m.eta1 - (double)(j0 + a));
     }
     const double idt = rcp(dt);
     const double hf = -0.5 * m.qw * idt;
     const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);
-    double fx[4], fy[4], runx = 0.0, runy = 0.0;
+    double fx[4], runx = 0.0, runy = 0.0;
     for (int a = 0; a < 4; ++a) {
         runx += wx1[a] - wx0[a];
-        runy += wy1[a] - wy0[a];
         fx[a] = hf * runx;
-        fy[a] = hf * runy;
     }
     for (int b = 0; b < 5; ++b) {
+        const double wy0 = shape3(m.eta0 - (double)(j0 + b)), wy1 = shape3(m.eta1 - (double)(j0 + b));
         const int jv = fold_vertex(j0 + b, nth);
-        const double sy = wy0[b] + wy1[b];
-        const double p1 = cp6 * fma(2.0, wy1[b], wy0[b]), p0 = cp6 * fma(2.0, wy0[b], wy1[b]);
+        const double sy = wy0 + wy1;
+        const double p1 = cp6 * fma(2.0, wy1, wy0), p0 = cp6 * fma(2.0, wy0, wy1);
         for (int a = 0; a < 4; ++a) add(0, i0 + a, jv, fx[a] * sy);
         for (int a = 0; a < 5; ++a) add(2, i0 + a, jv, fma(wx1[a], p1, wx0[a] * p0));
-    }
-    for (int b = 0; b < 4; ++b) {
-        double sg;
-        const int jf = fold_face(j0 + b, nth, sg);
-        for (int a = 0; a < 5; ++a) add(1, i0 + a, jf, sg * fy[b] * (wx0[a] + wx1[a]));
+        if (b < 4) {
+            runy += wy1 - wy0;
+            const double fy = hf * runy;
+            double sg;
+            const int jf = fold_face(j0 + b, nth, sg);
+            for (int a = 0; a < 5; ++a) add(1, i0 + a, jf, sg * fy * (wx0[a] + wx1[a]));
+        }
     }
 }
 

@@ -59,6 +59,11 @@ __device__ __forceinline__ double spline3_f64(const double* __restrict__ F, cons
         for (int b = 0; b < 4; ++b) row = fma(wy[b], *elem(F, o + (uint32_t)b), row);
         sum = fma(wx[a], row, sum);
     }
+    // an empty asm that takes the sum and clobbers memory: the next
+    // component's 16 loads are not hoisted above this one's sum, so at most
+    // one component's loads are in flight (issued all together, the 96
+    // loads' results outlived the register file: 256 VGPRs and spills)
+    asm volatile("" : "+v"(sum) : : "memory");
     return sum;
 }
 
@@ -431,10 +436,11 @@ template <bool SHORT, int KICK, int ORDER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64(const StepArgs A) {
     push_deposit_body<false, SHORT, KICK, ORDER>(A);
 }
-// The cubic shape's kernel (96 gather loads, a 5 x 5 deposit): no waves
-// per SIMD target, so that its larger register set does not spill.
+// The cubic shape's kernel (96 gather loads, a 5 x 5 deposit), at three
+// waves per SIMD like the CIC kernel (its gather loads one component at a
+// time).
 template <bool SHORT>
-__global__ __launch_bounds__(256) void push_deposit_f64_spline3(const StepArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_spline3(const StepArgs A) {
     push_deposit_body<false, SHORT, kBoris, 3>(A);
 }
 template <bool SHORT>
@@ -652,10 +658,9 @@ __global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3)
     int32_t* slice_live, const double* anchors) {
     push_deposit_tiled_body<false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
 }
-// The cubic shape's tiled kernel: two waves per SIMD (256 registers, a few
-// spilled) ran 19 % faster than one wave with no spills (290 registers).
+// The cubic shape's tiled kernel, at three waves per SIMD.
 template <bool SHORT>
-__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(2))) void push_deposit_f64_tiled_spline3(
+__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_spline3(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
     const double* anchors) {
     push_deposit_tiled_body<false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);

@@ -226,7 +226,13 @@ def test_full_step_batch_split_4096_1e9():
     i_star = int(np.argmin(np.abs(g.r(np.arange(g.nr) + 0.5) - 5.0)))
     lam = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     lam[0][G + i_star, :] = dt
-    start_rows = {k: parts[k][rows].cpu().numpy() for k in KEYS}
+    # the 20,000 sampled particles plus 400 from the cells next to the shell
+    # (rows of the sorted order, which the window does not re-sort)
+    shell_cells = np.arange((i_star - 2) * g.nth, (i_star + 3) * g.nth)
+    shell_rows = np.concatenate([np.arange(offs_h[c], offs_h[c + 1]) for c in shell_cells])
+    extra = np.random.default_rng(13).choice(shell_rows, 400, replace=False)
+    rows_adj = torch.cat([rows, torch.as_tensor(extra, device="cuda")])
+    start_rows = {k: parts[k][rows_adj].cpu().numpy() for k in KEYS}
     Lwin = 0.0
     for k in range(K):
         for c in range(6):
@@ -252,7 +258,7 @@ def test_full_step_batch_split_4096_1e9():
                                                 field_step_stride=plane)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(gu).all())
-    got_g = gu[:, rows].cpu().numpy().T
+    got_g = gu[:, rows_adj].cpu().numpy().T
     del ws, view
     _announce("adjoint window: oracle dual numbers on the sample with the recorded fields")
     hist_np = hist.cpu().numpy()
@@ -274,7 +280,7 @@ def test_full_step_batch_split_4096_1e9():
         return out
 
     near = np.flatnonzero(np.abs(start64["cell"] // g.nth - i_star) <= K // 2 + 2)
-    far = np.setdiff1d(np.arange(NSAMPLE), near)
+    far = np.setdiff1d(np.arange(len(start64["cell"])), near)
     assert np.all(got_g[far] == 0.0)                     # cannot reach the shell in the window: skipped, exact 0
     ref = oracle_grads({k: v[near] for k, v in start64.items()})
     pert = {k: np.array(v[near], copy=True) for k, v in start64.items()}
@@ -286,5 +292,5 @@ def test_full_step_batch_split_4096_1e9():
     bar = 1e-9 * gscale + 1e-13 * max(gscale.max(), 1e-300) + 64 * sens
     _announce(f"adjoint window: L = {Lwin:.6e}, {len(near)} sampled particles within reach of the shell "
               f"({int((gscale > 0).sum())} non-zero), max err/bar {float((err / np.maximum(bar, 1e-300)).max()):.3e}")
-    assert (gscale > 0).sum() >= 20
+    assert (gscale > 0).sum() >= 40
     assert np.all(err <= bar), np.flatnonzero(err > bar)[:5]
