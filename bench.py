@@ -501,9 +501,9 @@ def run_qed(args) -> dict:
     particles of the full-step batch's power-law recipe with a fifth of the
     pairs' e- slots turned into photons (FIDO energy uniform in [1, 10]);
     gamma_thr = 100, eps_ph = 4, tau = 2, dt = 5e-4; arrays with room for
-    twice the initial count; grpic_push_deposit_qed, re-sorted every
-    sort_every steps (the sort's live count feeds the step's count of
-    elements in use)."""
+    twice the initial count; grpic_push_deposit_qed with its staging
+    workspace, re-sorted every sort_every steps (the sort's live count feeds
+    the step's count of elements in use)."""
     import torch
 
     from paper_2503_04558_amd import grpic
@@ -528,6 +528,7 @@ def run_qed(args) -> dict:
     dt = 5e-4
     qed = grpic.make_qed(100.0, 4.0, 2.0, seed=0)
     sorter = grpic.Sorter(g, cap, with_tag=True)
+    ws = torch.empty(grpic.grpic_qed_workspace_bytes(g, cap), dtype=torch.uint8, device="cuda")
     n_used = torch.tensor([n0, 0], dtype=torch.int64, device="cuda")
     J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
@@ -539,7 +540,7 @@ def run_qed(args) -> dict:
             cur["p"] = sorter.sort(cur["p"])
             n_used[:1].copy_(sorter.n_alive)
         grpic.grpic_push_deposit_qed(metric, g, sp, cur["p"], F, J, dt, k, qed, n_used, args.ncorr,
-                                     tiling=sorter.tiling, counters=counters if timed else None,
+                                     tiling=sorter.tiling, ws=ws, counters=counters if timed else None,
                                      qcounters=qc if timed else None)
 
     for k in range(args.qed_warmup):
@@ -563,7 +564,7 @@ def run_qed(args) -> dict:
                                   f"{args.sort_every} steps", "capacity": cap},
            "elements_in_use": [start_n, int(n_used[0].item())], "events": q, "counters": cnt}
     log(f"qed: {out['ms_per_step']:.2f} ms/step, events {q}, in use {out['elements_in_use']}")
-    del parts, cur, sorter, F, J
+    del parts, cur, sorter, F, J, ws
     torch.cuda.empty_cache()
     return out
 

@@ -264,6 +264,13 @@ int grpic_charge3(const grpic_grid* grid, const grpic_species* species, int nsp,
  * tiling: NULL, or the tiling of the grpic_sort call that produced the
  *   current order; the particles appended since that sort are pushed
  *   without the LDS window.
+ * ws: NULL, or (with a tiling) a device workspace of at least
+ *   grpic_qed_workspace_bytes(grid, parts->n) bytes (contents on entry do
+ *   not matter).  With it each workgroup stages the particles its slice
+ *   creates, and a scan places them after the others in slice order, so the
+ *   step takes no same-address atomics for them (a slice's particles beyond
+ *   16 are appended one atomic each); without it every wave that creates
+ *   particles reserves their slots with one atomic on n_used[1].
  * step: the step number that keys the random numbers.
  * qcounters: optional device int64[GRPIC_NQCOUNTERS], accumulated.
  * Otherwise arguments and errors as in grpic_push_deposit, with nsteps = 1.
@@ -286,11 +293,13 @@ typedef struct {
 #define GRPIC_QCNT_DROPPED 2          /* created particles beyond the capacity      */
 #define GRPIC_NQCOUNTERS 3
 
+size_t grpic_qed_workspace_bytes(const grpic_grid* grid, int64_t n);
 int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
                            const grpic_species* species, int nsp,
                            grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
                            void* tiling, double dt, int64_t step, int ncorr, const grpic_qed* qed,
-                           int64_t* n_used, int64_t* counters, int64_t* qcounters, void* stream);
+                           int64_t* n_used, void* ws, size_t ws_bytes, int64_t* counters, int64_t* qcounters,
+                           void* stream);
 
 /* Gradient outputs of grpic_push_deposit_backward (device, double). */
 typedef struct {

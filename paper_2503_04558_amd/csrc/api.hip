@@ -346,11 +346,17 @@ int grpic_push_deposit_vay(const grpic_metric* metric, const grpic_grid* grid,
                         counters, stream, grpic::kVay);
 }
 
+size_t grpic_qed_workspace_bytes(const grpic_grid* grid, int64_t n) {
+    if (!grid || grid->nr <= 0 || grid->nth <= 0 || n < 0) return 0;
+    return grpic::qed_workspace_bytes(grpic::slice_capacity(n, grid->nr, grid->nth));
+}
+
 int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
                            const grpic_species* species, int nsp,
                            grpic_particles* parts, const grpic_fields* fields, grpic_current* J,
                            void* tiling, double dt, int64_t step, int ncorr, const grpic_qed* qed,
-                           int64_t* n_used, int64_t* counters, int64_t* qcounters, void* stream) {
+                           int64_t* n_used, void* ws, size_t ws_bytes, int64_t* counters, int64_t* qcounters,
+                           void* stream) {
     int rc;
     if ((rc = check_metric(metric)) || (rc = check_grid(grid)) || (rc = check_species(species, nsp)) ||
         (rc = check_particles(parts, "parts")))
@@ -385,6 +391,9 @@ int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
             return fail(GRPIC_EINVAL, "tiling was not written by grpic_sort for %lld particles on this grid",
                         (long long)parts->n);
     }
+    if (ws && tiling && ws_bytes < grpic_qed_workspace_bytes(grid, parts->n))
+        return fail(GRPIC_ENOMEM, "qed workspace needs %zu bytes, got %zu", grpic_qed_workspace_bytes(grid, parts->n),
+                    ws_bytes);
     if (parts->n == 0) return GRPIC_OK;
     grpic::StepArgs A;
     fill_common(A, metric, grid, species, nsp, parts);
@@ -406,7 +415,7 @@ int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
     Q.cap = parts->n;
     Q.qcounters = reinterpret_cast<unsigned long long*>(qcounters);
     const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
-    return hip_status(grpic::launch_push_deposit_qed(A, Q, tiling, cap, static_cast<hipStream_t>(stream)),
+    return hip_status(grpic::launch_push_deposit_qed(A, Q, tiling, cap, ws, static_cast<hipStream_t>(stream)),
                       "push_deposit_qed launch");
 }
 

@@ -83,8 +83,13 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream, int order = 1);
 struct QedArgs;
 // One QED step (FP64, Boris, CIC): the tiled slices if a tiling is given,
-// then the particles no slice covers; n_used updated on the device.
-hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap, hipStream_t stream);
+// then the particles no slice covers; n_used updated on the device.  With
+// a workspace (tiled only), each slice stages the particles it creates and
+// a scan places them after the others, so the step takes no same-address
+// atomics for them.
+hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap, void* ws,
+                                   hipStream_t stream);
+size_t qed_workspace_bytes(int64_t slice_cap);
 
 struct SortArgs {
     int64_t n;
@@ -140,6 +145,7 @@ size_t backward_aux_bytes(int rows, int pitch);
 hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t stream);
 
 int64_t sort_scan_blocks(int64_t len);
+void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* blocksums, hipStream_t stream);
 size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
 

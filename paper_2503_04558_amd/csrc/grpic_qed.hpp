@@ -17,6 +17,21 @@
 
 namespace grpic {
 
+// Particles a tiled workgroup (one slice) stages in the workspace; those
+// beyond go straight to the arrays with one global atomic each.
+constexpr int kQedStage = 16;
+
+// The workspace of the staged path (SoA, kQedStage entries per slice).
+struct QedStage {
+    unsigned long long* count;                // [slices + 1]: staged per slice, then scanned in place
+    unsigned long long* blocksums;            // the scan's
+    unsigned* ev;                             // [2][slices]: emitted, converted per slice
+    int32_t* cell;
+    double *xr, *xth, *ur, *uth, *uph, *w;
+    uint8_t* sp;
+    uint64_t* tag;
+};
+
 struct QedArgs {
     double gamma_thr, eps_ph, P;              // P = 1 - exp(-tau dt), formed on the host
     uint64_t seed, step;
@@ -26,6 +41,9 @@ struct QedArgs {
     int64_t cap;                              // capacity of the particle arrays
     const int64_t* tail_start;                // tiled: the sort's live count (NULL: 0)
     unsigned long long* qcounters;            // optional: emitted, converted, dropped
+    int staged;                               // tiled slices stage their created particles in st
+    int64_t slices;                           // slice table entries (staged path)
+    QedStage st;
 };
 
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of
@@ -169,6 +187,64 @@ __device__ __forceinline__ void qed_append(const StepArgs& A, const QedArgs& Q, 
         if (be) atomicAdd(Q.qcounters + 0, (unsigned long long)__popcll(be));
         if (bc) atomicAdd(Q.qcounters + 1, (unsigned long long)__popcll(bc));
     }
+}
+
+// The staged path of a tiled workgroup: each wave reserves its created
+// particles' slots among the slice's with one LDS atomic (total: the
+// slice's count, events: its event counts), writes the first kQedStage of
+// the slice into its staging entries and appends any beyond with one global
+// atomic each (rare: a slice makes ~1-2 particles in the monopole
+// workload).  Every lane of the wave calls it.
+__device__ __forceinline__ void qed_stage(const StepArgs& A, const QedArgs& Q, int64_t slice, const Created& cr,
+                                          const QedEvents& qe, unsigned* total, unsigned* ev) {
+    const unsigned long long b1 = __ballot(cr.n & 1), b2 = __ballot(cr.n >> 1);
+    const unsigned long long be = __ballot(qe.emitted), bc = __ballot(qe.converted);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+        if (be) atomicAdd(ev + 0, (unsigned)__popcll(be));
+        if (bc) atomicAdd(ev + 1, (unsigned)__popcll(bc));
+    }
+    if ((b1 | b2) == 0) return;                               // wave-uniform
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned wave_total = __popcll(b1) + 2 * __popcll(b2);
+    const unsigned before = __popcll(b1 & below) + 2 * __popcll(b2 & below);
+    unsigned off = 0;
+    if (lane == 0) off = atomicAdd(total, wave_total);
+    off = __shfl(off, 0) + before;
+    int dropped = 0;
+    auto put = [&](unsigned k, int sp, uint64_t tag) {
+        if (k < (unsigned)kQedStage) {
+            const int64_t e = slice * kQedStage + k;
+            Q.st.cell[e] = cr.cell;
+            Q.st.xr[e] = cr.xr;
+            Q.st.xth[e] = cr.xth;
+            Q.st.ur[e] = cr.u[0];
+            Q.st.uth[e] = cr.u[1];
+            Q.st.uph[e] = cr.u[2];
+            Q.st.w[e] = cr.w;
+            Q.st.sp[e] = (uint8_t)sp;
+            Q.st.tag[e] = tag;
+            return;
+        }
+        const int64_t q = Q.n_used[0] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(Q.n_used + 1), 1ull);
+        if (q >= Q.cap) {
+            ++dropped;
+            return;
+        }
+        A.cell[q] = cr.cell;
+        static_cast<double*>(A.xr)[q] = cr.xr;
+        static_cast<double*>(A.xth)[q] = cr.xth;
+        static_cast<double*>(A.ur)[q] = cr.u[0];
+        static_cast<double*>(A.uth)[q] = cr.u[1];
+        static_cast<double*>(A.uph)[q] = cr.u[2];
+        static_cast<double*>(A.w)[q] = cr.w;
+        const_cast<uint8_t*>(A.sp)[q] = (uint8_t)sp;
+        Q.tag[q] = tag;
+        if (A.phi) static_cast<double*>(A.phi)[q] = 0.0;
+    };
+    if (cr.n >= 1) put(off, cr.sp[0], cr.tag[0]);
+    if (cr.n == 2) put(off + 1, cr.sp[1], cr.tag[1]);
+    if (Q.qcounters && dropped) atomicAdd(Q.qcounters + 2, (unsigned long long)dropped);
 }
 
 }  // namespace grpic

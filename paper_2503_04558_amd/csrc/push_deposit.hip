@@ -189,7 +189,11 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         if constexpr (ORDER == 3) return spline3_f64(F[c], A, f, h);
         else return cic_f64(F[c], A, f, h);
     };
-    const double D[3] = {gather(0, xi0 - 0.5, eta0), gather(1, xi0, eta0 - 0.5), gather(2, xi0, eta0)};
+    double D[3] = {gather(0, xi0 - 0.5, eta0), gather(1, xi0, eta0 - 0.5), gather(2, xi0, eta0)};
+    // Vay's kick holds more values live than Boris's: its D^i are summed
+    // before the B^i loads are issued, which keeps it within three waves'
+    // registers without spills (slower for the Boris kernel, which fits)
+    if constexpr (KICK == kVay) asm volatile("" : "+v"(D[0]), "+v"(D[1]), "+v"(D[2]) : : "memory");
     const double B[3] = {gather(3, xi0, eta0 - 0.5), gather(4, xi0 - 0.5, eta0), gather(5, xi0 - 0.5, eta0 - 0.5)};
     const bool massless = A.massless[s] != 0;
     const double dt = A.dt;
@@ -423,7 +427,7 @@ __device__ __forceinline__ void push_deposit_body(const StepArgs& A) {
         const bool dep =
             advance<SPLIT, SHORT, KICK, ORDER>(A, pi, load_particle<Elem<SPLIT>>(A, pi), mv, ev, nullptr, out);
         store_particle(A, pi, out);
-        if (dep) scatter_global<ORDER>(A, mv);
+        if (dep && mv.qw != 0.0) scatter_global<ORDER>(A, mv);   // an uncharged move adds only zeros
     }
     if (!A.counters) return;                                 // uniform
     __syncthreads();
@@ -460,6 +464,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     __shared__ TileAnchors tab;
     __shared__ int cnt[5];
     __shared__ int touched[4];                           // lowest, highest window row; lowest, highest column
+    __shared__ unsigned q_total, q_ev[2];                // QED, staged: the slice's created particles, events
     // the slice's new particle states, by slot (one pad element per 32 keeps
     // the permuted lanes' writes on distinct banks): written back in slot
     // order after the deposit, so that consecutive lanes store consecutive
@@ -475,6 +480,13 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const Slice sl = slices[logical];
     if (sl.start < 0 || sl.len <= 0) {
         if (A.counters && threadIdx.x == 0) slice_live[logical] = 0;
+        if constexpr (QED) {
+            if (Q.staged && threadIdx.x == 0) {
+                Q.st.count[logical] = 0;
+                Q.st.ev[logical] = 0;
+                Q.st.ev[Q.slices + logical] = 0;
+            }
+        }
         return;
     }
     const int tpr = (A.nth + kTileCells - 1) / kTileCells;
@@ -499,6 +511,12 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     static_assert((3 * kWinRows * kWinCols) % 2 == 0, "the window is cleared in pairs");
     for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols / 2; e += kPushThreads) wflat[e] = make_double2(0.0, 0.0);
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+    if constexpr (QED) {
+        if (threadIdx.x == 0) {
+            q_total = 0;
+            q_ev[0] = q_ev[1] = 0;
+        }
+    }
     if (threadIdx.x == 0) {
         touched[0] = kWinRows;
         touched[1] = -1;
@@ -539,7 +557,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         st_kind[si] = out.kind;
         st_cell[si] = out.cell;
         for (int k = 0; k < 5; ++k) st_x[k][si] = out.x[k];
-        if (dep) {
+        if (dep && mv.qw != 0.0) {                           // an uncharged move (a photon) adds only zeros
             if constexpr (ORDER == 3) {
                 // the cubic window: rows i3 .. i3 + 4, columns j3 .. j3 + 4
                 // folded across the axes (vertex and face columns)
@@ -585,7 +603,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         col_lo = min(col_lo, __shfl_xor(col_lo, off));
         col_hi = max(col_hi, __shfl_xor(col_hi, off));
     }
-    if constexpr (QED) qed_append<double>(A, Q, Q.n_used[0], cr, qe);
+    if constexpr (QED) {
+        if (Q.staged) qed_stage(A, Q, logical, cr, qe, &q_total, q_ev);
+        else qed_append<double>(A, Q, Q.n_used[0], cr, qe);
+    }
     if ((threadIdx.x & 63) == 0 && row_hi >= 0) {
         atomicMin(&touched[0], row_lo);
         atomicMax(&touched[1], row_hi);
@@ -632,6 +653,14 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         slice_live[logical] = cnt[3];
         for (int k = 0; k < 5; ++k)
             if (k != 3 && cnt[k]) atomicAdd(A.counters + k, (unsigned long long)cnt[k]);
+    }
+    if constexpr (QED) {
+        // the slice's staged count and events, final after the barrier above
+        if (Q.staged && threadIdx.x == 0) {
+            Q.st.count[logical] = min(q_total, (unsigned)kQedStage);
+            Q.st.ev[logical] = q_ev[0];
+            Q.st.ev[Q.slices + logical] = q_ev[1];
+        }
     }
 }
 
@@ -689,7 +718,7 @@ __device__ __forceinline__ void qed_block(const StepArgs& A, const QedArgs& Q, i
         const bool dep = advance<false, SHORT, kBoris, 1>(A, pi, in, mv, ev, nullptr, out);
         qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
         store_particle(A, pi, out);
-        if (dep) scatter_global(A, mv);
+        if (dep && mv.qw != 0.0) scatter_global(A, mv);
     }
     qed_append<double>(A, Q, end, cr, qe);
     if (A.counters) {                                       // uniform
@@ -728,19 +757,97 @@ __global__ __launch_bounds__(256) void push_deposit_f64_qed_tail(const StepArgs 
 }
 
 // Before a QED step: the elements in use cover the tiling's sorted
-// particles, and the append counter starts at zero.
-__global__ void qed_begin(int64_t* n_used, const int64_t* tail_start, int64_t cap) {
+// particles, the append counter starts at zero, and so does the staged
+// counts' scan sentinel.
+__global__ void qed_begin(int64_t* n_used, const int64_t* tail_start, int64_t cap, unsigned long long* sentinel) {
     int64_t n0 = n_used[0];
     if (tail_start && *tail_start > n0) n0 = *tail_start;
     n_used[0] = n0 < 0 ? 0 : (n0 > cap ? cap : n0);
     n_used[1] = 0;
+    if (sentinel) *sentinel = 0ull;
 }
-// After it: the appended particles join the elements in use.
-__global__ void qed_end(int64_t* n_used, int64_t cap) {
-    const int64_t n = n_used[0] + n_used[1];
+// After it: the appended and the placed staged particles join the elements
+// in use (staged_total: the scan's total, NULL without staging).
+__global__ void qed_end(int64_t* n_used, int64_t cap, const unsigned long long* staged_total) {
+    const int64_t n = n_used[0] + n_used[1] + (staged_total ? (int64_t)*staged_total : 0);
     n_used[0] = n > cap ? cap : n;
     n_used[1] = 0;
 }
+
+// Staged path: particle k of slice s goes to the elements after those in
+// use and those appended directly, at the slice's scanned offset (so in
+// slice order); those beyond the capacity are dropped.
+__global__ __launch_bounds__(256) void qed_place(const StepArgs A, const QedArgs Q) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = t / kQedStage;
+    const int k = (int)(t - s * kQedStage);
+    if (s >= Q.slices) return;
+    const unsigned long long o0 = Q.st.count[s], o1 = Q.st.count[s + 1];
+    if ((unsigned long long)k >= o1 - o0) return;
+    const int64_t q = Q.n_used[0] + Q.n_used[1] + (int64_t)(o0 + (unsigned long long)k);
+    if (q >= Q.cap) {
+        if (Q.qcounters) atomicAdd(Q.qcounters + 2, 1ull);
+        return;
+    }
+    const int64_t e = s * kQedStage + k;
+    A.cell[q] = Q.st.cell[e];
+    static_cast<double*>(A.xr)[q] = Q.st.xr[e];
+    static_cast<double*>(A.xth)[q] = Q.st.xth[e];
+    static_cast<double*>(A.ur)[q] = Q.st.ur[e];
+    static_cast<double*>(A.uth)[q] = Q.st.uth[e];
+    static_cast<double*>(A.uph)[q] = Q.st.uph[e];
+    static_cast<double*>(A.w)[q] = Q.st.w[e];
+    const_cast<uint8_t*>(A.sp)[q] = Q.st.sp[e];
+    Q.tag[q] = Q.st.tag[e];
+    if (A.phi) static_cast<double*>(A.phi)[q] = 0.0;
+}
+
+// Staged path: the slices' event counts summed into the counters.
+__global__ __launch_bounds__(256) void qed_event_sum(const unsigned* __restrict__ ev, int64_t slices,
+                                                     unsigned long long* __restrict__ qcounters) {
+    unsigned long long v[2] = {0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slices; i += (int64_t)gridDim.x * blockDim.x) {
+        v[0] += ev[i];
+        v[1] += ev[slices + i];
+    }
+    __shared__ unsigned long long part[2][4];
+    for (int c = 0; c < 2; ++c) {
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+        if ((threadIdx.x & 63) == 0) part[c][threadIdx.x >> 6] = v[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const unsigned long long t = part[threadIdx.x][0] + part[threadIdx.x][1] + part[threadIdx.x][2] +
+                                     part[threadIdx.x][3];
+        if (t) atomicAdd(qcounters + threadIdx.x, t);
+    }
+}
+
+// Workspace of the staged path, each array 256-byte aligned:
+// count (slices + 1) and scan block sums (u64), events (2 x u32 per slice),
+// then the staging SoA (kQedStage entries per slice).
+namespace {
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+struct QedLayout {
+    size_t count, blocksums, ev, cell, real[6], sp, tag, total;
+};
+inline QedLayout qed_layout(int64_t slices) {
+    QedLayout L;
+    const size_t S = (size_t)slices * kQedStage;
+    size_t o = 0;
+    L.count = o; o += align256(8 * ((size_t)slices + 1));
+    L.blocksums = o; o += align256(8 * ((size_t)sort_scan_blocks(slices + 1) + 1));
+    L.ev = o; o += align256(4 * 2 * (size_t)slices);
+    L.cell = o; o += align256(4 * S);
+    for (int k = 0; k < 6; ++k) { L.real[k] = o; o += align256(8 * S); }
+    L.sp = o; o += align256(S);
+    L.tag = o; o += align256(8 * S);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+size_t qed_workspace_bytes(int64_t slice_cap) { return qed_layout(slice_cap).total; }
 
 template <bool SHORT>
 __global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
@@ -823,15 +930,31 @@ hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream
     return hipGetLastError();
 }
 
-hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap,
+hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, int64_t slice_cap, void* ws,
                                    hipStream_t stream) {
     const bool sh = A.small_steps == 2;
     Q.tail_start = nullptr;
+    Q.staged = 0;
     if (tiling) {
         const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
         Q.tail_start = &hdr->n_sorted;
+        if (ws) {
+            const QedLayout L = qed_layout(slice_cap);
+            char* b = static_cast<char*>(ws);
+            Q.staged = 1;
+            Q.slices = slice_cap;
+            Q.st.count = reinterpret_cast<unsigned long long*>(b + L.count);
+            Q.st.blocksums = reinterpret_cast<unsigned long long*>(b + L.blocksums);
+            Q.st.ev = reinterpret_cast<unsigned*>(b + L.ev);
+            Q.st.cell = reinterpret_cast<int32_t*>(b + L.cell);
+            double** real[6] = {&Q.st.xr, &Q.st.xth, &Q.st.ur, &Q.st.uth, &Q.st.uph, &Q.st.w};
+            for (int k = 0; k < 6; ++k) *real[k] = reinterpret_cast<double*>(b + L.real[k]);
+            Q.st.sp = reinterpret_cast<uint8_t*>(b + L.sp);
+            Q.st.tag = reinterpret_cast<uint64_t*>(b + L.tag);
+        }
     }
-    hipLaunchKernelGGL(qed_begin, dim3(1), dim3(1), 0, stream, Q.n_used, Q.tail_start, Q.cap);
+    hipLaunchKernelGGL(qed_begin, dim3(1), dim3(1), 0, stream, Q.n_used, Q.tail_start, Q.cap,
+                       Q.staged ? Q.st.count + slice_cap : nullptr);
     if (tiling) {
         const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
         const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
@@ -857,7 +980,15 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
         if (sh) hipLaunchKernelGGL(push_deposit_f64_qed<true>, g, dim3(256), 0, stream, A, Q);
         else hipLaunchKernelGGL(push_deposit_f64_qed<false>, g, dim3(256), 0, stream, A, Q);
     }
-    hipLaunchKernelGGL(qed_end, dim3(1), dim3(1), 0, stream, Q.n_used, Q.cap);
+    if (Q.staged) {                                      // place the staged particles after all others
+        scan_exclusive(Q.st.count, slice_cap + 1, Q.st.blocksums, stream);
+        const int64_t threads = slice_cap * kQedStage;
+        hipLaunchKernelGGL(qed_place, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, A, Q);
+        if (Q.qcounters)
+            hipLaunchKernelGGL(qed_event_sum, dim3(64), dim3(256), 0, stream, Q.st.ev, slice_cap, Q.qcounters);
+    }
+    hipLaunchKernelGGL(qed_end, dim3(1), dim3(1), 0, stream, Q.n_used, Q.cap,
+                       Q.staged ? Q.st.count + slice_cap : nullptr);
     return hipGetLastError();
 }
 

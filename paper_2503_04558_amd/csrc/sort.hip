@@ -191,7 +191,7 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // Exclusive scan of a[0..len) in place (a[len-1] should be a zero sentinel
 // so that it receives the total).
-static void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* blocksums, hipStream_t stream) {
+void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* blocksums, hipStream_t stream) {
     const int64_t nb = sort_scan_blocks(len);
     hipLaunchKernelGGL(scan_tiles, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, a, len, blocksums);
     hipLaunchKernelGGL(scan_top, dim3(1), dim3(kScanThreads), 0, stream, blocksums, nb);

@@ -83,7 +83,7 @@ class grpic_field_state(ctypes.Structure):
 
 
 EXPORTED = ("grpic_push_deposit", "grpic_push_deposit_vay", "grpic_push_deposit_spline3", "grpic_charge3",
-            "grpic_push_deposit_qed", "grpic_sort_noalloc", "grpic_push_deposit_backward_range",
+            "grpic_push_deposit_qed", "grpic_qed_workspace_bytes", "grpic_sort_noalloc", "grpic_push_deposit_backward_range",
             "grpic_push_deposit_backward", "grpic_checkpoint_bytes",
             "grpic_backward_workspace_bytes", "grpic_charge", "grpic_sort", "grpic_sort_workspace_bytes",
             "grpic_tiling_bytes", "grpic_crossing_time", "grpic_last_error", "grpic_version",
@@ -124,8 +124,11 @@ def lib():
         L.grpic_push_deposit_vay.restype = ctypes.c_int
         L.grpic_push_deposit_spline3.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, i32, vp, vp]
         L.grpic_push_deposit_spline3.restype = ctypes.c_int
-        L.grpic_push_deposit_qed.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i64, i32, vp, vp, vp, vp, vp]
+        L.grpic_push_deposit_qed.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i64, i32, vp, vp, vp, sz, vp, vp,
+                                             vp]
         L.grpic_push_deposit_qed.restype = ctypes.c_int
+        L.grpic_qed_workspace_bytes.argtypes = [vp, i64]
+        L.grpic_qed_workspace_bytes.restype = sz
         L.grpic_charge3.argtypes = [vp, vp, i32, vp, vp, vp]
         L.grpic_charge3.restype = ctypes.c_int
         L.grpic_charge.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -300,13 +303,19 @@ def make_qed(gamma_thr: float, eps_ph: float, tau: float, seed: int, electron_sp
                      int(positron_sp), int(photon_sp), 0)
 
 
+def grpic_qed_workspace_bytes(grid, n: int) -> int:
+    g = make_grid(grid)
+    return int(lib().grpic_qed_workspace_bytes(ctypes.byref(g), int(n)))
+
+
 def grpic_push_deposit_qed(metric: grpic_metric, grid, species, parts: dict, fields, J, dt: float, step: int,
                            qed: grpic_qed, n_used: torch.Tensor, ncorr: int = 3, tiling: torch.Tensor | None = None,
-                           counters: torch.Tensor | None = None, qcounters: torch.Tensor | None = None,
-                           stream=None) -> None:
+                           ws: torch.Tensor | None = None, counters: torch.Tensor | None = None,
+                           qcounters: torch.Tensor | None = None, stream=None) -> None:
     """One step with photon emission and pair conversion.  parts: FP64 with a
     "tag" tensor; its length is the capacity.  n_used: device int64 (2,),
-    n_used[0] the elements in use (updated on the device)."""
+    n_used[0] the elements in use (updated on the device).  ws: with a
+    tiling, the staging workspace (grpic_qed_workspace_bytes) or None."""
     g = make_grid(grid)
     sp = make_species(species)
     P = make_particles(parts)
@@ -317,12 +326,13 @@ def grpic_push_deposit_qed(metric: grpic_metric, grid, species, parts: dict, fie
         _need(counters, torch.int64, GRPIC_NCOUNTERS, "counters")
     if qcounters is not None:
         _need(qcounters, torch.int64, GRPIC_NQCOUNTERS, "qcounters")
-    if tiling is not None and (not tiling.is_cuda or not tiling.is_contiguous()):
-        raise ValueError("tiling: expected a contiguous device tensor")
+    for t, name in ((tiling, "tiling"), (ws, "ws")):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous device tensor")
     _check(lib().grpic_push_deposit_qed(ctypes.byref(metric), ctypes.byref(g), sp, len(species), ctypes.byref(P),
                                         ctypes.byref(F), ctypes.byref(C), _ptr(tiling), float(dt), int(step),
-                                        int(ncorr), ctypes.byref(qed), n_used.data_ptr(), _ptr(counters),
-                                        _ptr(qcounters), _stream(stream)))
+                                        int(ncorr), ctypes.byref(qed), n_used.data_ptr(), _ptr(ws), _nbytes(ws),
+                                        _ptr(counters), _ptr(qcounters), _stream(stream)))
 
 
 def grpic_checkpoint_bytes(n: int, nsteps: int, ckpt_every: int) -> int:

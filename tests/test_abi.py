@@ -294,7 +294,7 @@ def test_qed_entry_validation():
         Q = grpic.make_qed(**q)
         return L.grpic_push_deposit_qed(ctypes.byref(m), ctypes.byref(G), species, nsp, ctypes.byref(parts),
                                         ctypes.byref(fields), ctypes.byref(cur), None, dt, step, 3,
-                                        ctypes.byref(Q), n_used, None, None, None)
+                                        ctypes.byref(Q), n_used, None, 0, None, None, None)
 
     notag = grpic.grpic_particles(10, *([fake] * 8), None, grpic.GRPIC_FP64, 0, None)
     assert call(parts=notag) == grpic.GRPIC_EINVAL and b"tags" in L.grpic_last_error()

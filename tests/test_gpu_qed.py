@@ -49,11 +49,11 @@ def _padded(parts, cap):
     return out
 
 
-def _gpu_step(g, sp, parts_dev, F, J, dt, step, q, n_used, tiling=None):
+def _gpu_step(g, sp, parts_dev, F, J, dt, step, q, n_used, tiling=None, ws=None):
     counters = torch.zeros(grpic.GRPIC_NCOUNTERS, dtype=torch.int64, device="cuda")
     qc = torch.zeros(grpic.GRPIC_NQCOUNTERS, dtype=torch.int64, device="cuda")
     grpic.grpic_push_deposit_qed(grpic.make_metric(g.a, g.M), g, sp, parts_dev, F, J, dt, step,
-                                 grpic.make_qed(**q), n_used, tiling=tiling, counters=counters, qcounters=qc)
+                                 grpic.make_qed(**q), n_used, tiling=tiling, ws=ws, counters=counters, qcounters=qc)
     torch.cuda.synchronize()
     return (dict(zip(grpic.COUNTER_NAMES, counters.cpu().tolist())),
             dict(zip(grpic.QCOUNTER_NAMES, qc.cpu().tolist())))
@@ -144,11 +144,14 @@ def test_qed_charge_continuity_with_created_pairs():
     assert R.abs().max().item() <= 64 * EPS * dev["w"][: int(n_used[0])].abs().sum().item()
 
 
-def test_qed_steps_with_sorts_match_oracle():
+@pytest.mark.parametrize("staged", [False, True], ids=["atomic", "staged"])
+def test_qed_steps_with_sorts_match_oracle(staged):
     """Eight steps with a re-sort (tiled push) every third step, created
     particles appended on both sides: the live particle sets agree by tag
     after every step; the tiled push and the tail of particles appended
-    since the sort both run."""
+    since the sort both run.  staged: with the workspace, the tiled slices
+    stage what they create and a scan places it (without: one atomic per
+    creating wave)."""
     g, parts, fields = _workload(64, 64, 10_000, seed=7, B0=30.0)
     sp = wl.qed_species_table()
     dt = wl.crossing_dt(g)
@@ -158,6 +161,9 @@ def test_qed_steps_with_sorts_match_oracle():
     _announce(f"qed 8 steps with sorts, 64x64, {n} particles")
     dev = grpic.to_device(_padded(parts, cap))
     sorter = grpic.Sorter(g, cap, with_tag=True)
+    ws = None
+    if staged:                         # NaN bytes: nothing unwritten may be read
+        ws = torch.full((grpic.grpic_qed_workspace_bytes(g, cap),), 255, dtype=torch.uint8, device="cuda")
     F = [torch.as_tensor(f).cuda() for f in fields]
     J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
     n_used = torch.tensor([n, 0], dtype=torch.int64, device="cuda")
@@ -170,7 +176,7 @@ def test_qed_steps_with_sorts_match_oracle():
             dev = sorter.sort(dev)
             n_used[:1].copy_(sorter.n_alive)
             tiling = sorter.tiling
-        _, qc = _gpu_step(g, sp, dev, F, J, dt, step, q, n_used, tiling=tiling)
+        _, qc = _gpu_step(g, sp, dev, F, J, dt, step, q, n_used, tiling=tiling, ws=ws)
         po, Jo, Ao, co, _, qo = orc.run_qed(g, sp, host, fields, dt, step, q, J=Jo)
         host = {k: np.concatenate([po[k], co[k]]) for k in po}
         Asum = Ao if Asum is None else [x + y for x, y in zip(Asum, Ao)]
@@ -210,6 +216,57 @@ def test_qed_capacity_overflow_drops_and_counts():
     assert np.all(out["cell"][n:] >= 0)
     made_tags = set(int(t) for t in co["tag"])
     assert set(int(t) for t in out["tag"][n:]) <= made_tags
+
+
+def test_qed_staged_overflow_and_capacity():
+    """Staged path at its limits: with P = 0.9 a slice of converting photons
+    creates far more than the 16 particles it can stage (the rest go the
+    atomic way), and with room for half of the step's creations the arrays
+    fill exactly to capacity, the rest counted as dropped.  A workspace
+    below grpic_qed_workspace_bytes is rejected."""
+    g = wl.make_grid(48, 48, 0.9)
+    sp = wl.qed_species_table()
+    dt = wl.crossing_dt(g)
+    rng = np.random.default_rng(5)
+    n = 6000
+    cell = np.sort(rng.integers(0, g.ncell, n)).astype(np.int32)
+    xr, xth = rng.uniform(0, 1, n), rng.uniform(0, 1, n)
+    d = rng.normal(size=(3, n))
+    d /= np.linalg.norm(d, axis=0)
+    ci, cj = cell // g.nth, cell % g.nth
+    ur, uth, uph = wl.frame_to_covariant(g.a, g.M, g.r(ci + xr), g.theta(cj + xth), d * rng.uniform(3, 9, n))
+    photons = dict(cell=cell, xr=xr, xth=xth, ur=ur, uth=uth, uph=uph, w=np.ones(n), sp=np.full(n, 2, np.uint8),
+                   tag=np.arange(n, dtype=np.uint64))
+    F = [torch.as_tensor(f).cuda() for f in wl.monopole_fields(g, 5.0)]
+    q = _qed(dt, 0.9)
+    _, _, _, co, _, qo = orc.run_qed(g, sp, photons, wl.monopole_fields(g, 5.0), dt, 2, q)
+    made = len(co["cell"])
+    assert made > 8000
+    for cap, tag in ((n + made + 100, "room"), (n + made // 2, "half")):
+        dev = grpic.to_device(_padded(photons, cap))
+        sorter = grpic.Sorter(g, cap, with_tag=True)
+        dev = sorter.sort(dev)
+        n_used = sorter.n_alive.repeat(2)
+        n_used[1] = 0
+        ws = torch.full((grpic.grpic_qed_workspace_bytes(g, cap),), 255, dtype=torch.uint8, device="cuda")
+        J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        with pytest.raises(grpic.GrpicError, match="workspace"):
+            grpic.grpic_push_deposit_qed(grpic.make_metric(g.a, g.M), g, sp, dev, F, J, dt, 2, grpic.make_qed(**q),
+                                         n_used, tiling=sorter.tiling, ws=ws[:-1])
+        _, qc = _gpu_step(g, sp, dev, F, J, dt, 2, q, n_used, tiling=sorter.tiling, ws=ws)
+        out = grpic.to_host(dev)
+        assert qc["emitted"] == 0 and qc["converted"] == qo["converted"], (tag, qc, qo)
+        if tag == "room":
+            assert n_used.cpu().tolist() == [n + made, 0] and qc["dropped"] == 0
+            a, b = _by_tag({k: v[n:n + made] for k, v in out.items()}), _by_tag(co)
+            assert np.array_equal(a["tag"], b["tag"]) and np.array_equal(a["sp"], b["sp"])
+            e = compare_particles(g, a, b, TOL)
+            assert e["violations"] == 0 and e["err"] <= TOL, e
+        else:
+            assert n_used.cpu().tolist() == [cap, 0]
+            assert qc["dropped"] == made - (cap - n)
+            assert np.all(out["cell"][n:cap] >= 0)
+            assert set(int(t) for t in out["tag"][n:cap]) <= set(int(t) for t in co["tag"])
 
 
 def test_qed_empty_and_all_dead():
