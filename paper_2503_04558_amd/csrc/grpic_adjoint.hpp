@@ -12,7 +12,9 @@
 // on the same App. A formulas, which gives the second derivatives of the
 // metric that the geodesic right-hand side's derivative needs.
 //
-// Everything here is plain double arithmetic (host or device).
+// Everything here is plain double arithmetic (host or device), apart from the
+// reciprocal and square root below, which take the hardware's estimates on
+// the GPU.
 #pragma once
 
 #include <math.h>
@@ -20,6 +22,33 @@
 
 namespace grpic {
 namespace adj {
+
+// 1/x and sqrt(x).  Compiled for the GPU: the hardware estimates refined by
+// two Newton steps (1-2 ulp; the IEEE-rounded division and square root take
+// twice the instructions and more registers, which this register-bound sweep
+// spills).  Compiled for the host (the same per-particle sweep run on the
+// CPU): the library's.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline double inv_(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ inline double sqrt_(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    return fma(g, r, g);
+}
+#else
+inline double inv_(double x) { return 1.0 / x; }
+inline double sqrt_(double x) { return ::sqrt(x); }
+#endif
 
 constexpr int kMaxCorr = 8;            // predictor-corrector passes the adjoint supports
 
@@ -35,7 +64,7 @@ __host__ __device__ inline Dual2 operator*(Dual2 a, Dual2 b) {
     return {a.v * b.v, a.r * b.v + a.v * b.r, a.t * b.v + a.v * b.t};
 }
 __host__ __device__ inline Dual2 operator/(Dual2 a, Dual2 b) {
-    const double ib = 1.0 / b.v;
+    const double ib = inv_(b.v);
     const double q = a.v * ib;
     return {q, (a.r - q * b.r) * ib, (a.t - q * b.t) * ib};
 }
@@ -46,16 +75,21 @@ __host__ __device__ inline Dual2 operator-(Dual2 a, double b) { return {a.v - b,
 __host__ __device__ inline Dual2 operator*(double a, Dual2 b) { return {a * b.v, a * b.r, a * b.t}; }
 __host__ __device__ inline Dual2 operator*(Dual2 a, double b) { return {a.v * b, a.r * b, a.t * b}; }
 __host__ __device__ inline Dual2 operator/(double a, Dual2 b) {
-    const double ib = 1.0 / b.v;
+    const double ib = inv_(b.v);
     const double q = a * ib;
     return {q, -q * b.r * ib, -q * b.t * ib};
 }
 __host__ __device__ inline Dual2 sqrt(Dual2 a) {
-    const double s = ::sqrt(a.v);
-    const double h = 0.5 / s;
+    const double s = sqrt_(a.v);
+    const double h = 0.5 * inv_(s);
     return {s, a.r * h, a.t * h};
 }
 using ::sqrt;          // the double overload stays visible next to the Dual2 one
+// The same for the metric's template argument (double or Dual2).
+__host__ __device__ inline double inv_any(double x) { return inv_(x); }
+__host__ __device__ inline Dual2 inv_any(Dual2 b) { return 1.0 / b; }
+__host__ __device__ inline double sqrt_any(double x) { return sqrt_(x); }
+__host__ __device__ inline Dual2 sqrt_any(Dual2 a) { return sqrt(a); }
 
 // Metric quantities of App. A (mass M reinstated) as one array, so that an
 // adjoint can hold one cotangent per entry.
@@ -72,12 +106,12 @@ __host__ __device__ inline void metric_emit(double a, double M, T r, T s, T c, O
     const double a2 = a * a;
     const T r2 = r * r, s2 = s * s, sc = s * c;
     const T rho2 = r2 + a2 * (c * c);
-    const T irho2 = 1.0 / rho2;
+    const T irho2 = inv_any(rho2);
     const T z = 2.0 * M * r * irho2;
     const T opz = 1.0 + z;
-    const T sq = sqrt(opz);
-    const T iopz = 1.0 / opz;
-    const T is2 = 1.0 / s2;
+    const T sq = sqrt_any(opz);
+    const T iopz = inv_any(opz);
+    const T is2 = inv_any(s2);
     const T ra2 = r2 + a2;
     const T Delta = ra2 - 2.0 * M * r;
     const T Sigma = ra2 * ra2 - a2 * Delta * s2;
@@ -130,25 +164,30 @@ struct Geo {
     __host__ __device__ long index(int i, int j) const { return (long)(i + guard) * pitch + (j + guard); }
 };
 
-// Metric values at grid point (xi, eta).
-__host__ __device__ inline double point_r(const Geo& G, double xi) { return ::exp(G.lnr0 + xi * G.dlnr); }
-
-__host__ __device__ inline void metric_at(const Geo& G, double xi, double eta, double m[M_N], double& r) {
-    r = point_r(G, xi);
+// r, sin(theta), cos(theta) at grid point (xi, eta): the only transcendental
+// functions the metric needs.  The reverse forms them once per point for both
+// the metric and its derivatives (they are not kept in the step's tape: the
+// register file is the reverse sweep's limit, not its arithmetic).
+struct Trig {
+    double r, s, c;
+};
+__host__ __device__ inline Trig trig_at(const Geo& G, double xi, double eta) {
     const double th = eta * G.dth;
-    metric<double>(G.a, G.M, r, ::sin(th), ::cos(th), m);
+    return {::exp(G.lnr0 + xi * G.dlnr), ::sin(th), ::cos(th)};
 }
 
-// Cotangents mb of the metric quantities at (xi, eta) -> cotangents of r and
+__host__ __device__ inline void metric_at(const Geo& G, const Trig& t, double m[M_N]) {
+    metric<double>(G.a, G.M, t.r, t.s, t.c, m);
+}
+
+// Cotangents mb of the metric quantities at a point -> cotangents of r and
 // theta: the quantities' r and theta derivatives (forward mode, Dual2)
 // contracted with mb as they are formed.
-__host__ __device__ inline void metric_vjp_at(const Geo& G, double xi, double eta, const double mb[M_N], double& rb,
+__host__ __device__ inline void metric_vjp_at(const Geo& G, const Trig& t, const double mb[M_N], double& rb,
                                               double& thb) {
-    const double r = point_r(G, xi);
-    const double th = eta * G.dth;
-    const double s = ::sin(th), c = ::cos(th);
     double ar = 0.0, at = 0.0;
-    metric_emit<Dual2>(G.a, G.M, Dual2{r, 1.0, 0.0}, Dual2{s, 0.0, c}, Dual2{c, 0.0, -s}, [&](int i, const Dual2& v) {
+    metric_emit<Dual2>(G.a, G.M, Dual2{t.r, 1.0, 0.0}, Dual2{t.s, 0.0, t.c}, Dual2{t.c, 0.0, -t.s},
+                       [&](int i, const Dual2& v) {
         ar += mb[i] * v.r;
         at += mb[i] * v.t;
     });
@@ -162,9 +201,9 @@ __host__ __device__ inline void metric_vjp_at(const Geo& G, double xi, double et
 __host__ __device__ inline void rhs(const Geo& G, double eps, const double m[M_N], double r, double ur, double ut,
                                     double up, double f[5]) {
     const double uu = m[M_HRR] * ur * ur + 2.0 * m[M_HRP] * ur * up + m[M_HTT] * ut * ut + m[M_HPP] * up * up;
-    const double u0 = ::sqrt(eps + uu) * m[M_IALPHA];
-    const double iu0 = 1.0 / u0;
-    f[0] = ((m[M_HRR] * ur + m[M_HRP] * up) * iu0 - m[M_BETA]) * (G.idlnr / r);
+    const double u0 = sqrt_(eps + uu) * m[M_IALPHA];
+    const double iu0 = inv_(u0);
+    f[0] = ((m[M_HRR] * ur + m[M_HRP] * up) * iu0 - m[M_BETA]) * (G.idlnr * inv_(r));
     f[1] = m[M_HTT] * ut * iu0 * G.idth;
     f[2] = (m[M_HRP] * ur + m[M_HPP] * up) * iu0;
     for (int q = 0; q < 2; ++q) {
@@ -174,19 +213,21 @@ __host__ __device__ inline void rhs(const Geo& G, double eps, const double m[M_N
     }
 }
 
-// Cotangent g of f at point (xi, eta, ur, ut, up) -> cotangents of the
-// point (added to yb[0..1] = xi, eta and ub[0..2] = u_r, u_th, u_ph).
-__host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, double eta, double ur, double ut,
-                                        double up, const double g[5], double yb[2], double ub[3]) {
-    double m[M_N], mb[M_N], r;
-    metric_at(G, xi, eta, m, r);
+// Cotangent g of f at point (xi, eta, ur, ut, up), t = trig_at(xi, eta) ->
+// cotangents of the point (added to yb[0..1] = xi, eta and ub[0..2] = u_r,
+// u_th, u_ph).
+__host__ __device__ inline void rhs_vjp(const Geo& G, double eps, const Trig& t, double ur, double ut, double up,
+                                        const double g[5], double yb[2], double ub[3]) {
+    double m[M_N], mb[M_N];
+    const double r = t.r;
+    metric_at(G, t, m);
     for (int i = 0; i < M_N; ++i) mb[i] = 0.0;
     const double uu = m[M_HRR] * ur * ur + 2.0 * m[M_HRP] * ur * up + m[M_HTT] * ut * ut + m[M_HPP] * up * up;
-    const double S = ::sqrt(eps + uu);
+    const double S = sqrt_(eps + uu);
     const double u0 = S * m[M_IALPHA];
-    const double iu0 = 1.0 / u0;
-    const double ir = 1.0 / r;
-    const double iS = 1.0 / S;
+    const double iu0 = inv_(u0);
+    const double ir = inv_(r);
+    const double iS = inv_(S);
     const double A1 = m[M_HRR] * ur + m[M_HRP] * up;
     const double B1 = m[M_HRP] * ur + m[M_HPP] * up;
     double urb = 0.0, utb = 0.0, upb = 0.0, rb = 0.0, iu0b = 0.0, u0b = 0.0;
@@ -252,7 +293,7 @@ __host__ __device__ inline void rhs_vjp(const Geo& G, double eps, double xi, dou
     upb += uub * (2.0 * m[M_HRP] * ur + 2.0 * m[M_HPP] * up);
     // metric quantities -> r, theta -> xi, eta
     double thb = 0.0;
-    metric_vjp_at(G, xi, eta, mb, rb, thb);
+    metric_vjp_at(G, t, mb, rb, thb);
     yb[0] += rb * r * G.dlnr;
     yb[1] += thb * G.dth;
     ub[0] += urb;
@@ -303,15 +344,15 @@ __host__ __device__ inline void boris(const double m[M_N], double qm, double dt,
     for (int i = 0; i < 3; ++i) T.um[i] = u[i] + T.hk * T.Dl[i];
     const double uu = m[M_HRR] * T.um[0] * T.um[0] + 2.0 * m[M_HRP] * T.um[0] * T.um[2]
                     + m[M_HTT] * T.um[1] * T.um[1] + m[M_HPP] * T.um[2] * T.um[2];
-    T.S = ::sqrt(1.0 + uu);
+    T.S = sqrt_(1.0 + uu);
     T.u0b = T.S * m[M_IALPHA];
-    T.tf = 0.5 * qm * dt / T.u0b;
+    T.tf = 0.5 * qm * dt * inv_(T.u0b);
     for (int i = 0; i < 3; ++i) T.t[i] = T.tf * B[i];
     T.tt = m[M_GRR] * T.t[0] * T.t[0] + 2.0 * m[M_GRP] * T.t[0] * T.t[2]
          + m[M_GTT] * T.t[1] * T.t[1] + m[M_GPP] * T.t[2] * T.t[2];
     cross(m, T.um, T.t, T.x1);
     for (int i = 0; i < 3; ++i) T.ut[i] = T.um[i] + T.x1[i];
-    T.sf = 2.0 / (1.0 + T.tt);
+    T.sf = 2.0 * inv_(1.0 + T.tt);
     for (int i = 0; i < 3; ++i) T.s[i] = T.sf * T.t[i];
     double x2[3];
     cross(m, T.ut, T.s, x2);
@@ -350,10 +391,10 @@ __host__ __device__ inline void boris_vjp(const double m[M_N], double qm, double
     double tfb = 0.0;
     for (int i = 0; i < 3; ++i) { tfb += tb[i] * B[i]; Bb[i] += tb[i] * T.tf; }
     // tf = qm dt / (2 u0b); u0b = S ialpha; S = sqrt(1 + uu)
-    const double u0bb = -tfb * T.tf / T.u0b;
+    const double u0bb = -tfb * T.tf * inv_(T.u0b);
     const double Sb = u0bb * m[M_IALPHA];
     mb[M_IALPHA] += u0bb * T.S;
-    const double uub = 0.5 * Sb / T.S;
+    const double uub = 0.5 * Sb * inv_(T.S);
     mb[M_HRR] += uub * T.um[0] * T.um[0];
     mb[M_HRP] += uub * 2.0 * T.um[0] * T.um[2];
     mb[M_HTT] += uub * T.um[1] * T.um[1];
@@ -487,8 +528,9 @@ __host__ __device__ inline int replay_step(const Geo& G, const FieldT* const F[6
         T.D[c] = gather(G, F[c], xi0 - stag_r(c), eta0 - stag_t(c));
         T.B[c] = gather(G, F[3 + c], xi0 - stag_r(3 + c), eta0 - stag_t(3 + c));
     }
-    double m0[M_N], r0;
-    metric_at(G, xi0, eta0, m0, r0);
+    double m0[M_N];
+    const Trig t0 = trig_at(G, xi0, eta0);
+    metric_at(G, t0, m0);
     if (massless) {
         for (int c = 0; c < 3; ++c) T.up[c] = u[c];
     } else {
@@ -497,14 +539,15 @@ __host__ __device__ inline int replay_step(const Geo& G, const FieldT* const F[6
     }
     const double eps = massless ? 0.0 : 1.0;
     double f0[5], f1[5];
-    rhs(G, eps, m0, r0, T.up[0], T.up[1], T.up[2], f0);
+    rhs(G, eps, m0, t0.r, T.up[0], T.up[1], T.up[2], f0);
     const double y0[5] = {xi0, eta0, 0.0, T.up[0], T.up[1]};
     for (int c = 0; c < 5; ++c) { T.pts[0][c] = y0[c]; T.y[c] = y0[c] + dt * f0[c]; }
     for (int it = 0; it < ncorr; ++it) {
         for (int c = 0; c < 5; ++c) T.pts[it + 1][c] = T.y[c];
-        double m[M_N], r;
-        metric_at(G, T.y[0], T.y[1], m, r);
-        rhs(G, eps, m, r, T.y[3], T.y[4], T.up[2], f1);
+        double m[M_N];
+        const Trig t = trig_at(G, T.y[0], T.y[1]);
+        metric_at(G, t, m);
+        rhs(G, eps, m, t.r, T.y[3], T.y[4], T.up[2], f1);
         for (int c = 0; c < 5; ++c) T.y[c] = y0[c] + 0.5 * dt * (f1[c] + f0[c]);
     }
     bool finite = isfinite(T.y[0]) && isfinite(T.y[1]) && isfinite(T.y[2]) && isfinite(T.y[3]) &&
@@ -557,7 +600,7 @@ __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F
         double g[5], pyb[2] = {0.0, 0.0}, pub[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 5; ++c) { y0b[c] += z[c]; f0b[c] += h * z[c]; g[c] = h * z[c]; }
         const double* P = T.pts[m];
-        rhs_vjp(G, eps, P[0], P[1], P[3], P[4], T.up[2], g, pyb, pub);
+        rhs_vjp(G, eps, trig_at(G, P[0], P[1]), P[3], P[4], T.up[2], g, pyb, pub);
         z[0] = pyb[0];
         z[1] = pyb[1];
         z[2] = 0.0;                          // f does not depend on phi
@@ -567,9 +610,10 @@ __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F
     }
     for (int c = 0; c < 5; ++c) { y0b[c] += z[c]; f0b[c] += dt * z[c]; }
     // f0 = f(y0) at x^n; its metric adjoint goes into the position
+    const Trig t0 = trig_at(G, T.xi0, T.eta0);
     {
         double pyb[2] = {0.0, 0.0}, pub[3] = {0.0, 0.0, 0.0};
-        rhs_vjp(G, eps, T.xi0, T.eta0, T.up[0], T.up[1], T.up[2], f0b, pyb, pub);
+        rhs_vjp(G, eps, t0, T.up[0], T.up[1], T.up[2], f0b, pyb, pub);
         y0b[0] += pyb[0];
         y0b[1] += pyb[1];
         upb[0] += pub[0];
@@ -583,15 +627,16 @@ __host__ __device__ inline void reverse_step(const Geo& G, const FieldT* const F
     if (massless) {
         for (int c = 0; c < 3; ++c) ub[c] = upb[c];
     } else {
-        double m0[M_N], mb[M_N], r0;
-        metric_at(G, T.xi0, T.eta0, m0, r0);
+        double m0[M_N], mb[M_N];
+        const double r0 = t0.r;
+        metric_at(G, t0, m0);
         for (int i = 0; i < M_N; ++i) mb[i] = 0.0;
         BorisTape bt;
         double up[3];
         boris(m0, qm, dt, T.D, T.B, T.u, up, bt);
         boris_vjp(m0, qm, dt, T.D, T.B, bt, upb, ub, Db, Bb, mb);
         double rb = 0.0, thb = 0.0;
-        metric_vjp_at(G, T.xi0, T.eta0, mb, rb, thb);
+        metric_vjp_at(G, t0, mb, rb, thb);
         xib += rb * r0 * G.dlnr;
         etab0 += thb * G.dth;
     }
