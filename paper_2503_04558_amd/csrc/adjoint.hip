@@ -59,11 +59,14 @@ __global__ __launch_bounds__(256) void lam_row_any(const BackArgs B, int* __rest
     if (threadIdx.x == 0) row_flag[i] = any;
 }
 
-__global__ __launch_bounds__(256) void lam_col_any(const BackArgs B, int* __restrict__ col_flag) {
+// (only the rows that lam_row_any found non-zero are read)
+__global__ __launch_bounds__(256) void lam_col_any(const BackArgs B, const int* __restrict__ row_flag,
+                                                   int* __restrict__ col_flag) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= B.pitch) return;
     int any = 0;
     for (int i = 0; i < B.rows; ++i) {
+        if (!row_flag[i]) continue;
         const int64_t e = (int64_t)i * B.pitch + j;
         any |= (B.lam[0][e] != 0.0) | (B.lam[1][e] != 0.0) | (B.lam[2][e] != 0.0);
     }
@@ -139,7 +142,8 @@ hipError_t launch_push_deposit_backward(BackArgs B, void* aux, hipStream_t strea
     B.row_pre = row_pre;
     B.col_pre = col_pre;
     hipLaunchKernelGGL(lam_row_any, dim3((unsigned)B.rows), dim3(256), 0, stream, B, row_flag);
-    hipLaunchKernelGGL(lam_col_any, dim3((unsigned)((B.pitch + 255) / 256)), dim3(256), 0, stream, B, col_flag);
+    hipLaunchKernelGGL(lam_col_any, dim3((unsigned)((B.pitch + 255) / 256)), dim3(256), 0, stream, B, row_flag,
+                       col_flag);
     hipLaunchKernelGGL(lam_prefix, dim3(1), dim3(128), 0, stream, B, row_flag, col_flag, row_pre, col_pre);
     const dim3 grid((unsigned)((B.count + kBackThreads - 1) / kBackThreads));
     if (B.ncorr == kFastCorr)
