@@ -2,12 +2,7 @@
 
 Usage: python -m paper_2503_04558_amd.build
 
-Each source is compiled to an object (in parallel), then linked.  The
-adjoint kernels are compiled at -O2: at -O3 this compiler turns the reverse
-sweep (a 256-VGPR kernel that also spills to AGPRs and scratch) into code
-that returns NaN for every particle, while the same source at -O2, on the
-host at -O3, and under the host address and undefined-behaviour sanitizers
-gives the oracle's derivatives.
+Each source is compiled to an object (in parallel) at -O3, then linked.
 """
 from __future__ import annotations
 
@@ -31,7 +26,6 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",   # no packed FP32 ops
     "-Wno-unused-command-line-argument",
 ]
-OPT = {"adjoint.hip": "-O2"}                     # default -O3
 
 
 def sources() -> list[str]:
@@ -40,7 +34,7 @@ def sources() -> list[str]:
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, OPT.get(os.path.basename(src), "-O3"), *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+    cmd = [HIPCC, "-O3", *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
