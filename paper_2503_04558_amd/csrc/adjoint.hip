@@ -95,10 +95,19 @@ __global__ __launch_bounds__(128) void lam_prefix(const BackArgs B, const int* _
 // few times fewer global atomics than adding every step.
 constexpr int kBackThreads = 256;
 
+// The three-corrector kernel keeps each thread's step tape in LDS (the
+// register file is this sweep's limit; at one wave per SIMD a workgroup has
+// the CU's LDS to itself).  A tape of 43 doubles (an odd count) puts the
+// 64-bit accesses of 16 consecutive lanes on distinct banks.
+template <int NC>
+constexpr bool kTapeInLds = NC == kFastCorr;
+static_assert(sizeof(adj::StepTape<kFastCorr>) == 43 * 8, "an odd number of doubles per tape");
+
 template <int NC>
 __global__ __launch_bounds__(kBackThreads) void push_deposit_backward_f64(const BackArgs B) {
     __shared__ double acc[6][4][kBackThreads];
     __shared__ long base[6][kBackThreads];
+    __shared__ adj::StepTape<NC> tapes[kTapeInLds<NC> ? kBackThreads : 1];
     const int t = threadIdx.x;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + t;
     if (q >= B.count) return;                   // (no barrier below: the slots are per thread)
@@ -111,6 +120,8 @@ __global__ __launch_bounds__(kBackThreads) void push_deposit_backward_f64(const 
         for (int k = 0; k < 4; ++k)
             if (acc[c][k][t] != 0.0) atomicAdd(g + e + off[k], acc[c][k][t]);
     };
+    adj::StepTape<NC> reg_tape;
+    adj::StepTape<NC>& T = kTapeInLds<NC> ? tapes[t] : reg_tape;
     backward_particle<NC>(B, q, [&](int c, long e, double g00, double g10, double g01, double g11) {
         if (base[c][t] != e) {
             flush(c);
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(kBackThreads) void push_deposit_backward_f64(const 
             acc[c][2][t] += g01;
             acc[c][3][t] += g11;
         }
-    });
+    }, T);
     for (int c = 0; c < 6; ++c) flush(c);
 }
 

@@ -34,9 +34,11 @@ __host__ __device__ inline bool all_zero(const double a[5]) {
 // and is skipped: a move is below one cell per step, so a segment of C steps
 // from a checkpoint in cell (i, j) deposits only on vertices within C + 2 of it.
 // Step k gathers from the field arrays B.F[c] + k fstride and its field
-// cotangents go to element e + k gstride of the gradient arrays.
+// cotangents go to element e + k gstride of the gradient arrays.  T is the
+// storage of the step's tape (the caller's choice: registers, or the
+// thread's slot of an LDS array).
 template <int NC, class AddF>
-__host__ __device__ inline void backward_particle(const BackArgs& B, int64_t q, AddF addF) {
+__host__ __device__ inline void backward_particle(const BackArgs& B, int64_t q, AddF addF, adj::StepTape<NC>& T) {
     const int64_t n = B.n, nb = B.count;
     const int64_t p = B.first + q;
     const int ncorr = NC == kFastCorr ? kFastCorr : B.ncorr;
@@ -74,7 +76,6 @@ __host__ __device__ inline void backward_particle(const BackArgs& B, int64_t q, 
                 const size_t fo = (size_t)(seg * C + m) * B.fstride;
                 const double* const Fk[6] = {B.F[0] + fo, B.F[1] + fo, B.F[2] + fo,
                                              B.F[3] + fo, B.F[4] + fo, B.F[5] + fo};
-                adj::StepTape<NC> T;
                 const int st = adj::replay_step(G, Fk, qm, massless, B.dt, ncorr, xi, eta, u, T);
                 if (st != adj::ST_ALIVE) { alive = false; continue; }
                 xi = T.xi1;
@@ -96,7 +97,6 @@ __host__ __device__ inline void backward_particle(const BackArgs& B, int64_t q, 
                 const long go = (long)(k * B.gstride);
                 const double* const Fk[6] = {B.F[0] + fo, B.F[1] + fo, B.F[2] + fo,
                                              B.F[3] + fo, B.F[4] + fo, B.F[5] + fo};
-                adj::StepTape<NC> T;
                 adj::replay_step(G, Fk, qm, massless, B.dt, ncorr, x0, e0, u0, T);
                 adj::reverse_step(G, Fk, B.lam, qm, massless, qw, B.dt, ncorr, T, a,
                                   [&](int c, long e, double g00, double g10, double g01, double g11) {
