@@ -348,3 +348,52 @@ def test_adjoint_full_set_sampled_against_oracle():
     assert np.all(got[zero_ref] == 0.0)                   # skipped segments give exact zeros
     assert (~zero_ref).sum() >= 40 and zero_ref.sum() >= 900
     assert np.all(err <= bar), np.flatnonzero(err > bar)[:5]
+
+
+def test_scattered_lambda_support():
+    """lambda non-zero on a few scattered grid points only (different rows
+    and columns, all three current components): the support prepass marks
+    those rows and columns, the reverse skips segments and steps whose
+    boxes hold no marked row or no marked column (a box may hold a marked
+    row of one point and a marked column of another: then it is not
+    skipped).  Particles near the points, and far from all of them, against
+    the oracle's dual numbers (which skip nothing); the far ones must get
+    exactly zero."""
+    _announce("adjoint, lambda on scattered points")
+    g = wl.make_grid(128, 128, 0.9)
+    dt = wl.crossing_dt(g)
+    fields = wl.wald_fields(g, B0=2.0)
+    sp = wl.species_table()
+    rng = np.random.default_rng(31)
+    pts = [(20, 30), (20, 90), (60, 64), (100, 15), (100, 110)]
+    lam = [np.zeros(g.shape) for _ in range(3)]
+    for k, (i, j) in enumerate(pts):
+        lam[k % 3][g.guard + i, g.guard + j] = dt * (1.0 + k)
+    nsteps, every = 16, 4
+    allp = wl.pairs(g, 100_000, kind="mj", seed=7, params=dict(T=0.5))
+    ci, cj = allp["cell"] // g.nth, allp["cell"] % g.nth
+    near = np.zeros(len(ci), dtype=bool)
+    for i, j in pts:
+        near |= (np.abs(ci - i) <= 1) & (np.abs(cj - j) <= 1)
+    far = (np.abs(ci - 60) > 30) & (np.abs(cj - 64) > 40) & ~near
+    far &= np.min([np.abs(ci - i) + np.abs(cj - j) for i, j in pts], axis=0) > nsteps + 6
+    pick = np.concatenate([rng.choice(np.flatnonzero(near), 300, replace=False),
+                           rng.choice(np.flatnonzero(far), 100, replace=False)])
+    parts = {k: v[pick] for k, v in allp.items()}
+    start, F, J, ck, _ = forward(g, sp, parts, fields, dt, nsteps=nsteps, ckpt_every=every)
+    gu, _ = backward(g, sp, start, F, lam, dt, ck, nsteps=nsteps, ckpt_every=every)
+    assert np.all(np.isfinite(gu))
+    ref = np.zeros_like(gu)
+    for p in range(len(pick)):
+        one = {k: v[p:p + 1] for k, v in parts.items()}
+        for k in range(3):
+            t = [np.zeros(1) for _ in range(3)]
+            t[k][0] = 1.0
+            _, ref[p, k], _ = orc.loss_dual(g, sp, one, fields, lam, dt, nsteps, tu=t)
+    scale = np.abs(ref).max(axis=1)
+    nz = scale > 0
+    _announce(f"scattered lambda: {int(nz.sum())} of {len(pick)} particles with a non-zero gradient")
+    assert nz[:300].sum() >= 100
+    assert np.all(gu[300:] == 0.0) and np.all(ref[300:] == 0.0)
+    err = np.abs(gu - ref).max(axis=1)
+    assert np.all(err <= 1e-9 * scale + 1e-13 * scale.max()), np.flatnonzero(err > 1e-9 * scale)[:5]
