@@ -15,13 +15,20 @@ namespace grpic {
 // A tile is a segment of kTileCells consecutive cells of one grid row
 // (theta is the contiguous direction, so a tile's particles are contiguous
 // in a cell-sorted particle array).  Each tile's particles are cut into
-// balanced slices of at most kSliceMax particles; one workgroup pushes one
-// slice, one particle per thread, and accumulates its current in an LDS
-// window that covers the tile plus kMarginRows rows and kMarginCols columns
-// of drift on each side.
+// balanced slices of at most slice_max_for(n, ...) particles; one workgroup
+// pushes one slice, one particle per thread, and accumulates its current in
+// an LDS window that covers the tile plus kMarginRows rows and kMarginCols
+// columns of drift on each side.
 constexpr int kTileCells = 64;
-constexpr int kPushThreads = 256;
-constexpr int kSliceMax = kPushThreads;                    // one particle per thread
+// Slice sizes (= workgroup sizes of the tiled push).  With the window
+// (28.8 KB) and the staged states a three-wave workgroup takes ~39 KB of
+// LDS, so four fit on a CU: the three waves per SIMD that the push's
+// registers allow.  Four-wave workgroups fit three per CU, but where a
+// tile's particles fit one of them, cutting the tile in two would repeat
+// the window's clear, set-up and flush; so dense tilings (more than
+// kSliceSparse particles per tile on average) take kSliceDense.
+constexpr int kSliceDense = 192;
+constexpr int kSliceSparse = 256;
 constexpr int kLaneGroups = 8;                             // lane permutation inside a slice
 constexpr int kMarginRows = 6;
 constexpr int kMarginCols = 4;
@@ -41,15 +48,21 @@ struct TilingHeader {
 // L2); entries without a slice have len = 0.
 struct Slice {
     int64_t start;            // first particle
-    int32_t len;              // particles in the slice (<= kSliceMax)
+    int32_t len;              // particles in the slice (<= the tiling's slice size)
     int32_t tile;             // row * tiles_per_row + column block
 };
 
 inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; }
-// At most n / kSliceMax + ntiles slices; 8 more entries because the table
+// The slice size of a tiling of n particle elements on an nr x nth grid (a
+// function of the three, so the sort and the push agree on it).
+inline int slice_max_for(int64_t n, int nr, int nth) {
+    const int64_t ntiles = (int64_t)nr * tiles_per_row(nth);
+    return n > (int64_t)kSliceSparse * ntiles ? kSliceDense : kSliceSparse;
+}
+// At most n / slice size + ntiles slices; 8 more entries because the table
 // is kept in dispatch order (below), which rounds each XCD's band up.
 inline int64_t slice_capacity(int64_t n, int nr, int nth) {
-    return n / kSliceMax + (int64_t)nr * tiles_per_row(nth) + 8;
+    return n / slice_max_for(n, nr, nth) + (int64_t)nr * tiles_per_row(nth) + 8;
 }
 // Layout: header, slice table (capacity entries), one int32 per slice that
 // a push with counters fills with the slice's live particle count (so that

@@ -10,7 +10,7 @@
 // (push_deposit_f64 / _split, push_deposit_f64_tiled / _split_tiled):
 //   push_deposit_f64        one thread per particle, any particle order,
 //                           deposit with global FP64 atomics;
-//   push_deposit_f64_tiled  one workgroup per slice (<= 256 particles) of a
+//   push_deposit_f64_tiled  one workgroup per slice (192 or 256 particles) of a
 //                           cell-sorted tile (see grpic_launch.hpp), one
 //                           particle per thread, deposit into an LDS window
 //                           with LDS FP64 atomics, one flush of the window's
@@ -84,7 +84,7 @@ struct TileAnchors {
     double s[kAnchorCols], c[kAnchorCols];
 };
 
-static_assert(kPushThreads >= 64 + kAnchorCols, "waves 1 and 2 fill the anchor table's columns");
+static_assert(kSliceDense >= 64 + kAnchorCols, "waves 1 and 2 fill the anchor table's columns");
 
 template <class R>
 __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int cj, const TileAnchors* T) {
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void push_deposit_split(const StepArgs A) {
 
 // QED: photon emission and pair conversion after the push (FP64, Boris,
 // CIC), with the created particles appended after the elements in use.
-template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1, bool QED = false>
+template <int THREADS, bool SPLIT, bool SHORT, int KICK, int ORDER = 1, bool QED = false>
 __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const Slice* __restrict__ slices,
                                                         int64_t slice_cap,
                                                         int32_t* __restrict__ slice_live,
@@ -470,7 +470,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     // order after the deposit, so that consecutive lanes store consecutive
     // particles (the loads stay in the pushing lanes: staging them too would
     // make each wave wait for its loads before the first barrier)
-    constexpr int kStage = kSliceMax + kSliceMax / 32;
+    constexpr int kStage = THREADS + THREADS / 32;
     __shared__ int st_kind[kStage], st_cell[kStage];
     __shared__ Elem<SPLIT> st_x[5][kStage];
     // the slice table is in dispatch order (XCD-aware bands, written so by
@@ -494,13 +494,13 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
-    // one particle per thread; lane t pushes particle (t % 8) * 32 + t / 8 of
-    // the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
+    // one particle per thread; lane t pushes particle (t % 8) * (THREADS / 8)
+    // + t / 8 of the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
     // the slice's cells and their LDS atomics rarely hit one address.  Its
     // state is loaded before the LDS set-up and the barrier (which waits for
     // LDS accesses only), so the loads overlap them.
     const int t = threadIdx.x;
-    const int slot = (t % kLaneGroups) * (kSliceMax / kLaneGroups) + t / kLaneGroups;
+    const int slot = (t % kLaneGroups) * (THREADS / kLaneGroups) + t / kLaneGroups;
     const PIdx pi{sl.start, (uint32_t)slot};
     const int64_t p = sl.start + slot;
     const bool mine = slot < sl.len && p < A.n;
@@ -509,7 +509,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
 
     double2* wflat = reinterpret_cast<double2*>(&win[0][0][0]);
     static_assert((3 * kWinRows * kWinCols) % 2 == 0, "the window is cleared in pairs");
-    for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols / 2; e += kPushThreads) wflat[e] = make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < 3 * kWinRows * kWinCols / 2; e += THREADS) wflat[e] = make_double2(0.0, 0.0);
     if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
     if constexpr (QED) {
         if (threadIdx.x == 0) {
@@ -635,7 +635,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int r0 = touched[0], nrow = any ? touched[1] - touched[0] + 1 : 0;
     const int c0 = touched[2], ncol = any ? touched[3] - touched[2] + 1 : 1;
     // rows to groups of 32 threads, columns to the threads of a group
-    for (int rr = threadIdx.x >> 5; rr < nrow; rr += kPushThreads >> 5) {
+    for (int rr = threadIdx.x >> 5; rr < nrow; rr += THREADS >> 5) {
         for (int cc = threadIdx.x & 31; cc < ncol; cc += 32) {
             const int r = r0 + rr, c = c0 + cc;
             const int gi = wi0 + r, gj = wj0 + c;
@@ -681,24 +681,25 @@ __global__ __launch_bounds__(256) void slice_live_sum(const int32_t* __restrict_
     }
 }
 
-template <bool SHORT, int KICK>
-__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
+// THREADS: the tiling's slice size (kSliceDense or kSliceSparse).
+template <int THREADS, bool SHORT, int KICK>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap,
     int32_t* slice_live, const double* anchors) {
-    push_deposit_tiled_body<false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<THREADS, false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
 }
 // The cubic shape's tiled kernel, at three waves per SIMD.
-template <bool SHORT>
-__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_spline3(
+template <int THREADS, bool SHORT>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_spline3(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
     const double* anchors) {
-    push_deposit_tiled_body<false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);
+    push_deposit_tiled_body<THREADS, false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);
 }
-template <bool SHORT>
-__global__ __launch_bounds__(kPushThreads) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_qed(
+template <int THREADS, bool SHORT>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_qed(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
     const double* anchors, const QedArgs Q) {
-    push_deposit_tiled_body<false, SHORT, kBoris, 1, true>(A, slices, slice_cap, slice_live, anchors, Q);
+    push_deposit_tiled_body<THREADS, false, SHORT, kBoris, 1, true>(A, slices, slice_cap, slice_live, anchors, Q);
 }
 
 // The QED step of one block of particles b .. b + 255 below `end`: one
@@ -849,12 +850,11 @@ inline QedLayout qed_layout(int64_t slices) {
 
 size_t qed_workspace_bytes(int64_t slice_cap) { return qed_layout(slice_cap).total; }
 
-template <bool SHORT>
-__global__ __launch_bounds__(kPushThreads) void push_deposit_split_tiled(const StepArgs A,
-                                                                         const Slice* __restrict__ slices,
-                                                                         int64_t slice_cap, int32_t* slice_live,
-                                                                         const double* anchors) {
-    push_deposit_tiled_body<true, SHORT, kBoris>(A, slices, slice_cap, slice_live, anchors);
+template <int THREADS, bool SHORT>
+__global__ __launch_bounds__(THREADS) void push_deposit_split_tiled(const StepArgs A, const Slice* __restrict__ slices,
+                                                                    int64_t slice_cap, int32_t* slice_live,
+                                                                    const double* anchors) {
+    push_deposit_tiled_body<THREADS, true, SHORT, kBoris>(A, slices, slice_cap, slice_live, anchors);
 }
 
 // The anchor table of a tiled launch (layout in grpic_launch.hpp).
@@ -965,9 +965,20 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
             hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0,
                                stream, A, anchors, rows, cols);
         }
-        const dim3 g((unsigned)((slice_cap + 7) / 8 * 8)), b(kPushThreads);
-        if (sh) hipLaunchKernelGGL(push_deposit_f64_tiled_qed<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors, Q);
-        else hipLaunchKernelGGL(push_deposit_f64_tiled_qed<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors, Q);
+        const dim3 g((unsigned)((slice_cap + 7) / 8 * 8));
+        if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense) {
+            const dim3 b(kSliceDense);
+            if (sh) hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceDense, true>), g, b, 0, stream, A, slices,
+                                       slice_cap, live, anchors, Q);
+            else hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceDense, false>), g, b, 0, stream, A, slices,
+                                    slice_cap, live, anchors, Q);
+        } else {
+            const dim3 b(kSliceSparse);
+            if (sh) hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceSparse, true>), g, b, 0, stream, A, slices,
+                                       slice_cap, live, anchors, Q);
+            else hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceSparse, false>), g, b, 0, stream, A, slices,
+                                    slice_cap, live, anchors, Q);
+        }
         if (A.counters)
             hipLaunchKernelGGL(slice_live_sum, dim3(64), dim3(256), 0, stream, live, slice_cap, A.counters);
     }
@@ -992,6 +1003,38 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
     return hipGetLastError();
 }
 
+// The tiled kernel for the launch's shape, precision, kick and order, at
+// slice size THREADS.
+template <int THREADS>
+void launch_tiled_kernel(const StepArgs& A, bool split, bool sh, int kick, int order, dim3 g, const Slice* slices,
+                         int64_t slice_cap, int32_t* live, const double* anchors, hipStream_t stream) {
+    const dim3 b(THREADS);
+    if (order == 3 && sh)                                // FP64, Boris kick (checked by the caller)
+        hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<THREADS, true>), g, b, 0, stream, A, slices, slice_cap,
+                           live, anchors);
+    else if (order == 3)
+        hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<THREADS, false>), g, b, 0, stream, A, slices, slice_cap,
+                           live, anchors);
+    else if (split && sh)
+        hipLaunchKernelGGL((push_deposit_split_tiled<THREADS, true>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
+    else if (split)
+        hipLaunchKernelGGL((push_deposit_split_tiled<THREADS, false>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
+    else if (kick == kVay && sh)
+        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, true, kVay>), g, b, 0, stream, A, slices, slice_cap, live,
+                           anchors);
+    else if (kick == kVay)
+        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, false, kVay>), g, b, 0, stream, A, slices, slice_cap,
+                           live, anchors);
+    else if (sh)
+        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, true, kBoris>), g, b, 0, stream, A, slices, slice_cap,
+                           live, anchors);
+    else
+        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, false, kBoris>), g, b, 0, stream, A, slices, slice_cap,
+                           live, anchors);
+}
+
 hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
                                      hipStream_t stream, int kick, int order) {
     if (A.n <= 0) return hipSuccess;
@@ -1005,28 +1048,13 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
                            stream, A, anchors, rows, cols);
     }
     const int64_t grid = (slice_cap + 7) / 8 * 8;
-    const dim3 g((unsigned)grid), b(kPushThreads);
     const bool sh = A.small_steps == 2;
-    if (order == 3 && sh)                                // FP64, Boris kick (checked by the caller)
-        hipLaunchKernelGGL(push_deposit_f64_tiled_spline3<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
-    else if (order == 3)
-        hipLaunchKernelGGL(push_deposit_f64_tiled_spline3<false>, g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
-    else if (split && sh)
-        hipLaunchKernelGGL(push_deposit_split_tiled<true>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
-    else if (split)
-        hipLaunchKernelGGL(push_deposit_split_tiled<false>, g, b, 0, stream, A, slices, slice_cap, live, anchors);
-    else if (kick == kVay && sh)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<true, kVay>), g, b, 0, stream, A, slices, slice_cap, live, anchors);
-    else if (kick == kVay)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<false, kVay>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
-    else if (sh)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<true, kBoris>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
+    if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense)
+        launch_tiled_kernel<kSliceDense>(A, split, sh, kick, order, dim3((unsigned)grid), slices, slice_cap, live,
+                                         anchors, stream);
     else
-        hipLaunchKernelGGL((push_deposit_f64_tiled<false, kBoris>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
+        launch_tiled_kernel<kSliceSparse>(A, split, sh, kick, order, dim3((unsigned)grid), slices, slice_cap, live,
+                                          anchors, stream);
     if (A.counters)
         hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, live, slice_cap, A.counters);
     return hipGetLastError();

@@ -200,7 +200,7 @@ void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* bloc
 
 // Number of slices of each tile, from the scanned cell offsets.
 __global__ __launch_bounds__(256) void tile_slice_counts(const unsigned long long* __restrict__ offs, int nr, int nth,
-                                                         int tpr, unsigned long long* __restrict__ ns) {
+                                                         int tpr, int smax, unsigned long long* __restrict__ ns) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ntiles = (int64_t)nr * tpr;
     if (t > ntiles) return;
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void tile_slice_counts(const unsigned long lon
     const int64_t c0 = (int64_t)i * nth + (int64_t)jb * kTileCells;
     const int64_t c1 = c0 + min(kTileCells, nth - jb * kTileCells);
     const unsigned long long cnt = offs[c1] - offs[c0];
-    ns[t] = (cnt + kSliceMax - 1) / kSliceMax;
+    ns[t] = (cnt + smax - 1) / smax;
 }
 
 __global__ __launch_bounds__(256) void slices_empty(Slice* __restrict__ out, int64_t cap) {
@@ -329,7 +329,7 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
         TilingHeader* hdr = static_cast<TilingHeader*>(S.tiling);
         Slice* slices = reinterpret_cast<Slice*>(hdr + 1);
         hipLaunchKernelGGL(tile_slice_counts, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.nr, S.nth,
-                           tpr, S.tile_slices);
+                           tpr, slice_max_for(S.n, S.nr, S.nth), S.tile_slices);
         scan_exclusive(S.tile_slices, ntiles + 1, S.blocksums, stream);
         const int64_t cap = slice_capacity(S.n, S.nr, S.nth);
         hipLaunchKernelGGL(slices_empty, dim3(nblk(cap)), dim3(256), 0, stream, slices, cap);

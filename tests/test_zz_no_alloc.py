@@ -40,8 +40,12 @@ def _sort(g, parts, noalloc):
 
 
 def _slice_table_bytes(g, n):
-    """Header and slice table of a tiling (the parts the sort writes)."""
-    cap = n // 256 + g.nr * ((g.nth + 63) // 64) + 8
+    """Header and slice table of a tiling (the parts the sort writes): slices
+    of 192 particles where the tiles (64 cells of a row) hold more than 256
+    on average, else of 256."""
+    ntiles = g.nr * ((g.nth + 63) // 64)
+    smax = 192 if n > 256 * ntiles else 256
+    cap = n // smax + ntiles + 8
     return 40 + 16 * cap
 
 
