@@ -123,7 +123,11 @@ double crossing_time_cached(const grpic_metric* m, const grpic_grid* g) {
 struct TilingInfo {
     int64_t n;
     int nr, nth;
+    double lnr0, dlnr, dth;          // the grid its anchor table was computed for
 };
+bool tiling_matches(const TilingInfo& t, int64_t n, const grpic_grid* g) {
+    return t.n == n && t.nr == g->nr && t.nth == g->nth && t.lnr0 == g->lnr0 && t.dlnr == g->dlnr && t.dth == g->dth;
+}
 std::mutex g_tiling_mu;
 std::map<const void*, TilingInfo> g_tilings;
 
@@ -280,8 +284,7 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
     if (tiling) {
         std::lock_guard<std::mutex> lk(g_tiling_mu);
         auto it = g_tilings.find(tiling);
-        if (it == g_tilings.end() || it->second.n != parts->n || it->second.nr != grid->nr ||
-            it->second.nth != grid->nth)
+        if (it == g_tilings.end() || !tiling_matches(it->second, parts->n, grid))
             return fail(GRPIC_EINVAL, "tiling was not written by grpic_sort for %lld particles on this grid",
                         (long long)parts->n);
     }
@@ -386,8 +389,7 @@ int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
     if (tiling) {
         std::lock_guard<std::mutex> lk(g_tiling_mu);
         auto it = g_tilings.find(tiling);
-        if (it == g_tilings.end() || it->second.n != parts->n || it->second.nr != grid->nr ||
-            it->second.nth != grid->nth)
+        if (it == g_tilings.end() || !tiling_matches(it->second, parts->n, grid))
             return fail(GRPIC_EINVAL, "tiling was not written by grpic_sort for %lld particles on this grid",
                         (long long)parts->n);
     }
@@ -618,11 +620,14 @@ static int sort_checked(const grpic_grid* grid, const grpic_particles* in, grpic
     S.cell_offsets = cell_offsets;
     S.n_alive = n_alive_dev;
     S.tiling = tiling;
+    S.lnr0 = grid->lnr0;
+    S.dlnr = grid->dlnr;
+    S.dth = grid->dth;
     if ((rc = hip_status(grpic::launch_sort(S, static_cast<hipStream_t>(stream)), "sort launch"))) return rc;
     if (tiling) {
         std::lock_guard<std::mutex> lk(g_tiling_mu);
         if (g_tilings.size() > 4096) g_tilings.clear();
-        g_tilings[tiling] = TilingInfo{in->n, grid->nr, grid->nth};
+        g_tilings[tiling] = TilingInfo{in->n, grid->nr, grid->nth, grid->lnr0, grid->dlnr, grid->dth};
     }
     return GRPIC_OK;
 }

@@ -67,8 +67,9 @@ inline int64_t slice_capacity(int64_t n, int nr, int nth) {
 // Layout: header, slice table (capacity entries), one int32 per slice that
 // a push with counters fills with the slice's live particle count (so that
 // the count needs no same-address atomics; a small kernel sums it), then
-// (8-byte aligned) the anchor table that each tiled push fills before it
-// runs: r at the corners of rows -kMarginRows .. nr + kMarginRows - 1, then
+// (8-byte aligned) the anchor table, which depends on the grid only and is
+// written by the sort: r at the corners of rows -kMarginRows .. nr +
+// kMarginRows - 1, then
 // sin and cos at columns -kMarginCols .. tiles_per_row * kTileCells +
 // kMarginCols, i.e. every anchor a tile's window can ask for.
 inline int anchor_table_rows(int nr) { return nr + 2 * kMarginRows; }
@@ -124,6 +125,7 @@ struct SortArgs {
     int64_t* cell_offsets;            // optional output, ncell + 1
     int64_t* n_alive;                 // device output
     void* tiling;                     // optional output, tiling_bytes()
+    double lnr0, dlnr, dth;           // the grid's geometry (the tiling's anchor table)
 };
 
 // Reverse sweep of K push + deposit steps (adjoint.hip).
@@ -161,6 +163,10 @@ int64_t sort_scan_blocks(int64_t len);
 void scan_exclusive(unsigned long long* a, int64_t len, unsigned long long* blocksums, hipStream_t stream);
 size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
+// The anchor table of a tiling (r at the rows' corners, sin and cos at the
+// columns'), which depends on the grid only: written by the sort.
+hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, void* tiling,
+                               int64_t slice_cap, hipStream_t stream);
 
 // The sort workspace that grpic_sort_noalloc uses: a static device array of
 // kSortScratchBytes per GPU; sort_scratch returns its address on the current

@@ -857,7 +857,8 @@ __global__ __launch_bounds__(THREADS) void push_deposit_split_tiled(const StepAr
     push_deposit_tiled_body<THREADS, true, SHORT, kBoris>(A, slices, slice_cap, slice_live, anchors);
 }
 
-// The anchor table of a tiled launch (layout in grpic_launch.hpp).
+// The anchor table of a tiling (layout in grpic_launch.hpp), from the same
+// anchor_r / anchor_sc as the untiled kernels' anchors.
 __global__ __launch_bounds__(256) void tile_anchor_table(const StepArgs A, double* __restrict__ anchors, int rows,
                                                          int cols) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -868,6 +869,20 @@ __global__ __launch_bounds__(256) void tile_anchor_table(const StepArgs A, doubl
         anchors[rows + t] = s;
         anchors[rows + cols + t] = c;
     }
+}
+
+hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, void* tiling,
+                               int64_t slice_cap, hipStream_t stream) {
+    StepArgs A{};
+    A.lnr0 = lnr0;
+    A.dlnr = dlnr;
+    A.dth = dth;
+    A.nr = nr;
+    A.nth = nth;
+    const int rows = anchor_table_rows(nr), cols = anchor_table_cols(nth);
+    hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0, stream,
+                       A, tiling_anchors(tiling, slice_cap), rows, cols);
+    return hipGetLastError();
 }
 
 // Q_ij += q w S_ij(x_p) over live particles (FP64 or split offsets).
@@ -959,12 +974,7 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
         const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
         const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
         int32_t* live = tiling_slice_live(tiling, slice_cap);
-        double* anchors = tiling_anchors(tiling, slice_cap);
-        if (A.small_steps) {
-            const int rows = anchor_table_rows(A.nr), cols = anchor_table_cols(A.nth);
-            hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0,
-                               stream, A, anchors, rows, cols);
-        }
+        const double* anchors = tiling_anchors(tiling, slice_cap);     // written by the sort
         const dim3 g((unsigned)((slice_cap + 7) / 8 * 8));
         if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense) {
             const dim3 b(kSliceDense);
@@ -1041,12 +1051,7 @@ hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling
     const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
     const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
     int32_t* live = tiling_slice_live(tiling, slice_cap);
-    double* anchors = tiling_anchors(tiling, slice_cap);
-    if (A.small_steps) {
-        const int rows = anchor_table_rows(A.nr), cols = anchor_table_cols(A.nth);
-        hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0,
-                           stream, A, anchors, rows, cols);
-    }
+    const double* anchors = tiling_anchors(tiling, slice_cap);         // written by the sort
     const int64_t grid = (slice_cap + 7) / 8 * 8;
     const bool sh = A.small_steps == 2;
     if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense)

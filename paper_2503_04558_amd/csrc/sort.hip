@@ -335,6 +335,8 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
         hipLaunchKernelGGL(slices_empty, dim3(nblk(cap)), dim3(256), 0, stream, slices, cap);
         hipLaunchKernelGGL(tile_slices, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.tile_slices, S.nr,
                            S.nth, tpr, S.n, cap, hdr, slices);
+        const hipError_t e = launch_anchor_table(S.lnr0, S.dlnr, S.dth, S.nr, S.nth, S.tiling, cap, stream);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(sort_offsets_out, dim3(nblk(len)), dim3(256), 0, stream, S.counts, S.ncell,
                        S.cell_offsets, S.n_alive);

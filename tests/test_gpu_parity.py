@@ -324,3 +324,24 @@ def test_dense_and_sparse_slice_sizes_agree(kind):
         assert np.array_equal(outs[0][k], outs[1][k]), k
     for a, b in zip(*Js):
         assert (a - b).abs().max().item() <= 1e-13 * a.abs().max().item()
+
+
+def test_tiling_is_tied_to_its_grid():
+    """A tiling carries the anchor table of the grid it was sorted on (r and
+    the angles at the cells' corners): a push on a grid with the same shape
+    but another radial range is refused, the same grid is accepted."""
+    g = wl.make_grid(32, 64, 0.99)
+    other = wl.make_grid(32, 64, 0.5)                   # another horizon, so another lnr0
+    assert other.lnr0 != g.lnr0
+    host = wl.pairs(g, 2000, kind="uniform", seed=3)
+    sorter = grpic.Sorter(g, len(host["cell"]))
+    parts = sorter.sort(grpic.to_device(host))
+    F = [torch.as_tensor(f).cuda() for f in wl.wald_fields(g)]
+    J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    dt = wl.crossing_dt(other)
+    with pytest.raises(grpic.GrpicError, match="tiling"):
+        grpic.grpic_push_deposit(grpic.make_metric(0.5, 1.0), other, wl.species_table(), parts, F, J, dt, 1,
+                                 tiling=sorter.tiling)
+    grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, wl.species_table(), parts, F, J,
+                             min(dt, wl.crossing_dt(g)), 1, tiling=sorter.tiling)
+    torch.cuda.synchronize()
