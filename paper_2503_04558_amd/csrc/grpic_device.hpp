@@ -314,16 +314,70 @@ __device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, R r, c
     }
 }
 
+// The same right-hand side at a point given by r, sin(theta), cos(theta)
+// alone (the corrector points, where nothing else needs the metric), with
+// App. A's quantities substituted so that it takes two hardware estimates
+// instead of five:
+//  - with Q = rho^2 + 2Mr = rho^2 (1 + z), the reciprocals of r, sin^2,
+//    rho^2 and Q come from one reciprocal of r sin^2 rho^2 Q (double; float
+//    takes two, of r sin^2 and of rho^2 Q, to stay in range);
+//  - u^0 = sqrt(eps + u^2)/alpha = sqrt((eps + u^2) Q / rho^2) and 1/u^0 come
+//    from one square root;
+//  - alpha = (1+z)^(-1/2) and beta^r = z/(1+z) = 2Mr/Q give -alpha u^0
+//    d alpha = u^0 d beta^r / 2, with d beta^r = 2M (rho^2 - 2r^2)/Q^2 in r
+//    and 4 M a^2 r sin cos / Q^2 in theta;
+//  - the gamma^ij derivatives share their factor 1/rho^4, so the quadratic
+//    form u_i u_j d gamma^ij is summed inside it.
+// Same values as geodesic_rhs_at on ks_metric's output, up to rounding.
+template <class R>
+__device__ __forceinline__ void geodesic_rhs_point(const StepArgs& A, R eps, R r, R s, R c,
+                                                   R ur, R ut, R up, R f[5]) {
+    const R a = R(A.a), M = R(A.M);
+    const R a2 = a * a, r2 = r * r, s2 = s * s;
+    const R rho2 = r2 + a2 * (c * c);
+    const R tMr = R(2) * M * r;
+    const R Q = rho2 + tMr;
+    const R rs2 = r * s2, rQ = rho2 * Q;
+    R x1, x2;                                           // 1/(r sin^2), 1/(rho^2 Q)
+    if constexpr (std::is_same<R, float>::value) {
+        x1 = rcp(rs2);
+        x2 = rcp(rQ);
+    } else {
+        const R iP = rcp(rs2 * rQ);
+        x1 = rQ * iP;
+        x2 = rs2 * iP;
+    }
+    const R ir = s2 * x1, is2 = r * x1;
+    const R irho2 = Q * x2, iQ = rho2 * x2;
+    const R beta = tMr * iQ;
+    const R ra2 = r2 + a2;
+    const R aur = a * ur;
+    const R uu = irho2 * (ra2 * ur * ur + R(2) * aur * up + ut * ut + is2 * up * up) - beta * ur * ur;
+    R u0, iu0;
+    sqrt_rsqrt((eps + uu) * (Q * irho2), u0, iu0);
+    f[0] = (irho2 * (ra2 * ur + a * up) * iu0 - beta * fma(ur, iu0, R(1))) * ir * R(A.idlnr);
+    f[1] = irho2 * ut * iu0 * R(A.idth);
+    f[2] = irho2 * (aur + is2 * up) * iu0;
+    const R iQ2 = iQ * iQ, irho4 = irho2 * irho2;
+    const R sc = s * c;
+    const R dbe0 = R(2) * M * (rho2 - R(2) * r2) * iQ2;
+    const R dbe1 = R(4) * M * a2 * r * sc * iQ2;
+    const R ur2 = ur * ur, up2 = up * up, ut2 = ut * ut;
+    const R quad0 = R(-2) * r * irho4 * (a2 * s2 * ur2 + R(2) * aur * up + ut2 + is2 * up2) - ur2 * dbe0;
+    const R quad1 = R(2) * sc * irho4 * (a2 * (ra2 * ur2 + R(2) * aur * up + ut2) - (rho2 - a2 * s2) * is2 * is2 * up2)
+                  - ur2 * dbe1;
+    const R hu0 = R(0.5) * u0 + ur, hiu0 = R(0.5) * iu0;
+    f[3] = dbe0 * hu0 - quad0 * hiu0;
+    f[4] = dbe1 * hu0 - quad1 * hiu0;
+}
+
 // Same, evaluating the metric at (xi, eta) from the anchor.
 template <bool SHORT, class R>
 __device__ __forceinline__ void geodesic_rhs(const StepArgs& A, const Anchor<R>& an, R eps, R xi, R eta,
                                              R ur, R ut, R up, R f[5]) {
     R r, s, c;
     point_at<SHORT>(A, an, xi, eta, r, s, c);
-    Metric<R> k;
-    MetricDeriv<R> d;
-    ks_metric<R, true>(R(A.a), R(A.M), r, s, c, k, &d);
-    geodesic_rhs_at(A, eps, r, k, d, ur, ut, up, f);
+    geodesic_rhs_point(A, eps, r, s, c, ur, ut, up, f);
 }
 
 // (v x w)_i = sqrt(gamma) eps_ijk v^j w^k; v covariant (raised here), w contravariant.

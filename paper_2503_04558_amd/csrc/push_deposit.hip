@@ -290,10 +290,7 @@ __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R 
     for (int it = 0; it < A.ncorr; ++it) {
         R r, sn, cs;
         point_rel<SHORT>(A, an, yt[0], yt[1], r, sn, cs);
-        Metric<R> k;
-        MetricDeriv<R> d;
-        ks_metric<R, true>(R(A.a), R(A.M), r, sn, cs, k, &d);
-        geodesic_rhs_at(A, eps, r, k, d, yt[3], yt[4], u[2], f1);
+        geodesic_rhs_point(A, eps, r, sn, cs, yt[3], yt[4], u[2], f1);
         for (int c = 0; c < 5; ++c) yt[c] = y0[c] + R(0.5) * dt * (f1[c] + f0[c]);
     }
 }
