@@ -293,6 +293,7 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
     grpic::StepArgs A;
     fill_common(A, metric, grid, species, nsp, parts);
     A.dt = dt;
+    A.idt = 1.0 / dt;
     A.ncorr = ncorr;
     for (int c = 0; c < 3; ++c) { A.F[c] = fields->D[c]; A.F[3 + c] = fields->B[c]; }
     A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;
@@ -400,6 +401,7 @@ int grpic_push_deposit_qed(const grpic_metric* metric, const grpic_grid* grid,
     grpic::StepArgs A;
     fill_common(A, metric, grid, species, nsp, parts);
     A.dt = dt;
+    A.idt = 1.0 / dt;
     A.ncorr = ncorr;
     for (int c = 0; c < 3; ++c) { A.F[c] = fields->D[c]; A.F[3 + c] = fields->B[c]; }
     A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;

@@ -26,7 +26,7 @@ struct StepArgs {
     int small_steps;                        // Taylor offsets: 2 with 2 dlnr, 2 dth <= kTinyArg, 1 <= kSmallArg, else 0
     int fp64_rows;                          // split precision: rows i < fp64_rows run in FP64
     int pole_cols;                          // split precision: columns this close to the axis run in FP64
-    double dt;
+    double dt, idt;                         // step, 1/step
     int ncorr, nsp;
     double q[kMaxSpecies], m[kMaxSpecies];
     double qm[kMaxSpecies];                 // q/m (0 for massless species)
@@ -48,11 +48,12 @@ struct Metric {
     R h_rr, h_rp, h_tt, h_pp;               // gamma^ij
     R sqrtg;                                // sqrt(det gamma_ij) = rho^2 sin sqrt(1+z)
     R ialpha;                               // 1/alpha = sqrt(1+z)
+    R ir;                                   // 1/r
 };
 
 template <class R>
 struct MetricDeriv {                        // [0] = d/dr, [1] = d/dtheta
-    R dal[2], dbe[2], dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];
+    R dbe[2], dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];
 };
 
 // 1/x from the hardware reciprocal estimate, refined by two Newton steps for
@@ -87,19 +88,22 @@ __device__ __forceinline__ void sqrt_rsqrt(float x, float& sq, float& rsq) {
 }
 
 // Kerr-Schild 3+1 quantities of App. A (mass M reinstated) at radius r and
-// polar angle with sine s, cosine c; with D set, their r and theta
-// derivatives (analytic).
+// polar angle with sine s, cosine c; with D set, the r and theta derivatives
+// (analytic) of beta^r and gamma^ij (the lapse's enters the geodesic
+// equation through beta^r's, as alpha^2 = 1 - beta^r).  1/rho^2 and 1/sin^2
+// come from one reciprocal of their product.
 template <class R, bool D>
 __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k, MetricDeriv<R>* d) {
     const R a2 = a * a, r2 = r * r, s2 = s * s;
     const R rho2 = r2 + a2 * (c * c);
-    const R irho2 = rcp(rho2);
+    const R iP = rcp(s2 * rho2);
+    const R irho2 = s2 * iP;
     const R z = R(2) * M * r * irho2;
     const R opz = R(1) + z;
     R sq, rsq;                                    // sqrt(1+z) = 1/alpha, 1/sqrt(1+z) = alpha
     sqrt_rsqrt(opz, sq, rsq);
     const R iopz = rsq * rsq;
-    const R is2 = rcp(s2);
+    const R is2 = rho2 * iP;
     const R ra2 = r2 + a2;
     const R Delta = ra2 - R(2) * M * r;
     const R Sigma = ra2 * ra2 - a2 * Delta * s2;
@@ -115,6 +119,7 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
     k.h_tt = irho2;
     k.h_pp = irho2 * is2;
     k.sqrtg = rho2 * s * sq;
+    k.ir = rcp(r);
     if constexpr (D) {
         const R irho4 = irho2 * irho2;
         const R sc = s * c;
@@ -122,10 +127,7 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
         const R dt_rho2 = R(-2) * a2 * sc;
         const R dz_r = R(2) * M * (rho2 - R(2) * r2) * irho4;
         const R dz_t = R(4) * M * a2 * r * sc * irho4;
-        const R al3 = k.alpha * iopz;            // (1+z)^(-3/2)
         const R al4 = iopz * iopz;               // (1+z)^(-2)
-        d->dal[0] = R(-0.5) * al3 * dz_r;
-        d->dal[1] = R(-0.5) * al3 * dz_t;
         d->dbe[0] = al4 * dz_r;
         d->dbe[1] = al4 * dz_t;
         d->dh_rp[0] = -a * dr_rho2 * irho4;
@@ -294,23 +296,24 @@ __device__ __forceinline__ void point_rel(const StepArgs& A, const Anchor<R>& an
 
 // Geodesic right-hand side of eq. particle-eom (no Lorentz force) in grid
 // units at a point with metric k, d; f = (dxi/dt, deta/dt, dphi/dt,
-// du_r/dt, du_th/dt), du_ph/dt = 0.
+// du_r/dt, du_th/dt), du_ph/dt = 0.  The lapse term -alpha u^0 d alpha is
+// written u^0 d beta^r / 2 (alpha^2 = 1 - beta^r).
 template <class R>
-__device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, R r, const Metric<R>& k,
+__device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, const Metric<R>& k,
                                                 const MetricDeriv<R>& d, R ur, R ut, R up, R f[5]) {
     const R uu = k.h_rr * ur * ur + R(2) * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
     R su, rsu;
     sqrt_rsqrt(eps + uu, su, rsu);
     const R u0 = su * k.ialpha;                               // u^0 = sqrt(eps + u^2)/alpha
     const R iu0 = rsu * k.alpha;
-    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) * rcp(r) * R(A.idlnr);
+    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) * k.ir * R(A.idlnr);
     f[1] = k.h_tt * ut * iu0 * R(A.idth);
     f[2] = (k.h_rp * ur + k.h_pp * up) * iu0;
-    const R hiu0 = R(0.5) * iu0;
+    const R hu0 = R(0.5) * u0 + ur, hiu0 = R(0.5) * iu0;
     for (int q = 0; q < 2; ++q) {
         const R quad = ur * ur * d.dh_rr[q] + R(2) * ur * up * d.dh_rp[q]
                      + ut * ut * d.dh_tt[q] + up * up * d.dh_pp[q];
-        f[3 + q] = -k.alpha * u0 * d.dal[q] + ur * d.dbe[q] - quad * hiu0;
+        f[3 + q] = d.dbe[q] * hu0 - quad * hiu0;
     }
 }
 
@@ -501,7 +504,7 @@ __device__ __forceinline__ Move make_move(double qw, double xi0, double eta0, do
 //   S11/3 + S10/6 + S01/6 + S00/3 = (wx1_a (2 wy1_b + wy0_b) + wx0_a (wy1_b + 2 wy0_b))/6.
 // The same values as the term-by-term form, up to rounding.
 template <class Add>
-__device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
+__device__ __forceinline__ void esirkepov(const Move& m, double idt, Add&& add) {
     double wx0[3], wx1[3], wy0[3], wy1[3];
     for (int a = 0; a < 3; ++a) {
         wx0[a] = shape1(m.xi0 - (double)(m.i0 + a));
@@ -509,7 +512,6 @@ __device__ __forceinline__ void esirkepov(const Move& m, double dt, Add&& add) {
         wy0[a] = shape1(m.eta0 - (double)(m.j0 + a));
         wy1[a] = shape1(m.eta1 - (double)(m.j0 + a));
     }
-    const double idt = rcp(dt);
     const double hf = -0.5 * m.qw * idt;                // -(q w / dt) / 2
     const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);   // (q w dphi / dt) / 6
     // A move that stays in one cell row (column) touches vertex rows i0, i0+1
@@ -575,14 +577,13 @@ __device__ __forceinline__ int fold_face(int j, int nth, double& sign) {
 // F^th prefix sum runs along with them), so only the five r-direction
 // weights of each end point and their prefix sums stay live.
 template <class Add>
-__device__ __forceinline__ void esirkepov3(const Move& m, double dt, int nth, Add&& add) {
+__device__ __forceinline__ void esirkepov3(const Move& m, double idt, int nth, Add&& add) {
     const int i0 = (int)floor(fmin(m.xi0, m.xi1)) - 1, j0 = (int)floor(fmin(m.eta0, m.eta1)) - 1;
     double wx0[5], wx1[5];
     for (int a = 0; a < 5; ++a) {
         wx0[a] = shape3(m.xi0 - (double)(i0 + a));
         wx1[a] = shape3(m.xi1 - (double)(i0 + a));
     }
-    const double idt = rcp(dt);
     const double hf = -0.5 * m.qw * idt;
     const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);
     double fx[4], runx = 0.0, runy = 0.0;

@@ -209,9 +209,13 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         MetricDeriv<double> d0;
         ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
         if (!massless) kick<KICK>(k0, A.qm[s], dt, D, B, u);
-        geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
+        geodesic_rhs_at(A, eps, k0, d0, u[0], u[1], u[2], f0);
     }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
+    // The corrector sums f0 + f1 before adding y0: forming y0 + dt/2 f0 once
+    // would round the absolute position (xi and eta run up to the grid size,
+    // so an ulp is ~2e-13 cells) once more per corrector, and the momentum
+    // picks that up through the metric and field gradients.
     const double y0[5] = {xi0, eta0, 0.0, u[0], u[1]};
     for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
     for (int it = 0; it < A.ncorr; ++it) {
@@ -283,15 +287,20 @@ __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R 
         MetricDeriv<R> d0;
         ks_metric<R, true>(R(A.a), R(A.M), r0, s0, c0, k0, &d0);
         if (!massless) boris_kick(k0, qm, dt, D, B, u);
-        geodesic_rhs_at(A, eps, r0, k0, d0, u[0], u[1], u[2], f0);
+        geodesic_rhs_at(A, eps, k0, d0, u[0], u[1], u[2], f0);
     }
     const R y0[5] = {dxr, dxt, R(0), u[0], u[1]};
-    for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
+    const R hdt = R(0.5) * dt;
+    R yh[5];
+    for (int c = 0; c < 5; ++c) {
+        yt[c] = y0[c] + dt * f0[c];
+        yh[c] = y0[c] + hdt * f0[c];
+    }
     for (int it = 0; it < A.ncorr; ++it) {
         R r, sn, cs;
         point_rel<SHORT>(A, an, yt[0], yt[1], r, sn, cs);
         geodesic_rhs_point(A, eps, r, sn, cs, yt[3], yt[4], u[2], f1);
-        for (int c = 0; c < 5; ++c) yt[c] = y0[c] + R(0.5) * dt * (f1[c] + f0[c]);
+        for (int c = 0; c < 5; ++c) yt[c] = yh[c] + hdt * f1[c];
     }
 }
 
@@ -389,8 +398,8 @@ template <int ORDER = 1>
 __device__ __forceinline__ void scatter_global(const StepArgs& A, const Move& mv) {
     double* const J[3] = {A.Fr, A.Fth, A.Gph};
     auto add = [&](int c, int i, int j, double v) { atomicAdd(elem(J[c], grid_index(A, i, j)), v); };
-    if constexpr (ORDER == 3) esirkepov3(mv, A.dt, A.nth, add);
-    else esirkepov(mv, A.dt, add);
+    if constexpr (ORDER == 3) esirkepov3(mv, A.idt, A.nth, add);
+    else esirkepov(mv, A.idt, add);
 }
 
 // Event counts of a workgroup: each wave adds its ballot counts to five LDS
@@ -568,7 +577,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
                 }
                 const int li = i3 - wi0, ljl = jlo - wj0, ljh = jhi - wj0;
                 if (li >= 0 && li + 4 < kWinRows && ljl >= 0 && ljh < kWinCols) {
-                    esirkepov3(mv, A.dt, A.nth,
+                    esirkepov3(mv, A.idt, A.nth,
                                [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
                     row_lo = li;
                     row_hi = li + 4;
@@ -581,7 +590,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             } else {
                 const int li = mv.i0 - wi0, lj = mv.j0 - wj0;
                 if (li >= 0 && li + 2 < kWinRows && lj >= 0 && lj + 2 < kWinCols) {
-                    esirkepov(mv, A.dt,
+                    esirkepov(mv, A.idt,
                               [&](int c, int i, int j, double v) { atomicAdd(&win[c][i - wi0][j - wj0], v); });
                     row_lo = li;
                     row_hi = li + 2;
