@@ -405,9 +405,9 @@ int grpic_charge(const grpic_grid* grid, const grpic_species* species, int nsp,
  * prefix sum of the per-cell counts.  tiling (optional, device, at least
  * grpic_tiling_bytes(grid, in->n) bytes) receives the slice table that
  * grpic_push_deposit's tiled path runs on: each 64-cell tile of a grid row
- * cut into slices of at most 192 particles when the tiles hold more than 256
- * elements on average (in->n over the tile count), else 256; the push
- * derives the same size from its n, which must equal in->n (checked).
+ * cut into balanced slices, once of at most 256 particles (for the CIC
+ * kernels) and once of at most 192 (for the cubic shape); the push must be
+ * given n equal to in->n and the same grid (checked).
  * ws: device workspace of at least
  * grpic_sort_workspace_bytes() bytes.  n_alive_dev: device int64 receiving
  * the live count.  Tags move with their particles when in and out both

@@ -299,7 +299,6 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
     A.Fr = J->Fr; A.Fth = J->Fth; A.Gph = J->Gph;
     A.counters = reinterpret_cast<unsigned long long*>(counters);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t cap = grpic::slice_capacity(parts->n, grid->nr, grid->nth);
     const size_t slot = grpic::checkpoint_slot_bytes(parts->n);
     for (int step = 0; step < nsteps; ++step) {
         if (ckpt && step % ckpt_every == 0) {
@@ -309,7 +308,7 @@ static int push_deposit(const grpic_metric* metric, const grpic_grid* grid, cons
                 return rc;
         }
         const bool split = parts->precision == GRPIC_FP32_SPLIT;
-        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, cap, s, kick, order)
+        const hipError_t e = tiling ? grpic::launch_push_deposit_tiled(A, split, tiling, s, kick, order)
                                     : grpic::launch_push_deposit(A, split, s, kick, order);
         if ((rc = hip_status(e, "push_deposit launch"))) return rc;
     }

@@ -48,12 +48,6 @@ struct Metric {
     R h_rr, h_rp, h_tt, h_pp;               // gamma^ij
     R sqrtg;                                // sqrt(det gamma_ij) = rho^2 sin sqrt(1+z)
     R ialpha;                               // 1/alpha = sqrt(1+z)
-    R ir;                                   // 1/r
-};
-
-template <class R>
-struct MetricDeriv {                        // [0] = d/dr, [1] = d/dtheta
-    R dbe[2], dh_rr[2], dh_rp[2], dh_tt[2], dh_pp[2];
 };
 
 // 1/x from the hardware reciprocal estimate, refined by two Newton steps for
@@ -88,12 +82,10 @@ __device__ __forceinline__ void sqrt_rsqrt(float x, float& sq, float& rsq) {
 }
 
 // Kerr-Schild 3+1 quantities of App. A (mass M reinstated) at radius r and
-// polar angle with sine s, cosine c; with D set, the r and theta derivatives
-// (analytic) of beta^r and gamma^ij (the lapse's enters the geodesic
-// equation through beta^r's, as alpha^2 = 1 - beta^r).  1/rho^2 and 1/sin^2
-// come from one reciprocal of their product.
-template <class R, bool D>
-__device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k, MetricDeriv<R>* d) {
+// polar angle with sine s, cosine c, as the kick needs them.  1/rho^2 and
+// 1/sin^2 come from one reciprocal of their product.
+template <class R>
+__device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k) {
     const R a2 = a * a, r2 = r * r, s2 = s * s;
     const R rho2 = r2 + a2 * (c * c);
     const R iP = rcp(s2 * rho2);
@@ -119,26 +111,6 @@ __device__ __forceinline__ void ks_metric(R a, R M, R r, R s, R c, Metric<R>& k,
     k.h_tt = irho2;
     k.h_pp = irho2 * is2;
     k.sqrtg = rho2 * s * sq;
-    k.ir = rcp(r);
-    if constexpr (D) {
-        const R irho4 = irho2 * irho2;
-        const R sc = s * c;
-        const R dr_rho2 = R(2) * r;
-        const R dt_rho2 = R(-2) * a2 * sc;
-        const R dz_r = R(2) * M * (rho2 - R(2) * r2) * irho4;
-        const R dz_t = R(4) * M * a2 * r * sc * irho4;
-        const R al4 = iopz * iopz;               // (1+z)^(-2)
-        d->dbe[0] = al4 * dz_r;
-        d->dbe[1] = al4 * dz_t;
-        d->dh_rp[0] = -a * dr_rho2 * irho4;
-        d->dh_rp[1] = -a * dt_rho2 * irho4;
-        d->dh_tt[0] = -dr_rho2 * irho4;
-        d->dh_tt[1] = -dt_rho2 * irho4;
-        d->dh_rr[0] = R(-2) * r * a2 * s2 * irho4 - d->dbe[0];
-        d->dh_rr[1] = R(2) * a2 * ra2 * sc * irho4 - d->dbe[1];
-        d->dh_pp[0] = R(-2) * r * irho4 * is2;
-        d->dh_pp[1] = -(dt_rho2 * s2 + R(2) * rho2 * sc) * irho4 * is2 * is2;
-    }
 }
 
 // exp(x), sin(y), cos(y) for the small offsets of the predictor-corrector
@@ -295,32 +267,10 @@ __device__ __forceinline__ void point_rel(const StepArgs& A, const Anchor<R>& an
 }
 
 // Geodesic right-hand side of eq. particle-eom (no Lorentz force) in grid
-// units at a point with metric k, d; f = (dxi/dt, deta/dt, dphi/dt,
-// du_r/dt, du_th/dt), du_ph/dt = 0.  The lapse term -alpha u^0 d alpha is
-// written u^0 d beta^r / 2 (alpha^2 = 1 - beta^r).
-template <class R>
-__device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, const Metric<R>& k,
-                                                const MetricDeriv<R>& d, R ur, R ut, R up, R f[5]) {
-    const R uu = k.h_rr * ur * ur + R(2) * k.h_rp * ur * up + k.h_tt * ut * ut + k.h_pp * up * up;
-    R su, rsu;
-    sqrt_rsqrt(eps + uu, su, rsu);
-    const R u0 = su * k.ialpha;                               // u^0 = sqrt(eps + u^2)/alpha
-    const R iu0 = rsu * k.alpha;
-    f[0] = ((k.h_rr * ur + k.h_rp * up) * iu0 - k.beta) * k.ir * R(A.idlnr);
-    f[1] = k.h_tt * ut * iu0 * R(A.idth);
-    f[2] = (k.h_rp * ur + k.h_pp * up) * iu0;
-    const R hu0 = R(0.5) * u0 + ur, hiu0 = R(0.5) * iu0;
-    for (int q = 0; q < 2; ++q) {
-        const R quad = ur * ur * d.dh_rr[q] + R(2) * ur * up * d.dh_rp[q]
-                     + ut * ut * d.dh_tt[q] + up * up * d.dh_pp[q];
-        f[3 + q] = d.dbe[q] * hu0 - quad * hiu0;
-    }
-}
-
-// The same right-hand side at a point given by r, sin(theta), cos(theta)
-// alone (the corrector points, where nothing else needs the metric), with
-// App. A's quantities substituted so that it takes two hardware estimates
-// instead of five:
+// units at the point with radius r and polar angle of sine s, cosine c:
+// f = (dxi/dt, deta/dt, dphi/dt, du_r/dt, du_th/dt), du_ph/dt = 0.  App. A's
+// lapse, shift and gamma^ij and their r and theta derivatives are
+// substituted into it, so that it takes two hardware estimates:
 //  - with Q = rho^2 + 2Mr = rho^2 (1 + z), the reciprocals of r, sin^2,
 //    rho^2 and Q come from one reciprocal of r sin^2 rho^2 Q (double; float
 //    takes two, of r sin^2 and of rho^2 Q, to stay in range);
@@ -331,7 +281,6 @@ __device__ __forceinline__ void geodesic_rhs_at(const StepArgs& A, R eps, const 
 //    and 4 M a^2 r sin cos / Q^2 in theta;
 //  - the gamma^ij derivatives share their factor 1/rho^4, so the quadratic
 //    form u_i u_j d gamma^ij is summed inside it.
-// Same values as geodesic_rhs_at on ks_metric's output, up to rounding.
 template <class R>
 __device__ __forceinline__ void geodesic_rhs_point(const StepArgs& A, R eps, R r, R s, R c,
                                                    R ur, R ut, R up, R f[5]) {

@@ -15,22 +15,22 @@ namespace grpic {
 // A tile is a segment of kTileCells consecutive cells of one grid row
 // (theta is the contiguous direction, so a tile's particles are contiguous
 // in a cell-sorted particle array).  Each tile's particles are cut into
-// balanced slices of at most slice_max_for(n, ...) particles; one workgroup
-// pushes one slice, one particle per thread, and accumulates its current in
-// an LDS window that covers the tile plus kMarginRows rows and kMarginCols
-// columns of drift on each side.
+// balanced slices; one workgroup pushes one slice, one particle per thread,
+// and accumulates its current in an LDS window that covers the tile plus
+// kMarginRows rows and kMarginCols columns of drift on each side.  The
+// tiling holds two cuts of the same tiles, one per kind of tiled kernel.
 constexpr int kTileCells = 64;
-// Slice sizes (= workgroup sizes of the tiled push).  With the window
-// (28.8 KB) and the staged states a three-wave workgroup takes ~39 KB of
-// LDS, so four fit on a CU: the three waves per SIMD that the push's
-// registers allow.  Four-wave workgroups fit three per CU, but where a
-// tile's particles fit one of them, cutting the tile in two would repeat
-// the window's clear, set-up and flush; so dense tilings (more than
-// kSliceSparse particles per tile on average) take kSliceDense.
-constexpr int kSliceDense = 192;
-constexpr int kSliceSparse = 256;
+// Slice size (= workgroup size) of the CIC kernels: four waves.  Their
+// FP64 push needs at most 128 VGPRs, and the window (14 x 75 vertices x 3
+// arrays, 25.2 KB) with the staged states takes 38.1 KB of LDS, so four
+// workgroups share a CU: four waves per SIMD.
+constexpr int kSliceThreads = 256;
+// Slice size of the cubic-shape kernel: three waves.  Its 65 LDS adds and
+// 96 gather loads per particle run markedly slower in four-wave slices
+// (measured: 5.0 against 2.8 ms for 2e7 particles on 2048^2).
+constexpr int kSliceThreads3 = 192;
 constexpr int kLaneGroups = 8;                             // lane permutation inside a slice
-constexpr int kMarginRows = 6;
+constexpr int kMarginRows = 5;
 constexpr int kMarginCols = 4;
 constexpr int kWinRows = 2 * kMarginRows + 4;              // vertex rows of the LDS window
 constexpr int kWinCols = kTileCells + 2 * kMarginCols + 3; // vertex columns of the LDS window
@@ -53,47 +53,50 @@ struct Slice {
 };
 
 inline int tiles_per_row(int nth) { return (nth + kTileCells - 1) / kTileCells; }
-// The slice size of a tiling of n particle elements on an nr x nth grid (a
-// function of the three, so the sort and the push agree on it).
-inline int slice_max_for(int64_t n, int nr, int nth) {
-    const int64_t ntiles = (int64_t)nr * tiles_per_row(nth);
-    return n > (int64_t)kSliceSparse * ntiles ? kSliceDense : kSliceSparse;
+// At most n / smax + ntiles slices of at most smax particles; 8 more entries
+// because the table is kept in dispatch order (below), which rounds each
+// XCD's band up.
+inline int64_t slice_capacity(int64_t n, int nr, int nth, int smax = kSliceThreads) {
+    return n / smax + (int64_t)nr * tiles_per_row(nth) + 8;
 }
-// At most n / slice size + ntiles slices; 8 more entries because the table
-// is kept in dispatch order (below), which rounds each XCD's band up.
-inline int64_t slice_capacity(int64_t n, int nr, int nth) {
-    return n / slice_max_for(n, nr, nth) + (int64_t)nr * tiles_per_row(nth) + 8;
-}
-// Layout: header, slice table (capacity entries), one int32 per slice that
-// a push with counters fills with the slice's live particle count (so that
-// the count needs no same-address atomics; a small kernel sums it), then
-// (8-byte aligned) the anchor table, which depends on the grid only and is
-// written by the sort: r at the corners of rows -kMarginRows .. nr +
-// kMarginRows - 1, then
-// sin and cos at columns -kMarginCols .. tiles_per_row * kTileCells +
-// kMarginCols, i.e. every anchor a tile's window can ask for.
+// Layout (byte offsets, each 8-byte aligned): the header; the CIC slice
+// table (cap entries) and one int32 per slice that a push with counters
+// fills with the slice's live particle count (so that the count needs no
+// same-address atomics; a small kernel sums it); the same two for the cubic
+// cut (cap3 entries); then the anchor table, which depends on the grid only
+// and is written by the sort: r at the corners of rows -kMarginRows .. nr +
+// kMarginRows - 1, then sin and cos at columns -kMarginCols ..
+// tiles_per_row * kTileCells + kMarginCols, i.e. every anchor a tile's
+// window can ask for.
 inline int anchor_table_rows(int nr) { return nr + 2 * kMarginRows; }
 inline int anchor_table_cols(int nth) { return tiles_per_row(nth) * kTileCells + 2 * kMarginCols + 1; }
-inline size_t tiling_anchor_offset(int64_t slice_cap) {
-    return (sizeof(TilingHeader) + (size_t)slice_cap * (sizeof(Slice) + sizeof(int32_t)) + 7) / 8 * 8;
+struct TilingLayout {
+    int64_t cap, cap3;                    // entries of the CIC and the cubic slice tables
+    size_t slices, live, slices3, live3, anchors, bytes;
+};
+inline size_t align8(size_t b) { return (b + 7) / 8 * 8; }
+inline TilingLayout tiling_layout(int64_t n, int nr, int nth) {
+    TilingLayout L;
+    L.cap = slice_capacity(n, nr, nth, kSliceThreads);
+    L.cap3 = slice_capacity(n, nr, nth, kSliceThreads3);
+    L.slices = sizeof(TilingHeader);
+    L.live = L.slices + (size_t)L.cap * sizeof(Slice);
+    L.slices3 = align8(L.live + (size_t)L.cap * sizeof(int32_t));
+    L.live3 = L.slices3 + (size_t)L.cap3 * sizeof(Slice);
+    L.anchors = align8(L.live3 + (size_t)L.cap3 * sizeof(int32_t));
+    L.bytes = L.anchors + sizeof(double) * ((size_t)anchor_table_rows(nr) + 2 * (size_t)anchor_table_cols(nth));
+    return L;
 }
-inline size_t tiling_bytes(int64_t n, int nr, int nth) {
-    return tiling_anchor_offset(slice_capacity(n, nr, nth)) +
-           sizeof(double) * ((size_t)anchor_table_rows(nr) + 2 * (size_t)anchor_table_cols(nth));
-}
-inline int32_t* tiling_slice_live(void* tiling, int64_t slice_cap) {
-    return reinterpret_cast<int32_t*>(reinterpret_cast<Slice*>(static_cast<TilingHeader*>(tiling) + 1) + slice_cap);
-}
-inline double* tiling_anchors(void* tiling, int64_t slice_cap) {
-    return reinterpret_cast<double*>(static_cast<char*>(tiling) + tiling_anchor_offset(slice_cap));
-}
+inline size_t tiling_bytes(int64_t n, int nr, int nth) { return tiling_layout(n, nr, nth).bytes; }
+template <class T>
+inline T* tiling_at(void* tiling, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(tiling) + off); }
 
 // ---------------------------------------------------------------- launchers
 // kick: kBoris (the generalised Boris kick) or kVay (FP64 only).  order:
 // the shape, 1 (CIC) or 3 (cubic spline: FP64, Boris kick).
 hipError_t launch_push_deposit(const StepArgs& A, bool split, hipStream_t stream, int kick = kBoris, int order = 1);
-hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream, int kick = kBoris, int order = 1);
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, hipStream_t stream,
+                                     int kick = kBoris, int order = 1);
 hipError_t launch_charge(const StepArgs& A, bool split, double* Q, hipStream_t stream, int order = 1);
 struct QedArgs;
 // One QED step (FP64, Boris, CIC): the tiled slices if a tiling is given,
@@ -165,8 +168,8 @@ size_t sort_workspace_bytes(int nr, int nth);
 hipError_t launch_sort(const SortArgs& S, hipStream_t stream);
 // The anchor table of a tiling (r at the rows' corners, sin and cos at the
 // columns'), which depends on the grid only: written by the sort.
-hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, void* tiling,
-                               int64_t slice_cap, hipStream_t stream);
+hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, double* anchors,
+                               hipStream_t stream);
 
 // The sort workspace that grpic_sort_noalloc uses: a static device array of
 // kSortScratchBytes per GPU; sort_scratch returns its address on the current

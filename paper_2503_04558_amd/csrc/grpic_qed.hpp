@@ -105,7 +105,7 @@ __device__ __forceinline__ void qed_after_step(const StepArgs& A, const QedArgs&
     double sn, cs;
     sincos(eta * A.dth, &sn, &cs);
     Metric<double> k;
-    ks_metric<double, false>(A.a, A.M, r, sn, cs, k, nullptr);
+    ks_metric<double>(A.a, A.M, r, sn, cs, k);
     double u[3] = {out.x[2], out.x[3], out.x[4]};
     const double uu = k.h_rr * u[0] * u[0] + 2.0 * k.h_rp * u[0] * u[2] + k.h_tt * u[1] * u[1] + k.h_pp * u[2] * u[2];
     const double umag = sqrt(uu);

@@ -10,7 +10,7 @@
 // (push_deposit_f64 / _split, push_deposit_f64_tiled / _split_tiled):
 //   push_deposit_f64        one thread per particle, any particle order,
 //                           deposit with global FP64 atomics;
-//   push_deposit_f64_tiled  one workgroup per slice (192 or 256 particles) of a
+//   push_deposit_f64_tiled  one workgroup per slice (up to 256 particles) of a
 //                           cell-sorted tile (see grpic_launch.hpp), one
 //                           particle per thread, deposit into an LDS window
 //                           with LDS FP64 atomics, one flush of the window's
@@ -84,7 +84,8 @@ struct TileAnchors {
     double s[kAnchorCols], c[kAnchorCols];
 };
 
-static_assert(kSliceDense >= 64 + kAnchorCols, "waves 1 and 2 fill the anchor table's columns");
+static_assert(kSliceThreads >= 64 + kAnchorCols && kSliceThreads3 >= 64 + kAnchorCols,
+              "waves 1 and 2 fill the anchor table's columns");
 
 template <class R>
 __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int cj, const TileAnchors* T) {
@@ -202,14 +203,15 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
     const Anchor<double> an = anchor_for<double>(A, ci, cj, T);
     double f0[5], f1[5], yt[5];
     {
-        // metric and derivatives at x^n serve both the kick and the first RHS
+        // the kick takes the metric at x^n; the first RHS is evaluated from
+        // r, sin, cos after it (the metric's derivatives and the six field
+        // values are then never live together)
         double r0, s0, c0;
         point_at<SHORT>(A, an, xi0, eta0, r0, s0, c0);
         Metric<double> k0;
-        MetricDeriv<double> d0;
-        ks_metric<double, true>(A.a, A.M, r0, s0, c0, k0, &d0);
+        ks_metric<double>(A.a, A.M, r0, s0, c0, k0);
         if (!massless) kick<KICK>(k0, A.qm[s], dt, D, B, u);
-        geodesic_rhs_at(A, eps, k0, d0, u[0], u[1], u[2], f0);
+        geodesic_rhs_point(A, eps, r0, s0, c0, u[0], u[1], u[2], f0);
     }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
     // The corrector sums f0 + f1 before adding y0: forming y0 + dt/2 f0 once
@@ -284,10 +286,9 @@ __device__ __forceinline__ void split_core(const StepArgs& A, int ci, int cj, R 
         R r0, s0, c0;
         point_rel<SHORT>(A, an, dxr, dxt, r0, s0, c0);
         Metric<R> k0;
-        MetricDeriv<R> d0;
-        ks_metric<R, true>(R(A.a), R(A.M), r0, s0, c0, k0, &d0);
+        ks_metric<R>(R(A.a), R(A.M), r0, s0, c0, k0);
         if (!massless) boris_kick(k0, qm, dt, D, B, u);
-        geodesic_rhs_at(A, eps, k0, d0, u[0], u[1], u[2], f0);
+        geodesic_rhs_point(A, eps, r0, s0, c0, u[0], u[1], u[2], f0);
     }
     const R y0[5] = {dxr, dxt, R(0), u[0], u[1]};
     const R hdt = R(0.5) * dt;
@@ -477,7 +478,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     // particles (the loads stay in the pushing lanes: staging them too would
     // make each wave wait for its loads before the first barrier)
     constexpr int kStage = THREADS + THREADS / 32;
-    __shared__ int st_kind[kStage], st_cell[kStage];
+    __shared__ int st_cell[kStage];                       // new cell; -1: removed; -2: nothing to store
     __shared__ Elem<SPLIT> st_x[5][kStage];
     // the slice table is in dispatch order (XCD-aware bands, written so by
     // the sort): one load finds this workgroup's slice
@@ -500,16 +501,19 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     const int j_lo = (sl.tile - ti * tpr) * kTileCells;
     const int wi0 = ti - kMarginRows - 1;                // window origin (vertex indices)
     const int wj0 = j_lo - kMarginCols - 1;
-    // one particle per thread; lane t pushes particle (t % 8) * (THREADS / 8)
-    // + t / 8 of the slice, so a wave's 64 lanes cover 8 runs of 8 particles spread over
-    // the slice's cells and their LDS atomics rarely hit one address.  Its
-    // state is loaded before the LDS set-up and the barrier (which waits for
-    // LDS accesses only), so the loads overlap them.
+    // one particle per thread; with S = ceil(len / 8), thread t < 8 S pushes
+    // particle (t % 8) S + t / 8 of the slice (a bijection of [0, 8 S)), so a
+    // wave's 64 lanes cover 8 runs of 8 particles spread over the slice's
+    // cells and their LDS atomics rarely hit one address, and the threads of
+    // a short slice's particles are the first ones (the waves after them skip
+    // the push).  Its state is loaded before the LDS set-up and the barrier
+    // (which waits for LDS accesses only), so the loads overlap them.
     const int t = threadIdx.x;
-    const int slot = (t % kLaneGroups) * (THREADS / kLaneGroups) + t / kLaneGroups;
+    const int run = (sl.len + kLaneGroups - 1) / kLaneGroups;
+    const int slot = (t % kLaneGroups) * run + t / kLaneGroups;
     const PIdx pi{sl.start, (uint32_t)slot};
     const int64_t p = sl.start + slot;
-    const bool mine = slot < sl.len && p < A.n;
+    const bool mine = t / kLaneGroups < run && slot < sl.len && p < A.n;
     ParticleIn<Elem<SPLIT>> in;
     if (mine) in = load_particle<Elem<SPLIT>>(A, pi);
 
@@ -560,8 +564,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
         const bool dep = advance<SPLIT, SHORT, KICK, ORDER>(A, pi, in, mv, ev, &tab, out);
         if constexpr (QED) qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
         const int si = slot + slot / 32;
-        st_kind[si] = out.kind;
-        st_cell[si] = out.cell;
+        st_cell[si] = out.kind == 2 ? out.cell : out.kind - 2;
         for (int k = 0; k < 5; ++k) st_x[k][si] = out.x[k];
         if (dep && mv.qw != 0.0) {                           // an uncharged move (a photon) adds only zeros
             if constexpr (ORDER == 3) {
@@ -626,8 +629,9 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (t < sl.len && sl.start + t < A.n) {
         const int si = t + t / 32;
         ParticleOut<Elem<SPLIT>> o;
-        o.kind = st_kind[si];
-        o.cell = st_cell[si];
+        const int sc = st_cell[si];
+        o.kind = sc >= 0 ? 2 : sc + 2;
+        o.cell = sc;
         for (int k = 0; k < 5; ++k) o.x[k] = st_x[k][si];
         store_particle(A, PIdx{sl.start, (uint32_t)t}, o);
     }
@@ -687,14 +691,17 @@ __global__ __launch_bounds__(256) void slice_live_sum(const int32_t* __restrict_
     }
 }
 
-// THREADS: the tiling's slice size (kSliceDense or kSliceSparse).
+// THREADS: the tiling's slice size (kSliceThreads).  With the short series
+// the CIC kernels run at four waves per SIMD (at most 128 VGPRs; four
+// workgroups' LDS fit a CU); the long series needs more registers and runs
+// at three.
 template <int THREADS, bool SHORT, int KICK>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(SHORT ? 4 : 3))) void push_deposit_f64_tiled(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap,
     int32_t* slice_live, const double* anchors) {
     push_deposit_tiled_body<THREADS, false, SHORT, KICK>(A, slices, slice_cap, slice_live, anchors);
 }
-// The cubic shape's tiled kernel, at three waves per SIMD.
+// The cubic shape's tiled kernel, at three or more waves per SIMD.
 template <int THREADS, bool SHORT>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_spline3(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) vo
     push_deposit_tiled_body<THREADS, false, SHORT, kBoris, 3>(A, slices, slice_cap, slice_live, anchors);
 }
 template <int THREADS, bool SHORT>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(3))) void push_deposit_f64_tiled_qed(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(SHORT ? 4 : 3))) void push_deposit_f64_tiled_qed(
     const StepArgs A, const Slice* __restrict__ slices, int64_t slice_cap, int32_t* slice_live,
     const double* anchors, const QedArgs Q) {
     push_deposit_tiled_body<THREADS, false, SHORT, kBoris, 1, true>(A, slices, slice_cap, slice_live, anchors, Q);
@@ -877,8 +884,8 @@ __global__ __launch_bounds__(256) void tile_anchor_table(const StepArgs A, doubl
     }
 }
 
-hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, void* tiling,
-                               int64_t slice_cap, hipStream_t stream) {
+hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int nth, double* anchors,
+                               hipStream_t stream) {
     StepArgs A{};
     A.lnr0 = lnr0;
     A.dlnr = dlnr;
@@ -887,7 +894,7 @@ hipError_t launch_anchor_table(double lnr0, double dlnr, double dth, int nr, int
     A.nth = nth;
     const int rows = anchor_table_rows(nr), cols = anchor_table_cols(nth);
     hipLaunchKernelGGL(tile_anchor_table, dim3((unsigned)((std::max(rows, cols) + 255) / 256)), dim3(256), 0, stream,
-                       A, tiling_anchors(tiling, slice_cap), rows, cols);
+                       A, anchors, rows, cols);
     return hipGetLastError();
 }
 
@@ -977,24 +984,16 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
     hipLaunchKernelGGL(qed_begin, dim3(1), dim3(1), 0, stream, Q.n_used, Q.tail_start, Q.cap,
                        Q.staged ? Q.st.count + slice_cap : nullptr);
     if (tiling) {
-        const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
-        const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
-        int32_t* live = tiling_slice_live(tiling, slice_cap);
-        const double* anchors = tiling_anchors(tiling, slice_cap);     // written by the sort
+        const TilingLayout L = tiling_layout(A.n, A.nr, A.nth);     // slice_cap == L.cap
+        const Slice* slices = tiling_at<const Slice>(tiling, L.slices);
+        int32_t* live = tiling_at<int32_t>(tiling, L.live);
+        const double* anchors = tiling_at<const double>(tiling, L.anchors);   // written by the sort
         const dim3 g((unsigned)((slice_cap + 7) / 8 * 8));
-        if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense) {
-            const dim3 b(kSliceDense);
-            if (sh) hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceDense, true>), g, b, 0, stream, A, slices,
-                                       slice_cap, live, anchors, Q);
-            else hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceDense, false>), g, b, 0, stream, A, slices,
-                                    slice_cap, live, anchors, Q);
-        } else {
-            const dim3 b(kSliceSparse);
-            if (sh) hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceSparse, true>), g, b, 0, stream, A, slices,
-                                       slice_cap, live, anchors, Q);
-            else hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceSparse, false>), g, b, 0, stream, A, slices,
-                                    slice_cap, live, anchors, Q);
-        }
+        const dim3 b(kSliceThreads);
+        if (sh) hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceThreads, true>), g, b, 0, stream, A, slices,
+                                   slice_cap, live, anchors, Q);
+        else hipLaunchKernelGGL((push_deposit_f64_tiled_qed<kSliceThreads, false>), g, b, 0, stream, A, slices,
+                                slice_cap, live, anchors, Q);
         if (A.counters)
             hipLaunchKernelGGL(slice_live_sum, dim3(64), dim3(256), 0, stream, live, slice_cap, A.counters);
     }
@@ -1019,55 +1018,50 @@ hipError_t launch_push_deposit_qed(const StepArgs& A, QedArgs Q, void* tiling, i
     return hipGetLastError();
 }
 
-// The tiled kernel for the launch's shape, precision, kick and order, at
-// slice size THREADS.
-template <int THREADS>
-void launch_tiled_kernel(const StepArgs& A, bool split, bool sh, int kick, int order, dim3 g, const Slice* slices,
-                         int64_t slice_cap, int32_t* live, const double* anchors, hipStream_t stream) {
-    const dim3 b(THREADS);
-    if (order == 3 && sh)                                // FP64, Boris kick (checked by the caller)
-        hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<THREADS, true>), g, b, 0, stream, A, slices, slice_cap,
-                           live, anchors);
-    else if (order == 3)
-        hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<THREADS, false>), g, b, 0, stream, A, slices, slice_cap,
-                           live, anchors);
-    else if (split && sh)
-        hipLaunchKernelGGL((push_deposit_split_tiled<THREADS, true>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
-    else if (split)
-        hipLaunchKernelGGL((push_deposit_split_tiled<THREADS, false>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
-    else if (kick == kVay && sh)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, true, kVay>), g, b, 0, stream, A, slices, slice_cap, live,
-                           anchors);
-    else if (kick == kVay)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, false, kVay>), g, b, 0, stream, A, slices, slice_cap,
-                           live, anchors);
-    else if (sh)
-        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, true, kBoris>), g, b, 0, stream, A, slices, slice_cap,
-                           live, anchors);
-    else
-        hipLaunchKernelGGL((push_deposit_f64_tiled<THREADS, false, kBoris>), g, b, 0, stream, A, slices, slice_cap,
-                           live, anchors);
-}
-
-hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, int64_t slice_cap,
-                                     hipStream_t stream, int kick, int order) {
+// The tiled kernel for the launch's shape, precision, kick and order: the
+// cubic shape runs the tiling's cubic cut, the CIC kernels the other one.
+hipError_t launch_push_deposit_tiled(const StepArgs& A, bool split, void* tiling, hipStream_t stream, int kick,
+                                     int order) {
     if (A.n <= 0) return hipSuccess;
-    const TilingHeader* hdr = static_cast<const TilingHeader*>(tiling);
-    const Slice* slices = reinterpret_cast<const Slice*>(hdr + 1);
-    int32_t* live = tiling_slice_live(tiling, slice_cap);
-    const double* anchors = tiling_anchors(tiling, slice_cap);         // written by the sort
-    const int64_t grid = (slice_cap + 7) / 8 * 8;
+    const TilingLayout L = tiling_layout(A.n, A.nr, A.nth);
+    const double* anchors = tiling_at<const double>(tiling, L.anchors);   // written by the sort
     const bool sh = A.small_steps == 2;
-    if (slice_max_for(A.n, A.nr, A.nth) == kSliceDense)
-        launch_tiled_kernel<kSliceDense>(A, split, sh, kick, order, dim3((unsigned)grid), slices, slice_cap, live,
-                                         anchors, stream);
-    else
-        launch_tiled_kernel<kSliceSparse>(A, split, sh, kick, order, dim3((unsigned)grid), slices, slice_cap, live,
-                                          anchors, stream);
+    const bool cubic = order == 3;                       // FP64, Boris kick (checked by the caller)
+    const int64_t cap = cubic ? L.cap3 : L.cap;
+    const Slice* slices = tiling_at<const Slice>(tiling, cubic ? L.slices3 : L.slices);
+    int32_t* live = tiling_at<int32_t>(tiling, cubic ? L.live3 : L.live);
+    const dim3 g((unsigned)((cap + 7) / 8 * 8));
+    if (cubic) {
+        const dim3 b(kSliceThreads3);
+        if (sh)
+            hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<kSliceThreads3, true>), g, b, 0, stream, A, slices, cap,
+                               live, anchors);
+        else
+            hipLaunchKernelGGL((push_deposit_f64_tiled_spline3<kSliceThreads3, false>), g, b, 0, stream, A, slices,
+                               cap, live, anchors);
+    } else {
+        const dim3 b(kSliceThreads);
+        if (split && sh)
+            hipLaunchKernelGGL((push_deposit_split_tiled<kSliceThreads, true>), g, b, 0, stream, A, slices, cap, live,
+                               anchors);
+        else if (split)
+            hipLaunchKernelGGL((push_deposit_split_tiled<kSliceThreads, false>), g, b, 0, stream, A, slices, cap, live,
+                               anchors);
+        else if (kick == kVay && sh)
+            hipLaunchKernelGGL((push_deposit_f64_tiled<kSliceThreads, true, kVay>), g, b, 0, stream, A, slices, cap,
+                               live, anchors);
+        else if (kick == kVay)
+            hipLaunchKernelGGL((push_deposit_f64_tiled<kSliceThreads, false, kVay>), g, b, 0, stream, A, slices, cap,
+                               live, anchors);
+        else if (sh)
+            hipLaunchKernelGGL((push_deposit_f64_tiled<kSliceThreads, true, kBoris>), g, b, 0, stream, A, slices, cap,
+                               live, anchors);
+        else
+            hipLaunchKernelGGL((push_deposit_f64_tiled<kSliceThreads, false, kBoris>), g, b, 0, stream, A, slices, cap,
+                               live, anchors);
+    }
     if (A.counters)
-        hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, live, slice_cap, A.counters);
+        hipLaunchKernelGGL(slice_live_sum, dim3(256), dim3(256), 0, stream, live, cap, A.counters);
     return hipGetLastError();
 }
 

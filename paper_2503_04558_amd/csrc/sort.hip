@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void tile_slices(const unsigned long long* __r
                                                    Slice* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ntiles = (int64_t)nr * tpr;
-    if (t == 0) {
+    if (t == 0 && hdr) {                                // the header: written with the CIC cut
         hdr->nslices = (int64_t)base[ntiles];
         hdr->n = n;
         hdr->n_sorted = (int64_t)offs[(int64_t)nr * nth];
@@ -329,16 +329,22 @@ hipError_t launch_sort(const SortArgs& S, hipStream_t stream) {
     if (S.tiling) {
         const int tpr = tiles_per_row(S.nth);
         const int64_t ntiles = (int64_t)S.nr * tpr;
+        const TilingLayout L = tiling_layout(S.n, S.nr, S.nth);
         TilingHeader* hdr = static_cast<TilingHeader*>(S.tiling);
-        Slice* slices = reinterpret_cast<Slice*>(hdr + 1);
-        hipLaunchKernelGGL(tile_slice_counts, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.nr, S.nth,
-                           tpr, slice_max_for(S.n, S.nr, S.nth), S.tile_slices);
-        scan_exclusive(S.tile_slices, ntiles + 1, S.blocksums, stream);
-        const int64_t cap = slice_capacity(S.n, S.nr, S.nth);
-        hipLaunchKernelGGL(slices_empty, dim3(nblk(cap)), dim3(256), 0, stream, slices, cap);
-        hipLaunchKernelGGL(tile_slices, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.tile_slices, S.nr,
-                           S.nth, tpr, S.n, cap, hdr, slices);
-        const hipError_t e = launch_anchor_table(S.lnr0, S.dlnr, S.dth, S.nr, S.nth, S.tiling, cap, stream);
+        // the two cuts, one after the other (they share the tile_slices workspace)
+        for (int cut = 0; cut < 2; ++cut) {
+            const int smax = cut == 0 ? kSliceThreads : kSliceThreads3;
+            const int64_t cap = cut == 0 ? L.cap : L.cap3;
+            Slice* slices = tiling_at<Slice>(S.tiling, cut == 0 ? L.slices : L.slices3);
+            hipLaunchKernelGGL(tile_slice_counts, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.nr, S.nth,
+                               tpr, smax, S.tile_slices);
+            scan_exclusive(S.tile_slices, ntiles + 1, S.blocksums, stream);
+            hipLaunchKernelGGL(slices_empty, dim3(nblk(cap)), dim3(256), 0, stream, slices, cap);
+            hipLaunchKernelGGL(tile_slices, dim3(nblk(ntiles + 1)), dim3(256), 0, stream, S.counts, S.tile_slices,
+                               S.nr, S.nth, tpr, S.n, cap, cut == 0 ? hdr : nullptr, slices);
+        }
+        const hipError_t e = launch_anchor_table(S.lnr0, S.dlnr, S.dth, S.nr, S.nth,
+                                                 tiling_at<double>(S.tiling, L.anchors), stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(sort_offsets_out, dim3(nblk(len)), dim3(256), 0, stream, S.counts, S.ncell,

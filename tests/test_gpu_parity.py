@@ -287,14 +287,13 @@ def test_sort_then_push_matches_unsorted():
 
 
 @pytest.mark.parametrize("kind", ["boris", "vay", "spline3", "split"])
-def test_dense_and_sparse_slice_sizes_agree(kind):
-    """A tiling cuts its tiles into slices of 256 particles where the tiles
-    hold at most 256 elements on average, else of 192 (a three-wave
-    workgroup).  The same 30,000 live particles, alone (234 per tile: 256)
-    and with 12,000 removed elements appended (328 per tile: 192), sorted
-    and pushed 6 steps tiled: the same particles, matched by tag, bit for
-    bit, and the same current up to summation order."""
-    _announce(f"slice sizes 192 / 256 ({kind})")
+def test_tiled_equals_untiled_with_removed_elements(kind):
+    """Each tiled kernel (256-particle slices, four waves per SIMD for CIC)
+    against its untiled form: 30,000 live particles with 12,000 removed
+    elements appended, pushed 6 steps untiled in generator order and tiled
+    after a sort; the same particles, matched by tag, bit for bit, and the
+    same current up to summation order."""
+    _announce(f"tiled vs untiled with removed elements ({kind})")
     g = wl.make_grid(64, 128, 0.99, guard=3)             # 64 x 2 tiles
     host = wl.pairs(g, 15_000, kind="uniform", seed=14, params=dict(umax=2.0))
     n = len(host["cell"])
@@ -308,11 +307,15 @@ def test_dense_and_sparse_slice_sizes_agree(kind):
     dt = wl.crossing_dt(g)
     kw = dict(kick="vay") if kind == "vay" else dict(order=3) if kind == "spline3" else {}
     outs, Js = [], []
-    for src in (host, padded):
-        sorter = grpic.Sorter(g, len(src["cell"]), prec, with_tag=True)
-        parts = sorter.sort(grpic.to_device(src, prec))
+    for tiled in (False, True):
+        parts = grpic.to_device(padded, prec)
+        sorter = None
+        if tiled:
+            sorter = grpic.Sorter(g, len(padded["cell"]), prec, with_tag=True)
+            parts = sorter.sort(parts)
         J = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
-        grpic.grpic_push_deposit(m, g, wl.species_table(), parts, F, J, dt, 6, tiling=sorter.tiling, **kw)
+        grpic.grpic_push_deposit(m, g, wl.species_table(), parts, F, J, dt, 6,
+                                 tiling=sorter.tiling if tiled else None, **kw)
         torch.cuda.synchronize()
         h = grpic.to_host(parts)
         live = h["cell"] >= 0

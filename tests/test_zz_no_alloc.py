@@ -39,14 +39,15 @@ def _sort(g, parts, noalloc):
     return grpic.to_host(out), offs.cpu().numpy(), int(n_alive.item()), tiling.cpu().numpy()
 
 
-def _slice_table_bytes(g, n):
-    """Header and slice table of a tiling (the parts the sort writes): slices
-    of 192 particles where the tiles (64 cells of a row) hold more than 256
-    on average, else of 256."""
+def _slice_tables(g, n):
+    """Byte ranges of a tiling that the sort writes: the header with the cut
+    into slices of at most 256 particles, and the cut into slices of at most
+    192 (tiles of 64 cells of a row; each table is followed by a live count
+    per entry that the push writes)."""
     ntiles = g.nr * ((g.nth + 63) // 64)
-    smax = 192 if n > 256 * ntiles else 256
-    cap = n // smax + ntiles + 8
-    return 40 + 16 * cap
+    cap, cap3 = n // 256 + ntiles + 8, n // 192 + ntiles + 8
+    s3 = (40 + 20 * cap + 7) // 8 * 8
+    return [(0, 40 + 16 * cap), (s3, s3 + 16 * cap3)]
 
 
 def _check_same(g, a, b):
@@ -56,8 +57,8 @@ def _check_same(g, a, b):
     assert na == nb and np.array_equal(oa, ob)
     assert np.array_equal(pa["cell"], pb["cell"])
     assert np.all(pa["cell"][na:] == -1) and np.all(pa["cell"][:na] >= 0)
-    k = _slice_table_bytes(g, n)
-    assert np.array_equal(ta[:k], tb[:k])
+    for lo, hi in _slice_tables(g, n):
+        assert np.array_equal(ta[lo:hi], tb[lo:hi])
     # within each cell the same particles (sorted by cell, so order by (cell, tag))
     for p in (pa, pb):
         order = np.lexsort((p["tag"][:na], p["cell"][:na]))
