@@ -348,3 +348,72 @@ def test_tiling_is_tied_to_its_grid():
     grpic.grpic_push_deposit(grpic.make_metric(g.a, g.M), g, wl.species_table(), parts, F, J,
                              min(dt, wl.crossing_dt(g)), 1, tiling=sorter.tiling)
     torch.cuda.synchronize()
+
+
+def _tiling_cuts(raw, n, g):
+    """The header and the two slice tables of a tiling's bytes (layout of
+    grpic_launch.hpp: a 40-byte header, the 256-particle cut and its live
+    counts, then, 8-byte aligned, the 192-particle cut)."""
+    hdr = np.frombuffer(raw[:24].tobytes(), dtype=np.int64)
+    dims = np.frombuffer(raw[24:40].tobytes(), dtype=np.int32)
+    ntiles = g.nr * ((g.nth + 63) // 64)
+    rec = np.dtype([("start", "<i8"), ("len", "<i4"), ("tile", "<i4")])
+    cap, cap3 = n // 256 + ntiles + 8, n // 192 + ntiles + 8
+    s3 = (40 + 20 * cap + 7) // 8 * 8
+    cut = np.frombuffer(raw[40:40 + 16 * cap].tobytes(), dtype=rec)
+    cut3 = np.frombuffer(raw[s3:s3 + 16 * cap3].tobytes(), dtype=rec)
+    return hdr, dims, [(256, cut), (192, cut3)]
+
+
+def test_tiling_cuts_cover_every_particle_once():
+    """Both cuts of a sorted tiling, read back from its bytes: every live
+    particle in exactly one slice of each cut; a slice inside one tile and
+    at most the cut's size; each tile cut into ceil(count / size) slices of
+    ceil(count / slices) (the last one the rest); slice L of the tile order
+    at entry (L % per_xcd) * 8 + L // per_xcd.  Ragged tiles: empty ones, a
+    crowded cell, and removed elements."""
+    g = wl.make_grid(48, 200, 0.99)                     # 4 tiles per row, the last one 8 cells wide
+    host = wl.pairs(g, 9000, kind="uniform", seed=21)
+    n = len(host["cell"])
+    host["cell"][: n // 10] = -1                         # removed
+    host["cell"][n // 10: n // 10 + 900] = 20 * g.nth + 70   # one crowded cell
+    host["cell"][(host["cell"] // g.nth) == 7] = -1      # an empty row of tiles
+    sorter = grpic.Sorter(g, n)
+    parts = sorter.sort(grpic.to_device(host))
+    torch.cuda.synchronize()
+    n_alive = int(sorter.n_alive.item())
+    cells = parts["cell"][:n_alive].cpu().numpy().astype(np.int64)
+    raw = sorter.tiling.cpu().numpy()
+    hdr, dims, cuts = _tiling_cuts(raw, n, g)
+    tpr = (g.nth + 63) // 64
+    assert hdr[1] == n and hdr[2] == n_alive
+    assert list(dims) == [g.nr, g.nth, tpr, 64]
+    tile_of = (cells // g.nth) * tpr + (cells % g.nth) // 64
+    counts = np.bincount(tile_of, minlength=g.nr * tpr)
+    first = np.concatenate([[0], np.cumsum(counts)])
+    for smax, cut in cuts:
+        used = cut[cut["len"] > 0]
+        if smax == 256:
+            assert hdr[0] == len(used)
+        cover = np.zeros(n_alive, dtype=np.int64)
+        for s in used:
+            assert 0 < s["len"] <= smax
+            cover[s["start"]: s["start"] + s["len"]] += 1
+            assert np.all(tile_of[s["start"]: s["start"] + s["len"]] == s["tile"])
+        assert np.all(cover == 1), smax
+        ns = -(-counts // smax)
+        order = np.lexsort((used["start"], used["tile"]))
+        assert len(used) == ns.sum()
+        per_xcd = (len(used) + 7) // 8
+        entry = {int(s["start"]): e for e, s in enumerate(cut) if s["len"] > 0}
+        L = 0
+        for t in range(g.nr * tpr):
+            if ns[t] == 0:
+                continue
+            each = -(-counts[t] // ns[t])
+            for k in range(ns[t]):
+                start = first[t] + k * each
+                assert entry[int(start)] == (L % per_xcd) * 8 + L // per_xcd
+                assert cut[entry[int(start)]]["len"] == min(each, counts[t] - k * each)
+                L += 1
+        assert L == len(order)
