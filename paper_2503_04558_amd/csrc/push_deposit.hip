@@ -190,11 +190,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         if constexpr (ORDER == 3) return spline3_f64(F[c], A, f, h);
         else return cic_f64(F[c], A, f, h);
     };
-    double D[3] = {gather(0, xi0 - 0.5, eta0), gather(1, xi0, eta0 - 0.5), gather(2, xi0, eta0)};
-    // Vay's kick holds more values live than Boris's: its D^i are summed
-    // before the B^i loads are issued, which keeps it within three waves'
-    // registers without spills (slower for the Boris kernel, which fits)
-    if constexpr (KICK == kVay) asm volatile("" : "+v"(D[0]), "+v"(D[1]), "+v"(D[2]) : : "memory");
+    const double D[3] = {gather(0, xi0 - 0.5, eta0), gather(1, xi0, eta0 - 0.5), gather(2, xi0, eta0)};
     const double B[3] = {gather(3, xi0, eta0 - 0.5), gather(4, xi0 - 0.5, eta0), gather(5, xi0 - 0.5, eta0 - 0.5)};
     const bool massless = A.massless[s] != 0;
     const double dt = A.dt;
