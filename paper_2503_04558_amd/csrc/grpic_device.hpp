@@ -416,10 +416,16 @@ __device__ __forceinline__ void kick(const Metric<R>& k, R qm, R dt, const R D[3
     else boris_kick(k, qm, dt, D, B, u);
 }
 
-// CIC weight W(x) = max(0, 1 - |x|).
-template <class R>
-__device__ __forceinline__ R shape1(R x) {
-    return fmax(R(0), R(1) - fabs(x));
+// CIC weights W(d - a) = max(0, 1 - |d - a|) of the vertices a = 0, 1, 2 of
+// a move's window, for an end point at d = x - i0 in [0, 2) from the
+// window's first vertex: with e = d - 1 they are max(0, -e), 1 - |e| and
+// max(0, e).  d - 1 and d - 2 are exact (d is a multiple of x's ulp, below
+// 2), so these are the values of the plain formula, bit for bit.
+__device__ __forceinline__ void cic_window_weights(double d, double w[3]) {
+    const double e = d - 1.0;
+    w[0] = fmax(0.0, -e);
+    w[1] = 1.0 - fabs(e);
+    w[2] = fmax(0.0, e);
 }
 
 // One particle move to deposit: charge q w, start and end point in grid
@@ -455,12 +461,11 @@ __device__ __forceinline__ Move make_move(double qw, double xi0, double eta0, do
 template <class Add>
 __device__ __forceinline__ void esirkepov(const Move& m, double idt, Add&& add) {
     double wx0[3], wx1[3], wy0[3], wy1[3];
-    for (int a = 0; a < 3; ++a) {
-        wx0[a] = shape1(m.xi0 - (double)(m.i0 + a));
-        wx1[a] = shape1(m.xi1 - (double)(m.i0 + a));
-        wy0[a] = shape1(m.eta0 - (double)(m.j0 + a));
-        wy1[a] = shape1(m.eta1 - (double)(m.j0 + a));
-    }
+    const double fi0 = (double)m.i0, fj0 = (double)m.j0;
+    cic_window_weights(m.xi0 - fi0, wx0);
+    cic_window_weights(m.xi1 - fi0, wx1);
+    cic_window_weights(m.eta0 - fj0, wy0);
+    cic_window_weights(m.eta1 - fj0, wy1);
     const double hf = -0.5 * m.qw * idt;                // -(q w / dt) / 2
     const double cp6 = m.qw * m.dphi * idt * (1.0 / 6.0);   // (q w dphi / dt) / 6
     // A move that stays in one cell row (column) touches vertex rows i0, i0+1

@@ -23,6 +23,7 @@
 #include "grpic_qed.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 namespace grpic {
@@ -34,8 +35,9 @@ typedef double double2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
 __device__ __forceinline__ double cic_f64(const double* __restrict__ F, const StepArgs& A, double f, double h) {
-    const int i = (int)floor(f), j = (int)floor(h);
-    const double wf = f - (double)i, wh = h - (double)j;
+    const double ff = floor(f), fh = floor(h);
+    const int i = (int)ff, j = (int)fh;
+    const double wf = f - ff, wh = h - fh;
     const uint32_t o = grid_index(A, i, j);
     const double2_a8 lo = *reinterpret_cast<const double2_a8*>(elem(F, o));
     const double2_a8 hi = *reinterpret_cast<const double2_a8*>(elem(F, o + (uint32_t)A.pitch));
@@ -65,6 +67,25 @@ __device__ __forceinline__ double spline3_f64(const double* __restrict__ F, cons
     // loads' results outlived the register file: 256 VGPRs and spills)
     asm volatile("" : "+v"(sum) : : "memory");
     return sum;
+}
+
+// Minimum (MAX: maximum) of v over the 64 lanes of a wave, all of them
+// active, returned wave-uniform.  DPP lane permutations combine pairs,
+// quads, half rows and rows of 16; the row broadcasts of lanes 15 and 31
+// then fold rows 0 and 2 into 1 and 3, and rows 0-1 into 2-3, so lane 63
+// holds the result.  Lanes a broadcast does not write keep the operation's
+// identity, so each step is one DPP min or max.
+template <bool MAX>
+__device__ __forceinline__ int wave_reduce(int v) {
+    const int identity = MAX ? INT_MIN : INT_MAX;
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x140, 0xF, 0xF, false));   // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x142, 0xA, 0xF, false));   // row_bcast:15 to rows 1, 3
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x143, 0xC, 0xF, false));   // row_bcast:31 to rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 struct Events {
@@ -602,12 +623,10 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        row_lo = min(row_lo, __shfl_xor(row_lo, off));
-        row_hi = max(row_hi, __shfl_xor(row_hi, off));
-        col_lo = min(col_lo, __shfl_xor(col_lo, off));
-        col_hi = max(col_hi, __shfl_xor(col_hi, off));
-    }
+    row_lo = wave_reduce<false>(row_lo);                 // every lane of the wave is active here
+    row_hi = wave_reduce<true>(row_hi);
+    col_lo = wave_reduce<false>(col_lo);
+    col_hi = wave_reduce<true>(col_hi);
     if constexpr (QED) {
         if (Q.staged) qed_stage(A, Q, logical, cr, qe, &q_total, q_ev);
         else qed_append<double>(A, Q, Q.n_used[0], cr, qe);
