@@ -126,9 +126,9 @@ __device__ __forceinline__ Anchor<R> anchor_for(const StepArgs& A, int ci, int c
 }
 
 // A particle's state as read at the start of a step (element type T: double,
-// or float in split precision); the weight is read later, where the deposit
-// needs it.  The tiled kernel issues these loads before its LDS set-up so
-// that their latency overlaps it.
+// or float in split precision); the weight is read by the step itself, after
+// the input checks.  The tiled kernel issues these loads before its LDS
+// set-up so that their latency overlaps it.
 template <class T>
 struct ParticleIn {
     int cell, s;
@@ -187,7 +187,9 @@ __device__ __forceinline__ void store_particle(const StepArgs& A, const PIdx& p,
 // Advances live particle p by one step; its new state goes to out.  Returns
 // true when the move is to be deposited (mv filled), false when the particle
 // was or became removed without a deposit.
-template <bool SHORT, int KICK, int ORDER>
+// EARLY_QW: read the move's charge before the correctors (the monopole
+// kernel, whose emission test holds more values live, reads it at the end).
+template <bool SHORT, int KICK, int ORDER, bool EARLY_QW = true>
 __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, const ParticleIn<double>& in, Move& mv,
                                             Events& ev, const TileAnchors* T, ParticleOut<double>& out) {
     out.kind = 0;
@@ -236,6 +238,10 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
     // so an ulp is ~2e-13 cells) once more per corrector, and the momentum
     // picks that up through the metric and field gradients.
     const double y0[5] = {xi0, eta0, 0.0, u[0], u[1]};
+    // the move's charge q w, read here so that its loads complete during the
+    // correctors (before the kick they would raise the register peak)
+    double qw = 0.0;
+    if constexpr (EARLY_QW) qw = A.q[s] * *p.at(w);
     for (int c = 0; c < 5; ++c) yt[c] = y0[c] + dt * f0[c];
     for (int it = 0; it < A.ncorr; ++it) {
         geodesic_rhs<SHORT>(A, an, eps, yt[0], yt[1], yt[3], yt[4], u[2], f1);
@@ -251,7 +257,8 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
     }
     if (eta1 < 0.0) { eta1 = -eta1; u1t = -u1t; ev.refl = 1; }
     else if (eta1 > (double)A.nth) { eta1 = 2.0 * A.nth - eta1; u1t = -u1t; ev.refl = 1; }
-    mv = make_move(A.q[s] * *p.at(w), xi0, eta0, xi1, eta1, yt[2]);
+    if constexpr (!EARLY_QW) qw = A.q[s] * *p.at(w);
+    mv = make_move(qw, xi0, eta0, xi1, eta1, yt[2]);
     if (A.phi) *p.at<double>(A.phi) += yt[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
@@ -343,6 +350,7 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, const PIdx& p, 
         ev.bad = 1;
         return false;
     }
+    const double qw = A.q[s] * (double)*p.at(w);          // read early, as in the FP64 step
     const int ci = div_by(cell, A.nth, A.inv_nth), cj = cell - ci * A.nth;
     const float* const* F = reinterpret_cast<const float* const*>(A.F);
     const float Df[3] = {cic_f32(F[0], A, ci, cj, fxr - 0.5f, fxt), cic_f32(F[1], A, ci, cj, fxr, fxt - 0.5f),
@@ -381,7 +389,7 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, const PIdx& p, 
     int j1 = (int)floor(eta1);
     if (j1 >= A.nth) j1 = A.nth - 1;
     const float ox = offset_f32(xi1 - (double)i1), oy = offset_f32(eta1 - (double)j1);
-    mv = make_move(A.q[s] * (double)*p.at(w), xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2]);
+    mv = make_move(qw, xi0, eta0, (double)i1 + (double)ox, (double)j1 + (double)oy, y[2]);
     if (A.phi) *p.at<float>(A.phi) += (float)y[2];
     if (xi1 < 0.0 || xi1 >= (double)A.nr) {
         ev.out = 1;
@@ -403,13 +411,14 @@ using Elem = typename std::conditional<SPLIT, float, double>::type;
 // SHORT: the short Taylor series, for grids fine enough for them
 // (small_steps == 2); the launch picks the kernel variant.
 // KICK: the momentum kick (kBoris, or kVay for the FP64 path only).
-// ORDER: the shape, 1 (CIC) or 3 (cubic spline, FP64 only).
-template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1>
+// ORDER: the shape, 1 (CIC) or 3 (cubic spline, FP64 only).  QED: the
+// monopole step's kernels (the charge is read at the end there).
+template <bool SPLIT, bool SHORT, int KICK, int ORDER = 1, bool QED = false>
 __device__ __forceinline__ bool advance(const StepArgs& A, const PIdx& p, const ParticleIn<Elem<SPLIT>>& in, Move& mv,
                                         Events& ev, const TileAnchors* T, ParticleOut<Elem<SPLIT>>& out) {
     static_assert(!SPLIT || (KICK == kBoris && ORDER == 1), "the split form runs the Boris kick and CIC only");
     if constexpr (SPLIT) return advance_split<SHORT>(A, p, in, mv, ev, T, out);
-    else return advance_f64<SHORT, KICK, ORDER>(A, p, in, mv, ev, T, out);
+    else return advance_f64<SHORT, KICK, ORDER, !QED>(A, p, in, mv, ev, T, out);
 }
 
 template <int ORDER = 1>
@@ -578,7 +587,7 @@ __device__ __forceinline__ void push_deposit_tiled_body(const StepArgs& A, const
     if (mine) {
         Move mv;
         ParticleOut<Elem<SPLIT>> out;
-        const bool dep = advance<SPLIT, SHORT, KICK, ORDER>(A, pi, in, mv, ev, &tab, out);
+        const bool dep = advance<SPLIT, SHORT, KICK, ORDER, QED>(A, pi, in, mv, ev, &tab, out);
         if constexpr (QED) qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
         const int si = slot + slot / 32;
         st_cell[si] = out.kind == 2 ? out.cell : out.kind - 2;
@@ -744,7 +753,7 @@ __device__ __forceinline__ void qed_block(const StepArgs& A, const QedArgs& Q, i
         Move mv;
         ParticleOut<double> out;
         const ParticleIn<double> in = load_particle<double>(A, pi);
-        const bool dep = advance<false, SHORT, kBoris, 1>(A, pi, in, mv, ev, nullptr, out);
+        const bool dep = advance<false, SHORT, kBoris, 1, true>(A, pi, in, mv, ev, nullptr, out);
         qed_after_step(A, Q, in.s, *pi.at(Q.tag), *pi.at<double>(A.w), out, cr, qe);
         store_particle(A, pi, out);
         if (dep && mv.qw != 0.0) scatter_global(A, mv);
