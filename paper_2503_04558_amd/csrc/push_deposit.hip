@@ -205,6 +205,9 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         ev.bad = 1;
         return false;
     }
+    // the kick's q/m, a per-lane read of the argument block: issued here so
+    // that it completes during the gather (it is live until the kick anyway)
+    const double qm = A.qm[s];
     const int ci = div_by(cell, A.nth, A.inv_nth), cj = cell - ci * A.nth;
     const double xi0 = (double)ci + dxr, eta0 = (double)cj + dxt;
     double u[3] = {in.u[0], in.u[1], in.u[2]};
@@ -229,7 +232,7 @@ __device__ __forceinline__ bool advance_f64(const StepArgs& A, const PIdx& p, co
         point_at<SHORT>(A, an, xi0, eta0, r0, s0, c0);
         Metric<double> k0;
         ks_metric<double>(A.a, A.M, r0, s0, c0, k0);
-        if (!massless) kick<KICK>(k0, A.qm[s], dt, D, B, u);
+        if (!massless) kick<KICK>(k0, qm, dt, D, B, u);
         geodesic_rhs_point(A, eps, r0, s0, c0, u[0], u[1], u[2], f0);
     }
     // geodesic predictor-corrector on y = (xi, eta, phi, u_r, u_th); u_ph is constant
@@ -351,14 +354,14 @@ __device__ __forceinline__ bool advance_split(const StepArgs& A, const PIdx& p, 
         return false;
     }
     const double qw = A.q[s] * (double)*p.at(w);          // read early, as in the FP64 step
+    const bool massless = A.massless[s] != 0;
+    const double qm = A.qm[s];
     const int ci = div_by(cell, A.nth, A.inv_nth), cj = cell - ci * A.nth;
     const float* const* F = reinterpret_cast<const float* const*>(A.F);
     const float Df[3] = {cic_f32(F[0], A, ci, cj, fxr - 0.5f, fxt), cic_f32(F[1], A, ci, cj, fxr, fxt - 0.5f),
                          cic_f32(F[2], A, ci, cj, fxr, fxt)};
     const float Bf[3] = {cic_f32(F[3], A, ci, cj, fxr, fxt - 0.5f), cic_f32(F[4], A, ci, cj, fxr - 0.5f, fxt),
                          cic_f32(F[5], A, ci, cj, fxr - 0.5f, fxt - 0.5f)};
-    const bool massless = A.massless[s] != 0;
-    const double qm = A.qm[s];
     double y[5], uph1;
     const bool fp64 = ci < A.fp64_rows || cj < A.pole_cols || cj >= A.nth - A.pole_cols;
     if (fp64) {
