@@ -331,3 +331,20 @@ def test_sort_noalloc_rejects_grids_beyond_its_scratch():
     ok = grpic.make_grid(wl.make_grid(64, 64, 0.9))
     rc = L.grpic_sort_noalloc(ctypes.byref(ok), ctypes.byref(parts), ctypes.byref(out), None, None, 0, None, None)
     assert rc == grpic.GRPIC_EINVAL and b"n_alive" in L.grpic_last_error()
+
+
+@pytest.mark.parametrize("nr,nth,n", [(48, 200, 9000), (2048, 2048, 200_000_000), (7, 64, 0), (5, 70, 3)])
+def test_tiling_bytes_follow_the_documented_layout(nr, nth, n):
+    """grpic_tiling_bytes against the layout the GPU tests read back: a
+    40-byte header, the 256-particle cut (16 B per entry) and its int32 live
+    counts, then 8-byte aligned the 192-particle cut and its counts, then 8-byte
+    aligned the anchor table (r at nr + 10 row corners, sin and cos at
+    tiles * 64 + 9 column corners)."""
+    g = wl.make_grid(nr, nth, 0.9)
+    ntiles = nr * ((nth + 63) // 64)
+    cap, cap3 = n // 256 + ntiles + 8, n // 192 + ntiles + 8
+    al = lambda b: (b + 7) // 8 * 8
+    s3 = al(40 + 20 * cap)
+    anchors = al(s3 + 20 * cap3)
+    cols = ((nth + 63) // 64) * 64 + 9
+    assert grpic.grpic_tiling_bytes(g, n) == anchors + 8 * ((nr + 10) + 2 * cols)
